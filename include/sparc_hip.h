@@ -1,0 +1,226 @@
+/* sparc_hip.h — C ABI of libsparc_hip: the Chebyshev-filtered subspace
+ * iteration (CheFSI) of the real-space finite-difference Kohn–Sham method for
+ * periodic systems (Ghosh & Suryanarayana, "SPARC ... Extended systems"), on
+ * one AMD MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *   - Status: every int-returning call returns SPARC_OK (0) or a negative
+ *     sparc_status.  Argument errors are detected on the host before anything
+ *     is launched; device errors are reported by the call that sees them or by
+ *     sparc_ctx_sync.  sparc_last_error() gives a message for the calling thread.
+ *   - Streams: all device work of a call is enqueued on the stream of its
+ *     context and is asynchronous unless the call returns host scalars (stated).
+ *   - Memory: "device" pointers are HIP device memory owned by the caller; the
+ *     library never frees caller memory.  Handles own only their own tables.
+ *     Workspace is passed in by the caller (sizes from sparc_workspace_bytes);
+ *     hot calls allocate nothing.
+ *   - Grid layout (Sec. 3.1): nodes (i,j,k), 0-based, flattened x-fastest,
+ *     g = i + n1*(j + n2*k); N_d = n1*n2*n3.
+ *   - Orbital blocks (Sec. 3.1, dense U(k) with orbitals as columns): column-
+ *     major N_d x N_s with leading dimension ld >= N_d; complex values are
+ *     interleaved (re, im).  Element type by the Hamiltonian's dtype: SPARC_R64
+ *     double, SPARC_R32 float (Gamma point, real), SPARC_C128 complex double,
+ *     SPARC_C64 complex float (any k).
+ *   - Orbitals are Euclidean-orthonormal (X^H X = I); densities carry 1/(h1h2h3).
+ *   - Bloch form: the operator acts on psi = e^{ik.x}u with the periodic index
+ *     map psi(i + n_s) = e^{i k_s L_s} psi(i) (Sec. 2 Kohn–Sham equations with
+ *     Bloch's theorem, Sec. 3.1 periodic boundary conditions).
+ */
+#ifndef SPARC_HIP_H
+#define SPARC_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPARC_OK = 0,
+  SPARC_EINVAL = -1,   /* bad argument (null pointer, bad enum, bad count)         */
+  SPARC_ESHAPE = -2,   /* inconsistent sizes (ld < N_d, n_s < 1, n_s > limits)     */
+  SPARC_ENOMEM = -3,   /* workspace too small, or a handle allocation failed       */
+  SPARC_ENOTSPD = -4,  /* Gram matrix not positive definite; info = failing column */
+  SPARC_ENOCONV = -5,  /* iteration limit reached without convergence              */
+  SPARC_EDEVICE = -6,  /* HIP runtime error                                        */
+  SPARC_ENAN = -7      /* NaN or Inf detected in a result                          */
+} sparc_status;
+
+typedef enum { SPARC_R64 = 0, SPARC_R32 = 1, SPARC_C128 = 2, SPARC_C64 = 3 } sparc_dtype;
+
+/* Precision of the N_d-long Rayleigh–Ritz contractions; the Cholesky factors,
+ * the subspace eigensolve and all N_s x N_s work stay in FP64. */
+typedef enum {
+  SPARC_GEMM_NATIVE = 0, /* in the element type of the orbitals (FP64 or FP32)     */
+  SPARC_GEMM_BF16X3 = 1  /* FP32 orbitals split into bf16 hi + lo, 3 MFMA products  */
+} sparc_gemm_mode;
+
+/* Uniform periodic grid on an axis-aligned cuboid (Sec. 3.1): n grid points and
+ * L lengths (bohr) per direction, stencil half-width n_o (12th order: 6), Bloch
+ * wavevector kpt (bohr^-1). */
+typedef struct {
+  int32_t n[3];
+  double L[3];
+  int32_t n_o;
+  double kpt[3];
+} sparc_grid;
+
+/* Synthetic atoms (host pointers, read during sparc_ham_create only).
+ * Local potential V_loc(x) = -sum_J sum_images D_J exp(-|x-R_J-L|^2/(2 w_J^2)),
+ * every image within 10 w_J.  Projector channel c belongs to atom chan_atom[c],
+ * has angular momentum chan_l[c] (0: one s function; 1: three real p functions
+ * x, y, z), energy chan_gamma[c] (Ha) and cutoff radius chan_rc[c] (bohr):
+ * chi_s = c exp(-r^2/(2 s^2)), chi_p,m = c (r_m/s) exp(-r^2/(2 s^2)) for r <= rc,
+ * s = rc/4, c normalising h1h2h3 * sum over the unwrapped grid of chi^2 to 1.
+ * Z: valence charge per atom (used for the atomic-superposition density). */
+typedef struct {
+  int32_t n_atoms;
+  const double* R;          /* [3*n_atoms], bohr                */
+  const double* vloc_depth; /* [n_atoms] D_J, Ha                */
+  const double* vloc_width; /* [n_atoms] w_J, bohr              */
+  int32_t n_chan;
+  const int32_t* chan_atom; /* [n_chan]                         */
+  const int32_t* chan_l;    /* [n_chan] 0 or 1                  */
+  const double* chan_gamma; /* [n_chan]                         */
+  const double* chan_rc;    /* [n_chan]                         */
+  const double* Z;          /* [n_atoms]                        */
+} sparc_atoms;
+
+typedef struct sparc_ctx sparc_ctx; /* device + stream                                    */
+typedef struct sparc_ham sparc_ham; /* one (cell, k, dtype): weights, V_eff, projector table */
+
+/* Context on device `device` enqueuing on `hip_stream` (a hipStream_t, or NULL
+ * for the default stream).  Returns SPARC_EDEVICE if the device is missing. */
+int sparc_ctx_create(int device, void* hip_stream, sparc_ctx** out);
+void sparc_ctx_destroy(sparc_ctx* ctx);
+/* Blocks until the context's stream is idle; returns the first pending device
+ * error as SPARC_EDEVICE. */
+int sparc_ctx_sync(sparc_ctx* ctx);
+/* Kernel timing by HIP events recorded on the context's stream around each
+ * launch of the named kernels ("hstep": the fused stencil/potential/non-local
+ * step; "nl_gather": the projections).  set_timing clears earlier records;
+ * kernel_time synchronises the stream and returns the summed milliseconds and
+ * the number of launches recorded since. */
+int sparc_ctx_set_timing(sparc_ctx* ctx, int enable);
+int sparc_ctx_kernel_time(sparc_ctx* ctx, const char* kernel, double* total_ms, int64_t* launches);
+/* Message describing the last error of the calling thread (never NULL). */
+const char* sparc_last_error(void);
+const char* sparc_status_string(int status);
+
+/* Builds the Hamiltonian of Sec. 2 / Sec. 3.1 for one cell at grid->kpt:
+ * FD weights (Sec. 3.1, weights of the Laplacian), the local potential on the
+ * grid (kept as V_loc) and the Bloch-phased projector table chi~_J(x) =
+ * sum_L e^{ik.L} chi_J(x - R_J - L) (Sec. 2, non-local operator; Sec. 3.1,
+ * discrete form with the trapezoidal rule).  V_eff starts equal to V_loc.
+ * dtype: SPARC_R64/SPARC_R32 need kpt = 0.  Synchronous.
+ * Errors: EINVAL (null, n_o outside 1..8, l outside {0,1}, R64/R32 with k != 0),
+ * ESHAPE (n outside 1..4096, N_d >= 2^31). */
+int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
+                     sparc_dtype dtype, sparc_ham** out);
+void sparc_ham_destroy(sparc_ham* ham);
+/* Sets V_eff (Sec. 2: V_eff = V_xc + phi, here V_loc + V_H + V_x) from a
+ * device array of N_d doubles; copied (and rounded for FP32 dtypes). */
+int sparc_ham_set_veff(sparc_ham* ham, const double* veff_dev);
+/* Writes the local potential V_loc (N_d doubles) into a device array. */
+int sparc_ham_get_vloc(const sparc_ham* ham, double* vloc_dev);
+/* Host query: N_d, number of projector functions, total support entries. */
+int sparc_ham_info(const sparc_ham* ham, int64_t* n_d, int32_t* n_proj, int64_t* n_entries);
+
+/* Operation codes for sparc_workspace_bytes. */
+enum { SPARC_OP_APPLY = 0, SPARC_OP_FILTER = 1, SPARC_OP_RR = 2, SPARC_OP_LANCZOS = 3 };
+/* Bytes of device workspace an operation needs for n_s states (0 for none). */
+size_t sparc_workspace_bytes(const sparc_ham* ham, int32_t n_s, int32_t op);
+
+/* Y = H X for n_s orbitals (Sec. 2 Hamiltonian in Bloch form, discretised by
+ * Sec. 3.1): Y = -1/2 Lap_h X + V_eff X + h1h2h3 sum_J gamma_J chi~_J (chi~_J^H X).
+ * X, Y device, column-major, ldx, ldy >= N_d, no aliasing.  work: workspace of
+ * SPARC_OP_APPLY bytes (projections).  Errors: EINVAL, ESHAPE, ENOMEM. */
+int fd_hamiltonian_apply(sparc_ham* ham, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                         int32_t n_s, void* work, size_t work_bytes);
+
+/* Chebyshev filter (Sec. 3.4, Eq. of the filter): X <- C_m((H - c)/e) X with
+ * c = (lambda_max + lambda_cut)/2, e = (lambda_max - lambda_cut)/2, by the
+ * three-term recurrence Y_1 = (H - c)X/e, Y_{j+1} = 2(H - c)Y_j/e - Y_{j-1}
+ * (unscaled; m = degree >= 1 applications of H).  In place on X (device,
+ * ld >= N_d).  work: SPARC_OP_FILTER bytes (one N_d x n_s block + projections).
+ * Errors: EINVAL (degree < 1, lambda_max <= lambda_cut), ESHAPE, ENOMEM. */
+int chebyshev_filter(sparc_ham* ham, void* X, int64_t ldx, int32_t n_s, int32_t degree,
+                     double lambda_cut, double lambda_max, void* work, size_t work_bytes);
+
+/* Rayleigh–Ritz step of CheFSI (Sec. 3.4: projected pencil H~ = U_f^H H U_f,
+ * M~ = U_f^H U_f, generalized eigenproblem, rotation U = U_f Y).  The pencil is
+ * reduced by two Cholesky-QR passes of the column-scaled block (an orthonormal
+ * basis Q of span(U_f), then Q^H H Q), the N_s x N_s problem is solved in FP64
+ * on the GPU (Householder tridiagonalisation, bisection, inverse iteration),
+ * and X is overwritten with the rotated orbitals (Euclidean-orthonormal Ritz
+ * vectors).  ritz_dev: device, n_s doubles, ascending.  mode: precision of the
+ * N_d-long contractions.  info (host, may be NULL): failing column + 1 on
+ * ENOTSPD.  work: SPARC_OP_RR bytes.  Errors: ENOTSPD (rank-deficient block),
+ * EINVAL, ESHAPE, ENOMEM.  Synchronous (reads back the Cholesky status). */
+int rayleigh_ritz(sparc_ham* ham, void* X, int64_t ldx, int32_t n_s, sparc_gemm_mode mode,
+                  double* ritz_dev, void* work, size_t work_bytes, int32_t* info);
+
+/* Lanczos estimate of the extremal eigenvalues of H (Sec. 4, Lanczos for the
+ * filter bounds): `steps` steps with full reorthogonalisation from the device
+ * start vector v0 (N_d elements of the element type).  lmin = smallest Ritz
+ * value; lmax = largest Ritz value + |beta_k s_k| (its residual bound), enlarged
+ * by 1% of its magnitude.  Host outputs; synchronous.  work: SPARC_OP_LANCZOS
+ * bytes for `steps` (pass steps as n_s to sparc_workspace_bytes). */
+int lanczos_bounds(sparc_ham* ham, const void* v0, int32_t steps, void* work, size_t work_bytes,
+                   double* lmin, double* lmax);
+
+/* Electron density (Sec. 3.4): rho_g = (2/dV) sum_b sum_n occ_w[b*n_s+n]
+ * |X_b(g,n)|^2 with occ_w = w_b g_nb (device, n_k*n_s doubles).  X: host array
+ * of n_k device pointers, ldx host array; dtype of all blocks; rho_dev device,
+ * n_d doubles (overwritten).  FP64 accumulation for every dtype. */
+int density_from_orbitals(sparc_ctx* ctx, int32_t n_k, const void* const* X, const int64_t* ldx,
+                          int32_t n_s, sparc_dtype dtype, const double* occ_w, int64_t n_d,
+                          double dV, double* rho_dev);
+
+/* Fermi level and occupations (Sec. 3.4 electron-count constraint; Sec. 2
+ * Fermi-Dirac occupations): mu with 2 sum_b w_b sum_n g_nb = n_elec by
+ * bisection to 1e-13 relative charge, g = (1 - tanh((lambda - mu)/(2 kT)))/2.
+ * lambda_dev: device [n_k*n_s]; wk host [n_k]; occ_w_dev (out, device, may be
+ * NULL): w_b g_nb; mu (host out).  Synchronous. */
+int sparc_fermi(sparc_ctx* ctx, int32_t n_k, int32_t n_s, const double* lambda_dev, const double* wk,
+                double n_elec, double kT, double* occ_w_dev, double* mu);
+
+/* Minimal self-consistent field (Sec. 2 SCF fixed point with mixing, Sec. 3.4
+ * CheFSI schedule, Sec. 3.5 free energy) at the Gamma point in the reduced
+ * model: V_eff = V_loc + V_H + V_x (Slater exchange), -Lap_h V_H =
+ * 4 pi (rho - mean rho) solved by conjugate gradients on the FD Laplacian,
+ * linear density mixing, Harris–Foulkes energy at the input density, stop when
+ * ||rho_out - rho_in|| / ||rho_in|| < tol.  The first step runs n_first_passes
+ * CheFSI passes from X0 before forming the density.
+ */
+typedef struct {
+  int32_t n_s, degree, n_first_passes, max_iter, lanczos_steps;
+  double kT, mix, tol, n_elec, poisson_tol;
+  sparc_dtype filt;            /* SPARC_R64, or SPARC_R32 for an FP32 filter          */
+  sparc_gemm_mode rr;          /* contraction precision for FP32 passes              */
+  int32_t final_fp64_pass;     /* with an FP32 filter: finish with FP64 passes        */
+  const double* rho_init_dev;  /* device [N_d] start density (NULL: superposition of
+                                  atomic Gaussians of width w_J and charge Z_J)        */
+  const double* x0_dev;        /* device [N_d*n_s] FP64 start orbitals (column-major) */
+  const double* lanczos_v0_dev;/* device [N_d] FP64 Lanczos start vector              */
+} sparc_scf_params;
+
+typedef struct {
+  double energy, mu;
+  int32_t iterations, converged;
+  double* rho_dev;     /* caller-provided device [N_d]: final input density (out)   */
+  double* ritz_dev;    /* caller-provided device [n_s]: final Ritz values (out)      */
+  double* x_dev;       /* caller-provided device [N_d*n_s] FP64: final orbitals (out, may be NULL) */
+  double* history;     /* caller-provided host [3*max_iter]: (energy, rho_err, t_s) per iteration (may be NULL) */
+} sparc_scf_result;
+
+/* Runs the SCF; synchronous.  Errors: ENOCONV (max_iter reached; result holds
+ * the last iterate), ENOTSPD, ENAN, EINVAL, ESHAPE, ENOMEM. */
+int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
+                  const sparc_scf_params* params, sparc_scf_result* result);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPARC_HIP_H */

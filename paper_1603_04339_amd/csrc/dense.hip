@@ -1,0 +1,495 @@
+// Dense FP64 linear algebra on the N_s x N_s subspace matrices of the
+// Rayleigh-Ritz step, all on the GPU:
+//   * column-scaled Cholesky factorisation and triangular inverse (the
+//     orthonormalising transform of a Cholesky-QR pass);
+//   * Hermitian eigensolver: Householder reduction to a real symmetric
+//     tridiagonal (one work-group, matrix resident in L2), eigenvalues by Sturm
+//     bisection (one thread per eigenvalue), eigenvectors by inverse iteration
+//     with pivoted tridiagonal LU (one thread per cluster of close eigenvalues,
+//     Gram-Schmidt inside a cluster), and the back-transformation by the
+//     Householder reflectors (one work-group per block of columns).
+// Matrices are column-major with leading dimension n; complex matrices are
+// interleaved (re, im).
+#include <cmath>
+
+#include "devmath.hpp"
+
+namespace sparc {
+
+template <bool C> struct scal;
+template <> struct scal<false> { typedef double t; };
+template <> struct scal<true> { typedef cd t; };
+
+__device__ __forceinline__ double conj_(double v) { return v; }
+__device__ __forceinline__ cd conj_(cd v) { return {v.re, -v.im}; }
+__device__ __forceinline__ double re_(double v) { return v; }
+__device__ __forceinline__ double re_(cd v) { return v.re; }
+__device__ __forceinline__ double mk(double r, double) { return r; }
+template <typename T> __device__ __forceinline__ T mkT(double r, double i);
+template <> __device__ __forceinline__ double mkT<double>(double r, double) { return r; }
+template <> __device__ __forceinline__ cd mkT<cd>(double r, double i) { return {r, i}; }
+__device__ __forceinline__ double mul_(double a, double b) { return a * b; }
+__device__ __forceinline__ cd mul_(cd a, cd b) { return a * b; }
+__device__ __forceinline__ double sub_(double a, double b) { return a - b; }
+__device__ __forceinline__ cd sub_(cd a, cd b) { return a - b; }
+__device__ __forceinline__ double add_(double a, double b) { return a + b; }
+__device__ __forceinline__ cd add_(cd a, cd b) { return a + b; }
+__device__ __forceinline__ double rscale(double s, double v) { return s * v; }
+__device__ __forceinline__ cd rscale(double s, cd v) { return {s * v.re, s * v.im}; }
+
+// block-wide sum of a double (blockDim multiple of 64, <= 1024)
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  for (int i = 0; i < nw; ++i) s += sh[i];
+  __syncthreads();
+  return s;
+}
+
+// ------------------------------------------------------------ scaled Cholesky
+// S = D^{-1} M D^{-1} (D = sqrt(diag M)), in place Cholesky S = R^H R (upper),
+// info = failing column + 1.  One work-group.
+template <typename T>
+__global__ __launch_bounds__(1024) void chol_kernel(int n, const T* __restrict__ M, T* __restrict__ S,
+                                                    double* __restrict__ dinv, double shift, double min_rel_diag,
+                                                    int* info) {
+  __shared__ int s_fail;
+  __shared__ double s_piv;
+  __shared__ double s_dmax;
+  if (threadIdx.x == 0) {
+    s_fail = 0x7fffffff;
+    double dm = 0;
+    for (int i = 0; i < n; ++i) dm = fmax(dm, re_(M[i + (int64_t)i * n]));
+    s_dmax = dm;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double d = re_(M[i + (int64_t)i * n]);
+    // a non-positive, non-finite or (relative to the largest) vanishing column norm
+    if (!(d > 0.0) || !isfinite(d) || d < min_rel_diag * s_dmax) atomicMin(&s_fail, i + 1);
+    dinv[i] = (d > 0.0) ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  if (s_fail != 0x7fffffff) {
+    if (threadIdx.x == 0) *info = s_fail;
+    return;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) s_fail = 0;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
+    int i = (int)(idx % n), j = (int)(idx / n);
+    T v = rscale(dinv[i] * dinv[j], M[idx]);
+    if (i == j) v = mkT<T>(re_(v) + shift, 0.0);
+    S[idx] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      double a = re_(S[k + (int64_t)k * n]);
+      if (!(a > 1e-15) || !isfinite(a)) {  // unit-diagonal S: relative pivot floor
+        s_fail = k + 1;
+      } else {
+        s_piv = sqrt(a);
+        S[k + (int64_t)k * n] = mkT<T>(s_piv, 0.0);
+      }
+    }
+    __syncthreads();
+    if (s_fail) break;
+    const double rinv = 1.0 / s_piv;
+    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) S[k + (int64_t)j * n] = rscale(rinv, S[k + (int64_t)j * n]);
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += blockDim.x) {
+      int i = k + 1 + (int)(idx % m), j = k + 1 + (int)(idx / m);
+      if (i <= j) S[i + (int64_t)j * n] = sub_(S[i + (int64_t)j * n], mul_(conj_(S[k + (int64_t)i * n]), S[k + (int64_t)j * n]));
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *info = s_fail;
+}
+
+// T[:, j] = D^{-1} R^{-1} e_j (upper triangular), one wave per column.
+template <typename T>
+__global__ __launch_bounds__(64) void trinv_kernel(int n, const T* __restrict__ R, const double* __restrict__ dinv,
+                                                   T* __restrict__ Tout, const int* info) {
+  extern __shared__ char smem[];
+  T* x = (T*)smem;
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (*info != 0) return;
+  for (int i = j; i >= 0; --i) {
+    double sr = 0, si = 0;
+    for (int k = i + 1 + lane; k <= j; k += 64) {
+      T p = mul_(R[i + (int64_t)k * n], x[k]);
+      if constexpr (sizeof(T) == 16) {
+        sr += ((const cd&)p).re;
+        si += ((const cd&)p).im;
+      } else {
+        sr += (double&)p;
+      }
+    }
+    sr = wave_sum(sr);
+    if constexpr (sizeof(T) == 16) si = wave_sum(si);
+    if (lane == 0) {
+      double rii = re_(R[i + (int64_t)i * n]);
+      double br = (i == j ? 1.0 : 0.0) - sr;
+      x[i] = mkT<T>(br / rii, -si / rii);
+    }
+    __syncthreads();
+  }
+  for (int i = lane; i < n; i += 64) Tout[i + (int64_t)j * n] = (i <= j) ? rscale(dinv[i], x[i]) : mkT<T>(0.0, 0.0);
+}
+
+size_t chol_orth_work_bytes(int32_t n, bool cplx) { return (size_t)n * n * (cplx ? 16 : 8) + (size_t)n * 8 + 256; }
+
+template <typename T>
+static int chol_orth_t(hipStream_t s, int n, const T* M, T* Tout, int* info, void* work, double shift,
+                       double min_rel_diag) {
+  T* S = (T*)work;
+  double* dinv = (double*)((char*)work + (size_t)n * n * sizeof(T));
+  chol_kernel<T><<<1, 1024, 0, s>>>(n, M, S, dinv, shift, min_rel_diag, info);
+  SPARC_TRY(check_launch("chol_kernel"));
+  trinv_kernel<T><<<n, 64, n * sizeof(T), s>>>(n, S, dinv, Tout, info);
+  return check_launch("trinv_kernel");
+}
+
+int chol_orth(hipStream_t s, bool cplx, int32_t n, const void* M, void* T, int32_t* info_dev, void* work,
+              double shift, double min_rel_diag) {
+  if (cplx) return chol_orth_t<cd>(s, n, (const cd*)M, (cd*)T, info_dev, work, shift, min_rel_diag);
+  return chol_orth_t<double>(s, n, (const double*)M, (double*)T, info_dev, work, shift, min_rel_diag);
+}
+
+// ------------------------------------------------------------ Householder tridiagonalisation
+// Lower Hermitian reduction A = Q T Q^H, Q = H_0 H_1 ... H_{n-2}, H_i = I - tau_i v_i v_i^H,
+// v_i = (0..0, 1, A[i+2:, i]) after the call.  d, e: real tridiagonal.
+template <typename T>
+__global__ __launch_bounds__(1024) void hetrd_kernel(int n, T* __restrict__ A, double* __restrict__ d,
+                                                     double* __restrict__ e, T* __restrict__ tau) {
+  extern __shared__ char smem[];
+  T* v = (T*)smem;        // [n]
+  T* w = v + n;           // [n]
+  __shared__ double red[16];
+  __shared__ T s_tau, s_scale;
+  __shared__ double s_beta;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = 0; i < n - 1; ++i) {
+    const int m = n - i - 1;  // rows i+1 .. n-1
+    double xn = 0;
+    for (int r = i + 2 + tid; r < n; r += nt) {
+      T x = A[r + (int64_t)i * n];
+      xn += re_(mul_(conj_(x), x));
+    }
+    xn = block_sum(xn, red);
+    if (tid == 0) {
+      T alpha = A[i + 1 + (int64_t)i * n];
+      double ar = re_(alpha);
+      double ai = 0;
+      if constexpr (sizeof(T) == 16) ai = ((cd&)alpha).im;
+      if (xn == 0.0 && ai == 0.0) {
+        s_tau = mkT<T>(0.0, 0.0);
+        s_beta = ar;
+        s_scale = mkT<T>(0.0, 0.0);
+      } else {
+        double beta = -copysign(sqrt(ar * ar + ai * ai + xn), ar);
+        s_beta = beta;
+        s_tau = mkT<T>((beta - ar) / beta, -ai / beta);
+        // 1 / (alpha - beta)
+        double dr = ar - beta, di = ai, den = dr * dr + di * di;
+        s_scale = mkT<T>(dr / den, -di / den);
+      }
+    }
+    __syncthreads();
+    const T tau_i = s_tau;
+    const double beta = s_beta;
+    if (tid == 0) tau[i] = tau_i;
+    const bool trivial = (re_(tau_i) == 0.0) && (re_(mul_(conj_(tau_i), tau_i)) == 0.0);
+    // v = (1, x * scale)
+    for (int r = i + 1 + tid; r < n; r += nt) {
+      T val;
+      if (r == i + 1) val = mkT<T>(1.0, 0.0);
+      else {
+        val = mul_(A[r + (int64_t)i * n], s_scale);
+        A[r + (int64_t)i * n] = val;
+      }
+      v[r] = val;
+    }
+    __syncthreads();
+    if (!trivial) {
+      // p = tau * A_sub v  (rows and columns i+1..n-1)
+      for (int r = i + 1 + tid; r < n; r += nt) {
+        T acc = mkT<T>(0.0, 0.0);
+        for (int c = i + 1; c < n; ++c) acc = add_(acc, mul_(A[r + (int64_t)c * n], v[c]));
+        w[r] = mul_(tau_i, acc);
+      }
+      __syncthreads();
+      // alpha2 = -1/2 tau (p^H v)
+      double pr = 0, pi = 0;
+      for (int r = i + 1 + tid; r < n; r += nt) {
+        T t = mul_(conj_(w[r]), v[r]);
+        pr += re_(t);
+        if constexpr (sizeof(T) == 16) pi += ((cd&)t).im;
+      }
+      pr = block_sum(pr, red);
+      if constexpr (sizeof(T) == 16) pi = block_sum(pi, red);
+      T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(pr, pi)));
+      for (int r = i + 1 + tid; r < n; r += nt) w[r] = add_(w[r], mul_(a2, v[r]));
+      __syncthreads();
+      // A_sub -= v w^H + w v^H
+      for (int64_t idx = tid; idx < (int64_t)m * m; idx += nt) {
+        int r = i + 1 + (int)(idx % m), c = i + 1 + (int)(idx / m);
+        T upd = add_(mul_(v[r], conj_(w[c])), mul_(w[r], conj_(v[c])));
+        A[r + (int64_t)c * n] = sub_(A[r + (int64_t)c * n], upd);
+      }
+    }
+    if (tid == 0) {
+      e[i] = beta;
+      d[i] = re_(A[i + (int64_t)i * n]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) d[n - 1] = re_(A[(n - 1) + (int64_t)(n - 1) * n]);
+}
+
+// ------------------------------------------------------------ tridiagonal eigenvalues (bisection)
+__device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+__global__ void bisect_kernel(int n, const double* __restrict__ d, const double* __restrict__ e,
+                              double* __restrict__ w, double* __restrict__ e2g) {
+  extern __shared__ double sm[];
+  double* ds = sm;
+  double* e2 = sm + n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    ds[i] = d[i];
+    e2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
+  }
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  // Gershgorin interval and pivot floor
+  double lo = ds[0], hi = ds[0], emax = 0;
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + (i < n - 1 ? sqrt(e2[i]) : 0.0);
+    lo = fmin(lo, ds[i] - r);
+    hi = fmax(hi, ds[i] + r);
+    emax = fmax(emax, e2[i]);
+  }
+  const double pivmin = 1e-290 * fmax(1.0, emax);
+  double tnorm = fmax(fabs(lo), fabs(hi));
+  lo -= 2.2e-16 * tnorm * n + 2 * pivmin;
+  hi += 2.2e-16 * tnorm * n + 2 * pivmin;
+  if (j >= n) return;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 2.2e-16 * tnorm + pivmin) break;
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(n, ds, e2, mid, pivmin) > j) hi = mid;
+    else lo = mid;
+  }
+  w[j] = 0.5 * (lo + hi);
+  if (j == 0) e2g[0] = tnorm;
+}
+
+// ------------------------------------------------------------ inverse iteration
+// One thread per cluster of eigenvalues (gap < gtol); Y (n x n, real) column j = eigenvector j of T.
+// Scratch per eigenvalue index j (column-strided): dl, dd, du, du2, b (n each) and ipiv.
+__global__ void inviter_kernel(int n, const double* __restrict__ d, const double* __restrict__ e,
+                               const double* __restrict__ w, const double* __restrict__ tnorm_p, double* __restrict__ Y,
+                               double* __restrict__ scratch, int* __restrict__ piv) {
+  const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j0 >= n) return;
+  const double tnorm = fmax(*tnorm_p, 1e-300);
+  const double gtol = 1e-6 * tnorm;
+  if (j0 > 0 && w[j0] - w[j0 - 1] <= gtol) return;  // not the start of a cluster
+  int j1 = j0;
+  while (j1 + 1 < n && w[j1 + 1] - w[j1] <= gtol) ++j1;
+  const int64_t S = n;  // stride between rows of one scratch vector (column-strided by j0)
+  double* dl = scratch + (int64_t)0 * n * n;
+  double* dd = scratch + (int64_t)1 * n * n;
+  double* du = scratch + (int64_t)2 * n * n;
+  double* du2 = scratch + (int64_t)3 * n * n;
+  double* b = scratch + (int64_t)4 * n * n;
+  int* ip = piv;
+#define AT(arr, i) arr[(int64_t)(i) * S + j0]
+  const double eps = 2.2e-16;
+  double prev = -1e300;
+  for (int j = j0; j <= j1; ++j) {
+    double lam = w[j];
+    if (lam - prev < 10.0 * eps * tnorm) lam = prev + 10.0 * eps * tnorm;
+    prev = lam;
+    // LU with partial pivoting of T - lam I (general tridiagonal form)
+    for (int i = 0; i < n; ++i) {
+      AT(dd, i) = d[i] - lam;
+      if (i < n - 1) { AT(dl, i) = e[i]; AT(du, i) = e[i]; }
+    }
+    for (int i = 0; i < n - 1; ++i) {
+      double di = AT(dd, i), li = AT(dl, i);
+      if (fabs(di) >= fabs(li)) {
+        AT(ip, i) = 0;
+        if (di == 0.0) { di = eps * tnorm; AT(dd, i) = di; }
+        double f = li / di;
+        AT(dl, i) = f;
+        AT(dd, i + 1) = AT(dd, i + 1) - f * AT(du, i);
+        if (i < n - 2) AT(du2, i) = 0.0;
+      } else {
+        AT(ip, i) = 1;
+        double f = di / li;
+        AT(dd, i) = li;
+        AT(dl, i) = f;
+        double t = AT(du, i);
+        AT(du, i) = AT(dd, i + 1);
+        AT(dd, i + 1) = t - f * AT(dd, i + 1);
+        if (i < n - 2) {
+          AT(du2, i) = AT(du, i + 1);
+          AT(du, i + 1) = -f * AT(du, i + 1);
+        }
+      }
+    }
+    if (AT(dd, n - 1) == 0.0) AT(dd, n - 1) = eps * tnorm;
+    // deterministic start vector
+    double nrm = 0;
+    for (int i = 0; i < n; ++i) {
+      uint32_t h = (uint32_t)(i * 2654435761u) ^ (uint32_t)(j * 40503u + 0x9e3779b9u);
+      h ^= h >> 16; h *= 0x7feb352du; h ^= h >> 15; h *= 0x846ca68bu; h ^= h >> 16;
+      double r = ((h & 0xffffff) / 16777216.0) - 0.5 + 1e-3;
+      AT(b, i) = r;
+      nrm += r * r;
+    }
+    for (int it = 0; it < 4; ++it) {
+      // forward: apply row interchanges and multipliers
+      for (int i = 0; i < n - 1; ++i) {
+        if (AT(ip, i) == 0) AT(b, i + 1) = AT(b, i + 1) - AT(dl, i) * AT(b, i);
+        else {
+          double t = AT(b, i);
+          AT(b, i) = AT(b, i + 1);
+          AT(b, i + 1) = t - AT(dl, i) * AT(b, i);
+        }
+      }
+      // back substitution with U (diag dd, super du, super-2 du2)
+      AT(b, n - 1) = AT(b, n - 1) / AT(dd, n - 1);
+      if (n > 1) AT(b, n - 2) = (AT(b, n - 2) - AT(du, n - 2) * AT(b, n - 1)) / AT(dd, n - 2);
+      for (int i = n - 3; i >= 0; --i)
+        AT(b, i) = (AT(b, i) - AT(du, i) * AT(b, i + 1) - AT(du2, i) * AT(b, i + 2)) / AT(dd, i);
+      // orthogonalise against the earlier vectors of the cluster (twice)
+      for (int pass = 0; pass < 2; ++pass)
+        for (int q = j0; q < j; ++q) {
+          double dot = 0;
+          for (int i = 0; i < n; ++i) dot += Y[i + (int64_t)q * n] * AT(b, i);
+          for (int i = 0; i < n; ++i) AT(b, i) = AT(b, i) - dot * Y[i + (int64_t)q * n];
+        }
+      nrm = 0;
+      for (int i = 0; i < n; ++i) nrm += AT(b, i) * AT(b, i);
+      double inv = 1.0 / sqrt(nrm);
+      for (int i = 0; i < n; ++i) AT(b, i) = AT(b, i) * inv;
+    }
+    for (int i = 0; i < n; ++i) Y[i + (int64_t)j * n] = AT(b, i);
+  }
+#undef AT
+}
+
+// ------------------------------------------------------------ back-transformation Z = Q Y
+template <typename T>
+__global__ __launch_bounds__(256) void ormtr_kernel(int n, const T* __restrict__ A, const T* __restrict__ tau,
+                                                    const double* __restrict__ Y, T* __restrict__ Z) {
+  constexpr int NC = 16;
+  __shared__ double part_r[16][NC], part_i[16][NC];
+  __shared__ T s[NC];
+  const int c0 = blockIdx.x * NC;
+  const int tid = threadIdx.x, col = tid % NC, grp = tid / NC;
+  for (int idx = tid; idx < n * NC; idx += 256) {
+    int r = idx % n, c = c0 + idx / n;
+    if (c < n) Z[r + (int64_t)c * n] = mkT<T>(Y[r + (int64_t)c * n], 0.0);
+  }
+  __syncthreads();
+  for (int i = n - 2; i >= 0; --i) {
+    const T ti = tau[i];
+    const int c = c0 + col;
+    double sr = 0, si = 0;
+    if (c < n) {
+      for (int r = i + 1 + grp; r < n; r += 16) {
+        T vr = (r == i + 1) ? mkT<T>(1.0, 0.0) : A[r + (int64_t)i * n];
+        T p = mul_(conj_(vr), Z[r + (int64_t)c * n]);
+        sr += re_(p);
+        if constexpr (sizeof(T) == 16) si += ((cd&)p).im;
+      }
+    }
+    part_r[grp][col] = sr;
+    part_i[grp][col] = si;
+    __syncthreads();
+    if (tid < NC) {
+      double a = 0, b = 0;
+      for (int g = 0; g < 16; ++g) { a += part_r[g][tid]; b += part_i[g][tid]; }
+      s[tid] = mul_(ti, mkT<T>(a, b));
+    }
+    __syncthreads();
+    if (c < n) {
+      for (int r = i + 1 + grp; r < n; r += 16) {
+        T vr = (r == i + 1) ? mkT<T>(1.0, 0.0) : A[r + (int64_t)i * n];
+        Z[r + (int64_t)c * n] = sub_(Z[r + (int64_t)c * n], mul_(vr, s[col]));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+size_t heev_work_bytes(int32_t n, bool cplx) {
+  size_t b = (size_t)n * 8 * 3 + 64;                  // d, e, tnorm
+  b += (size_t)n * (cplx ? 16 : 8);                   // tau
+  b += (size_t)n * n * 8;                             // Y
+  b += (size_t)5 * n * n * 8 + (size_t)n * n * 4;     // inverse-iteration scratch and pivots
+  return b + 1024;
+}
+
+template <typename T>
+static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
+  char* p = (char*)work;
+  auto take = [&](size_t bytes) { char* q = p; p += ((bytes + 255) / 256) * 256; return q; };
+  double* d = (double*)take(n * 8);
+  double* e = (double*)take(n * 8);
+  double* tn = (double*)take(64);
+  T* tau = (T*)take(n * sizeof(T));
+  double* Y = (double*)take((size_t)n * n * 8);
+  double* scr = (double*)take((size_t)5 * n * n * 8);
+  int* piv = (int*)take((size_t)n * n * 4);
+  if (n == 1) {
+    hetrd_kernel<T><<<1, 64, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
+  } else {
+    int nt = n >= 1024 ? 1024 : ((n + 63) / 64) * 64;
+    hetrd_kernel<T><<<1, nt, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
+  }
+  SPARC_TRY(check_launch("hetrd_kernel"));
+  int bt = 256;
+  bisect_kernel<<<(n + bt - 1) / bt, bt, 2 * n * 8, s>>>(n, d, e, w, tn);
+  SPARC_TRY(check_launch("bisect_kernel"));
+  inviter_kernel<<<(n + 63) / 64, 64, 0, s>>>(n, d, e, w, tn, Y, scr, piv);
+  SPARC_TRY(check_launch("inviter_kernel"));
+  ormtr_kernel<T><<<(n + 15) / 16, 256, 0, s>>>(n, A, tau, Y, Z);
+  return check_launch("ormtr_kernel");
+}
+
+int heev(hipStream_t s, bool cplx, int32_t n, void* A, double* w, void* Z, void* work) {
+  if (n > 2048) return fail(SPARC_ESHAPE, "heev: n=%d above 2048", n);
+  if (cplx) return heev_t<cd>(s, n, (cd*)A, w, (cd*)Z, work);
+  return heev_t<double>(s, n, (double*)A, w, (double*)Z, work);
+}
+
+int small_gemm(hipStream_t s, bool cplx, int32_t n, int opA, const void* A, const void* B, void* C, void* work,
+               size_t work_bytes, int n_cu) {
+  sparc_dtype dt = cplx ? SPARC_C128 : SPARC_R64;
+  if (opA == 1) return gram(s, dt, n, n, n, A, n, B, n, C, n, work, work_bytes, SPARC_GEMM_NATIVE, n_cu);
+  return rotate(s, dt, n, n, n, A, n, B, n, C, n, 0);
+}
+
+}  // namespace sparc

@@ -1,0 +1,84 @@
+// Device arithmetic on the four orbital element types (double, float and their
+// complex forms stored as interleaved (re, im)).
+#pragma once
+#include "internal.hpp"
+
+namespace sparc {
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(T s, cplx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+template <typename E> __device__ __forceinline__ E zero();
+template <> __device__ __forceinline__ double zero<double>() { return 0.0; }
+template <> __device__ __forceinline__ float zero<float>() { return 0.0f; }
+template <> __device__ __forceinline__ cd zero<cd>() { return {0.0, 0.0}; }
+template <> __device__ __forceinline__ cf zero<cf>() { return {0.0f, 0.0f}; }
+
+// acc + w * v with a real weight w
+__device__ __forceinline__ double fmar(double acc, double w, double v) { return fma(w, v, acc); }
+__device__ __forceinline__ float fmar(float acc, float w, float v) { return fmaf(w, v, acc); }
+__device__ __forceinline__ cd fmar(cd acc, double w, cd v) { return {fma(w, v.re, acc.re), fma(w, v.im, acc.im)}; }
+__device__ __forceinline__ cf fmar(cf acc, float w, cf v) { return {fmaf(w, v.re, acc.re), fmaf(w, v.im, acc.im)}; }
+
+// acc + a * b (element product)
+__device__ __forceinline__ double fmae(double acc, double a, double b) { return fma(a, b, acc); }
+__device__ __forceinline__ float fmae(float acc, float a, float b) { return fmaf(a, b, acc); }
+__device__ __forceinline__ cd fmae(cd acc, cd a, cd b) {
+  return {fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im))};
+}
+__device__ __forceinline__ cf fmae(cf acc, cf a, cf b) {
+  return {fmaf(a.re, b.re, fmaf(-a.im, b.im, acc.re)), fmaf(a.re, b.im, fmaf(a.im, b.re, acc.im))};
+}
+
+// acc + conj(a) * b
+__device__ __forceinline__ double fmac(double acc, double a, double b) { return fma(a, b, acc); }
+__device__ __forceinline__ float fmac(float acc, float a, float b) { return fmaf(a, b, acc); }
+__device__ __forceinline__ cd fmac(cd acc, cd a, cd b) {
+  return {fma(a.re, b.re, fma(a.im, b.im, acc.re)), fma(a.re, b.im, fma(-a.im, b.re, acc.im))};
+}
+__device__ __forceinline__ cf fmac(cf acc, cf a, cf b) {
+  return {fmaf(a.re, b.re, fmaf(a.im, b.im, acc.re)), fmaf(a.re, b.im, fmaf(-a.im, b.re, acc.im))};
+}
+
+__device__ __forceinline__ double scale(double s, double v) { return s * v; }
+__device__ __forceinline__ float scale(float s, float v) { return s * v; }
+__device__ __forceinline__ cd scale(double s, cd v) { return {s * v.re, s * v.im}; }
+__device__ __forceinline__ cf scale(float s, cf v) { return {s * v.re, s * v.im}; }
+
+// multiply by the unit phase (c, s) = e^{i theta}; identity for real types
+__device__ __forceinline__ double rot(double v, double, double) { return v; }
+__device__ __forceinline__ float rot(float v, float, float) { return v; }
+__device__ __forceinline__ cd rot(cd v, double c, double s) { return {c * v.re - s * v.im, c * v.im + s * v.re}; }
+__device__ __forceinline__ cf rot(cf v, float c, float s) { return {c * v.re - s * v.im, c * v.im + s * v.re}; }
+
+__device__ __forceinline__ double abs2(double v) { return v * v; }
+__device__ __forceinline__ double abs2(float v) { return (double)v * (double)v; }
+__device__ __forceinline__ double abs2(cd v) { return v.re * v.re + v.im * v.im; }
+__device__ __forceinline__ double abs2(cf v) { return (double)v.re * v.re + (double)v.im * v.im; }
+
+// wave64 butterfly sum
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int floordiv_i(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+}  // namespace sparc

@@ -1,0 +1,339 @@
+// Application of the finite-difference Hamiltonian to a block of orbitals:
+// the fused stencil + local potential + non-local scatter step that every H*X,
+// Chebyshev recurrence step and Lanczos step runs, and the non-local gather
+// (projections of the orbitals onto the Kleinman-Bylander projectors).
+//
+// Stencil step (one work-group = one TX x TY column tile of one orbital, a
+// chunk of z planes): the tile streams along z.  Each thread keeps the 2*NO+1
+// values of its own (x, y) column around the current plane in registers
+// (z-direction taps); the current plane, with NO-wide x and y halos, is staged
+// in LDS (double-buffered, one barrier per plane) for the x and y taps.  Loads
+// are x-fastest and coalesced; nodes outside the cell are fetched from their
+// periodic image with the Bloch factor e^{i k_s L_s w}.
+#include "devmath.hpp"
+
+namespace sparc {
+
+template <typename E>
+struct StepArgs {
+  typedef typename elem<E>::real R;
+  int n1, n2, n3;
+  int tiles_x, zchunk;
+  int64_t ldx, ldz, ldo;
+  const E* __restrict__ x;
+  const E* z;
+  E* out;
+  const R* __restrict__ veff;
+  R centre;        // a * centre coefficient of -1/2 Lap_h
+  R tx[8], ty[8], tz[8];
+  R va, vb, zc;    // out = lap*a + (a V + b) x + zc z (+ a NL)
+  R nl_a;
+  double kl[3];    // k_s L_s
+  const int32_t* __restrict__ pt_ptr;
+  const int32_t* __restrict__ ent_proj;
+  const E* __restrict__ ent_coef;
+  const E* __restrict__ alpha;
+  int n_proj;
+};
+
+template <typename E>
+__device__ __forceinline__ void bloch_factor(const double* kl, int wx, int wy, int wz, typename elem<E>::real& c,
+                                             typename elem<E>::real& s) {
+  if constexpr (elem<E>::is_cplx) {
+    double th = kl[0] * wx + kl[1] * wy + kl[2] * wz;
+    if (th == 0.0) {
+      c = 1;
+      s = 0;
+    } else {
+      double sn, cs;
+      sincos(th, &sn, &cs);
+      c = (typename elem<E>::real)cs;
+      s = (typename elem<E>::real)sn;
+    }
+  } else {
+    c = 1;
+    s = 0;
+  }
+}
+
+template <typename E, int TX, int TY, int NO>
+__global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
+  typedef typename elem<E>::real R;
+  constexpr int PX = TX + 2 * NO, PY = TY + 2 * NO;
+  __shared__ E plane[2][PY][PX];
+
+  const int tid = threadIdx.x;
+  const int hx = tid % TX, hy = tid / TX;
+  const int tile = blockIdx.x;
+  const int x0 = (tile % A.tiles_x) * TX, y0 = (tile / A.tiles_x) * TY;
+  const int n = blockIdx.y;
+  const int zb = blockIdx.z * A.zchunk;
+  const int ze = min(A.n3, zb + A.zchunk);
+  const int n1 = A.n1, n2 = A.n2, n3 = A.n3;
+  const int64_t plane_sz = (int64_t)n1 * n2;
+
+  const E* __restrict__ xc = A.x + (int64_t)n * A.ldx;
+  // own column: extended coordinates, periodic source and Bloch factor in x, y
+  const int ex = x0 + hx, ey = y0 + hy;
+  const int wx = floordiv_i(ex, n1), wy = floordiv_i(ey, n2);
+  const int sx = ex - wx * n1, sy = ey - wy * n2;
+  const bool inside = (ex < n1) && (ey < n2);
+  const int64_t col = sx + (int64_t)n1 * sy;
+
+  auto load_col = [&](int zz) -> E {
+    int wz = floordiv_i(zz, n3);
+    int sz = zz - wz * n3;
+    E v = xc[col + plane_sz * sz];
+    if constexpr (elem<E>::is_cplx) {
+      if (wx != 0 || wy != 0 || wz != 0) {
+        R c, s;
+        bloch_factor<E>(A.kl, wx, wy, wz, c, s);
+        v = rot(v, c, s);
+      }
+    }
+    return v;
+  };
+
+  E q[2 * NO + 1];
+#pragma unroll
+  for (int d = 0; d < 2 * NO; ++d) q[d] = load_col(zb - NO + d);
+
+  constexpr int HC = 2 * NO * (TX + TY);  // halo cells of one plane (no corners)
+  int step = 0;
+  for (int z = zb; z < ze; ++z, ++step) {
+    q[2 * NO] = load_col(z + NO);
+    const int b = step & 1;
+    plane[b][hy + NO][hx + NO] = q[NO];
+    // halo of plane z (z is inside the cell)
+    const E* __restrict__ pz = xc + plane_sz * z;
+    for (int c = tid; c < HC; c += TX * TY) {
+      int cx, cy;
+      if (c < 2 * NO * TY) {  // x strips
+        int r = c / (2 * NO), k = c % (2 * NO);
+        cy = r;
+        cx = (k < NO) ? (k - NO) : (TX + k - NO);
+      } else {  // y strips
+        int c2 = c - 2 * NO * TY;
+        int r = c2 / TX, k = c2 % TX;
+        cx = k;
+        cy = (r < NO) ? (r - NO) : (TY + r - NO);
+      }
+      int gx = x0 + cx, gy = y0 + cy;
+      int hwx = floordiv_i(gx, n1), hwy = floordiv_i(gy, n2);
+      E v = pz[(gx - hwx * n1) + (int64_t)n1 * (gy - hwy * n2)];
+      if constexpr (elem<E>::is_cplx) {
+        if (hwx != 0 || hwy != 0) {
+          R cc, ss;
+          bloch_factor<E>(A.kl, hwx, hwy, 0, cc, ss);
+          v = rot(v, cc, ss);
+        }
+      }
+      plane[b][cy + NO][cx + NO] = v;
+    }
+    __syncthreads();
+    if (inside) {
+      E lap = scale(A.centre, q[NO]);
+#pragma unroll
+      for (int p = 1; p <= NO; ++p) {
+        lap = fmar(lap, A.tz[p - 1], q[NO + p] + q[NO - p]);
+        lap = fmar(lap, A.tx[p - 1], plane[b][hy + NO][hx + NO + p] + plane[b][hy + NO][hx + NO - p]);
+        lap = fmar(lap, A.ty[p - 1], plane[b][hy + NO + p][hx + NO] + plane[b][hy + NO - p][hx + NO]);
+      }
+      const int64_t g = col + plane_sz * z;
+      R v = A.veff[g];
+      E r = fmar(lap, (R)(A.va * v + A.vb), q[NO]);
+      if (A.alpha) {
+        int e0 = A.pt_ptr[g], e1 = A.pt_ptr[g + 1];
+        if (e0 < e1) {
+          const E* __restrict__ al = A.alpha + (int64_t)n * A.n_proj;
+          E nl = zero<E>();
+          for (int e = e0; e < e1; ++e) nl = fmae(nl, A.ent_coef[e], al[A.ent_proj[e]]);
+          r = fmar(r, A.nl_a, nl);
+        }
+      }
+      if (A.z) r = fmar(r, A.zc, A.z[g + (int64_t)n * A.ldz]);
+      A.out[g + (int64_t)n * A.ldo] = r;
+    }
+#pragma unroll
+    for (int d = 0; d < 2 * NO; ++d) q[d] = q[d + 1];
+  }
+}
+
+// Non-local gather: alpha[n][p] = dV * sum_{t in supp(atom)} conj(chi~_p(t)) x(g_t, n)
+// One work-group per (atom, block of NB orbitals).
+template <typename E, int MAXP, int NB>
+__global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x, int64_t ldx, int n_s,
+                                                        const int32_t* __restrict__ sup_ptr,
+                                                        const int32_t* __restrict__ sup_idx,
+                                                        const int32_t* __restrict__ atom_pbeg,
+                                                        const int64_t* __restrict__ proj_voff,
+                                                        const E* __restrict__ pval, double dV,
+                                                        E* __restrict__ alpha, int n_proj) {
+  typedef typename elem<E>::real R;
+  constexpr int NV = elem<E>::is_cplx ? 2 : 1;
+  const int a = blockIdx.x;
+  const int nb0 = blockIdx.y * NB;
+  const int t0 = sup_ptr[a], t1 = sup_ptr[a + 1];
+  const int pb = atom_pbeg[a], np = atom_pbeg[a + 1] - pb;
+  E acc[MAXP][NB];
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[p][j] = zero<E>();
+  int64_t voff[MAXP];
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p) voff[p] = (p < np) ? proj_voff[pb + p] : 0;
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
+    const int64_t g = sup_idx[t];
+    E chi[MAXP];
+#pragma unroll
+    for (int p = 0; p < MAXP; ++p) chi[p] = (p < np) ? pval[voff[p] + (t - t0)] : zero<E>();
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (nb0 + j < n_s) {
+        E xv = x[g + (int64_t)(nb0 + j) * ldx];
+#pragma unroll
+        for (int p = 0; p < MAXP; ++p) acc[p][j] = fmac(acc[p][j], chi[p], xv);
+      }
+    }
+  }
+  // block reduction: wave butterflies, then across the 4 waves through LDS
+  __shared__ R red[4][MAXP * NB * NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < MAXP; ++p)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const R* comp = (const R*)&acc[p][j];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) {
+        R s = wave_sum(comp[c]);
+        if (lane == 0) red[wv][(p * NB + j) * NV + c] = s;
+      }
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < MAXP * NB * NV; i += blockDim.x) {
+    int pj = i / NV, c = i % NV;
+    int p = pj / NB, j = pj % NB;
+    if (p < np && nb0 + j < n_s) {
+      R s = red[0][i] + red[1][i] + red[2][i] + red[3][i];
+      ((R*)&alpha[(int64_t)(nb0 + j) * n_proj + pb + p])[c] = (R)(dV * (double)s);
+    }
+  }
+}
+
+size_t alpha_bytes(const sparc_ham* H, int32_t n_s) {
+  return (size_t)std::max(H->n_proj, 1) * (size_t)n_s * elem_bytes(H->dtype);
+}
+
+template <typename E>
+static int nl_project_t(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha) {
+  if (H->n_proj == 0) return SPARC_OK;
+  hipStream_t st = H->ctx->stream;
+  constexpr int NB = elem<E>::is_cplx ? 4 : 8;
+  dim3 grid(H->n_atoms_nl, (n_s + NB - 1) / NB);
+  int t = timer_begin(H->ctx, "nl_gather");
+  struct End { sparc_ctx* c; int t; ~End() { timer_end(c, t); } } end_{H->ctx, t};
+  if (H->max_proj_per_atom <= 1)
+    nl_gather_kernel<E, 1, NB><<<grid, 256, 0, st>>>((const E*)x, ldx, n_s, H->sup_ptr, H->sup_idx, H->atom_pbeg,
+                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, H->n_proj);
+  else if (H->max_proj_per_atom <= 4)
+    nl_gather_kernel<E, 4, NB><<<grid, 256, 0, st>>>((const E*)x, ldx, n_s, H->sup_ptr, H->sup_idx, H->atom_pbeg,
+                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, H->n_proj);
+  else
+    return fail(SPARC_EINVAL, "nl_project: more than 4 projector functions on one atom");
+  return check_launch("nl_gather_kernel");
+}
+
+int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha) {
+  switch (H->dtype) {
+    case SPARC_R64: return nl_project_t<double>(H, x, ldx, n_s, alpha);
+    case SPARC_R32: return nl_project_t<float>(H, x, ldx, n_s, alpha);
+    case SPARC_C128: return nl_project_t<cd>(H, x, ldx, n_s, alpha);
+    case SPARC_C64: return nl_project_t<cf>(H, x, ldx, n_s, alpha);
+  }
+  return fail(SPARC_EINVAL, "nl_project: bad dtype");
+}
+
+template <typename E, int TX, int TY, int NO>
+static int launch_step(sparc_ham* H, StepArgs<E>& A, int32_t n_s) {
+  A.tiles_x = (A.n1 + TX - 1) / TX;
+  int tiles_y = (A.n2 + TY - 1) / TY;
+  // z chunks: enough work-groups to fill the chip, at least 4*NO planes per chunk
+  int64_t base = (int64_t)A.tiles_x * tiles_y * n_s;
+  int nz = 1;
+  int64_t want = 4 * (int64_t)H->ctx->n_cu * 2;
+  while (base * nz < want && A.n3 / (nz * 2) >= 4 * NO) nz *= 2;
+  A.zchunk = (A.n3 + nz - 1) / nz;
+  nz = (A.n3 + A.zchunk - 1) / A.zchunk;
+  dim3 grid((unsigned)(A.tiles_x * tiles_y), (unsigned)n_s, (unsigned)nz);
+  int t = timer_begin(H->ctx, "hstep");
+  hstep_kernel<E, TX, TY, NO><<<grid, TX * TY, 0, H->ctx->stream>>>(A);
+  timer_end(H->ctx, t);
+  return check_launch("hstep_kernel");
+}
+
+template <typename E, int NO>
+static int dispatch_tile(sparc_ham* H, StepArgs<E>& A, int32_t n_s) {
+  if (A.n1 >= 64) return launch_step<E, 64, 4, NO>(H, A, n_s);
+  if (A.n1 >= 32) return launch_step<E, 32, 8, NO>(H, A, n_s);
+  return launch_step<E, 16, 16, NO>(H, A, n_s);
+}
+
+template <typename E>
+static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
+                      int32_t n_s, double a, double b, double c, const void* alpha) {
+  typedef typename elem<E>::real R;
+  StepArgs<E> A;
+  A.n1 = H->grid.n[0];
+  A.n2 = H->grid.n[1];
+  A.n3 = H->grid.n[2];
+  A.ldx = ldx;
+  A.ldz = ldz;
+  A.ldo = ldo;
+  A.x = (const E*)x;
+  A.z = (const E*)z;
+  A.out = (E*)out;
+  if constexpr (sizeof(R) == 8) A.veff = (const R*)H->veff;
+  else A.veff = (const R*)H->veff32;
+  A.centre = (R)(a * H->centre);
+  for (int p = 0; p < 8; ++p) {
+    A.tx[p] = (R)(a * H->tap[0][p]);
+    A.ty[p] = (R)(a * H->tap[1][p]);
+    A.tz[p] = (R)(a * H->tap[2][p]);
+  }
+  A.va = (R)a;
+  A.vb = (R)b;
+  A.zc = (R)c;
+  A.nl_a = (R)a;
+  for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
+  A.pt_ptr = H->pt_ptr;
+  A.ent_proj = H->ent_proj;
+  A.ent_coef = (const E*)H->ent_coef;
+  A.alpha = (H->n_proj > 0) ? (const E*)alpha : nullptr;
+  A.n_proj = H->n_proj;
+  switch (H->grid.n_o) {
+    case 1: return dispatch_tile<E, 1>(H, A, n_s);
+    case 2: return dispatch_tile<E, 2>(H, A, n_s);
+    case 3: return dispatch_tile<E, 3>(H, A, n_s);
+    case 4: return dispatch_tile<E, 4>(H, A, n_s);
+    case 5: return dispatch_tile<E, 5>(H, A, n_s);
+    case 6: return dispatch_tile<E, 6>(H, A, n_s);
+    case 7: return dispatch_tile<E, 7>(H, A, n_s);
+    case 8: return dispatch_tile<E, 8>(H, A, n_s);
+  }
+  return fail(SPARC_EINVAL, "ham_step: n_o=%d unsupported", H->grid.n_o);
+}
+
+int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
+             int32_t n_s, double a, double b, double c, const void* alpha) {
+  switch (H->dtype) {
+    case SPARC_R64: return ham_step_t<double>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
+    case SPARC_R32: return ham_step_t<float>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
+    case SPARC_C128: return ham_step_t<cd>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
+    case SPARC_C64: return ham_step_t<cf>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
+  }
+  return fail(SPARC_EINVAL, "ham_step: bad dtype");
+}
+
+}  // namespace sparc

@@ -1,0 +1,158 @@
+// Internal declarations of libsparc_hip (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/sparc_hip.h"
+
+namespace sparc {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int status, const char* fmt, ...);
+
+#define SPARC_HIP(call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::sparc::fail(SPARC_EDEVICE, "%s failed: %s (%s:%d)", #call,                \
+                           hipGetErrorString(e_), __FILE__, __LINE__);                   \
+  } while (0)
+
+#define SPARC_TRY(expr)          \
+  do {                           \
+    int s_ = (expr);             \
+    if (s_ != SPARC_OK) return s_; \
+  } while (0)
+
+// ---------------------------------------------------------------- element types
+template <typename T>
+struct cplx {
+  T re, im;
+};
+typedef cplx<double> cd;
+typedef cplx<float> cf;
+
+template <typename E> struct elem;
+template <> struct elem<double> { typedef double real; static constexpr bool is_cplx = false; };
+template <> struct elem<float> { typedef float real; static constexpr bool is_cplx = false; };
+template <> struct elem<cd> { typedef double real; static constexpr bool is_cplx = true; };
+template <> struct elem<cf> { typedef float real; static constexpr bool is_cplx = true; };
+
+inline size_t elem_bytes(sparc_dtype d) {
+  switch (d) {
+    case SPARC_R64: return 8;
+    case SPARC_R32: return 4;
+    case SPARC_C128: return 16;
+    case SPARC_C64: return 8;
+  }
+  return 0;
+}
+inline bool dtype_complex(sparc_dtype d) { return d == SPARC_C128 || d == SPARC_C64; }
+inline bool dtype_single(sparc_dtype d) { return d == SPARC_R32 || d == SPARC_C64; }
+
+// ---------------------------------------------------------------- handles
+}  // namespace sparc
+
+struct sparc_ctx {
+  int device;
+  hipStream_t stream;
+  int n_cu;
+  double* scalars;  // device scratch for scalar results (64 doubles), owned by the context
+  // optional kernel timing: HIP events recorded around launches on `stream`
+  bool timing = false;
+  struct TimeRec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<TimeRec> recs;
+  std::vector<hipEvent_t> pool;
+};
+
+struct sparc_ham {
+  sparc_ctx* ctx;
+  sparc_grid grid;
+  sparc_dtype dtype;
+  int64_t n_d;
+  double h[3];
+  double dV;
+  // kinetic stencil coefficients of -1/2 Lap_h: centre and per-direction taps p = 1..n_o
+  double centre;
+  double tap[3][8];
+  // Bloch factors e^{i k_s L_s} per direction
+  double ph_re[3], ph_im[3];
+  bool gamma;
+  // potentials (device)
+  double* vloc;       // [n_d]
+  double* veff;       // [n_d] FP64
+  float* veff32;      // [n_d] FP32 copy (single-precision dtypes)
+  // non-local projector table (device)
+  int32_t n_atoms_nl;   // atoms carrying projectors
+  int32_t n_proj;       // projector functions
+  int32_t max_proj_per_atom;
+  int64_t n_sup;        // support points summed over atoms
+  int64_t n_ent;        // (point, projector) entries
+  int32_t* sup_ptr;     // [n_atoms_nl+1] offsets into sup_idx
+  int32_t* sup_idx;     // [n_sup] grid index of support points (ascending per atom)
+  int32_t* atom_pbeg;   // [n_atoms_nl+1] first projector of each atom
+  int64_t* proj_voff;   // [n_proj] offset of the projector's values in pval
+  void* pval;           // [sum over projectors of support size] chi~ values (element type)
+  void* gamma_d;        // [n_proj] gamma per projector (real of the element precision)
+  int32_t* pt_ptr;      // [n_d+1] CSR: entries touching grid point g
+  int32_t* ent_proj;    // [n_ent] projector of the entry
+  void* ent_coef;       // [n_ent] gamma_p * chi~_p(g) (element type)
+};
+
+namespace sparc {
+
+// ---------------------------------------------------------------- launch helpers
+inline int check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(SPARC_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return SPARC_OK;
+}
+
+// kernel timing (setup.hip): begin returns a record index (or -1 when timing is off)
+int timer_begin(sparc_ctx* c, const char* name);
+void timer_end(sparc_ctx* c, int idx);
+
+// Hamiltonian application kernels (hamiltonian.hip)
+//   out = a*(H x) + b*x + c*z ; z may alias out (in-place recurrence), x must not.
+//   alpha: projections [n_s][n_proj] of x (already scaled by dV), from nl_project.
+int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
+             int32_t n_s, double a, double b, double c, const void* alpha);
+int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha);
+size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
+
+// GEMMs (gemm.hip)
+//   gram:   C[n_a x n_b] (FP64 or complex FP64, column-major, ldc) = A^H B, A: N x n_a, B: N x n_b
+//           in the orbital element type; split over N with a deterministic reduction.
+size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt);
+int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_a, int32_t n_b, const void* A, int64_t lda,
+         const void* B, int64_t ldb, void* C, int32_t ldc, void* work, size_t work_bytes,
+         sparc_gemm_mode mode, int n_cu);
+//   rotate: Out[N x n_out] = A[N x n_in] * Q[n_in x n_out] (Q FP64 / complex FP64, column-major ldq)
+//   q_upper: Q is upper triangular (entries below the diagonal are not read).
+int rotate(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A, int64_t lda,
+           const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper = 0);
+
+// Dense N_s x N_s FP64 linear algebra (dense.hip); complex when cplx = true.
+//   scaled Cholesky: M = D S D with D = diag(M)^{1/2}; S = R^H R; T = D^{-1} R^{-1} (upper)
+//   so that (A T) has orthonormal columns when M = A^H A. info (device int) = failing col+1 or 0.
+//   shift: added to the unit diagonal of S before factorising (0 for plain Cholesky-QR);
+//   min_rel_diag: fail when a diagonal entry of M is below this fraction of the largest.
+int chol_orth(hipStream_t s, bool cplx, int32_t n, const void* M, void* T, int32_t* info_dev, void* work,
+              double shift, double min_rel_diag = 0.0);
+size_t chol_orth_work_bytes(int32_t n, bool cplx);
+//   symmetric / Hermitian eigensolve: A (n x n, overwritten) -> ascending w, eigenvectors Z (n x n)
+int heev(hipStream_t s, bool cplx, int32_t n, void* A, double* w, void* Z, void* work);
+size_t heev_work_bytes(int32_t n, bool cplx);
+//   small products: C = op(A) * B for n x n FP64 (or complex) matrices; opA: 0 none, 1 conj-transpose
+int small_gemm(hipStream_t s, bool cplx, int32_t n, int opA, const void* A, const void* B, void* C, void* work,
+               size_t work_bytes, int n_cu);
+
+}  // namespace sparc

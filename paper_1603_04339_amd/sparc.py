@@ -1,0 +1,332 @@
+"""Thin ctypes binding of libsparc_hip (argument marshalling only).
+
+Every function here forwards to the C-ABI entry point of the same name in
+include/sparc_hip.h; all arithmetic runs in the library's HIP kernels.  PyTorch
+supplies device memory and the stream: orbital blocks are CUDA(HIP) tensors of
+shape (n_s, ld) whose row n is orbital n, i.e. exactly the column-major
+N_d x n_s block with leading dimension ld that the library expects.
+
+If the shared library has not been built the import fails with an error; there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsparc_hip.so")
+
+OK, EINVAL, ESHAPE, ENOMEM, ENOTSPD, ENOCONV, EDEVICE, ENAN = 0, -1, -2, -3, -4, -5, -6, -7
+R64, R32, C128, C64 = 0, 1, 2, 3
+GEMM_NATIVE, GEMM_BF16X3 = 0, 1
+OP_APPLY, OP_FILTER, OP_RR, OP_LANCZOS = 0, 1, 2, 3
+
+TORCH_DTYPE = {R64: torch.float64, R32: torch.float32, C128: torch.complex128, C64: torch.complex64}
+
+
+class SparcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+class sparc_grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3), ("n_o", C.c_int32), ("kpt", C.c_double * 3)]
+
+
+class sparc_atoms(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("R", C.POINTER(C.c_double)), ("vloc_depth", C.POINTER(C.c_double)),
+                ("vloc_width", C.POINTER(C.c_double)), ("n_chan", C.c_int32),
+                ("chan_atom", C.POINTER(C.c_int32)), ("chan_l", C.POINTER(C.c_int32)),
+                ("chan_gamma", C.POINTER(C.c_double)), ("chan_rc", C.POINTER(C.c_double)),
+                ("Z", C.POINTER(C.c_double))]
+
+
+class sparc_scf_params(C.Structure):
+    _fields_ = [("n_s", C.c_int32), ("degree", C.c_int32), ("n_first_passes", C.c_int32),
+                ("max_iter", C.c_int32), ("lanczos_steps", C.c_int32),
+                ("kT", C.c_double), ("mix", C.c_double), ("tol", C.c_double), ("n_elec", C.c_double),
+                ("poisson_tol", C.c_double), ("filt", C.c_int), ("rr", C.c_int), ("final_fp64_pass", C.c_int32),
+                ("rho_init_dev", C.c_void_p), ("x0_dev", C.c_void_p), ("lanczos_v0_dev", C.c_void_p)]
+
+
+class sparc_scf_result(C.Structure):
+    _fields_ = [("energy", C.c_double), ("mu", C.c_double), ("iterations", C.c_int32), ("converged", C.c_int32),
+                ("rho_dev", C.c_void_p), ("ritz_dev", C.c_void_p), ("x_dev", C.c_void_p),
+                ("history", C.POINTER(C.c_double))]
+
+
+# entry points: name -> (restype, argtypes)
+_SIGS = {
+    "sparc_ctx_create": (C.c_int, [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "sparc_ctx_destroy": (None, [C.c_void_p]),
+    "sparc_ctx_sync": (C.c_int, [C.c_void_p]),
+    "sparc_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "sparc_ctx_kernel_time": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "sparc_last_error": (C.c_char_p, []),
+    "sparc_status_string": (C.c_char_p, [C.c_int]),
+    "sparc_ham_create": (C.c_int, [C.c_void_p, C.POINTER(sparc_grid), C.POINTER(sparc_atoms), C.c_int,
+                                   C.POINTER(C.c_void_p)]),
+    "sparc_ham_destroy": (None, [C.c_void_p]),
+    "sparc_ham_set_veff": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sparc_ham_get_vloc": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sparc_ham_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "sparc_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32, C.c_int32]),
+    "fd_hamiltonian_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                       C.c_void_p, C.c_size_t]),
+    "chebyshev_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_double,
+                                   C.c_double, C.c_void_p, C.c_size_t]),
+    "rayleigh_ritz": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int, C.c_void_p, C.c_void_p,
+                                C.c_size_t, C.POINTER(C.c_int32)]),
+    "lanczos_bounds": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "density_from_orbitals": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                        C.c_int32, C.c_int, C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
+    "sparc_fermi": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.c_double,
+                              C.c_double, C.c_void_p, C.POINTER(C.c_double)]),
+}
+_OPTIONAL = {
+    "sparc_scf_run": (C.c_int, [C.c_void_p, C.POINTER(sparc_grid), C.POINTER(sparc_atoms),
+                                C.POINTER(sparc_scf_params), C.POINTER(sparc_scf_result)]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (once) and declare every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1603_04339_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS.keys())
+
+
+def _check(status: int):
+    if status != OK:
+        raise SparcError(status, load().sparc_last_error().decode())
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dptr(arr):
+    return arr.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(arr):
+    return arr.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class Context:
+    """Device + stream (torch's current stream on that device by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib.sparc_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def sync(self):
+        _check(load().sparc_ctx_sync(self.handle))
+
+    def set_timing(self, enable: bool):
+        _check(load().sparc_ctx_set_timing(self.handle, int(bool(enable))))
+
+    def kernel_time(self, kernel: str):
+        """(total milliseconds, launches) of a named kernel since set_timing."""
+        ms, n = C.c_double(), C.c_int64()
+        _check(load().sparc_ctx_kernel_time(self.handle, kernel.encode(), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if self.handle:
+            load().sparc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_grid(n, L, n_o=6, kpt=(0.0, 0.0, 0.0)):
+    g = sparc_grid()
+    for s in range(3):
+        g.n[s] = int(n[s])
+        g.L[s] = float(L[s])
+        g.kpt[s] = float(kpt[s])
+    g.n_o = int(n_o)
+    return g
+
+
+class _Atoms:
+    """Keeps the numpy arrays alive while the C struct points at them."""
+
+    def __init__(self, cell):
+        self.R = np.ascontiguousarray(cell.positions, dtype=np.float64).reshape(-1)
+        self.D = np.ascontiguousarray(cell.depth, dtype=np.float64)
+        self.W = np.ascontiguousarray(cell.width, dtype=np.float64)
+        self.ca = np.ascontiguousarray(cell.chan_atom, dtype=np.int32)
+        self.cl = np.ascontiguousarray(cell.chan_l, dtype=np.int32)
+        self.cg = np.ascontiguousarray(cell.chan_gamma, dtype=np.float64)
+        self.cr = np.ascontiguousarray(cell.chan_rc, dtype=np.float64)
+        self.Z = np.ascontiguousarray(cell.Z, dtype=np.float64)
+        a = sparc_atoms()
+        a.n_atoms = len(self.D)
+        a.R, a.vloc_depth, a.vloc_width = _dptr(self.R), _dptr(self.D), _dptr(self.W)
+        a.n_chan = len(self.ca)
+        a.chan_atom, a.chan_l = _iptr(self.ca), _iptr(self.cl)
+        a.chan_gamma, a.chan_rc, a.Z = _dptr(self.cg), _dptr(self.cr), _dptr(self.Z)
+        self.struct = a
+
+
+class Hamiltonian:
+    """One (cell, k, dtype) Hamiltonian (sparc_ham)."""
+
+    def __init__(self, ctx: Context, cell, dtype: int = R64, kpt=(0.0, 0.0, 0.0), n_o: int = 6):
+        lib = load()
+        self.ctx = ctx
+        self.dtype = dtype
+        self.grid = make_grid(cell.n, cell.L, n_o, kpt)
+        self._atoms = _Atoms(cell)
+        h = C.c_void_p()
+        _check(lib.sparc_ham_create(ctx.handle, C.byref(self.grid), C.byref(self._atoms.struct), dtype, C.byref(h)))
+        self.handle = h
+        nd, npj, ne = C.c_int64(), C.c_int32(), C.c_int64()
+        _check(lib.sparc_ham_info(h, C.byref(nd), C.byref(npj), C.byref(ne)))
+        self.n_d, self.n_proj, self.n_entries = nd.value, npj.value, ne.value
+        self.dV = float(np.prod([cell.L[s] / cell.n[s] for s in range(3)]))
+
+    def set_veff(self, veff):
+        _check(load().sparc_ham_set_veff(self.handle, _ptr(veff)))
+
+    def get_vloc(self, out):
+        _check(load().sparc_ham_get_vloc(self.handle, _ptr(out)))
+        return out
+
+    def close(self):
+        if self.handle:
+            load().sparc_ham_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sparc_workspace_bytes(ham: Hamiltonian, n_s: int, op: int) -> int:
+    return int(load().sparc_workspace_bytes(ham.handle, n_s, op))
+
+
+def workspace(ham: Hamiltonian, n_s: int, op: int, device=None):
+    nb = max(sparc_workspace_bytes(ham, n_s, op), 256)
+    return torch.empty(nb, dtype=torch.uint8, device=device or f"cuda:{ham.ctx.device}")
+
+
+def _block(X, ham):
+    if X.dtype != TORCH_DTYPE[ham.dtype]:
+        raise TypeError(f"block dtype {X.dtype} does not match the Hamiltonian's {TORCH_DTYPE[ham.dtype]}")
+    if X.dim() == 1:
+        return X, X.shape[0], 1
+    if X.stride(1) != 1:
+        raise ValueError("orbital blocks must be (n_s, ld) with unit stride along the grid")
+    return X, X.stride(0), X.shape[0]
+
+
+def fd_hamiltonian_apply(ham: Hamiltonian, X, Y, work):
+    X, ldx, ns = _block(X, ham)
+    Y, ldy, _ = _block(Y, ham)
+    _check(load().fd_hamiltonian_apply(ham.handle, _ptr(X), ldx, _ptr(Y), ldy, ns, _ptr(work), work.numel()))
+    return Y
+
+
+def chebyshev_filter(ham: Hamiltonian, X, degree: int, lambda_cut: float, lambda_max: float, work):
+    X, ldx, ns = _block(X, ham)
+    _check(load().chebyshev_filter(ham.handle, _ptr(X), ldx, ns, int(degree), float(lambda_cut),
+                                   float(lambda_max), _ptr(work), work.numel()))
+    return X
+
+
+def rayleigh_ritz(ham: Hamiltonian, X, ritz, work, mode: int = GEMM_NATIVE):
+    X, ldx, ns = _block(X, ham)
+    info = C.c_int32(0)
+    st = load().rayleigh_ritz(ham.handle, _ptr(X), ldx, ns, int(mode), _ptr(ritz), _ptr(work), work.numel(),
+                              C.byref(info))
+    _check(st)
+    return ritz
+
+
+def lanczos_bounds(ham: Hamiltonian, v0, steps: int, work):
+    lo, hi = C.c_double(), C.c_double()
+    _check(load().lanczos_bounds(ham.handle, _ptr(v0), int(steps), _ptr(work), work.numel(), C.byref(lo),
+                                 C.byref(hi)))
+    return lo.value, hi.value
+
+
+def density_from_orbitals(ctx: Context, Xs, occ_w, dV: float, rho, dtype: int):
+    nk = len(Xs)
+    ptrs = (C.c_void_p * nk)(*[X.data_ptr() for X in Xs])
+    lds = (C.c_int64 * nk)(*[X.stride(0) for X in Xs])
+    ns = Xs[0].shape[0]
+    nd = Xs[0].shape[1]
+    _check(load().density_from_orbitals(ctx.handle, nk, ptrs, lds, ns, dtype, _ptr(occ_w), nd, float(dV),
+                                        _ptr(rho)))
+    return rho
+
+
+def sparc_fermi(ctx: Context, lam, wk, n_elec: float, kT: float, occ_w=None):
+    nk, ns = lam.shape
+    w = np.ascontiguousarray(wk, dtype=np.float64)
+    mu = C.c_double()
+    _check(load().sparc_fermi(ctx.handle, nk, ns, _ptr(lam), _dptr(w), float(n_elec), float(kT), _ptr(occ_w),
+                              C.byref(mu)))
+    return mu.value
+
+
+def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=None, n_o: int = 6):
+    """Minimal SCF through the library; params keys follow sparc_scf_params."""
+    lib = load()
+    grid = make_grid(cell.n, cell.L, n_o)
+    atoms = _Atoms(cell)
+    p = sparc_scf_params()
+    for k, v in params.items():
+        if k.endswith("_dev"):
+            setattr(p, k, C.c_void_p(v.data_ptr()) if v is not None else None)
+        else:
+            setattr(p, k, v)
+    res = sparc_scf_result()
+    res.rho_dev = C.c_void_p(rho_out.data_ptr())
+    res.ritz_dev = C.c_void_p(ritz_out.data_ptr())
+    res.x_dev = C.c_void_p(x_out.data_ptr()) if x_out is not None else None
+    hist = np.zeros(3 * max(1, params.get("max_iter", 1)))
+    res.history = _dptr(hist)
+    st = lib.sparc_scf_run(ctx.handle, C.byref(grid), C.byref(atoms.struct), C.byref(p), C.byref(res))
+    out = {"energy": res.energy, "mu": res.mu, "iterations": res.iterations, "converged": bool(res.converged),
+           "history": hist[:3 * max(res.iterations, 0)].reshape(-1, 3), "status": st}
+    if st not in (OK, ENOCONV):
+        _check(st)
+    return out

@@ -1,0 +1,280 @@
+"""GPU <-> oracle parity of the CheFSI hot path through the C ABI (libsparc_hip).
+
+Tolerances (FP64): H X column-normwise 1e-12; Chebyshev filter column-normwise
+1e-10 (20 steps of a recurrence whose amplification reaches ~1e15); Ritz values
+1e-8 Ha; density 1e-12 relative.  FP32 forms: 2e-5 column-normwise on H X.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.fd import Grid, apply_H
+from oracle.chefsi import cheb_filter, rayleigh_ritz, lanczos_bounds
+from oracle.scf import density, fermi_level, occupations
+from paper_1603_04339_amd import sparc as sp
+from paper_1603_04339_amd import workloads as wl
+from tests.helpers import oracle_setup, colnorm_err, to_dev, block_to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+def _cell(n, L, n_atoms, ls, rc, seed, n_s=0):
+    cell, rng = wl.draw_cell(90, seed, n, L, n_atoms, ls, rc, n_s)
+    return cell, rng
+
+
+def _xblock(rng, nd, ns, cplx, ld=None):
+    ld = ld or nd
+    X = rng.standard_normal((ns, ld))
+    if cplx:
+        X = X + 1j * rng.standard_normal((ns, ld))
+    return X
+
+
+CASES = [
+    # (name, n, L, n_o, k, dtype, ls, rc, n_atoms, n_s, ld_pad)
+    ("c1", (24, 24, 24), (12.0, 12.0, 12.0), 6, (0, 0, 0), sp.R64, (0,), 3.0, 8, 32, 0),
+    ("ragged_sp", (7, 12, 13), (3.5, 6.6, 6.5), 6, (0, 0, 0), sp.R64, (0, 1), 2.0, 3, 5, 3),
+    ("bloch_no2", (12, 13, 7), (6.0, 6.5, 4.2), 2, (0.3, -0.2, 0.45), sp.C128, (0, 1), 2.0, 3, 3, 0),
+    ("multiwrap", (5, 6, 9), (2.5, 3.0, 4.5), 6, (0.9, 0.4, -0.7), sp.C128, (0,), 1.2, 2, 3, 1),
+    ("no1_single", (16, 16, 16), (8.0, 8.0, 8.0), 1, (0, 0, 0), sp.R64, (0,), 2.5, 2, 1, 0),
+    ("wide48_k", (48, 40, 33), (24.0, 20.0, 16.5), 6, (0.1, 0.05, -0.08), sp.C128, (0, 1), 3.0, 5, 7, 0),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_vloc_and_apply_parity(ctx, case):
+    name, n, L, n_o, k, dt, ls, rc, na, ns, pad = case
+    print(f"\n[case {name}] n={n} n_o={n_o} k={k} dtype={dt} n_s={ns}", flush=True)
+    cell, rng = _cell(n, L, na, ls, rc, [c[0] for c in CASES].index(name))
+    grid, V, P = oracle_setup(cell, k, n_o)
+    ham = sp.Hamiltonian(ctx, cell, dt, kpt=k, n_o=n_o)
+    vl = torch.empty(grid.n_d, dtype=torch.float64, device="cuda:0")
+    ham.get_vloc(vl)
+    np.testing.assert_allclose(vl.cpu().numpy(), V, rtol=0, atol=1e-12 * max(1.0, np.abs(V).max()))
+    cplx = dt in (sp.C128, sp.C64)
+    Xh = _xblock(rng, grid.n_d, ns, cplx, grid.n_d + pad)
+    X = to_dev(Xh)
+    Y = torch.zeros_like(X)
+    work = sp.workspace(ham, ns, sp.OP_APPLY)
+    sp.fd_hamiltonian_apply(ham, X, Y, work)
+    torch.cuda.synchronize()
+    Yref = apply_H(Xh[:, :grid.n_d].T, grid, V, P)
+    assert colnorm_err(block_to_oracle(Y)[:grid.n_d], Yref) < 1e-12
+    # padding rows of Y are not written
+    if pad:
+        assert torch.all(Y[:, grid.n_d:] == 0)
+
+
+@pytest.mark.parametrize("dt", [sp.R32, sp.C64])
+def test_apply_single_precision(ctx, dt):
+    cplx = dt == sp.C64
+    k = (0.2, -0.1, 0.3) if cplx else (0, 0, 0)
+    cell, rng = _cell((20, 18, 16), (10.0, 9.0, 8.0), 4, (0, 1), 2.5, 7)
+    grid, V, P = oracle_setup(cell, k)
+    ham = sp.Hamiltonian(ctx, cell, dt, kpt=k)
+    Xh = _xblock(rng, grid.n_d, 6, cplx)
+    X = to_dev(Xh, sp.TORCH_DTYPE[dt])
+    Y = torch.zeros_like(X)
+    sp.fd_hamiltonian_apply(ham, X, Y, sp.workspace(ham, 6, sp.OP_APPLY))
+    Yref = apply_H(X.cpu().numpy().astype(np.complex128 if cplx else np.float64).T, grid, V, P)
+    assert colnorm_err(block_to_oracle(Y).astype(Yref.dtype), Yref) < 2e-5
+
+
+def test_filter_parity_c1(ctx):
+    cell, X0, rng = wl.config_cell("c1")
+    grid, V, P = oracle_setup(cell)
+    v0 = wl.lanczos_start(rng, grid.n_d)
+    lmin, lmax = lanczos_bounds(grid, V, P, v0, 20)
+    lcut = 0.5 * (lmin + lmax)
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    X = to_dev(X0)
+    sp.chebyshev_filter(ham, X, 20, lcut, lmax, sp.workspace(ham, 32, sp.OP_FILTER))
+    Yref = cheb_filter(X0.T, grid, V, P, 20, lcut, lmax)
+    err = colnorm_err(block_to_oracle(X), Yref)
+    print(f"filter c1 colnorm err {err:.3e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("degree", [1, 2, 7])
+def test_filter_parity_bloch(ctx, degree):
+    k = (0.25, -0.3, 0.1)
+    cell, rng = _cell((12, 14, 10), (6.0, 7.0, 5.0), 3, (0, 1), 2.0, 11)
+    grid, V, P = oracle_setup(cell, k)
+    Xh = _xblock(rng, grid.n_d, 4, True)
+    ham = sp.Hamiltonian(ctx, cell, sp.C128, kpt=k)
+    X = to_dev(Xh)
+    sp.chebyshev_filter(ham, X, degree, 1.0, 60.0, sp.workspace(ham, 4, sp.OP_FILTER))
+    Yref = cheb_filter(Xh.T, grid, V, P, degree, 1.0, 60.0)
+    assert colnorm_err(block_to_oracle(X), Yref) < 1e-11
+
+
+def test_lanczos_parity_c1(ctx):
+    cell, X0, rng = wl.config_cell("c1")
+    grid, V, P = oracle_setup(cell)
+    v0 = wl.lanczos_start(rng, grid.n_d)
+    ref = lanczos_bounds(grid, V, P, v0, 20)
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    got = sp.lanczos_bounds(ham, to_dev(v0), 20, sp.workspace(ham, 20, sp.OP_LANCZOS))
+    print("lanczos", got, ref)
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
+
+
+def test_rayleigh_ritz_parity_c1(ctx):
+    """Same filtered block on both sides: Ritz values within 1e-8 Ha, the
+    rotated block orthonormal and diagonalising H."""
+    cell, X0, rng = wl.config_cell("c1")
+    grid, V, P = oracle_setup(cell)
+    v0 = wl.lanczos_start(rng, grid.n_d)
+    lmin, lmax = lanczos_bounds(grid, V, P, v0, 20)
+    Xf = cheb_filter(X0.T, grid, V, P, 20, 0.5 * (lmin + lmax), lmax)
+    lam_ref, _ = rayleigh_ritz(Xf, grid, V, P)
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    X = to_dev(Xf.T)
+    ritz = torch.zeros(32, dtype=torch.float64, device="cuda:0")
+    sp.rayleigh_ritz(ham, X, ritz, sp.workspace(ham, 32, sp.OP_RR))
+    lam = ritz.cpu().numpy()
+    print("ritz max err", np.abs(lam - lam_ref).max(), "cond", np.linalg.cond(Xf))
+    np.testing.assert_allclose(lam, lam_ref, atol=1e-8, rtol=0)
+    Xo = block_to_oracle(X)
+    np.testing.assert_allclose(Xo.T @ Xo, np.eye(32), atol=1e-10)
+    Hs = Xo.T @ apply_H(Xo, grid, V, P)
+    np.testing.assert_allclose(Hs, np.diag(lam_ref), atol=1e-8)
+
+
+def test_chefsi_passes_c1(ctx):
+    """Four filter + Rayleigh-Ritz passes from the seeded start (the c1
+    schedule): Ritz values of every pass within 1e-8 Ha of the oracle's."""
+    cell, X0, rng = wl.config_cell("c1")
+    grid, V, P = oracle_setup(cell)
+    v0 = wl.lanczos_start(rng, grid.n_d)
+    lmin, lmax = lanczos_bounds(grid, V, P, v0, 20)
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    X = to_dev(X0)
+    wf = sp.workspace(ham, 32, sp.OP_FILTER)
+    wr = sp.workspace(ham, 32, sp.OP_RR)
+    ritz = torch.zeros(32, dtype=torch.float64, device="cuda:0")
+    Xr = X0.T.copy()
+    lam_ref = None
+    for it in range(4):
+        lcut = 0.5 * (lmin + lmax) if lam_ref is None else lam_ref[-1]
+        Xr = cheb_filter(Xr, grid, V, P, 20, lcut, lmax)
+        lam_ref, Xr = rayleigh_ritz(Xr, grid, V, P)
+        sp.chebyshev_filter(ham, X, 20, lcut, lmax, wf)
+        sp.rayleigh_ritz(ham, X, ritz, wr)
+        lam = ritz.cpu().numpy()
+        print(f"pass {it}: max |dritz| = {np.abs(lam - lam_ref).max():.2e}")
+        np.testing.assert_allclose(lam, lam_ref, atol=1e-8, rtol=0)
+
+
+def test_rayleigh_ritz_complex(ctx):
+    k = (0.3, 0.2, -0.25)
+    cell, rng = _cell((14, 12, 13), (7.0, 6.0, 6.5), 3, (0, 1), 2.2, 21)
+    grid, V, P = oracle_setup(cell, k)
+    Xh = _xblock(rng, grid.n_d, 9, True)
+    Xf = cheb_filter(Xh.T, grid, V, P, 8, 5.0, 80.0)
+    lam_ref, _ = rayleigh_ritz(Xf, grid, V, P)
+    ham = sp.Hamiltonian(ctx, cell, sp.C128, kpt=k)
+    X = to_dev(Xf.T)
+    ritz = torch.zeros(9, dtype=torch.float64, device="cuda:0")
+    sp.rayleigh_ritz(ham, X, ritz, sp.workspace(ham, 9, sp.OP_RR))
+    np.testing.assert_allclose(ritz.cpu().numpy(), lam_ref, atol=1e-8)
+    Xo = block_to_oracle(X)
+    np.testing.assert_allclose(Xo.conj().T @ Xo, np.eye(9), atol=1e-10)
+
+
+def test_degenerate_spectrum_rr(ctx):
+    """Empty cell: exactly degenerate plane-wave shells; Ritz vectors must stay
+    orthonormal and the Ritz values reproduce the closed-shell levels."""
+    cell = wl.Cell(n=(24, 24, 24), L=(12.0, 12.0, 12.0), positions=np.zeros((0, 3)), depth=np.zeros(0),
+                   width=np.zeros(0), chan_atom=np.zeros(0, np.int32), chan_l=np.zeros(0, np.int32),
+                   chan_gamma=np.zeros(0), chan_rc=np.zeros(0), Z=np.zeros(0))
+    grid, V, P = oracle_setup(cell)
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    rng = np.random.default_rng(0)
+    X = to_dev(rng.standard_normal((40, grid.n_d)))
+    wf, wr = sp.workspace(ham, 40, sp.OP_FILTER), sp.workspace(ham, 40, sp.OP_RR)
+    ritz = torch.zeros(40, dtype=torch.float64, device="cuda:0")
+    lmax = 3.53647 * 3 / 0.25 * 1.01
+    lcut = 2.0
+    for it in range(8):
+        sp.chebyshev_filter(ham, X, 20, lcut, lmax, wf)
+        sp.rayleigh_ritz(ham, X, ritz, wr)
+        lcut = float(ritz[-1])
+    ref = [0.0] + [0.137078] * 6 + [0.274156] * 12 + [0.411234] * 8 + [0.548311] * 6
+    np.testing.assert_allclose(ritz.cpu().numpy()[:33], ref, atol=2e-6)
+    Xo = block_to_oracle(X)
+    np.testing.assert_allclose(Xo.T @ Xo, np.eye(40), atol=1e-9)
+
+
+@pytest.mark.parametrize("dt", [sp.R64, sp.C128, sp.R32])
+def test_density_parity(ctx, dt):
+    rng = np.random.default_rng(5)
+    nd, ns, nk = 13 * 11 * 9, 7, (2 if dt == sp.C128 else 1)
+    cplx = dt == sp.C128
+    Xs = [_xblock(rng, nd, ns, cplx, nd + 5) for _ in range(nk)]
+    occ = rng.uniform(0, 0.5, (nk, ns))
+    dV = 0.37
+    tX = [to_dev(X, sp.TORCH_DTYPE[dt]) for X in Xs]
+    rho = torch.zeros(nd, dtype=torch.float64, device="cuda:0")
+    sp.density_from_orbitals(ctx, [t[:, :nd] for t in tX], to_dev(occ), dV, rho, dt)
+    ref = density([t.cpu().numpy()[:, :nd].T.astype(np.complex128 if cplx else np.float64) for t in tX], occ, dV)
+    np.testing.assert_allclose(rho.cpu().numpy(), ref, rtol=1e-12)
+
+
+def test_fermi_parity(ctx):
+    rng = np.random.default_rng(3)
+    lam = np.sort(rng.uniform(-1, 1, (4, 20)), axis=1)
+    wk = np.array([0.1, 0.2, 0.3, 0.4])
+    mu_ref = fermi_level(lam, wk, 11.0, 0.01)
+    occ = torch.zeros(4, 20, dtype=torch.float64, device="cuda:0")
+    mu = sp.sparc_fermi(ctx, to_dev(lam), wk, 11.0, 0.01, occ)
+    assert mu == pytest.approx(mu_ref, abs=1e-12)
+    np.testing.assert_allclose(occ.cpu().numpy(), wk[:, None] * occupations(lam, mu_ref, 0.01), atol=1e-11)
+
+
+def test_error_paths(ctx):
+    cell, rng = _cell((10, 10, 10), (5.0, 5.0, 5.0), 2, (0,), 2.0, 1)
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    X = torch.zeros(3, 1000, dtype=torch.float64, device="cuda:0")
+    Y = torch.zeros_like(X)
+    with pytest.raises(sp.SparcError) as e:
+        sp.fd_hamiltonian_apply(ham, torch.zeros(3, 999, dtype=torch.float64, device="cuda:0"), Y,
+                                sp.workspace(ham, 3, sp.OP_APPLY))
+    assert e.value.status in (sp.ESHAPE, sp.EINVAL)
+    with pytest.raises(sp.SparcError) as e:
+        sp.chebyshev_filter(ham, X, 5, 1.0, 2.0, torch.zeros(16, dtype=torch.uint8, device="cuda:0"))
+    assert e.value.status == sp.ENOMEM
+    with pytest.raises(sp.SparcError) as e:
+        sp.chebyshev_filter(ham, X, 5, 3.0, 2.0, sp.workspace(ham, 3, sp.OP_FILTER))
+    assert e.value.status == sp.EINVAL
+    # a zero column or a NaN cannot be orthonormalised
+    ritz = torch.zeros(3, dtype=torch.float64, device="cuda:0")
+    wr = sp.workspace(ham, 3, sp.OP_RR)
+    for bad in (0.0, float("nan")):
+        Xd = to_dev(rng.standard_normal((3, 1000)))
+        Xd[1] = bad
+        with pytest.raises(sp.SparcError) as e:
+            sp.rayleigh_ritz(ham, Xd, ritz, wr)
+        assert e.value.status == sp.ENOTSPD
+    # numerically rank-deficient (duplicate columns): like a Householder QR, the
+    # shifted Cholesky-QR completes the basis; the result must be orthonormal
+    Xd = to_dev(np.tile(rng.standard_normal((1, 1000)), (3, 1)))
+    sp.rayleigh_ritz(ham, Xd, ritz, wr)
+    Xo = block_to_oracle(Xd)
+    np.testing.assert_allclose(Xo.T @ Xo, np.eye(3), atol=1e-8)
+    with pytest.raises(sp.SparcError) as e:
+        sp.Hamiltonian(ctx, cell, sp.R64, kpt=(0.1, 0, 0))
+    assert e.value.status == sp.EINVAL
