@@ -64,6 +64,30 @@ __device__ __forceinline__ double abs2(float v) { return (double)v * (double)v; 
 __device__ __forceinline__ double abs2(cd v) { return v.re * v.re + v.im * v.im; }
 __device__ __forceinline__ double abs2(cf v) { return (double)v.re * v.re + (double)v.im * v.im; }
 
+// streaming (non-temporal) loads and stores
+__device__ __forceinline__ double nt_load(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float nt_load(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ cd nt_load(const cd* p) {
+  const double* q = (const double*)p;
+  return {__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1)};
+}
+__device__ __forceinline__ cf nt_load(const cf* p) {
+  const float* q = (const float*)p;
+  return {__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1)};
+}
+__device__ __forceinline__ void nt_store(double v, double* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(float v, float* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void nt_store(cd v, cd* p) {
+  double* q = (double*)p;
+  __builtin_nontemporal_store(v.re, q);
+  __builtin_nontemporal_store(v.im, q + 1);
+}
+__device__ __forceinline__ void nt_store(cf v, cf* p) {
+  float* q = (float*)p;
+  __builtin_nontemporal_store(v.re, q);
+  __builtin_nontemporal_store(v.im, q + 1);
+}
+
 // wave64 butterfly sum
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -10,6 +10,8 @@
 // in LDS (double-buffered, one barrier per plane) for the x and y taps.  Loads
 // are x-fastest and coalesced; nodes outside the cell are fetched from their
 // periodic image with the Bloch factor e^{i k_s L_s w}.
+#include <cstdlib>
+
 #include "devmath.hpp"
 
 namespace sparc {
@@ -26,14 +28,8 @@ struct StepArgs {
   const R* __restrict__ veff;
   R centre;        // a * centre coefficient of -1/2 Lap_h
   R tx[8], ty[8], tz[8];
-  R va, vb, zc;    // out = lap*a + (a V + b) x + zc z (+ a NL)
-  R nl_a;
+  R va, vb, zc;    // out = lap*a + (a V + b) x + zc z
   double kl[3];    // k_s L_s
-  const int32_t* __restrict__ pt_ptr;
-  const int32_t* __restrict__ ent_proj;
-  const E* __restrict__ ent_coef;
-  const E* __restrict__ alpha;
-  int n_proj;
 };
 
 template <typename E>
@@ -59,8 +55,11 @@ __device__ __forceinline__ void bloch_factor(const double* kl, int wx, int wy, i
 template <typename E, int TX, int TY, int NO>
 __global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
   typedef typename elem<E>::real R;
+  constexpr int NT = TX * TY;
   constexpr int PX = TX + 2 * NO, PY = TY + 2 * NO;
-  __shared__ E plane[2][PY][PX];
+  constexpr int HC = 2 * NO * (TX + TY);         // halo cells of one plane (no corners)
+  constexpr int HM = (HC + NT - 1) / NT;         // halo cells per thread
+  __shared__ E plane[2][PY * PX];
 
   const int tid = threadIdx.x;
   const int hx = tid % TX, hy = tid / TX;
@@ -76,59 +75,112 @@ __global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
   // own column: extended coordinates, periodic source and Bloch factor in x, y
   const int ex = x0 + hx, ey = y0 + hy;
   const int wx = floordiv_i(ex, n1), wy = floordiv_i(ey, n2);
-  const int sx = ex - wx * n1, sy = ey - wy * n2;
+  const int col = (ex - wx * n1) + n1 * (ey - wy * n2);
   const bool inside = (ex < n1) && (ey < n2);
-  const int64_t col = sx + (int64_t)n1 * sy;
+  R cxy = 1, sxy = 0;
+  bloch_factor<E>(A.kl, wx, wy, 0, cxy, sxy);
+  const int own = (hy + NO) * PX + hx + NO;
 
-  auto load_col = [&](int zz) -> E {
-    int wz = floordiv_i(zz, n3);
-    int sz = zz - wz * n3;
+  // halo cells owned by this thread: LDS slot, offset inside a plane, Bloch factor
+  int h_lds[HM], h_off[HM];
+  R h_c[HM], h_s[HM];
+#pragma unroll
+  for (int u = 0; u < HM; ++u) {
+    const int c = tid + u * NT;
+    h_lds[u] = -1;
+    h_off[u] = 0;
+    h_c[u] = 1;
+    h_s[u] = 0;
+    if (c < HC) {
+      int cx, cy;
+      if (c < 2 * NO * TY) {  // x strips
+        const int r = c / (2 * NO), k = c % (2 * NO);
+        cy = r;
+        cx = (k < NO) ? (k - NO) : (TX + k - NO);
+      } else {  // y strips
+        const int c2 = c - 2 * NO * TY;
+        const int r = c2 / TX, k = c2 % TX;
+        cx = k;
+        cy = (r < NO) ? (r - NO) : (TY + r - NO);
+      }
+      const int gx = x0 + cx, gy = y0 + cy;
+      const int hwx = floordiv_i(gx, n1), hwy = floordiv_i(gy, n2);
+      h_off[u] = (gx - hwx * n1) + n1 * (gy - hwy * n2);
+      h_lds[u] = (cy + NO) * PX + cx + NO;
+      bloch_factor<E>(A.kl, hwx, hwy, 0, h_c[u], h_s[u]);
+    }
+  }
+
+  // z-direction register queue q[d] = x(column, z - NO + d); the plane index of the
+  // next load and its number of cell wraps are advanced without divisions
+  int zl = zb - NO;
+  int wz = floordiv_i(zl, n3);
+  int sz = zl - wz * n3;
+  auto load_next = [&]() -> E {
     E v = xc[col + plane_sz * sz];
     if constexpr (elem<E>::is_cplx) {
-      if (wx != 0 || wy != 0 || wz != 0) {
-        R c, s;
-        bloch_factor<E>(A.kl, wx, wy, wz, c, s);
+      if (wz != 0 || cxy != 1 || sxy != 0) {
+        R c = cxy, s = sxy;
+        if (wz != 0) {
+          R cz, szn;
+          bloch_factor<E>(A.kl, wx, wy, wz, cz, szn);
+          c = cz;
+          s = szn;
+        }
         v = rot(v, c, s);
       }
+    }
+    if (++sz == n3) {
+      sz = 0;
+      ++wz;
     }
     return v;
   };
 
   E q[2 * NO + 1];
 #pragma unroll
-  for (int d = 0; d < 2 * NO; ++d) q[d] = load_col(zb - NO + d);
+  for (int d = 0; d < 2 * NO; ++d) q[d] = load_next();
 
-  constexpr int HC = 2 * NO * (TX + TY);  // halo cells of one plane (no corners)
+  // software pipeline: the column value and halo cells of plane z+1 are loaded while
+  // plane z is computed (their latency is hidden behind one plane of work)
+  const E* __restrict__ pz = xc + plane_sz * zb;
+  E qn = load_next();
+  E hn[HM];
+#pragma unroll
+  for (int u = 0; u < HM; ++u) {
+    hn[u] = zero<E>();
+    if (h_lds[u] >= 0 && zb < ze) hn[u] = pz[h_off[u]];
+  }
+  int64_t g = col + plane_sz * zb;
+  const R* __restrict__ vp = A.veff;
+  const E* __restrict__ zp = A.z ? A.z + (int64_t)n * A.ldz : nullptr;
+  E* __restrict__ op = A.out + (int64_t)n * A.ldo;
   int step = 0;
-  for (int z = zb; z < ze; ++z, ++step) {
-    q[2 * NO] = load_col(z + NO);
-    const int b = step & 1;
-    plane[b][hy + NO][hx + NO] = q[NO];
-    // halo of plane z (z is inside the cell)
-    const E* __restrict__ pz = xc + plane_sz * z;
-    for (int c = tid; c < HC; c += TX * TY) {
-      int cx, cy;
-      if (c < 2 * NO * TY) {  // x strips
-        int r = c / (2 * NO), k = c % (2 * NO);
-        cy = r;
-        cx = (k < NO) ? (k - NO) : (TX + k - NO);
-      } else {  // y strips
-        int c2 = c - 2 * NO * TY;
-        int r = c2 / TX, k = c2 % TX;
-        cx = k;
-        cy = (r < NO) ? (r - NO) : (TY + r - NO);
+  for (int z = zb; z < ze; ++z, ++step, g += plane_sz) {
+    q[2 * NO] = qn;
+    E* __restrict__ pl = plane[step & 1];
+    pl[own] = q[NO];
+#pragma unroll
+    for (int u = 0; u < HM; ++u) {
+      if (h_lds[u] >= 0) {
+        E v = hn[u];
+        if constexpr (elem<E>::is_cplx) v = rot(v, h_c[u], h_s[u]);
+        pl[h_lds[u]] = v;
       }
-      int gx = x0 + cx, gy = y0 + cy;
-      int hwx = floordiv_i(gx, n1), hwy = floordiv_i(gy, n2);
-      E v = pz[(gx - hwx * n1) + (int64_t)n1 * (gy - hwy * n2)];
-      if constexpr (elem<E>::is_cplx) {
-        if (hwx != 0 || hwy != 0) {
-          R cc, ss;
-          bloch_factor<E>(A.kl, hwx, hwy, 0, cc, ss);
-          v = rot(v, cc, ss);
-        }
-      }
-      plane[b][cy + NO][cx + NO] = v;
+    }
+    // issue the loads of the next plane and of this plane's point data
+    pz += plane_sz;
+    if (z + 1 < ze) {
+      qn = load_next();
+#pragma unroll
+      for (int u = 0; u < HM; ++u)
+        if (h_lds[u] >= 0) hn[u] = pz[h_off[u]];
+    }
+    R v = 0;
+    E zv = zero<E>();
+    if (inside) {
+      v = vp[g];
+      if (zp) zv = nt_load(zp + g);
     }
     __syncthreads();
     if (inside) {
@@ -136,30 +188,54 @@ __global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
 #pragma unroll
       for (int p = 1; p <= NO; ++p) {
         lap = fmar(lap, A.tz[p - 1], q[NO + p] + q[NO - p]);
-        lap = fmar(lap, A.tx[p - 1], plane[b][hy + NO][hx + NO + p] + plane[b][hy + NO][hx + NO - p]);
-        lap = fmar(lap, A.ty[p - 1], plane[b][hy + NO + p][hx + NO] + plane[b][hy + NO - p][hx + NO]);
+        lap = fmar(lap, A.tx[p - 1], pl[own + p] + pl[own - p]);
+        lap = fmar(lap, A.ty[p - 1], pl[own + p * PX] + pl[own - p * PX]);
       }
-      const int64_t g = col + plane_sz * z;
-      R v = A.veff[g];
       E r = fmar(lap, (R)(A.va * v + A.vb), q[NO]);
-      if (A.alpha) {
-        int e0 = A.pt_ptr[g], e1 = A.pt_ptr[g + 1];
-        if (e0 < e1) {
-          const E* __restrict__ al = A.alpha + (int64_t)n * A.n_proj;
-          E nl = zero<E>();
-          for (int e = e0; e < e1; ++e) nl = fmae(nl, A.ent_coef[e], al[A.ent_proj[e]]);
-          r = fmar(r, A.nl_a, nl);
-        }
-      }
-      if (A.z) r = fmar(r, A.zc, A.z[g + (int64_t)n * A.ldz]);
-      A.out[g + (int64_t)n * A.ldo] = r;
+      if (zp) r = fmar(r, A.zc, zv);
+      nt_store(r, op + g);
     }
 #pragma unroll
     for (int d = 0; d < 2 * NO; ++d) q[d] = q[d + 1];
   }
 }
 
-// Non-local gather: alpha[n][p] = dV * sum_{t in supp(atom)} conj(chi~_p(t)) x(g_t, n)
+// Non-local scatter: y(g, n) += a * sum_{entries e at g} gamma_p chi~_p(g) alpha[p][n] over the
+// nodes that carry projector support (point-major CSR).  One thread per node and
+// block of NB orbitals; alpha is projector-major with the orbitals contiguous
+// (leading dimension lda, a multiple of NB), so each entry reads NB coefficients
+// in one vector load.
+template <typename E, int NB>
+__global__ __launch_bounds__(256) void nl_scatter_kernel(int n_pts, const int32_t* __restrict__ pts,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ ent_proj,
+                                                         const E* __restrict__ ent_coef,
+                                                         const E* __restrict__ alpha, int lda, int n_s,
+                                                         typename elem<E>::real a, E* __restrict__ y, int64_t ldy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pts) return;
+  const int nb0 = blockIdx.y * NB;
+  const int64_t g = pts[i];
+  const int e0 = ptr[i], ne = ptr[i + 1] - e0;
+  E acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = zero<E>();
+  for (int u = 0; u < ne; ++u) {
+    const E c = ent_coef[e0 + u];
+    const E* __restrict__ ap = alpha + (int64_t)ent_proj[e0 + u] * lda + nb0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = fmae(acc[j], c, ap[j]);
+  }
+  E yv[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    if (nb0 + j < n_s) yv[j] = y[g + (int64_t)(nb0 + j) * ldy];
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    if (nb0 + j < n_s) y[g + (int64_t)(nb0 + j) * ldy] = fmar(yv[j], a, acc[j]);
+}
+
+// Non-local gather: alpha[p][n] = dV * sum_{t in supp(atom)} conj(chi~_p(t)) x(g_t, n)
 // One work-group per (atom, block of NB orbitals).
 template <typename E, int MAXP, int NB>
 __global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x, int64_t ldx, int n_s,
@@ -168,7 +244,7 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x,
                                                         const int32_t* __restrict__ atom_pbeg,
                                                         const int64_t* __restrict__ proj_voff,
                                                         const E* __restrict__ pval, double dV,
-                                                        E* __restrict__ alpha, int n_proj) {
+                                                        E* __restrict__ alpha, int lda) {
   typedef typename elem<E>::real R;
   constexpr int NV = elem<E>::is_cplx ? 2 : 1;
   const int a = blockIdx.x;
@@ -183,6 +259,7 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x,
   int64_t voff[MAXP];
 #pragma unroll
   for (int p = 0; p < MAXP; ++p) voff[p] = (p < np) ? proj_voff[pb + p] : 0;
+#pragma unroll 2
   for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
     const int64_t g = sup_idx[t];
     E chi[MAXP];
@@ -217,13 +294,16 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x,
     int p = pj / NB, j = pj % NB;
     if (p < np && nb0 + j < n_s) {
       R s = red[0][i] + red[1][i] + red[2][i] + red[3][i];
-      ((R*)&alpha[(int64_t)(nb0 + j) * n_proj + pb + p])[c] = (R)(dV * (double)s);
+      ((R*)&alpha[(int64_t)(pb + p) * lda + nb0 + j])[c] = (R)(dV * (double)s);
     }
   }
 }
 
+// projections are stored [projector][orbital] with the orbital count padded to a multiple of 8
+static inline int alpha_ld(int32_t n_s) { return ((n_s + 7) / 8) * 8; }
+
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s) {
-  return (size_t)std::max(H->n_proj, 1) * (size_t)n_s * elem_bytes(H->dtype);
+  return (size_t)std::max(H->n_proj, 1) * (size_t)alpha_ld(n_s) * elem_bytes(H->dtype);
 }
 
 template <typename E>
@@ -236,10 +316,10 @@ static int nl_project_t(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, v
   struct End { sparc_ctx* c; int t; ~End() { timer_end(c, t); } } end_{H->ctx, t};
   if (H->max_proj_per_atom <= 1)
     nl_gather_kernel<E, 1, NB><<<grid, 256, 0, st>>>((const E*)x, ldx, n_s, H->sup_ptr, H->sup_idx, H->atom_pbeg,
-                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, H->n_proj);
+                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, alpha_ld(n_s));
   else if (H->max_proj_per_atom <= 4)
     nl_gather_kernel<E, 4, NB><<<grid, 256, 0, st>>>((const E*)x, ldx, n_s, H->sup_ptr, H->sup_idx, H->atom_pbeg,
-                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, H->n_proj);
+                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, alpha_ld(n_s));
   else
     return fail(SPARC_EINVAL, "nl_project: more than 4 projector functions on one atom");
   return check_launch("nl_gather_kernel");
@@ -273,11 +353,44 @@ static int launch_step(sparc_ham* H, StepArgs<E>& A, int32_t n_s) {
   return check_launch("hstep_kernel");
 }
 
+// Tile shapes (TX x TY threads).  The default picks the widest x extent that
+// divides n1 (no idle columns), else the one with the least waste; SPARC_HSTEP_TILE
+// (an index into this list) overrides the choice.
+struct TileShape { int tx, ty; };
+static const TileShape kTiles[] = {{32, 8}, {32, 16}, {64, 4}, {64, 8}, {16, 16}, {24, 8}, {48, 8}, {32, 32}};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+static int pick_tile(int n1, int n2) {
+  const char* env = getenv("SPARC_HSTEP_TILE");
+  if (env) {
+    int t = atoi(env);
+    if (t >= 0 && t < kNumTiles) return t;
+  }
+  int best = 0;
+  double best_cost = 1e30;
+  for (int t = 0; t < kNumTiles; ++t) {
+    const int tx = kTiles[t].tx, ty = kTiles[t].ty;
+    if (tx * ty > 512) continue;
+    const double waste = (double)((n1 + tx - 1) / tx * tx) / n1 * ((n2 + ty - 1) / ty * ty) / n2;
+    const double halo = 1.0 + 12.0 * (tx + ty) / (double)(tx * ty) * 0.25;
+    const double cost = waste * halo;
+    if (cost < best_cost - 1e-12) { best_cost = cost; best = t; }
+  }
+  return best;
+}
+
 template <typename E, int NO>
 static int dispatch_tile(sparc_ham* H, StepArgs<E>& A, int32_t n_s) {
-  if (A.n1 >= 64) return launch_step<E, 64, 4, NO>(H, A, n_s);
-  if (A.n1 >= 32) return launch_step<E, 32, 8, NO>(H, A, n_s);
-  return launch_step<E, 16, 16, NO>(H, A, n_s);
+  switch (pick_tile(A.n1, A.n2)) {
+    case 0: return launch_step<E, 32, 8, NO>(H, A, n_s);
+    case 1: return launch_step<E, 32, 16, NO>(H, A, n_s);
+    case 2: return launch_step<E, 64, 4, NO>(H, A, n_s);
+    case 3: return launch_step<E, 64, 8, NO>(H, A, n_s);
+    case 4: return launch_step<E, 16, 16, NO>(H, A, n_s);
+    case 5: return launch_step<E, 24, 8, NO>(H, A, n_s);
+    case 6: return launch_step<E, 48, 8, NO>(H, A, n_s);
+    default: return launch_step<E, 32, 32, NO>(H, A, n_s);
+  }
 }
 
 template <typename E>
@@ -305,24 +418,29 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   A.va = (R)a;
   A.vb = (R)b;
   A.zc = (R)c;
-  A.nl_a = (R)a;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
-  A.pt_ptr = H->pt_ptr;
-  A.ent_proj = H->ent_proj;
-  A.ent_coef = (const E*)H->ent_coef;
-  A.alpha = (H->n_proj > 0) ? (const E*)alpha : nullptr;
-  A.n_proj = H->n_proj;
+  int rc;
   switch (H->grid.n_o) {
-    case 1: return dispatch_tile<E, 1>(H, A, n_s);
-    case 2: return dispatch_tile<E, 2>(H, A, n_s);
-    case 3: return dispatch_tile<E, 3>(H, A, n_s);
-    case 4: return dispatch_tile<E, 4>(H, A, n_s);
-    case 5: return dispatch_tile<E, 5>(H, A, n_s);
-    case 6: return dispatch_tile<E, 6>(H, A, n_s);
-    case 7: return dispatch_tile<E, 7>(H, A, n_s);
-    case 8: return dispatch_tile<E, 8>(H, A, n_s);
+    case 1: rc = dispatch_tile<E, 1>(H, A, n_s); break;
+    case 2: rc = dispatch_tile<E, 2>(H, A, n_s); break;
+    case 3: rc = dispatch_tile<E, 3>(H, A, n_s); break;
+    case 4: rc = dispatch_tile<E, 4>(H, A, n_s); break;
+    case 5: rc = dispatch_tile<E, 5>(H, A, n_s); break;
+    case 6: rc = dispatch_tile<E, 6>(H, A, n_s); break;
+    case 7: rc = dispatch_tile<E, 7>(H, A, n_s); break;
+    case 8: rc = dispatch_tile<E, 8>(H, A, n_s); break;
+    default: return fail(SPARC_EINVAL, "ham_step: n_o=%d unsupported", H->grid.n_o);
   }
-  return fail(SPARC_EINVAL, "ham_step: n_o=%d unsupported", H->grid.n_o);
+  if (rc != SPARC_OK || H->n_proj == 0 || H->n_nlpts == 0) return rc;
+  if (!alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
+  constexpr int NB = 8;
+  dim3 grid((unsigned)((H->n_nlpts + 255) / 256), (unsigned)((n_s + NB - 1) / NB));
+  int t = timer_begin(H->ctx, "nl_scatter");
+  nl_scatter_kernel<E, NB><<<grid, 256, 0, H->ctx->stream>>>(
+      (int)H->n_nlpts, H->nl_pts, H->nl_ptr, H->ent_proj, (const E*)H->ent_coef, (const E*)alpha, alpha_ld(n_s), n_s,
+      (R)a, (E*)out, ldo);
+  timer_end(H->ctx, t);
+  return check_launch("nl_scatter_kernel");
 }
 
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,

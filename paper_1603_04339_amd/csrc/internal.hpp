@@ -102,7 +102,9 @@ struct sparc_ham {
   int64_t* proj_voff;   // [n_proj] offset of the projector's values in pval
   void* pval;           // [sum over projectors of support size] chi~ values (element type)
   void* gamma_d;        // [n_proj] gamma per projector (real of the element precision)
-  int32_t* pt_ptr;      // [n_d+1] CSR: entries touching grid point g
+  int64_t n_nlpts;      // grid nodes carrying projector support
+  int32_t* nl_pts;      // [n_nlpts] those nodes (ascending grid index)
+  int32_t* nl_ptr;      // [n_nlpts+1] CSR: entries of each such node
   int32_t* ent_proj;    // [n_ent] projector of the entry
   void* ent_coef;       // [n_ent] gamma_p * chi~_p(g) (element type)
 };
@@ -122,6 +124,7 @@ void timer_end(sparc_ctx* c, int idx);
 
 // Hamiltonian application kernels (hamiltonian.hip)
 //   out = a*(H x) + b*x + c*z ; z may alias out (in-place recurrence), x must not.
+//   Runs the stencil/potential/recurrence kernel, then the non-local scatter into out.
 //   alpha: projections [n_s][n_proj] of x (already scaled by dV), from nl_project.
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
              int32_t n_s, double a, double b, double c, const void* alpha);

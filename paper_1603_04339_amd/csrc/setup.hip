@@ -426,18 +426,31 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
     int np = T.atom_pbeg[a + 1] - T.atom_pbeg[a];
     for (int t = T.sup_ptr[a]; t < T.sup_ptr[a + 1]; ++t) cnt[T.sup_idx[t] + 1] += np;
   }
-  std::vector<int32_t> pt_ptr(nd + 1, 0);
+  std::vector<int64_t> pt_ptr(nd + 1, 0);
   for (int64_t g = 0; g < nd; ++g) pt_ptr[g + 1] = pt_ptr[g] + cnt[g + 1];
   H->n_ent = pt_ptr[nd];
+  if (H->n_ent >= (int64_t(1) << 31)) {
+    sparc_ham_destroy(H);
+    return fail(SPARC_ESHAPE, "sparc_ham_create: %lld projector entries exceed int32", (long long)H->n_ent);
+  }
+  // compressed to the nodes that carry support
+  std::vector<int32_t> nl_pts, nl_ptr;
+  for (int64_t g = 0; g < nd; ++g)
+    if (cnt[g + 1] > 0) {
+      nl_pts.push_back((int32_t)g);
+      nl_ptr.push_back((int32_t)pt_ptr[g]);
+    }
+  nl_ptr.push_back((int32_t)H->n_ent);
+  H->n_nlpts = (int64_t)nl_pts.size();
   std::vector<int32_t> ent_proj(H->n_ent);
   std::vector<double> ere(H->n_ent), eim(H->n_ent);
   {
-    std::vector<int32_t> fill(pt_ptr.begin(), pt_ptr.end() - 1);
+    std::vector<int64_t> fill(pt_ptr.begin(), pt_ptr.end() - 1);
     for (int a = 0; a < H->n_atoms_nl; ++a)
       for (int p = T.atom_pbeg[a]; p < T.atom_pbeg[a + 1]; ++p)
         for (int t = T.sup_ptr[a]; t < T.sup_ptr[a + 1]; ++t) {
           int64_t g = T.sup_idx[t];
-          int32_t e = fill[g]++;
+          int64_t e = fill[g]++;
           int64_t vi = T.proj_voff[p] + (t - T.sup_ptr[a]);
           ent_proj[e] = p;
           ere[e] = T.gamma[p] * T.vre[vi];
@@ -452,7 +465,7 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
   if ((rc = upload(T.sup_ptr, &H->sup_ptr)) || (rc = upload(T.sup_idx, &H->sup_idx)) ||
       (rc = upload(T.atom_pbeg, &H->atom_pbeg)) || (rc = upload(T.proj_voff, &H->proj_voff)) ||
       (rc = upload(pv, (char**)&H->pval)) || (rc = upload(gm, (char**)&H->gamma_d)) ||
-      (rc = upload(pt_ptr, &H->pt_ptr)) || (rc = upload(ent_proj, &H->ent_proj)) ||
+      (rc = upload(nl_pts, &H->nl_pts)) || (rc = upload(nl_ptr, &H->nl_ptr)) || (rc = upload(ent_proj, &H->ent_proj)) ||
       (rc = upload(ec, (char**)&H->ent_coef))) {
     sparc_ham_destroy(H);
     return rc;
@@ -472,7 +485,7 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
 void sparc_ham_destroy(sparc_ham* H) {
   if (!H) return;
   void* ptrs[] = {H->vloc, H->veff, H->veff32, H->sup_ptr, H->sup_idx, H->atom_pbeg, H->proj_voff,
-                  H->pval, H->gamma_d, H->pt_ptr, H->ent_proj, H->ent_coef};
+                  H->pval, H->gamma_d, H->nl_pts, H->nl_ptr, H->ent_proj, H->ent_coef};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete H;
