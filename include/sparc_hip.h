@@ -190,12 +190,15 @@ int sparc_fermi(sparc_ctx* ctx, int32_t n_k, int32_t n_s, const double* lambda_d
  * CheFSI schedule, Sec. 3.5 free energy) at the Gamma point in the reduced
  * model: V_eff = V_loc + V_H + V_x (Slater exchange), -Lap_h V_H =
  * 4 pi (rho - mean rho) solved by conjugate gradients on the FD Laplacian,
- * linear density mixing, Harris–Foulkes energy at the input density, stop when
+ * density mixing (linear, or Anderson with relaxation `mix` and history
+ * `mix_history`), Harris–Foulkes energy at the input density, stop when
  * ||rho_out - rho_in|| / ||rho_in|| < tol.  The first step runs n_first_passes
  * CheFSI passes from X0 before forming the density.
  */
 typedef struct {
   int32_t n_s, degree, n_first_passes, max_iter, lanczos_steps;
+  int32_t mix_history;         /* 0: linear mixing; m > 0: Anderson extrapolation with m
+                                  previous iterates (the SCF acceleration of Sec. 4)      */
   double kT, mix, tol, n_elec, poisson_tol;
   sparc_dtype filt;            /* SPARC_R64, or SPARC_R32 for an FP32 filter          */
   sparc_gemm_mode rr;          /* contraction precision for FP32 passes              */

@@ -8,7 +8,8 @@ Reduced model (readings listed in the design doc):
   * exchange only (Slater): eps_x = -(3/4)(3/pi)^{1/3} rho^{1/3}, V_x = (4/3) eps_x;
   * jellium electrostatics: the Gaussian local potential is external, the
     Hartree potential solves -Lap_h V_H = 4 pi (rho - mean(rho)) with zero mean;
-  * density mixing rho_in <- rho_in + beta (rho_out - rho_in);
+  * density mixing: linear rho_in <- rho_in + beta (rho_out - rho_in), or
+    Anderson extrapolation (relaxation beta, history m) as named in Sec. 4;
   * Harris-Foulkes free energy at rho_in.
 """
 from __future__ import annotations
@@ -153,9 +154,32 @@ def sad_density(grid: Grid, R, width, Z, n_elec: float):
     return rho * (n_elec / (grid.dV * rho.sum()))
 
 
+def anderson_update(x, f, hist_x, hist_f, beta: float, m: int):
+    """Anderson extrapolation of the fixed-point iteration x -> x + f (the SCF
+    acceleration named in Sec. 4, relaxation beta, history m): with the
+    differences dX_i = x_i - x_{i-1} and dF_i = f_i - f_{i-1} of the last m
+    iterates, gamma minimises ||f - dF gamma||_2, and
+    x_new = (x - dX gamma) + beta (f - dF gamma).  hist_x, hist_f hold the
+    previous iterates and residuals (updated in place).  m = 0 is linear mixing."""
+    if m > 0 and hist_x:
+        dX = np.stack([x - hist_x[-1]] + [hist_x[i + 1] - hist_x[i] for i in range(len(hist_x) - 1)][::-1], axis=1)
+        dF = np.stack([f - hist_f[-1]] + [hist_f[i + 1] - hist_f[i] for i in range(len(hist_f) - 1)][::-1], axis=1)
+        dX, dF = dX[:, :m], dF[:, :m]
+        gamma, *_ = np.linalg.lstsq(dF, f, rcond=None)
+        xb = x - dX @ gamma
+        fb = f - dF @ gamma
+    else:
+        xb, fb = x, f
+    hist_x.append(x.copy())
+    hist_f.append(f.copy())
+    del hist_x[:-m or None]
+    del hist_f[:-m or None]
+    return xb + beta * fb
+
+
 def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.01,
         mix: float = 0.3, tol: float = 1e-6, max_iter: int = 100, n_first_passes: int = 4,
-        rho_init=None, lanczos_v0=None, lanczos_steps: int = 20, callback=None):
+        rho_init=None, lanczos_v0=None, lanczos_steps: int = 20, callback=None, mix_history: int = 0):
     """Minimal SCF of Sec. 2 ("fixed-point iteration ... accelerated using
     mixing") with the CheFSI policy of Sec. 3.4: the first SCF step runs
     n_first_passes filter + Rayleigh-Ritz passes from the random X0 before the
@@ -165,8 +189,11 @@ def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.0
     Filter bounds: lambda_max from Lanczos (once, on the first Hamiltonian);
     lambda_cut = (lambda_min + lambda_max)/2 for the first pass, then the largest
     Ritz value of the previous pass.
+    Mixing: mix_history = 0 is linear density mixing rho_in + mix (rho_out - rho_in);
+    mix_history > 0 is Anderson extrapolation with relaxation mix and that history.
     Returns dict(energy, mu, iterations, converged, rho, ritz, history).
     """
+    hx, hf = [], []
     rho_in = np.asarray(rho_init, dtype=np.float64).copy()
     X = np.array(X0, copy=True)
     vh = poisson(rho_in, grid)
@@ -196,7 +223,7 @@ def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.0
         if err < tol:
             converged = True
             break
-        rho_in = rho_in + mix * (rho_out - rho_in)
+        rho_in = anderson_update(rho_in, rho_out - rho_in, hx, hf, mix, mix_history)
         vh = poisson(rho_in, grid)
     return {"energy": F, "mu": mu, "iterations": it, "converged": converged,
             "rho": rho_in, "ritz": lam, "history": history, "X": X}

@@ -10,6 +10,7 @@
 //     Householder reflectors (one work-group per block of columns).
 // Matrices are column-major with leading dimension n; complex matrices are
 // interleaved (re, im).
+#include <algorithm>
 #include <cmath>
 
 #include "devmath.hpp"
@@ -50,26 +51,31 @@ __device__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// ------------------------------------------------------------ scaled Cholesky
-// S = D^{-1} M D^{-1} (D = sqrt(diag M)), in place Cholesky S = R^H R (upper),
-// info = failing column + 1.  One work-group.
+// ------------------------------------------------------------ scaled Cholesky (blocked)
+// S = D^{-1} M D^{-1} + shift I (D = sqrt(diag M)); then S = R^H R (upper) by a
+// right-looking blocked factorisation with 64-column panels: the diagonal block is
+// factorised in LDS by one work-group, the row panel R12 = R11^{-H} S12 is formed by
+// one work-group per 64 columns, and the trailing update S22 -= R12^H R12 runs on
+// one work-group per 64 x 64 upper tile.  info = failing column + 1 (0: success);
+// every kernel returns early once info is set.
+constexpr int CB = 64;
+
 template <typename T>
-__global__ __launch_bounds__(1024) void chol_kernel(int n, const T* __restrict__ M, T* __restrict__ S,
-                                                    double* __restrict__ dinv, double shift, double min_rel_diag,
-                                                    int* info) {
+__global__ __launch_bounds__(256) void chol_scale_kernel(int n, const T* __restrict__ M, T* __restrict__ S,
+                                                         double* __restrict__ dinv, double shift, double min_rel_diag,
+                                                         int* info) {
   __shared__ int s_fail;
-  __shared__ double s_piv;
   __shared__ double s_dmax;
   if (threadIdx.x == 0) {
     s_fail = 0x7fffffff;
     double dm = 0;
     for (int i = 0; i < n; ++i) dm = fmax(dm, re_(M[i + (int64_t)i * n]));
     s_dmax = dm;
+    if (blockIdx.x == 0) *info = 0;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double d = re_(M[i + (int64_t)i * n]);
-    // a non-positive, non-finite or (relative to the largest) vanishing column norm
     if (!(d > 0.0) || !isfinite(d) || d < min_rel_diag * s_dmax) atomicMin(&s_fail, i + 1);
     dinv[i] = (d > 0.0) ? 1.0 / sqrt(d) : 0.0;
   }
@@ -78,38 +84,126 @@ __global__ __launch_bounds__(1024) void chol_kernel(int n, const T* __restrict__
     if (threadIdx.x == 0) *info = s_fail;
     return;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) s_fail = 0;
   for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
     int i = (int)(idx % n), j = (int)(idx / n);
     T v = rscale(dinv[i] * dinv[j], M[idx]);
     if (i == j) v = mkT<T>(re_(v) + shift, 0.0);
     S[idx] = v;
   }
+}
+
+// factor the diagonal block S[k0:k0+kb, k0:k0+kb] in LDS; also R11^{-1} -> Rinv (kb x kb)
+template <typename T>
+__global__ __launch_bounds__(256) void chol_diag_kernel(int n, T* __restrict__ S, int k0, int kb,
+                                                        T* __restrict__ Rinv, int* info) {
+  __shared__ T a[CB * CB];
+  __shared__ T r[CB * CB];
+  __shared__ int s_fail;
+  if (*info != 0) return;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
+    int i = idx % kb, j = idx / kb;
+    a[idx] = (i <= j) ? S[(k0 + i) + (int64_t)(k0 + j) * n] : mkT<T>(0.0, 0.0);
+  }
+  if (tid == 0) s_fail = 0;
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      double a = re_(S[k + (int64_t)k * n]);
-      if (!(a > 1e-15) || !isfinite(a)) {  // unit-diagonal S: relative pivot floor
-        s_fail = k + 1;
-      } else {
-        s_piv = sqrt(a);
-        S[k + (int64_t)k * n] = mkT<T>(s_piv, 0.0);
-      }
+  for (int k = 0; k < kb; ++k) {
+    if (tid == 0) {
+      double akk = re_(a[k + k * kb]);
+      if (!(akk > 1e-15) || !isfinite(akk)) s_fail = k0 + k + 1;  // unit-diagonal S: relative floor
+      else a[k + k * kb] = mkT<T>(sqrt(akk), 0.0);
     }
     __syncthreads();
     if (s_fail) break;
-    const double rinv = 1.0 / s_piv;
-    for (int j = k + 1 + threadIdx.x; j < n; j += blockDim.x) S[k + (int64_t)j * n] = rscale(rinv, S[k + (int64_t)j * n]);
+    const double rinv = 1.0 / re_(a[k + k * kb]);
+    for (int j = k + 1 + tid; j < kb; j += blockDim.x) a[k + j * kb] = rscale(rinv, a[k + j * kb]);
     __syncthreads();
-    const int m = n - k - 1;
-    for (int64_t idx = threadIdx.x; idx < (int64_t)m * m; idx += blockDim.x) {
-      int i = k + 1 + (int)(idx % m), j = k + 1 + (int)(idx / m);
-      if (i <= j) S[i + (int64_t)j * n] = sub_(S[i + (int64_t)j * n], mul_(conj_(S[k + (int64_t)i * n]), S[k + (int64_t)j * n]));
+    const int m = kb - k - 1;
+    for (int idx = tid; idx < m * m; idx += blockDim.x) {
+      int i = k + 1 + idx % m, j = k + 1 + idx / m;
+      if (i <= j) a[i + j * kb] = sub_(a[i + j * kb], mul_(conj_(a[k + i * kb]), a[k + j * kb]));
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) *info = s_fail;
+  if (s_fail) {
+    if (tid == 0) *info = s_fail;
+    return;
+  }
+  // R11^{-1}: column j by back substitution, one thread per column
+  if (tid < kb) {
+    const int j = tid;
+    for (int i = kb - 1; i >= 0; --i) {
+      T x = mkT<T>(0.0, 0.0);
+      if (i <= j) {
+        T s = mkT<T>(i == j ? 1.0 : 0.0, 0.0);
+        for (int k = i + 1; k <= j; ++k) s = sub_(s, mul_(a[i + k * kb], r[k + j * kb]));
+        x = rscale(1.0 / re_(a[i + i * kb]), s);
+      }
+      r[i + j * kb] = x;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
+    int i = idx % kb, j = idx / kb;
+    if (i <= j) S[(k0 + i) + (int64_t)(k0 + j) * n] = a[idx];
+    Rinv[idx] = r[idx];
+  }
+}
+
+// row panel: S[k0:k0+kb, c] <- R11^{-H} S[k0:k0+kb, c] for the columns c of this work-group
+template <typename T>
+__global__ __launch_bounds__(256) void chol_panel_kernel(int n, T* __restrict__ S, int k0, int kb,
+                                                         const T* __restrict__ Rinv, const int* info) {
+  __shared__ T ri[CB * CB];
+  __shared__ T col[CB * CB];
+  if (*info != 0) return;
+  const int c0 = k0 + kb + blockIdx.x * CB;
+  const int nc = min(CB, n - c0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kb * kb; idx += blockDim.x) ri[idx] = Rinv[idx];
+  for (int idx = tid; idx < kb * nc; idx += blockDim.x) {
+    int l = idx % kb, c = idx / kb;
+    col[idx] = S[(k0 + l) + (int64_t)(c0 + c) * n];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < kb * nc; idx += blockDim.x) {
+    int i = idx % kb, c = idx / kb;
+    T acc = mkT<T>(0.0, 0.0);
+    for (int l = 0; l <= i; ++l) acc = add_(acc, mul_(conj_(ri[l + i * kb]), col[l + c * kb]));
+    S[(k0 + i) + (int64_t)(c0 + c) * n] = acc;
+  }
+}
+
+// trailing update: upper tiles of S22 -= R12^H R12 (R12 = S[k0:k0+kb, k0+kb:n])
+template <typename T>
+__global__ __launch_bounds__(256) void chol_syrk_kernel(int n, T* __restrict__ S, int k0, int kb, int tiles,
+                                                        const int* info) {
+  __shared__ T pa[CB * CB];
+  __shared__ T pb[CB * CB];
+  if (*info != 0) return;
+  // upper-triangular tile enumeration
+  const int t = blockIdx.x;
+  int tj = 0;
+  while ((tj + 1) * (tj + 2) / 2 <= t) ++tj;
+  const int ti = t - tj * (tj + 1) / 2;
+  const int base = k0 + kb;
+  const int i0 = base + ti * CB, j0 = base + tj * CB;
+  const int ni = min(CB, n - i0), nj = min(CB, n - j0);
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kb * CB; idx += blockDim.x) {
+    int l = idx % kb, c = idx / kb;
+    pa[idx] = (c < ni) ? S[(k0 + l) + (int64_t)(i0 + c) * n] : mkT<T>(0.0, 0.0);
+    pb[idx] = (c < nj) ? S[(k0 + l) + (int64_t)(j0 + c) * n] : mkT<T>(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < CB * CB; idx += blockDim.x) {
+    int i = idx % CB, j = idx / CB;
+    if (i >= ni || j >= nj || i0 + i > j0 + j) continue;
+    T acc = mkT<T>(0.0, 0.0);
+    for (int l = 0; l < kb; ++l) acc = add_(acc, mul_(conj_(pa[l + i * kb]), pb[l + j * kb]));
+    T* sp = &S[(i0 + i) + (int64_t)(j0 + j) * n];
+    *sp = sub_(*sp, acc);
+  }
 }
 
 // T[:, j] = D^{-1} R^{-1} e_j (upper triangular), one wave per column.
@@ -144,15 +238,34 @@ __global__ __launch_bounds__(64) void trinv_kernel(int n, const T* __restrict__ 
   for (int i = lane; i < n; i += 64) Tout[i + (int64_t)j * n] = (i <= j) ? rscale(dinv[i], x[i]) : mkT<T>(0.0, 0.0);
 }
 
-size_t chol_orth_work_bytes(int32_t n, bool cplx) { return (size_t)n * n * (cplx ? 16 : 8) + (size_t)n * 8 + 256; }
+size_t chol_orth_work_bytes(int32_t n, bool cplx) {
+  const size_t e = cplx ? 16 : 8;
+  return (size_t)n * n * e + 256 + (size_t)n * 8 + 256 + (size_t)CB * CB * e + 256;
+}
 
 template <typename T>
 static int chol_orth_t(hipStream_t s, int n, const T* M, T* Tout, int* info, void* work, double shift,
                        double min_rel_diag) {
-  T* S = (T*)work;
-  double* dinv = (double*)((char*)work + (size_t)n * n * sizeof(T));
-  chol_kernel<T><<<1, 1024, 0, s>>>(n, M, S, dinv, shift, min_rel_diag, info);
-  SPARC_TRY(check_launch("chol_kernel"));
+  char* p = (char*)work;
+  T* S = (T*)p;
+  p += (((size_t)n * n * sizeof(T) + 255) / 256) * 256;
+  double* dinv = (double*)p;
+  p += (((size_t)n * 8 + 255) / 256) * 256;
+  T* Rinv = (T*)p;
+  chol_scale_kernel<T><<<1, 256, 0, s>>>(n, M, S, dinv, shift, min_rel_diag, info);
+  SPARC_TRY(check_launch("chol_scale_kernel"));
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    const int kb = std::min(CB, n - k0);
+    chol_diag_kernel<T><<<1, 256, 0, s>>>(n, S, k0, kb, Rinv, info);
+    SPARC_TRY(check_launch("chol_diag_kernel"));
+    const int m = n - k0 - kb;
+    if (m <= 0) break;
+    const int tiles = (m + CB - 1) / CB;
+    chol_panel_kernel<T><<<tiles, 256, 0, s>>>(n, S, k0, kb, Rinv, info);
+    SPARC_TRY(check_launch("chol_panel_kernel"));
+    chol_syrk_kernel<T><<<tiles * (tiles + 1) / 2, 256, 0, s>>>(n, S, k0, kb, tiles, info);
+    SPARC_TRY(check_launch("chol_syrk_kernel"));
+  }
   trinv_kernel<T><<<n, 64, n * sizeof(T), s>>>(n, S, dinv, Tout, info);
   return check_launch("trinv_kernel");
 }

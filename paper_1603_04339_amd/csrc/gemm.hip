@@ -46,20 +46,29 @@ template <> __device__ __forceinline__ void split<float>(float v, float& r, floa
 template <> __device__ __forceinline__ void split<cd>(cd v, double& r, double& i) { r = v.re; i = v.im; }
 template <> __device__ __forceinline__ void split<cf>(cf v, float& r, float& i) { r = v.re; i = v.im; }
 
-constexpr int GT = 64;   // output tile edge
-constexpr int GKC = 32;  // k chunk staged in LDS
+constexpr int GT = 64;   // tile-edge unit of the Hermitian fill and of the work-space layout
+
+template <typename E> struct gram_tile { static constexpr int T = elem<E>::is_cplx ? 64 : 128; };
 
 // ---------------------------------------------------------------- gram
-template <typename E>
+// One work-group: a T x T output tile of one slab.  4 waves in 2 x 2, each wave
+// (T/2) x (T/2) = WB x WB MFMA blocks.  The next k-chunk is loaded into registers
+// while the current one is consumed from LDS.
+template <typename E, int T>
 __global__ __launch_bounds__(256) void gram_kernel(int64_t N, int na, int nb, const E* __restrict__ A, int64_t lda,
                                                    const E* __restrict__ B, int64_t ldb, int n_slab, int64_t slab_len,
                                                    int tiles_a, int n_tiles, int herm,
                                                    double* __restrict__ part, int xcd_remap) {
   typedef typename elem<E>::real R;
   constexpr bool CPX = elem<E>::is_cplx;
+  constexpr int NCP = CPX ? 2 : 1;
+  constexpr int KC = 16;
+  constexpr int WB = T / 32;
+  constexpr int PER = T * KC / 256;     // values per thread per operand per chunk
+  constexpr int TPC = KC / PER;         // threads per column
   typedef mfma_t<R> M;
-  __shared__ R As[CPX ? 2 : 1][GT][GKC + 1];
-  __shared__ R Bs[CPX ? 2 : 1][GT][GKC + 1];
+  __shared__ R As[NCP][T][KC + 1];
+  __shared__ R Bs[NCP][T][KC + 1];
 
   int bid = blockIdx.x;
   const int total = n_slab * n_tiles;
@@ -75,51 +84,57 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t N, int na, int nb, co
     ti = tile % tiles_a;
     tj = tile / tiles_a;
   }
-  const int i0 = ti * GT, j0 = tj * GT;
+  const int i0 = ti * T, j0 = tj * T;
   const int64_t k_beg = (int64_t)slab * slab_len;
   const int64_t k_end = min(N, k_beg + slab_len);
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wi = (wv & 1) * 32, wj = (wv >> 1) * 32;  // wave's 32 x 32 sub-tile
-  typename M::acc acc_r[2][2], acc_i[2][2];
+  const int wi = (wv & 1) * (T / 2), wj = (wv >> 1) * (T / 2);
+  typename M::acc acc_r[WB][WB], acc_i[WB][WB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WB; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; acc_i[a][b][v] = 0; }
+      for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; if constexpr (CPX) acc_i[a][b][v] = 0; }
 
-  // loader mapping: thread -> (column c = tid/4, 8 consecutive k at (tid%4)*8)
-  const int lc = tid >> 2, lk = (tid & 3) * 8;
-  for (int64_t k0 = k_beg; k0 < k_end; k0 += GKC) {
-    {
-      const int ia = i0 + lc, jb = j0 + lc;
+  const int lc = tid / TPC, lk = (tid % TPC) * PER;
+  const int ia = i0 + lc, jb = j0 + lc;
+  E ra[PER], rb[PER];
+  auto fetch = [&](int64_t k0) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        int64_t k = k0 + lk + u;
-        E va = zero<E>(), vb = zero<E>();
-        if (k < k_end) {
-          if (ia < na) va = A[k + (int64_t)ia * lda];
-          if (jb < nb) vb = B[k + (int64_t)jb * ldb];
-        }
-        R ar, ai, br, bi;
-        split<E>(va, ar, ai);
-        split<E>(vb, br, bi);
-        As[0][lc][lk + u] = ar;
-        Bs[0][lc][lk + u] = br;
-        if constexpr (CPX) {
-          As[1][lc][lk + u] = ai;
-          Bs[1][lc][lk + u] = bi;
-        }
+    for (int u = 0; u < PER; ++u) {
+      const int64_t k = k0 + lk + u;
+      ra[u] = zero<E>();
+      rb[u] = zero<E>();
+      if (k < k_end) {
+        if (ia < na) ra[u] = A[k + (int64_t)ia * lda];
+        if (jb < nb) rb[u] = B[k + (int64_t)jb * ldb];
+      }
+    }
+  };
+  fetch(k_beg);
+  for (int64_t k0 = k_beg; k0 < k_end; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      R ar, ai, br, bi;
+      split<E>(ra[u], ar, ai);
+      split<E>(rb[u], br, bi);
+      As[0][lc][lk + u] = ar;
+      Bs[0][lc][lk + u] = br;
+      if constexpr (CPX) {
+        As[1][lc][lk + u] = ai;
+        Bs[1][lc][lk + u] = bi;
       }
     }
     __syncthreads();
+    if (k0 + KC < k_end) fetch(k0 + KC);
 #pragma unroll
-    for (int kk = 0; kk < GKC; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
       const int kq = kk + (lane >> 4), r16 = lane & 15;
-      R a_r[2], a_i[2], b_r[2], b_i[2];
+      R a_r[WB], a_i[WB], b_r[WB], b_i[WB];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < WB; ++a) {
         a_r[a] = As[0][wi + 16 * a + r16][kq];
         b_r[a] = Bs[0][wj + 16 * a + r16][kq];
         if constexpr (CPX) {
@@ -128,9 +143,9 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t N, int na, int nb, co
         }
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < WB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < WB; ++b) {
           acc_r[a][b] = M::step(a_r[a], b_r[b], acc_r[a][b]);
           if constexpr (CPX) {
             // conj(A)^T B: re += ar br + ai bi ; im += ar bi - ai br
@@ -143,12 +158,12 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t N, int na, int nb, co
     __syncthreads();
   }
   // partial tile -> part[slab] (column-major na x nb, FP64; complex interleaved)
-  const int64_t mat = (int64_t)na * nb * (CPX ? 2 : 1);
+  const int64_t mat = (int64_t)na * nb * NCP;
   double* P = part + (int64_t)slab * mat;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WB; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int i = i0 + wi + 16 * a + M::row(lane, v);
@@ -195,10 +210,10 @@ struct GramPlan {
   int64_t slab_len;
 };
 
-static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu) {
+static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T) {
   GramPlan p;
-  p.tiles_a = (na + GT - 1) / GT;
-  p.tiles_b = (nb + GT - 1) / GT;
+  p.tiles_a = (na + T - 1) / T;
+  p.tiles_b = (nb + T - 1) / T;
   p.n_tiles = 0;
   for (int tj = 0; tj < p.tiles_b; ++tj)
     for (int ti = 0; ti < p.tiles_a; ++ti)
@@ -212,13 +227,13 @@ static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu) {
   // make the work-group count a multiple of 8 where possible (XCD placement)
   while (s < smax && s < 256 && ((s * p.n_tiles) % 8) != 0) ++s;
   p.slab_len = (N + s - 1) / s;
-  p.slab_len = ((p.slab_len + GKC - 1) / GKC) * GKC;
+  p.slab_len = ((p.slab_len + 15) / 16) * 16;
   p.n_slab = (int)((N + p.slab_len - 1) / p.slab_len);
   return p;
 }
 
 size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt) {
-  GramPlan p = gram_plan(N, n_a, n_b, false, 256);
+  GramPlan p = gram_plan(N, n_a, n_b, false, 256, 64);
   // plans for other CU counts use at most 256 slabs
   int64_t slabs = std::max<int64_t>(p.n_slab, 256);
   return (size_t)slabs * n_a * n_b * 8 * (dtype_complex(dt) ? 2 : 1);
@@ -228,15 +243,16 @@ template <typename E>
 static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t lda, const E* B, int64_t ldb, void* C,
                   int ldc, void* work, size_t work_bytes, int n_cu) {
   const bool herm = (A == B) && (na == nb) && (lda == ldb);
-  GramPlan p = gram_plan(N, na, nb, herm, n_cu);
+  constexpr int T = gram_tile<E>::T;
+  GramPlan p = gram_plan(N, na, nb, herm, n_cu, T);
   const bool cplx = elem<E>::is_cplx;
   size_t part_bytes = (size_t)p.n_slab * na * nb * 8 * (cplx ? 2 : 1);
   if (part_bytes > work_bytes) return fail(SPARC_ENOMEM, "gram: workspace %zu < %zu bytes", work_bytes, part_bytes);
   double* part = (double*)work;
   int total = p.n_slab * p.n_tiles;
   int remap = (total % 8 == 0) ? 1 : 0;
-  gram_kernel<E><<<total, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
-                                       herm ? 1 : 0, part, remap);
+  gram_kernel<E, T><<<total, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
+                                          herm ? 1 : 0, part, remap);
   SPARC_TRY(check_launch("gram_kernel"));
   int64_t ne = (int64_t)na * nb;
   gram_reduce_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(na, nb, p.n_slab, part, (double*)C, ldc,
@@ -257,74 +273,83 @@ int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t na, int32_t nb, const
 }
 
 // ---------------------------------------------------------------- rotate
-constexpr int RM = 64;   // rows of A (grid nodes) per tile
-constexpr int RN = 64;   // output columns per tile
-constexpr int RKC = 32;  // k chunk
-
-template <typename E>
+// One work-group: T rows of A (grid nodes) x T output columns; 4 waves in 2 x 2,
+// each (T/2) x (T/2); next k-chunk prefetched into registers.
+template <typename E, int T>
 __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_out, const E* __restrict__ A,
                                                      int64_t lda, const double* __restrict__ Q, int ldq,
                                                      E* __restrict__ Out, int64_t ldo, int tiles_n, int xcd_remap,
                                                      int64_t total, int q_upper) {
   typedef typename elem<E>::real R;
   constexpr bool CPX = elem<E>::is_cplx;
+  constexpr int NCP = CPX ? 2 : 1;
+  constexpr int KC = 16;
+  constexpr int WB = T / 32;
+  constexpr int PER = T * KC / 256;
   typedef mfma_t<R> M;
-  __shared__ R As[CPX ? 2 : 1][RKC][RM + 1];
-  __shared__ R Qs[CPX ? 2 : 1][RKC][RN + 1];
+  __shared__ R As[NCP][KC][T + 1];
+  __shared__ R Qs[NCP][KC][T + 1];
   int64_t bid = blockIdx.x;
   if (xcd_remap) bid = (bid % 8) * (total / 8) + bid / 8;
   const int tn = (int)(bid % tiles_n);
-  const int64_t m0 = (bid / tiles_n) * RM;
-  const int j0 = tn * RN;
+  const int64_t m0 = (bid / tiles_n) * T;
+  const int j0 = tn * T;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wj = (wv & 1) * 32, wm = (wv >> 1) * 32;
-  typename M::acc acc_r[2][2], acc_i[2][2];
+  const int wj = (wv & 1) * (T / 2), wm = (wv >> 1) * (T / 2);
+  typename M::acc acc_r[WB][WB], acc_i[WB][WB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WB; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; acc_i[a][b][v] = 0; }
-  // A loader: column k = tid/8, 8 consecutive rows at (tid%8)*8
-  const int ak = tid >> 3, am = (tid & 7) * 8;
-  // Q loader: column j = tid/4 (of 64), 8 consecutive k at (tid%4)*8
-  const int qj = tid >> 2, qk = (tid & 3) * 8;
-  // an upper-triangular Q has no entries below row j0 + RN - 1 in this column tile
-  const int k_stop = q_upper ? min(n_in, j0 + RN) : n_in;
-  for (int k0 = 0; k0 < k_stop; k0 += RKC) {
+      for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; if constexpr (CPX) acc_i[a][b][v] = 0; }
+  // A loader: column k = tid / (T/PER), PER consecutive rows; Q loader: column j = tid / (KC/PER), PER consecutive k
+  constexpr int ATPC = T / PER;
+  const int ak = tid / ATPC, am = (tid % ATPC) * PER;
+  constexpr int QTPC = KC / PER;
+  const int qj = tid / QTPC, qk = (tid % QTPC) * PER;
+  // an upper-triangular Q has no entries below row j0 + T - 1 in this column tile
+  const int k_stop = q_upper ? min(n_in, j0 + T) : n_in;
+  E ra[PER];
+  double qr_[PER], qi_[PER];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      int64_t m = m0 + am + u;
-      int k = k0 + ak;
-      E v = zero<E>();
-      if (m < N && k < n_in) v = A[m + (int64_t)k * lda];
-      R vr, vi;
-      split<E>(v, vr, vi);
-      As[0][ak][am + u] = vr;
-      if constexpr (CPX) As[1][ak][am + u] = vi;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      int k = k0 + qk + u, j = j0 + qj;
-      double qr = 0, qi = 0;
-      if (k < n_in && j < n_out) {
+    for (int u = 0; u < PER; ++u) {
+      const int64_t m = m0 + am + u;
+      const int k = k0 + ak;
+      ra[u] = (m < N && k < n_in) ? A[m + (int64_t)k * lda] : zero<E>();
+      const int kq = k0 + qk + u, j = j0 + qj;
+      qr_[u] = 0;
+      qi_[u] = 0;
+      if (kq < n_in && j < n_out) {
         if constexpr (CPX) {
-          qr = Q[2 * (k + (int64_t)j * ldq)];
-          qi = Q[2 * (k + (int64_t)j * ldq) + 1];
+          qr_[u] = Q[2 * (kq + (int64_t)j * ldq)];
+          qi_[u] = Q[2 * (kq + (int64_t)j * ldq) + 1];
         } else {
-          qr = Q[k + (int64_t)j * ldq];
+          qr_[u] = Q[kq + (int64_t)j * ldq];
         }
       }
-      Qs[0][qk + u][qj] = (R)qr;
-      if constexpr (CPX) Qs[1][qk + u][qj] = (R)qi;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < k_stop; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      R vr, vi;
+      split<E>(ra[u], vr, vi);
+      As[0][ak][am + u] = vr;
+      if constexpr (CPX) As[1][ak][am + u] = vi;
+      Qs[0][qk + u][qj] = (R)qr_[u];
+      if constexpr (CPX) Qs[1][qk + u][qj] = (R)qi_[u];
     }
     __syncthreads();
+    if (k0 + KC < k_stop) fetch(k0 + KC);
 #pragma unroll
-    for (int kk = 0; kk < RKC; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
       const int kq = kk + (lane >> 4), r16 = lane & 15;
-      R q_r[2], q_i[2], a_r[2], a_i[2];
+      R q_r[WB], q_i[WB], a_r[WB], a_i[WB];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < WB; ++a) {
         q_r[a] = Qs[0][kq][wj + 16 * a + r16];  // Q^T[j][k]
         a_r[a] = As[0][kq][wm + 16 * a + r16];  // A^T[k][m]
         if constexpr (CPX) {
@@ -333,9 +358,9 @@ __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_
         }
       }
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < WB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < WB; ++b) {
           acc_r[a][b] = M::step(q_r[a], a_r[b], acc_r[a][b]);
           if constexpr (CPX) {
             // (A Q): re = Ar Qr - Ai Qi ; im = Ar Qi + Ai Qr
@@ -348,9 +373,9 @@ __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < WB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WB; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int j = j0 + wj + 16 * a + M::row(lane, v);
@@ -371,13 +396,14 @@ __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_
 template <typename E>
 static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, int64_t lda, const double* Q, int ldq,
                     E* Out, int64_t ldo, int q_upper) {
-  int tiles_n = (n_out + RN - 1) / RN;
-  int64_t tiles_m = (N + RM - 1) / RM;
+  constexpr int T = gram_tile<E>::T;
+  int tiles_n = (n_out + T - 1) / T;
+  int64_t tiles_m = (N + T - 1) / T;
   int64_t total = tiles_m * tiles_n;
   if (total > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "rotate: too many tiles");
   int remap = (total % 8 == 0) ? 1 : 0;
-  rotate_kernel<E><<<(unsigned)total, 256, 0, s>>>(N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap, total,
-                                                    q_upper);
+  rotate_kernel<E, T><<<(unsigned)total, 256, 0, s>>>(N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap,
+                                                       total, q_upper);
   return check_launch("rotate_kernel");
 }
 

@@ -395,7 +395,7 @@ static int dispatch_tile(sparc_ham* H, StepArgs<E>& A, int32_t n_s) {
 
 template <typename E>
 static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
-                      int32_t n_s, double a, double b, double c, const void* alpha) {
+                      int32_t n_s, double a, double b, double c, const void* alpha, int flags) {
   typedef typename elem<E>::real R;
   StepArgs<E> A;
   A.n1 = H->grid.n[0];
@@ -415,7 +415,7 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
     A.ty[p] = (R)(a * H->tap[1][p]);
     A.tz[p] = (R)(a * H->tap[2][p]);
   }
-  A.va = (R)a;
+  A.va = (flags & STEP_NO_VEFF) ? (R)0 : (R)a;
   A.vb = (R)b;
   A.zc = (R)c;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
@@ -431,7 +431,7 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
     case 8: rc = dispatch_tile<E, 8>(H, A, n_s); break;
     default: return fail(SPARC_EINVAL, "ham_step: n_o=%d unsupported", H->grid.n_o);
   }
-  if (rc != SPARC_OK || H->n_proj == 0 || H->n_nlpts == 0) return rc;
+  if (rc != SPARC_OK || H->n_proj == 0 || H->n_nlpts == 0 || (flags & STEP_NO_NONLOCAL)) return rc;
   if (!alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
   constexpr int NB = 8;
   dim3 grid((unsigned)((H->n_nlpts + 255) / 256), (unsigned)((n_s + NB - 1) / NB));
@@ -444,12 +444,12 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
 }
 
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
-             int32_t n_s, double a, double b, double c, const void* alpha) {
+             int32_t n_s, double a, double b, double c, const void* alpha, int flags) {
   switch (H->dtype) {
-    case SPARC_R64: return ham_step_t<double>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
-    case SPARC_R32: return ham_step_t<float>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
-    case SPARC_C128: return ham_step_t<cd>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
-    case SPARC_C64: return ham_step_t<cf>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha);
+    case SPARC_R64: return ham_step_t<double>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha, flags);
+    case SPARC_R32: return ham_step_t<float>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha, flags);
+    case SPARC_C128: return ham_step_t<cd>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha, flags);
+    case SPARC_C64: return ham_step_t<cf>(H, x, ldx, z, ldz, out, ldo, n_s, a, b, c, alpha, flags);
   }
   return fail(SPARC_EINVAL, "ham_step: bad dtype");
 }

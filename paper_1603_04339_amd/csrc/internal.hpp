@@ -126,8 +126,11 @@ void timer_end(sparc_ctx* c, int idx);
 //   out = a*(H x) + b*x + c*z ; z may alias out (in-place recurrence), x must not.
 //   Runs the stencil/potential/recurrence kernel, then the non-local scatter into out.
 //   alpha: projections [n_s][n_proj] of x (already scaled by dV), from nl_project.
+//   flags: STEP_NO_VEFF drops the potential term, STEP_NO_NONLOCAL the projector term
+//   (both together give a * (-1/2 Lap_h x) + b x + c z, used by the Poisson solver).
+enum { STEP_NO_VEFF = 1, STEP_NO_NONLOCAL = 2 };
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
-             int32_t n_s, double a, double b, double c, const void* alpha);
+             int32_t n_s, double a, double b, double c, const void* alpha, int flags = 0);
 int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha);
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
 

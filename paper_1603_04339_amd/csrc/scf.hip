@@ -1,0 +1,590 @@
+// Minimal self-consistent field driver (Gamma point, reduced model):
+//   V_eff = V_loc + V_H[rho_in] + V_x[rho_in]   (Slater exchange; jellium Hartree)
+//   -Lap_h V_H = 4 pi (rho - mean rho)          (conjugate gradients, FD Laplacian)
+//   CheFSI: n_first_passes filter + Rayleigh-Ritz passes on the first step, then one
+//   Fermi level, occupations, density; Harris-Foulkes free energy at rho_in
+//   rho_in <- rho_in + mix (rho_out - rho_in) until ||rho_out - rho_in|| < tol ||rho_in||
+// Every step runs in device kernels; the host only sequences calls and reads
+// back scalars (Fermi level, residuals, energy).  With an FP32 filter the passes
+// run on an FP32 copy of the orbitals until the density residual stalls near
+// FP32 resolution, then switch to FP64 passes (the final FP64 correction).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "devmath.hpp"
+
+namespace sparc {
+
+// ------------------------------------------------------------ reductions
+// partial sums of f(i) per block (deterministic two-pass reduction)
+enum RedOp { RED_SUM = 0, RED_DOT = 1, RED_DIFF2 = 2 };
+
+__global__ __launch_bounds__(256) void reduce_partial_kernel(int64_t n, const double* __restrict__ a,
+                                                             const double* __restrict__ b, int op,
+                                                             double* __restrict__ part) {
+  double s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v;
+    if (op == RED_SUM) v = a[i];
+    else if (op == RED_DOT) v = a[i] * b[i];
+    else { double d = a[i] - b[i]; v = d * d; }
+    s += v;
+  }
+  __shared__ double red[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void reduce_final_kernel(int nparts, const double* __restrict__ part,
+                                                           double* __restrict__ out) {
+  double s = 0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+  __shared__ double red[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
+constexpr int RED_BLOCKS = 1024;
+
+static int reduce(hipStream_t s, int64_t n, const double* a, const double* b, int op, double* part, double* out) {
+  reduce_partial_kernel<<<RED_BLOCKS, 256, 0, s>>>(n, a, b, op, part);
+  reduce_final_kernel<<<1, 256, 0, s>>>(RED_BLOCKS, part, out);
+  return check_launch("reduce");
+}
+
+// ------------------------------------------------------------ element-wise kernels
+#define GRID1(n) dim3((unsigned)(((n) + 255) / 256)), dim3(256), 0, s
+
+// atomic superposition: Z_J (2 pi w^2)^{-3/2} exp(-r^2/(2 w^2)), images within 10 w
+__global__ void sad_kernel(int n1, int n2, int n3, double h1, double h2, double h3, double L1, double L2, double L3,
+                           int n_atoms, const double* __restrict__ R, const double* __restrict__ W,
+                           const double* __restrict__ Z, double* __restrict__ rho) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n1 * n2 * n3) return;
+  int i = (int)(g % n1), j = (int)((g / n1) % n2), k = (int)(g / ((int64_t)n1 * n2));
+  double x = i * h1, y = j * h2, z = k * h3, acc = 0;
+  for (int a = 0; a < n_atoms; ++a) {
+    double w = W[a], rc = 10.0 * w, amp = Z[a] * pow(2.0 * M_PI * w * w, -1.5);
+    double dx0 = x - R[3 * a], dy0 = y - R[3 * a + 1], dz0 = z - R[3 * a + 2];
+    for (int az = (int)ceil((dz0 - rc) / L3); az <= (int)floor((dz0 + rc) / L3); ++az)
+      for (int ay = (int)ceil((dy0 - rc) / L2); ay <= (int)floor((dy0 + rc) / L2); ++ay)
+        for (int ax = (int)ceil((dx0 - rc) / L1); ax <= (int)floor((dx0 + rc) / L1); ++ax) {
+          double dx = dx0 - ax * L1, dy = dy0 - ay * L2, dz = dz0 - az * L3;
+          double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 <= rc * rc) acc += amp * exp(-r2 / (2.0 * w * w));
+        }
+  }
+  rho[g] = acc;
+}
+
+// y = alpha * x (alpha from a device scalar expression: num / den)
+__global__ void scale_ratio_kernel(int64_t n, double* __restrict__ y, const double* num, const double* den, double c) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] *= c * (*num) / (*den);
+}
+
+// b = 4 pi (rho - sum/n)
+__global__ void poisson_rhs_kernel(int64_t n, const double* __restrict__ rho, const double* sum, double* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = 4.0 * M_PI * (rho[i] - (*sum) / (double)n);
+}
+
+// CG updates with device scalars: alpha = rr / pAp
+__global__ void cg_update_xr_kernel(int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                                    const double* __restrict__ Ap, const double* rr, const double* pAp) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = (*rr) / (*pAp);
+  x[i] += a * p[i];
+  r[i] -= a * Ap[i];
+}
+__global__ void cg_update_p_kernel(int64_t n, double* __restrict__ p, const double* __restrict__ r, const double* rr_new,
+                                   const double* rr_old) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = r[i] + ((*rr_new) / (*rr_old)) * p[i];
+}
+__global__ void sub_mean_kernel(int64_t n, double* __restrict__ x, const double* sum) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] -= (*sum) / (double)n;
+}
+__global__ void copy_kernel(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+// r = b - A x  with Ax in r on entry
+__global__ void residual_kernel(int64_t n, const double* __restrict__ b, double* __restrict__ r) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) r[i] = b[i] - r[i];
+}
+
+// Slater exchange and the effective potential; e_dc = eps*rho - vx*rho - 1/2 vh*rho
+__global__ void xc_veff_kernel(int64_t n, const double* __restrict__ rho, const double* __restrict__ vloc,
+                               const double* __restrict__ vh, double* __restrict__ veff, double* __restrict__ edc) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double r = fmax(rho[i], 0.0);
+  const double r13 = cbrt(r);
+  const double eps = -0.75 * cbrt(3.0 / M_PI) * r13;
+  const double vx = -cbrt(3.0 / M_PI) * r13;
+  veff[i] = vloc[i] + vh[i] + vx;
+  edc[i] = eps * r - vx * r - 0.5 * vh[i] * r;
+}
+
+__global__ void mix_kernel(int64_t n, double* __restrict__ rin, const double* __restrict__ rout, double beta) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) rin[i] += beta * (rout[i] - rin[i]);
+}
+
+// band and entropy terms from occupations (occ = g for one k-point of weight 1)
+__global__ void band_entropy_kernel(int ns, const double* __restrict__ lam, const double* __restrict__ g, double kT,
+                                    double* out) {
+  double band = 0, ent = 0;
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    double gi = g[i];
+    band += 2.0 * gi * lam[i];
+    double t = 0;
+    if (gi > 0) t += gi * log(gi);
+    if (gi < 1) t += (1 - gi) * log(1 - gi);
+    ent += 2.0 * kT * t;
+  }
+  __shared__ double rb[4], re[4];
+  band = wave_sum(band);
+  ent = wave_sum(ent);
+  if ((threadIdx.x & 63) == 0) { rb[threadIdx.x >> 6] = band; re[threadIdx.x >> 6] = ent; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = rb[0] + rb[1] + rb[2] + rb[3];
+    out[1] = re[0] + re[1] + re[2] + re[3];
+  }
+}
+
+// Anderson extrapolation: normal equations of min ||f - dF gamma|| from all pairwise dot
+// products (one block per chunk of the grid), a single-thread solve, and the update
+constexpr int AMAX = 8;
+struct VecSet {
+  const double* v[AMAX + 1];
+};
+template <int NV>
+__global__ __launch_bounds__(256) void multi_dot_partial_kernel(int64_t n, VecSet S, double* __restrict__ part) {
+  // all pairs (a <= b) of the NV vectors (the last one is f); NP = NV (NV + 1) / 2
+  constexpr int NP = NV * (NV + 1) / 2;
+  __shared__ double red[4][NP];
+  double acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double x[NV];
+#pragma unroll
+    for (int a = 0; a < NV; ++a) x[a] = S.v[a][i];
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < NV; ++a)
+#pragma unroll
+      for (int b = a; b < NV; ++b) acc[q++] += x[a] * x[b];
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    double v = wave_sum(acc[q]);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][q] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NP; q += blockDim.x)
+    part[(int64_t)blockIdx.x * NP + q] = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+}
+
+static void launch_multi_dot(hipStream_t s, int nblk, int64_t n, int m, const VecSet& vs, double* part) {
+  switch (m + 1) {
+    case 2: multi_dot_partial_kernel<2><<<nblk, 256, 0, s>>>(n, vs, part); break;
+    case 3: multi_dot_partial_kernel<3><<<nblk, 256, 0, s>>>(n, vs, part); break;
+    case 4: multi_dot_partial_kernel<4><<<nblk, 256, 0, s>>>(n, vs, part); break;
+    case 5: multi_dot_partial_kernel<5><<<nblk, 256, 0, s>>>(n, vs, part); break;
+    case 6: multi_dot_partial_kernel<6><<<nblk, 256, 0, s>>>(n, vs, part); break;
+    case 7: multi_dot_partial_kernel<7><<<nblk, 256, 0, s>>>(n, vs, part); break;
+    case 8: multi_dot_partial_kernel<8><<<nblk, 256, 0, s>>>(n, vs, part); break;
+    default: multi_dot_partial_kernel<9><<<nblk, 256, 0, s>>>(n, vs, part); break;
+  }
+}
+__global__ void multi_dot_final_kernel(int nblocks, int npairs, const double* __restrict__ part, double* __restrict__ out) {
+  for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
+    double s = 0;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * npairs + q];
+    out[q] = s;
+  }
+}
+// gamma from (dF^T dF) gamma = dF^T f by Gaussian elimination with partial pivoting;
+// a pivot below 1e-14 of the largest diagonal drops that direction (gamma_k = 0)
+__global__ void anderson_solve_kernel(int m, const double* __restrict__ pairs, double* __restrict__ gamma) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double A[AMAX][AMAX + 1];
+  const int nv = m + 1;
+  auto pidx = [&](int a, int b) {  // index of pair (a <= b)
+    int q = 0;
+    for (int r = 0; r < a; ++r) q += nv - r;
+    return q + (b - a);
+  };
+  double dmax = 0;
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) A[i][j] = pairs[pidx(min(i, j), max(i, j))];
+    A[i][m] = pairs[pidx(i, m)];
+    dmax = fmax(dmax, A[i][i]);
+  }
+  int perm[AMAX];
+  bool dead[AMAX];
+  for (int i = 0; i < m; ++i) { perm[i] = i; dead[i] = false; }
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i) if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
+    if (p != k) for (int j = 0; j <= m; ++j) { double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
+    if (fabs(A[k][k]) <= 1e-14 * dmax) { dead[k] = true; continue; }
+    for (int i = k + 1; i < m; ++i) {
+      double f = A[i][k] / A[k][k];
+      for (int j = k; j <= m; ++j) A[i][j] -= f * A[k][j];
+    }
+  }
+  double x[AMAX];
+  for (int k = m - 1; k >= 0; --k) {
+    if (dead[k]) { x[k] = 0; continue; }
+    double s = A[k][m];
+    for (int j = k + 1; j < m; ++j) s -= A[k][j] * x[j];
+    x[k] = s / A[k][k];
+  }
+  for (int i = 0; i < m; ++i) gamma[i] = x[i];
+}
+struct GammaSet {
+  const double* dx[AMAX];
+  const double* df[AMAX];
+};
+__global__ void anderson_update_kernel(int64_t n, int m, GammaSet S, const double* __restrict__ gamma,
+                                       const double* __restrict__ f, double beta, double* __restrict__ x) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double xb = x[i], fb = f[i];
+  for (int k = 0; k < m; ++k) {
+    const double g = gamma[k];
+    xb -= g * S.dx[k][i];
+    fb -= g * S.df[k][i];
+  }
+  x[i] = xb + beta * fb;
+}
+__global__ void diff_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+__global__ void d2f_block_kernel(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+__global__ void f2d_block_kernel(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)a[i];
+}
+
+// ------------------------------------------------------------ device buffers owned by one SCF run
+struct Buffers {
+  std::vector<void*> ptrs;
+  ~Buffers() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  template <typename T>
+  int alloc(T** p, size_t count) {
+    *p = nullptr;
+    void* q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess)
+      return fail(SPARC_ENOMEM, "sparc_scf_run: device allocation of %zu bytes failed", count * sizeof(T));
+    ptrs.push_back(q);
+    *p = (T*)q;
+    return SPARC_OK;
+  }
+};
+
+// -Lap_h V = b by conjugate gradients (V warm-started, zero mean on exit)
+struct Poisson {
+  sparc_ham* H;
+  int64_t n;
+  double *b, *r, *p, *Ap, *part, *sc;  // sc: [0] rr, [1] pAp, [2] rr_new, [3] sum, [4] bb
+  int iters_total = 0;
+
+  int apply(const double* x, double* y) {
+    // -Lap_h x = 2 * (-1/2 Lap_h x): stencil only
+    return ham_step(H, x, n, nullptr, 0, y, n, 1, 2.0, 0.0, 0.0, nullptr, STEP_NO_VEFF | STEP_NO_NONLOCAL);
+  }
+
+  int solve(hipStream_t s, const double* rho, double* v, double tol, int max_it) {
+    SPARC_TRY(reduce(s, n, rho, nullptr, RED_SUM, part, sc + 3));
+    poisson_rhs_kernel<<<GRID1(n)>>>(n, rho, sc + 3, b);
+    SPARC_TRY(reduce(s, n, b, b, RED_DOT, part, sc + 4));
+    SPARC_TRY(apply(v, r));
+    residual_kernel<<<GRID1(n)>>>(n, b, r);
+    copy_kernel<<<GRID1(n)>>>(n, r, p);
+    SPARC_TRY(reduce(s, n, r, r, RED_DOT, part, sc + 0));
+    double bb = 0, rr = 0;
+    SPARC_HIP(hipMemcpyAsync(&bb, sc + 4, 8, hipMemcpyDeviceToHost, s));
+    SPARC_HIP(hipStreamSynchronize(s));
+    if (bb == 0.0) return SPARC_OK;
+    int it = 0;
+    for (; it < max_it; ++it) {
+      SPARC_TRY(apply(p, Ap));
+      SPARC_TRY(reduce(s, n, p, Ap, RED_DOT, part, sc + 1));
+      cg_update_xr_kernel<<<GRID1(n)>>>(n, v, r, p, Ap, sc + 0, sc + 1);
+      SPARC_TRY(reduce(s, n, r, r, RED_DOT, part, sc + 2));
+      cg_update_p_kernel<<<GRID1(n)>>>(n, p, r, sc + 2, sc + 0);
+      SPARC_HIP(hipMemcpyAsync(sc + 0, sc + 2, 8, hipMemcpyDeviceToDevice, s));
+      if (it % 8 == 7) {
+        SPARC_HIP(hipMemcpyAsync(&rr, sc + 2, 8, hipMemcpyDeviceToHost, s));
+        SPARC_HIP(hipStreamSynchronize(s));
+        if (!std::isfinite(rr)) return fail(SPARC_ENAN, "poisson: non-finite residual");
+        if (rr <= tol * tol * bb) break;
+      }
+    }
+    iters_total += it + 1;
+    if (it >= max_it) return fail(SPARC_ENOCONV, "poisson: CG did not converge in %d iterations", max_it);
+    SPARC_TRY(reduce(s, n, v, nullptr, RED_SUM, part, sc + 3));
+    sub_mean_kernel<<<GRID1(n)>>>(n, v, sc + 3);
+    return check_launch("poisson");
+  }
+};
+
+static double host_scalar(hipStream_t s, const double* d) {
+  double h = NAN;
+  if (hipMemcpyAsync(&h, d, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return NAN;
+  if (hipStreamSynchronize(s) != hipSuccess) return NAN;
+  return h;
+}
+
+}  // namespace sparc
+
+using namespace sparc;
+
+extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
+                             const sparc_scf_params* P, sparc_scf_result* res) {
+  if (!ctx || !grid || !atoms || !P || !res) return fail(SPARC_EINVAL, "sparc_scf_run: null argument");
+  if (grid->kpt[0] != 0 || grid->kpt[1] != 0 || grid->kpt[2] != 0)
+    return fail(SPARC_EINVAL, "sparc_scf_run: the SCF driver runs at the Gamma point");
+  if (P->n_s < 1 || P->degree < 1 || P->max_iter < 1 || P->n_first_passes < 1 || P->lanczos_steps < 2)
+    return fail(SPARC_EINVAL, "sparc_scf_run: bad schedule parameters");
+  if (!(P->kT > 0) || !(P->mix > 0 && P->mix <= 1) || !(P->tol > 0) || !(P->n_elec > 0))
+    return fail(SPARC_EINVAL, "sparc_scf_run: bad kT, mix, tol or n_elec");
+  if (P->n_elec > 2.0 * P->n_s) return fail(SPARC_EINVAL, "sparc_scf_run: n_s too small for n_elec");
+  if (!P->x0_dev || !P->lanczos_v0_dev) return fail(SPARC_EINVAL, "sparc_scf_run: x0_dev and lanczos_v0_dev needed");
+  if (P->filt != SPARC_R64 && P->filt != SPARC_R32) return fail(SPARC_EINVAL, "sparc_scf_run: filt must be R64 or R32");
+  if (P->mix_history < 0 || P->mix_history > AMAX) return fail(SPARC_EINVAL, "sparc_scf_run: mix_history outside 0..%d", AMAX);
+  if (!res->rho_dev || !res->ritz_dev) return fail(SPARC_EINVAL, "sparc_scf_run: result buffers missing");
+  const auto t_start = std::chrono::steady_clock::now();
+  hipStream_t s = ctx->stream;
+  SPARC_HIP(hipSetDevice(ctx->device));
+
+  sparc_ham* H64 = nullptr;
+  sparc_ham* H32 = nullptr;
+  SPARC_TRY(sparc_ham_create(ctx, grid, atoms, SPARC_R64, &H64));
+  struct HamGuard { sparc_ham* a; sparc_ham** b; ~HamGuard() { sparc_ham_destroy(a); if (*b) sparc_ham_destroy(*b); } } hg{H64, &H32};
+  const bool mixed = P->filt == SPARC_R32;
+  if (mixed) SPARC_TRY(sparc_ham_create(ctx, grid, atoms, SPARC_R32, &H32));
+  const int64_t n = H64->n_d;
+  const int ns = P->n_s;
+  const double dV = H64->dV;
+
+  Buffers B;
+  double *rho_in, *rho_out, *vh, *veff, *edc, *X, *ritz, *occ, *part, *sc;
+  double *pb, *pr, *pp, *pAp;
+  float* X32 = nullptr;
+  SPARC_TRY(B.alloc(&rho_in, n));
+  SPARC_TRY(B.alloc(&rho_out, n));
+  SPARC_TRY(B.alloc(&vh, n));
+  SPARC_TRY(B.alloc(&veff, n));
+  SPARC_TRY(B.alloc(&edc, n));
+  SPARC_TRY(B.alloc(&X, (size_t)n * ns));
+  SPARC_TRY(B.alloc(&ritz, ns));
+  SPARC_TRY(B.alloc(&occ, ns));
+  SPARC_TRY(B.alloc(&part, RED_BLOCKS));
+  SPARC_TRY(B.alloc(&sc, 16));
+  SPARC_TRY(B.alloc(&pb, n));
+  SPARC_TRY(B.alloc(&pr, n));
+  SPARC_TRY(B.alloc(&pp, n));
+  SPARC_TRY(B.alloc(&pAp, n));
+  if (mixed) SPARC_TRY(B.alloc(&X32, (size_t)n * ns));
+  // Anderson history: previous iterate and residual, ring of m differences
+  const int am = P->mix_history;
+  double *xprev = nullptr, *fprev = nullptr, *fcur = nullptr, *apairs = nullptr, *agamma = nullptr, *apart = nullptr;
+  std::vector<double*> dXh(am, nullptr), dFh(am, nullptr);
+  constexpr int ABLK = 256;
+  if (am > 0) {
+    SPARC_TRY(B.alloc(&xprev, n));
+    SPARC_TRY(B.alloc(&fprev, n));
+    SPARC_TRY(B.alloc(&fcur, n));
+    for (int k = 0; k < am; ++k) {
+      SPARC_TRY(B.alloc(&dXh[k], n));
+      SPARC_TRY(B.alloc(&dFh[k], n));
+    }
+    SPARC_TRY(B.alloc(&apairs, (AMAX + 1) * (AMAX + 2) / 2));
+    SPARC_TRY(B.alloc(&agamma, AMAX));
+    SPARC_TRY(B.alloc(&apart, (size_t)ABLK * (AMAX + 1) * (AMAX + 2) / 2));
+  }
+  int a_count = 0, a_head = 0;
+  size_t wf64 = sparc_workspace_bytes(H64, ns, SPARC_OP_FILTER), wr64 = sparc_workspace_bytes(H64, ns, SPARC_OP_RR);
+  size_t wl = sparc_workspace_bytes(H64, P->lanczos_steps, SPARC_OP_LANCZOS);
+  size_t wbytes = std::max({wf64, wr64, wl});
+  if (mixed)
+    wbytes = std::max({wbytes, sparc_workspace_bytes(H32, ns, SPARC_OP_FILTER), sparc_workspace_bytes(H32, ns, SPARC_OP_RR)});
+  char* work = nullptr;
+  SPARC_TRY(B.alloc(&work, wbytes));
+
+  // start density and orbitals
+  if (P->rho_init_dev) {
+    SPARC_HIP(hipMemcpyAsync(rho_in, P->rho_init_dev, n * 8, hipMemcpyDeviceToDevice, s));
+  } else {
+    std::vector<double> R(3 * atoms->n_atoms), W(atoms->n_atoms), Z(atoms->n_atoms);
+    for (int a = 0; a < atoms->n_atoms; ++a) {
+      for (int c = 0; c < 3; ++c) R[3 * a + c] = atoms->R[3 * a + c];
+      W[a] = atoms->vloc_width[a];
+      Z[a] = atoms->Z ? atoms->Z[a] : 2.0;
+    }
+    double *dR, *dW, *dZ;
+    SPARC_TRY(B.alloc(&dR, R.size()));
+    SPARC_TRY(B.alloc(&dW, W.size()));
+    SPARC_TRY(B.alloc(&dZ, Z.size()));
+    SPARC_HIP(hipMemcpy(dR, R.data(), R.size() * 8, hipMemcpyHostToDevice));
+    SPARC_HIP(hipMemcpy(dW, W.data(), W.size() * 8, hipMemcpyHostToDevice));
+    SPARC_HIP(hipMemcpy(dZ, Z.data(), Z.size() * 8, hipMemcpyHostToDevice));
+    sad_kernel<<<GRID1(n)>>>(grid->n[0], grid->n[1], grid->n[2], H64->h[0], H64->h[1], H64->h[2], grid->L[0],
+                             grid->L[1], grid->L[2], atoms->n_atoms, dR, dW, dZ, rho_in);
+    SPARC_TRY(check_launch("sad_kernel"));
+    SPARC_TRY(reduce(s, n, rho_in, nullptr, RED_SUM, part, sc + 5));
+    // rho *= N_e / (dV * sum rho)
+    double tot = host_scalar(s, sc + 5);
+    if (!(tot > 0)) return fail(SPARC_ENAN, "sparc_scf_run: atomic superposition has no charge");
+    double f = P->n_elec / (dV * tot);
+    std::vector<double> one(1, f);
+    SPARC_HIP(hipMemcpy(sc + 6, one.data(), 8, hipMemcpyHostToDevice));
+    one[0] = 1.0;
+    SPARC_HIP(hipMemcpy(sc + 7, one.data(), 8, hipMemcpyHostToDevice));
+    scale_ratio_kernel<<<GRID1(n)>>>(n, rho_in, sc + 6, sc + 7, 1.0);
+  }
+  SPARC_HIP(hipMemcpyAsync(X, P->x0_dev, (size_t)n * ns * 8, hipMemcpyDeviceToDevice, s));
+  SPARC_HIP(hipMemsetAsync(vh, 0, n * 8, s));
+  double* vloc;
+  SPARC_TRY(B.alloc(&vloc, n));
+  SPARC_TRY(sparc_ham_get_vloc(H64, vloc));
+
+  Poisson PS{H64, n, pb, pr, pp, pAp, part, sc};
+  const double ptol = P->poisson_tol > 0 ? P->poisson_tol : 1e-10;
+  SPARC_TRY(PS.solve(s, rho_in, vh, ptol, 20000));
+
+  double lmin = 0, lmax = 0, lcut = 0;
+  bool have_ritz = false;
+  bool use32 = mixed;
+  if (mixed) {
+    d2f_block_kernel<<<GRID1((int64_t)n * ns)>>>((int64_t)n * ns, X, X32);
+    SPARC_TRY(check_launch("d2f_block_kernel"));
+  }
+  double F = 0, mu = 0, err = 1, prev_err = 1e300;
+  int it = 1;
+  int converged = 0;
+  for (; it <= P->max_iter; ++it) {
+    xc_veff_kernel<<<GRID1(n)>>>(n, rho_in, vloc, vh, veff, edc);
+    SPARC_TRY(check_launch("xc_veff_kernel"));
+    SPARC_TRY(sparc_ham_set_veff(H64, veff));
+    if (mixed) SPARC_TRY(sparc_ham_set_veff(H32, veff));
+    if (it == 1) SPARC_TRY(lanczos_bounds(H64, P->lanczos_v0_dev, P->lanczos_steps, work, wbytes, &lmin, &lmax));
+    const int passes = (it == 1) ? P->n_first_passes : 1;
+    for (int ps = 0; ps < passes; ++ps) {
+      lcut = have_ritz ? host_scalar(s, ritz + ns - 1) : 0.5 * (lmin + lmax);
+      if (use32) {
+        SPARC_TRY(chebyshev_filter(H32, X32, n, ns, P->degree, lcut, lmax, work, wbytes));
+        SPARC_TRY(rayleigh_ritz(H32, X32, n, ns, P->rr, ritz, work, wbytes, nullptr));
+      } else {
+        SPARC_TRY(chebyshev_filter(H64, X, n, ns, P->degree, lcut, lmax, work, wbytes));
+        SPARC_TRY(rayleigh_ritz(H64, X, n, ns, SPARC_GEMM_NATIVE, ritz, work, wbytes, nullptr));
+      }
+      have_ritz = true;
+    }
+    const double wk = 1.0;
+    SPARC_TRY(sparc_fermi(ctx, 1, ns, ritz, &wk, P->n_elec, P->kT, occ, &mu));
+    // Harris-Foulkes free energy at rho_in
+    band_entropy_kernel<<<1, 256, 0, s>>>(ns, ritz, occ, P->kT, sc + 8);
+    SPARC_TRY(reduce(s, n, edc, nullptr, RED_SUM, part, sc + 10));
+    double be[3];
+    SPARC_HIP(hipMemcpyAsync(be, sc + 8, 3 * 8, hipMemcpyDeviceToHost, s));
+    SPARC_HIP(hipStreamSynchronize(s));
+    F = be[0] + dV * be[2] + be[1];
+    if (!std::isfinite(F)) return fail(SPARC_ENAN, "sparc_scf_run: non-finite energy at iteration %d", it);
+    // output density from the current block
+    const void* xs[1] = {use32 ? (const void*)X32 : (const void*)X};
+    const int64_t lds[1] = {n};
+    SPARC_TRY(density_from_orbitals(ctx, 1, xs, lds, ns, use32 ? SPARC_R32 : SPARC_R64, occ, n, dV, rho_out));
+    SPARC_TRY(reduce(s, n, rho_out, rho_in, RED_DIFF2, part, sc + 11));
+    SPARC_TRY(reduce(s, n, rho_in, rho_in, RED_DOT, part, sc + 12));
+    double dd[2];
+    SPARC_HIP(hipMemcpyAsync(dd, sc + 11, 16, hipMemcpyDeviceToHost, s));
+    SPARC_HIP(hipStreamSynchronize(s));
+    err = std::sqrt(dd[0] / dd[1]);
+    if (res->history) {
+      res->history[3 * (it - 1)] = F;
+      res->history[3 * (it - 1) + 1] = err;
+      res->history[3 * (it - 1) + 2] =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (!std::isfinite(err)) return fail(SPARC_ENAN, "sparc_scf_run: non-finite density residual");
+    if (use32 && P->final_fp64_pass && (err < 1e-4 || (it > 2 && err > 0.8 * prev_err))) {
+      // hand the FP32 orbitals over to FP64 passes; this iterate is not accepted as converged
+      f2d_block_kernel<<<GRID1((int64_t)n * ns)>>>((int64_t)n * ns, X32, X);
+      SPARC_TRY(check_launch("f2d_block_kernel"));
+      use32 = false;
+    } else if (err < P->tol) {
+      converged = 1;
+      break;
+    }
+    prev_err = err;
+    if (am == 0) {
+      mix_kernel<<<GRID1(n)>>>(n, rho_in, rho_out, P->mix);
+    } else {
+      diff_kernel<<<GRID1(n)>>>(n, rho_out, rho_in, fcur);
+      if (it > 1) {  // new differences into the ring
+        diff_kernel<<<GRID1(n)>>>(n, rho_in, xprev, dXh[a_head]);
+        diff_kernel<<<GRID1(n)>>>(n, fcur, fprev, dFh[a_head]);
+        a_head = (a_head + 1) % am;
+        a_count = std::min(a_count + 1, am);
+      }
+      SPARC_HIP(hipMemcpyAsync(xprev, rho_in, n * 8, hipMemcpyDeviceToDevice, s));
+      SPARC_HIP(hipMemcpyAsync(fprev, fcur, n * 8, hipMemcpyDeviceToDevice, s));
+      if (a_count == 0) {
+        mix_kernel<<<GRID1(n)>>>(n, rho_in, rho_out, P->mix);
+      } else {
+        VecSet vs;
+        GammaSet gs;
+        for (int k = 0; k < a_count; ++k) {
+          vs.v[k] = dFh[k];
+          gs.dx[k] = dXh[k];
+          gs.df[k] = dFh[k];
+        }
+        vs.v[a_count] = fcur;
+        const int npairs = (a_count + 1) * (a_count + 2) / 2;
+        launch_multi_dot(s, ABLK, n, a_count, vs, apart);
+        multi_dot_final_kernel<<<1, 256, 0, s>>>(ABLK, npairs, apart, apairs);
+        anderson_solve_kernel<<<1, 64, 0, s>>>(a_count, apairs, agamma);
+        anderson_update_kernel<<<GRID1(n)>>>(n, a_count, gs, agamma, fcur, P->mix, rho_in);
+      }
+    }
+    SPARC_TRY(check_launch("density mixing"));
+    SPARC_TRY(PS.solve(s, rho_in, vh, ptol, 20000));
+  }
+  res->energy = F;
+  res->mu = mu;
+  res->iterations = std::min(it, P->max_iter);
+  res->converged = converged;
+  SPARC_HIP(hipMemcpyAsync(res->rho_dev, rho_in, n * 8, hipMemcpyDeviceToDevice, s));
+  SPARC_HIP(hipMemcpyAsync(res->ritz_dev, ritz, ns * 8, hipMemcpyDeviceToDevice, s));
+  if (res->x_dev) {
+    if (use32) f2d_block_kernel<<<GRID1((int64_t)n * ns)>>>((int64_t)n * ns, X32, X);
+    SPARC_HIP(hipMemcpyAsync(res->x_dev, X, (size_t)n * ns * 8, hipMemcpyDeviceToDevice, s));
+  }
+  SPARC_HIP(hipStreamSynchronize(s));
+  if (!converged) return fail(SPARC_ENOCONV, "sparc_scf_run: not converged in %d iterations (residual %.3e)", P->max_iter, err);
+  return SPARC_OK;
+}

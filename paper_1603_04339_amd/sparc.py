@@ -48,7 +48,7 @@ class sparc_atoms(C.Structure):
 
 class sparc_scf_params(C.Structure):
     _fields_ = [("n_s", C.c_int32), ("degree", C.c_int32), ("n_first_passes", C.c_int32),
-                ("max_iter", C.c_int32), ("lanczos_steps", C.c_int32),
+                ("max_iter", C.c_int32), ("lanczos_steps", C.c_int32), ("mix_history", C.c_int32),
                 ("kT", C.c_double), ("mix", C.c_double), ("tol", C.c_double), ("n_elec", C.c_double),
                 ("poisson_tol", C.c_double), ("filt", C.c_int), ("rr", C.c_int), ("final_fp64_pass", C.c_int32),
                 ("rho_init_dev", C.c_void_p), ("x0_dev", C.c_void_p), ("lanczos_v0_dev", C.c_void_p)]
@@ -88,8 +88,6 @@ _SIGS = {
                                         C.c_int32, C.c_int, C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
     "sparc_fermi": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.c_double,
                               C.c_double, C.c_void_p, C.POINTER(C.c_double)]),
-}
-_OPTIONAL = {
     "sparc_scf_run": (C.c_int, [C.c_void_p, C.POINTER(sparc_grid), C.POINTER(sparc_atoms),
                                 C.POINTER(sparc_scf_params), C.POINTER(sparc_scf_result)]),
 }

@@ -1,0 +1,110 @@
+"""GPU SCF driver (sparc_scf_run) against the oracle SCF: converged free
+energy within 1e-6 Ha/atom (both sides to a 1e-9 density residual), the
+uniform-gas fixed point, and the mixed-precision (FP32 filter + final FP64
+passes) form against the same FP64 oracle energy."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.fd import Grid
+from oracle.cell import local_potential, projectors
+from oracle.scf import scf as oracle_scf, sad_density
+from paper_1603_04339_amd import sparc as sp
+from paper_1603_04339_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+def _small_scf_cell():
+    cell, rng = wl.draw_cell(91, 0, 24, 12.0, 4, (0,), 3.0, 8)
+    X0 = wl.draw_orbitals(rng, cell.n_d, 8)
+    v0 = wl.lanczos_start(rng, cell.n_d)
+    return cell, X0, v0
+
+
+def _params(cell, X0, v0, filt=sp.R64, tol=1e-9, max_iter=200):
+    return dict(n_s=cell.n_s, degree=20, n_first_passes=4, max_iter=max_iter, lanczos_steps=20, mix_history=7,
+                kT=0.01, mix=0.3,
+                tol=tol, n_elec=cell.n_elec, poisson_tol=1e-12, filt=filt, rr=sp.GEMM_NATIVE, final_fp64_pass=1,
+                rho_init_dev=None, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda())
+
+
+@pytest.fixture(scope="module")
+def oracle_ref():
+    cell, X0, v0 = _small_scf_cell()
+    grid = Grid(n=cell.n, L=cell.L)
+    V = local_potential(grid, cell.positions, cell.depth, cell.width)
+    P = projectors(grid, cell.positions, cell.chan_atom, cell.chan_l, cell.chan_gamma, cell.chan_rc)
+    rho0 = sad_density(grid, cell.positions, cell.width, cell.Z, cell.n_elec)
+    out = oracle_scf(grid, V, P, X0.T, cell.n_elec, degree=20, rho_init=rho0, lanczos_v0=v0, tol=1e-9,
+                     max_iter=200, mix=0.3, mix_history=7)
+    assert out["converged"]
+    return cell, X0, v0, out
+
+
+def _run(ctx, cell, prm):
+    rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    ritz = torch.zeros(cell.n_s, dtype=torch.float64, device="cuda:0")
+    out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz)
+    return out, rho, ritz
+
+
+def test_scf_matches_oracle(ctx, oracle_ref):
+    cell, X0, v0, ref = oracle_ref
+    out, rho, ritz = _run(ctx, cell, _params(cell, X0, v0))
+    print(f"gpu: {out['iterations']} it, F={out['energy']:.10f}; oracle {ref['iterations']} it, F={ref['energy']:.10f}")
+    assert out["converged"]
+    assert abs(out["energy"] - ref["energy"]) / cell.n_atoms < 1e-6
+    np.testing.assert_allclose(rho.cpu().numpy(), ref["rho"], atol=1e-6 * np.abs(ref["rho"]).max())
+    np.testing.assert_allclose(ritz.cpu().numpy(), ref["ritz"], atol=1e-6)
+
+
+def test_scf_mixed_precision(ctx, oracle_ref):
+    cell, X0, v0, ref = oracle_ref
+    out, rho, ritz = _run(ctx, cell, _params(cell, X0, v0, filt=sp.R32))
+    err = abs(out["energy"] - ref["energy"]) / cell.n_atoms
+    print(f"mixed: {out['iterations']} it, F={out['energy']:.10f}, |dF|/atom = {err:.2e}")
+    assert out["converged"]
+    assert err < 1e-6
+
+
+def test_scf_uniform_gas(ctx):
+    """Empty cell, 14 electrons in the closed shell of 7 plane waves (12^3,
+    L = 6): the uniform start density is a fixed point (one iteration)."""
+    cell = wl.Cell(n=(12, 12, 12), L=(6.0, 6.0, 6.0), positions=np.zeros((0, 3)), depth=np.zeros(0),
+                   width=np.zeros(0), chan_atom=np.zeros(0, np.int32), chan_l=np.zeros(0, np.int32),
+                   chan_gamma=np.zeros(0), chan_rc=np.zeros(0), Z=np.zeros(0), n_s=10)
+    rng = np.random.default_rng(4)
+    X0 = rng.standard_normal((10, cell.n_d))
+    v0 = rng.standard_normal(cell.n_d)
+    prm = _params(cell, X0, v0)
+    prm["n_elec"] = 14.0
+    prm["n_first_passes"] = 8
+    prm["rho_init_dev"] = torch.full((cell.n_d,), 14.0 / 216.0, dtype=torch.float64, device="cuda:0")
+    out, rho, ritz = _run(ctx, cell, prm)
+    assert out["converged"] and out["iterations"] == 1
+    np.testing.assert_allclose(rho.cpu().numpy(), 14.0 / 216.0, rtol=1e-12)
+
+
+def test_scf_error_paths(ctx):
+    cell, X0, v0 = _small_scf_cell()
+    prm = _params(cell, X0, v0, tol=1e-12, max_iter=2)
+    rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    ritz = torch.zeros(cell.n_s, dtype=torch.float64, device="cuda:0")
+    out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz)
+    assert out["status"] == sp.ENOCONV and not out["converged"] and out["iterations"] == 2
+    prm = _params(cell, X0, v0)
+    prm["n_elec"] = 100.0   # more electrons than 2 n_s
+    with pytest.raises(sp.SparcError) as e:
+        sp.sparc_scf_run(ctx, cell, prm, rho, ritz)
+    assert e.value.status == sp.EINVAL
