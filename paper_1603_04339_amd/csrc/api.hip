@@ -307,6 +307,7 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
   const sparc_dtype sdt = cp ? SPARC_C128 : SPARC_R64;
   const int64_t N = H->n_d;
   const int ncu = H->ctx->n_cu;
+  g_timer_ctx = H->ctx;
   int info = 0;
   // pass 1: T1 from the Gram matrix of X (shifted if it is numerically singular)
   SPARC_TRY(gram(s, dt, N, n, n, X, ldx, X, ldx, w.M, n, w.gw, w.gw_bytes, mode, ncu));

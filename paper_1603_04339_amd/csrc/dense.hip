@@ -367,6 +367,116 @@ __global__ __launch_bounds__(1024) void hetrd_kernel(int n, T* __restrict__ A, d
   if (tid == 0) d[n - 1] = re_(A[(n - 1) + (int64_t)(n - 1) * n]);
 }
 
+// Same reduction with a two-dimensional thread map for memory-level parallelism:
+// lanes run over 64 consecutive rows (coalesced column segments), the 16 waves over
+// interleaved columns; the matrix-vector product is reduced across waves in LDS.
+// LDS: 16 partial vectors + v + w (n <= 1066 real, n <= 533 complex).
+template <typename T>
+__global__ __launch_bounds__(1024) void hetrd2_kernel(int n, T* __restrict__ A, double* __restrict__ d,
+                                                      double* __restrict__ e, T* __restrict__ tau) {
+  extern __shared__ char smem[];
+  T* v = (T*)smem;           // [n]
+  T* w = v + n;              // [n]
+  T* part = w + n;           // [16][n]
+  __shared__ double red[16];
+  __shared__ T s_tau, s_scale;
+  __shared__ double s_beta;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+  for (int i = 0; i < n - 1; ++i) {
+    const int r0 = i + 1;       // first row/column of the trailing block
+    const int m = n - r0;
+    double xn = 0;
+    for (int r = i + 2 + tid; r < n; r += nt) {
+      T x = A[r + (int64_t)i * n];
+      xn += re_(mul_(conj_(x), x));
+    }
+    xn = block_sum(xn, red);
+    if (tid == 0) {
+      T alpha = A[i + 1 + (int64_t)i * n];
+      double ar = re_(alpha);
+      double ai = 0;
+      if constexpr (sizeof(T) == 16) ai = ((cd&)alpha).im;
+      if (xn == 0.0 && ai == 0.0) {
+        s_tau = mkT<T>(0.0, 0.0);
+        s_beta = ar;
+        s_scale = mkT<T>(0.0, 0.0);
+      } else {
+        double beta = -copysign(sqrt(ar * ar + ai * ai + xn), ar);
+        s_beta = beta;
+        s_tau = mkT<T>((beta - ar) / beta, -ai / beta);
+        double dr = ar - beta, di = ai, den = dr * dr + di * di;
+        s_scale = mkT<T>(dr / den, -di / den);
+      }
+    }
+    __syncthreads();
+    const T tau_i = s_tau;
+    const double beta = s_beta;
+    if (tid == 0) tau[i] = tau_i;
+    const bool trivial = re_(mul_(conj_(tau_i), tau_i)) == 0.0;
+    for (int r = r0 + tid; r < n; r += nt) {
+      T val;
+      if (r == r0) val = mkT<T>(1.0, 0.0);
+      else {
+        val = mul_(A[r + (int64_t)i * n], s_scale);
+        A[r + (int64_t)i * n] = val;
+      }
+      v[r] = val;
+    }
+    __syncthreads();
+    if (!trivial) {
+      // partial products over this wave's columns
+      for (int rb = r0; rb < n; rb += 64) {
+        const int r = rb + lane;
+        T acc = mkT<T>(0.0, 0.0);
+        if (r < n) {
+          int c = r0 + wave;
+#pragma unroll 4
+          for (; c < n; c += nwave) acc = add_(acc, mul_(A[r + (int64_t)c * n], v[c]));
+        }
+        if (r < n) part[wave * n + r] = acc;
+      }
+      __syncthreads();
+      for (int r = r0 + tid; r < n; r += nt) {
+        T acc = mkT<T>(0.0, 0.0);
+        for (int q = 0; q < nwave; ++q) acc = add_(acc, part[q * n + r]);
+        w[r] = mul_(tau_i, acc);
+      }
+      __syncthreads();
+      double pr = 0, pi = 0;
+      for (int r = r0 + tid; r < n; r += nt) {
+        T t = mul_(conj_(w[r]), v[r]);
+        pr += re_(t);
+        if constexpr (sizeof(T) == 16) pi += ((cd&)t).im;
+      }
+      pr = block_sum(pr, red);
+      if constexpr (sizeof(T) == 16) pi = block_sum(pi, red);
+      T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(pr, pi)));
+      for (int r = r0 + tid; r < n; r += nt) w[r] = add_(w[r], mul_(a2, v[r]));
+      __syncthreads();
+      // A_sub -= v w^H + w v^H
+      for (int rb = r0; rb < n; rb += 64) {
+        const int r = rb + lane;
+        if (r < n) {
+          const T vr = v[r], wr = w[r];
+          int c = r0 + wave;
+#pragma unroll 4
+          for (; c < n; c += nwave) {
+            T upd = add_(mul_(vr, conj_(w[c])), mul_(wr, conj_(v[c])));
+            A[r + (int64_t)c * n] = sub_(A[r + (int64_t)c * n], upd);
+          }
+        }
+      }
+    }
+    if (tid == 0) {
+      e[i] = beta;
+      d[i] = re_(A[i + (int64_t)i * n]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) d[n - 1] = re_(A[(n - 1) + (int64_t)(n - 1) * n]);
+}
+
 // ------------------------------------------------------------ tridiagonal eigenvalues (bisection)
 __device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
   double q = d[0] - x;
@@ -576,8 +686,12 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
   double* Y = (double*)take((size_t)n * n * 8);
   double* scr = (double*)take((size_t)5 * n * n * 8);
   int* piv = (int*)take((size_t)n * n * 4);
+  const size_t lds2 = (size_t)18 * n * sizeof(T);
   if (n == 1) {
     hetrd_kernel<T><<<1, 64, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
+  } else if (lds2 <= 150 * 1024) {
+    SPARC_HIP(hipFuncSetAttribute((const void*)hetrd2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    hetrd2_kernel<T><<<1, 1024, lds2, s>>>(n, A, d, e, tau);
   } else {
     int nt = n >= 1024 ? 1024 : ((n + 63) / 64) * 64;
     hetrd_kernel<T><<<1, nt, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);

@@ -16,9 +16,13 @@
 // four real MFMAs on the (re, im) parts.  Operand lane layout (both types):
 // A[i][k] in lane i + 16k, B[k][j] in lane j + 16k.  Result element v of lane
 // l is C[l/16 + 4v][l%16] for f64 and C[4(l/16) + v][l%16] for f32.
+#include <cstdint>
+
 #include "devmath.hpp"
 
 namespace sparc {
+
+sparc_ctx* g_timer_ctx = nullptr;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -54,129 +58,165 @@ template <typename E> struct gram_tile { static constexpr int T = elem<E>::is_cp
 // One work-group: a T x T output tile of one slab.  4 waves in 2 x 2, each wave
 // (T/2) x (T/2) = WB x WB MFMA blocks.  The next k-chunk is loaded into registers
 // while the current one is consumed from LDS.
-template <typename E, int T>
+// Loader for one T x KC operand chunk (columns c of a tall block, KC consecutive rows k):
+// element pairs (k, k+1) of one column per lane, 8 lanes per 128-byte column segment,
+// so that every wave-wide load covers whole cache lines.  `vec` selects 16-byte loads
+// (leading dimension even and base 16-byte aligned), else two 8-byte loads.
+template <typename E, int T, int KC>
+struct PairLoader {
+  static constexpr int PAIRS = T * KC / 2 / 256;  // pairs per thread
+  E v0[PAIRS], v1[PAIRS];
+  __device__ __forceinline__ void fetch(const E* __restrict__ A, int64_t lda, int c0, int ncol, int64_t k0,
+                                        int64_t k_end, bool vec) {
+#pragma unroll
+    for (int u = 0; u < PAIRS; ++u) {
+      const int q = threadIdx.x + 256 * u;
+      const int c = q / (KC / 2), kk = (q % (KC / 2)) * 2;
+      const int64_t k = k0 + kk;
+      v0[u] = zero<E>();
+      v1[u] = zero<E>();
+      if (c0 + c < ncol) {
+        const E* p = A + k + (int64_t)(c0 + c) * lda;
+        if constexpr (!elem<E>::is_cplx && sizeof(E) == 8) {
+          if (vec && k + 1 < k_end) {
+            double2 t = *(const double2*)p;
+            v0[u] = t.x;
+            v1[u] = t.y;
+            continue;
+          }
+        }
+        if (k < k_end) v0[u] = p[0];
+        if (k + 1 < k_end) v1[u] = p[1];
+      }
+    }
+  }
+};
+
+// One work-group: a T x T output tile of one slab.  4 waves in 2 x 2, each wave
+// (T/2) x (T/2) = WB x WB MFMA blocks.  The next k-chunk is loaded into registers
+// while the current one is consumed from LDS (k-major: operand reads are
+// conflict-free rows).
+template <typename E, int T, int KC>
 __global__ __launch_bounds__(256) void gram_kernel(int64_t N, int na, int nb, const E* __restrict__ A, int64_t lda,
                                                    const E* __restrict__ B, int64_t ldb, int n_slab, int64_t slab_len,
                                                    int tiles_a, int n_tiles, int herm,
-                                                   double* __restrict__ part, int xcd_remap) {
+                                                   double* __restrict__ part, int xcd_remap, int vec) {
   typedef typename elem<E>::real R;
   constexpr bool CPX = elem<E>::is_cplx;
   constexpr int NCP = CPX ? 2 : 1;
-  constexpr int KC = 16;
   constexpr int WB = T / 32;
-  constexpr int PER = T * KC / 256;     // values per thread per operand per chunk
-  constexpr int TPC = KC / PER;         // threads per column
   typedef mfma_t<R> M;
-  __shared__ R As[NCP][T][KC + 1];
-  __shared__ R Bs[NCP][T][KC + 1];
+  typedef PairLoader<E, T, KC> LD;
+  __shared__ R As[NCP][KC][T + 1];
+  __shared__ R Bs[NCP][KC][T + 1];
 
-  int bid = blockIdx.x;
+  // persistent: the grid (a multiple of 8 work-groups) walks the (slab, tile) items in rounds;
+  // within a round the work-groups of one XCD take consecutive items (tiles of the same slab)
   const int total = n_slab * n_tiles;
-  if (xcd_remap) bid = (bid % 8) * (total / 8) + bid / 8;
-  const int slab = bid / n_tiles;
-  const int tile = bid % n_tiles;
-  int ti, tj;
-  if (herm) {  // upper-triangular tile enumeration: tile = tj (tj + 1) / 2 + ti, ti <= tj
-    tj = 0;
-    while ((tj + 1) * (tj + 2) / 2 <= tile) ++tj;
-    ti = tile - tj * (tj + 1) / 2;
-  } else {
-    ti = tile % tiles_a;
-    tj = tile / tiles_a;
-  }
-  const int i0 = ti * T, j0 = tj * T;
-  const int64_t k_beg = (int64_t)slab * slab_len;
-  const int64_t k_end = min(N, k_beg + slab_len);
-
+  const int G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = (wv & 1) * (T / 2), wj = (wv >> 1) * (T / 2);
-  typename M::acc acc_r[WB][WB], acc_i[WB][WB];
-#pragma unroll
-  for (int a = 0; a < WB; ++a)
-#pragma unroll
-    for (int b = 0; b < WB; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; if constexpr (CPX) acc_i[a][b][v] = 0; }
+  for (int round = 0;; ++round) {
+    const int bid = xcd_remap ? round * G + (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8)
+                              : round * G + (int)blockIdx.x;
+    if (bid >= total) break;
+    const int slab = bid / n_tiles;
+    const int tile = bid % n_tiles;
+    int ti, tj;
+    if (herm) {  // upper-triangular tile enumeration: tile = tj (tj + 1) / 2 + ti, ti <= tj
+      tj = 0;
+      while ((tj + 1) * (tj + 2) / 2 <= tile) ++tj;
+      ti = tile - tj * (tj + 1) / 2;
+    } else {
+      ti = tile % tiles_a;
+      tj = tile / tiles_a;
+    }
+    const int i0 = ti * T, j0 = tj * T;
+    const int64_t k_beg = (int64_t)slab * slab_len;
+    const int64_t k_end = min(N, k_beg + slab_len);
 
-  const int lc = tid / TPC, lk = (tid % TPC) * PER;
-  const int ia = i0 + lc, jb = j0 + lc;
-  E ra[PER], rb[PER];
-  auto fetch = [&](int64_t k0) {
+    typename M::acc acc_r[WB][WB], acc_i[WB][WB];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int64_t k = k0 + lk + u;
-      ra[u] = zero<E>();
-      rb[u] = zero<E>();
-      if (k < k_end) {
-        if (ia < na) ra[u] = A[k + (int64_t)ia * lda];
-        if (jb < nb) rb[u] = B[k + (int64_t)jb * ldb];
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+      for (int b = 0; b < WB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; if constexpr (CPX) acc_i[a][b][v] = 0; }
+
+    LD la, lb;
+    la.fetch(A, lda, i0, na, k_beg, k_end, vec);
+    lb.fetch(B, ldb, j0, nb, k_beg, k_end, vec);
+    for (int64_t k0 = k_beg; k0 < k_end; k0 += KC) {
+#pragma unroll
+      for (int u = 0; u < LD::PAIRS; ++u) {
+        const int q = tid + 256 * u;
+        const int c = q / (KC / 2), kk = (q % (KC / 2)) * 2;
+        R r0, i0_, r1, i1_;
+        split<E>(la.v0[u], r0, i0_);
+        split<E>(la.v1[u], r1, i1_);
+        As[0][kk][c] = r0;
+        As[0][kk + 1][c] = r1;
+        if constexpr (CPX) { As[1][kk][c] = i0_; As[1][kk + 1][c] = i1_; }
+        split<E>(lb.v0[u], r0, i0_);
+        split<E>(lb.v1[u], r1, i1_);
+        Bs[0][kk][c] = r0;
+        Bs[0][kk + 1][c] = r1;
+        if constexpr (CPX) { Bs[1][kk][c] = i0_; Bs[1][kk + 1][c] = i1_; }
       }
-    }
-  };
-  fetch(k_beg);
-  for (int64_t k0 = k_beg; k0 < k_end; k0 += KC) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      R ar, ai, br, bi;
-      split<E>(ra[u], ar, ai);
-      split<E>(rb[u], br, bi);
-      As[0][lc][lk + u] = ar;
-      Bs[0][lc][lk + u] = br;
-      if constexpr (CPX) {
-        As[1][lc][lk + u] = ai;
-        Bs[1][lc][lk + u] = bi;
-      }
-    }
-    __syncthreads();
-    if (k0 + KC < k_end) fetch(k0 + KC);
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const int kq = kk + (lane >> 4), r16 = lane & 15;
-      R a_r[WB], a_i[WB], b_r[WB], b_i[WB];
-#pragma unroll
-      for (int a = 0; a < WB; ++a) {
-        a_r[a] = As[0][wi + 16 * a + r16][kq];
-        b_r[a] = Bs[0][wj + 16 * a + r16][kq];
-        if constexpr (CPX) {
-          a_i[a] = As[1][wi + 16 * a + r16][kq];
-          b_i[a] = Bs[1][wj + 16 * a + r16][kq];
-        }
+      __syncthreads();
+      if (k0 + KC < k_end) {
+        la.fetch(A, lda, i0, na, k0 + KC, k_end, vec);
+        lb.fetch(B, ldb, j0, nb, k0 + KC, k_end, vec);
       }
 #pragma unroll
-      for (int a = 0; a < WB; ++a)
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int kq = kk + (lane >> 4), r16 = lane & 15;
+        R a_r[WB], a_i[WB], b_r[WB], b_i[WB];
 #pragma unroll
-        for (int b = 0; b < WB; ++b) {
-          acc_r[a][b] = M::step(a_r[a], b_r[b], acc_r[a][b]);
+        for (int a = 0; a < WB; ++a) {
+          a_r[a] = As[0][kq][wi + 16 * a + r16];
+          b_r[a] = Bs[0][kq][wj + 16 * a + r16];
           if constexpr (CPX) {
-            // conj(A)^T B: re += ar br + ai bi ; im += ar bi - ai br
-            acc_r[a][b] = M::step(a_i[a], b_i[b], acc_r[a][b]);
-            acc_i[a][b] = M::step(a_r[a], b_i[b], acc_i[a][b]);
-            acc_i[a][b] = M::step(-a_i[a], b_r[b], acc_i[a][b]);
+            a_i[a] = As[1][kq][wi + 16 * a + r16];
+            b_i[a] = Bs[1][kq][wj + 16 * a + r16];
           }
         }
+#pragma unroll
+        for (int a = 0; a < WB; ++a)
+#pragma unroll
+          for (int b = 0; b < WB; ++b) {
+            acc_r[a][b] = M::step(a_r[a], b_r[b], acc_r[a][b]);
+            if constexpr (CPX) {
+              // conj(A)^T B: re += ar br + ai bi ; im += ar bi - ai br
+              acc_r[a][b] = M::step(a_i[a], b_i[b], acc_r[a][b]);
+              acc_i[a][b] = M::step(a_r[a], b_i[b], acc_i[a][b]);
+              acc_i[a][b] = M::step(-a_i[a], b_r[b], acc_i[a][b]);
+            }
+          }
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    // partial tile -> part[slab] (column-major na x nb, FP64; complex interleaved)
+    const int64_t mat = (int64_t)na * nb * NCP;
+    double* P = part + (int64_t)slab * mat;
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+      for (int b = 0; b < WB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int i = i0 + wi + 16 * a + M::row(lane, v);
+          int j = j0 + wj + 16 * b + (lane & 15);
+          if (i < na && j < nb) {
+            if constexpr (CPX) {
+              P[2 * (i + (int64_t)j * na)] = (double)acc_r[a][b][v];
+              P[2 * (i + (int64_t)j * na) + 1] = (double)acc_i[a][b][v];
+            } else {
+              P[i + (int64_t)j * na] = (double)acc_r[a][b][v];
+            }
+          }
+        }
   }
-  // partial tile -> part[slab] (column-major na x nb, FP64; complex interleaved)
-  const int64_t mat = (int64_t)na * nb * NCP;
-  double* P = part + (int64_t)slab * mat;
-#pragma unroll
-  for (int a = 0; a < WB; ++a)
-#pragma unroll
-    for (int b = 0; b < WB; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        int i = i0 + wi + 16 * a + M::row(lane, v);
-        int j = j0 + wj + 16 * b + (lane & 15);
-        if (i < na && j < nb) {
-          if constexpr (CPX) {
-            P[2 * (i + (int64_t)j * na)] = (double)acc_r[a][b][v];
-            P[2 * (i + (int64_t)j * na) + 1] = (double)acc_i[a][b][v];
-          } else {
-            P[i + (int64_t)j * na] = (double)acc_r[a][b][v];
-          }
-        }
-      }
 }
 
 // C = sum over slabs; herm: only tiles with ti <= tj were computed, fill the
@@ -218,14 +258,10 @@ static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T)
   for (int tj = 0; tj < p.tiles_b; ++tj)
     for (int ti = 0; ti < p.tiles_a; ++ti)
       if (!herm || ti <= tj) p.n_tiles++;
-  // enough work-groups for ~4 per CU, each slab at least 2048 nodes long
-  int64_t want = 4 * (int64_t)n_cu;
-  int64_t s = (want + p.n_tiles - 1) / p.n_tiles;
-  int64_t smax = std::max<int64_t>(1, N / 2048);
-  s = std::max<int64_t>(1, std::min<int64_t>(s, smax));
-  s = std::min<int64_t>(s, 256);
-  // make the work-group count a multiple of 8 where possible (XCD placement)
-  while (s < smax && s < 256 && ((s * p.n_tiles) % 8) != 0) ++s;
+  // 256 slabs (each at least 2048 nodes): with an even tile count the items fill whole
+  // rounds of the persistent grid (two work-groups on each of 256 CUs)
+  (void)n_cu;
+  int64_t s = std::max<int64_t>(1, std::min<int64_t>(256, N / 2048));
   p.slab_len = (N + s - 1) / s;
   p.slab_len = ((p.slab_len + 15) / 16) * 16;
   p.n_slab = (int)((N + p.slab_len - 1) / p.slab_len);
@@ -235,7 +271,7 @@ static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T)
 size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt) {
   GramPlan p = gram_plan(N, n_a, n_b, false, 256, 64);
   // plans for other CU counts use at most 256 slabs
-  int64_t slabs = std::max<int64_t>(p.n_slab, 256);
+  int64_t slabs = 256;  // plans never use more slabs
   return (size_t)slabs * n_a * n_b * 8 * (dtype_complex(dt) ? 2 : 1);
 }
 
@@ -245,14 +281,20 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
   const bool herm = (A == B) && (na == nb) && (lda == ldb);
   constexpr int T = gram_tile<E>::T;
   GramPlan p = gram_plan(N, na, nb, herm, n_cu, T);
+  // persistent grid: two work-groups per CU (a multiple of 8), at most one per item
+  const int items = p.n_slab * p.n_tiles;
+  int grid = std::min(items, 2 * n_cu);
+  if (grid >= 8) grid -= grid % 8;
   const bool cplx = elem<E>::is_cplx;
   size_t part_bytes = (size_t)p.n_slab * na * nb * 8 * (cplx ? 2 : 1);
   if (part_bytes > work_bytes) return fail(SPARC_ENOMEM, "gram: workspace %zu < %zu bytes", work_bytes, part_bytes);
   double* part = (double*)work;
-  int total = p.n_slab * p.n_tiles;
-  int remap = (total % 8 == 0) ? 1 : 0;
-  gram_kernel<E, T><<<total, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
-                                          herm ? 1 : 0, part, remap);
+  int remap = (grid % 8 == 0) ? 1 : 0;
+  int tmr = timer_begin(g_timer_ctx, "gram");
+  const int vec = (lda % 2 == 0 && ldb % 2 == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0) ? 1 : 0;
+  gram_kernel<E, T, 16><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
+                                              herm ? 1 : 0, part, remap, vec);
+  timer_end(g_timer_ctx, tmr);
   SPARC_TRY(check_launch("gram_kernel"));
   int64_t ne = (int64_t)na * nb;
   gram_reduce_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(na, nb, p.n_slab, part, (double*)C, ldc,
@@ -279,7 +321,7 @@ template <typename E, int T>
 __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_out, const E* __restrict__ A,
                                                      int64_t lda, const double* __restrict__ Q, int ldq,
                                                      E* __restrict__ Out, int64_t ldo, int tiles_n, int xcd_remap,
-                                                     int64_t total, int q_upper) {
+                                                     int64_t total, int q_upper, int vec, int qvec) {
   typedef typename elem<E>::real R;
   constexpr bool CPX = elem<E>::is_cplx;
   constexpr int NCP = CPX ? 2 : 1;
@@ -303,30 +345,59 @@ __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_
     for (int b = 0; b < WB; ++b)
 #pragma unroll
       for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; if constexpr (CPX) acc_i[a][b][v] = 0; }
-  // A loader: column k = tid / (T/PER), PER consecutive rows; Q loader: column j = tid / (KC/PER), PER consecutive k
-  constexpr int ATPC = T / PER;
-  const int ak = tid / ATPC, am = (tid % ATPC) * PER;
-  constexpr int QTPC = KC / PER;
-  const int qj = tid / QTPC, qk = (tid % QTPC) * PER;
+  // A loader: pairs of consecutive rows, T/2 lanes per column (whole cache lines per wave);
+  // Q loader: pairs of consecutive k of one column j, KC/2 lanes per column
+  constexpr int APAIRS = T * KC / 2 / 256;
+  constexpr int QPAIRS = T * KC / 2 / 256;
   // an upper-triangular Q has no entries below row j0 + T - 1 in this column tile
   const int k_stop = q_upper ? min(n_in, j0 + T) : n_in;
-  E ra[PER];
-  double qr_[PER], qi_[PER];
+  E ra0[APAIRS], ra1[APAIRS];
+  double qr0[QPAIRS], qr1[QPAIRS], qi0[QPAIRS], qi1[QPAIRS];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int64_t m = m0 + am + u;
-      const int k = k0 + ak;
-      ra[u] = (m < N && k < n_in) ? A[m + (int64_t)k * lda] : zero<E>();
-      const int kq = k0 + qk + u, j = j0 + qj;
-      qr_[u] = 0;
-      qi_[u] = 0;
-      if (kq < n_in && j < n_out) {
+    for (int u = 0; u < APAIRS; ++u) {
+      const int q = tid + 256 * u;
+      const int k = k0 + q / (T / 2);
+      const int64_t m = m0 + (q % (T / 2)) * 2;
+      ra0[u] = zero<E>();
+      ra1[u] = zero<E>();
+      if (k < n_in) {
+        const E* p = A + m + (int64_t)k * lda;
+        bool done = false;
+        if constexpr (!elem<E>::is_cplx && sizeof(E) == 8) {
+          if (vec && m + 1 < N) {
+            double2 t = *(const double2*)p;
+            ra0[u] = t.x;
+            ra1[u] = t.y;
+            done = true;
+          }
+        }
+        if (!done) {
+          if (m < N) ra0[u] = p[0];
+          if (m + 1 < N) ra1[u] = p[1];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < QPAIRS; ++u) {
+      const int q = tid + 256 * u;
+      const int j = j0 + q / (KC / 2), kq = k0 + (q % (KC / 2)) * 2;
+      qr0[u] = qr1[u] = qi0[u] = qi1[u] = 0;
+      if (j < n_out) {
         if constexpr (CPX) {
-          qr_[u] = Q[2 * (kq + (int64_t)j * ldq)];
-          qi_[u] = Q[2 * (kq + (int64_t)j * ldq) + 1];
+          const double* p = Q + 2 * (kq + (int64_t)j * ldq);
+          if (kq < n_in) { qr0[u] = p[0]; qi0[u] = p[1]; }
+          if (kq + 1 < n_in) { qr1[u] = p[2]; qi1[u] = p[3]; }
         } else {
-          qr_[u] = Q[kq + (int64_t)j * ldq];
+          const double* p = Q + kq + (int64_t)j * ldq;
+          if (qvec && kq + 1 < n_in) {
+            double2 t = *(const double2*)p;
+            qr0[u] = t.x;
+            qr1[u] = t.y;
+          } else {
+            if (kq < n_in) qr0[u] = p[0];
+            if (kq + 1 < n_in) qr1[u] = p[1];
+          }
         }
       }
     }
@@ -334,13 +405,27 @@ __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_
   fetch(0);
   for (int k0 = 0; k0 < k_stop; k0 += KC) {
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
+    for (int u = 0; u < APAIRS; ++u) {
+      const int q = tid + 256 * u;
+      const int k = q / (T / 2), m = (q % (T / 2)) * 2;
       R vr, vi;
-      split<E>(ra[u], vr, vi);
-      As[0][ak][am + u] = vr;
-      if constexpr (CPX) As[1][ak][am + u] = vi;
-      Qs[0][qk + u][qj] = (R)qr_[u];
-      if constexpr (CPX) Qs[1][qk + u][qj] = (R)qi_[u];
+      split<E>(ra0[u], vr, vi);
+      As[0][k][m] = vr;
+      if constexpr (CPX) As[1][k][m] = vi;
+      split<E>(ra1[u], vr, vi);
+      As[0][k][m + 1] = vr;
+      if constexpr (CPX) As[1][k][m + 1] = vi;
+    }
+#pragma unroll
+    for (int u = 0; u < QPAIRS; ++u) {
+      const int q = tid + 256 * u;
+      const int jj = q / (KC / 2), kk = (q % (KC / 2)) * 2;
+      Qs[0][kk][jj] = (R)qr0[u];
+      Qs[0][kk + 1][jj] = (R)qr1[u];
+      if constexpr (CPX) {
+        Qs[1][kk][jj] = (R)qi0[u];
+        Qs[1][kk + 1][jj] = (R)qi1[u];
+      }
     }
     __syncthreads();
     if (k0 + KC < k_stop) fetch(k0 + KC);
@@ -402,8 +487,12 @@ static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, i
   int64_t total = tiles_m * tiles_n;
   if (total > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "rotate: too many tiles");
   int remap = (total % 8 == 0) ? 1 : 0;
+  int tmr = timer_begin(g_timer_ctx, "rotate");
+  const int vec = (lda % 2 == 0 && ((uintptr_t)A % 16) == 0) ? 1 : 0;
+  const int qvec = (ldq % 2 == 0 && ((uintptr_t)Q % 16) == 0) ? 1 : 0;
   rotate_kernel<E, T><<<(unsigned)total, 256, 0, s>>>(N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap,
-                                                       total, q_upper);
+                                                       total, q_upper, vec, qvec);
+  timer_end(g_timer_ctx, tmr);
   return check_launch("rotate_kernel");
 }
 

@@ -121,6 +121,8 @@ inline int check_launch(const char* what) {
 // kernel timing (setup.hip): begin returns a record index (or -1 when timing is off)
 int timer_begin(sparc_ctx* c, const char* name);
 void timer_end(sparc_ctx* c, int idx);
+// context whose timer records the GEMM launches (set by the calls that issue them)
+extern sparc_ctx* g_timer_ctx;
 
 // Hamiltonian application kernels (hamiltonian.hip)
 //   out = a*(H x) + b*x + c*z ; z may alias out (in-place recurrence), x must not.
