@@ -186,6 +186,41 @@ int density_from_orbitals(sparc_ctx* ctx, int32_t n_k, const void* const* X, con
 int sparc_fermi(sparc_ctx* ctx, int32_t n_k, int32_t n_s, const double* lambda_dev, const double* wk,
                 double n_elec, double kT, double* occ_w_dev, double* mu);
 
+/* ---- batched forms: several (cell, k) problems advanced together --------------------
+ * A filter plan binds n_prob Hamiltonians (same context, dtype and stencil order) to
+ * their orbital blocks X[p] (ld ldx[p], n_s[p] states) and filter degrees.  Each
+ * recurrence step of every problem runs in one stencil launch covering all problems
+ * (per-problem arguments in a device table); the projector gather/scatter run per
+ * problem.  With use_graph the whole sequence is captured once into a HIP graph
+ * (on a private stream) and replayed by sparc_filter_plan_run; the coefficients,
+ * which depend on the bounds, are uploaded to device tables before each replay.
+ * Results equal those of chebyshev_filter on each problem.  work: caller-owned,
+ * sparc_filter_plan_workspace_bytes bytes, kept until the plan is destroyed.
+ * sparc_filter_plan_run is synchronous.  Errors: EINVAL (mixed dtypes/orders/contexts,
+ * degree < 1, bad bounds), ESHAPE, ENOMEM, EDEVICE (graph capture). */
+typedef struct sparc_filter_plan sparc_filter_plan;
+size_t sparc_filter_plan_workspace_bytes(int32_t n_prob, sparc_ham* const* H, const int32_t* n_s,
+                                         const int32_t* degree);
+int sparc_filter_plan_create(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H, void* const* X,
+                             const int64_t* ldx, const int32_t* n_s, const int32_t* degree, int32_t use_graph,
+                             void* work, size_t work_bytes, sparc_filter_plan** out);
+int sparc_filter_plan_run(sparc_filter_plan* plan, const double* lambda_cut, const double* lambda_max);
+void sparc_filter_plan_destroy(sparc_filter_plan* plan);
+/* One-shot batched filter (plan without graph, run once). */
+int chebyshev_filter_batched(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H, void* const* X,
+                             const int64_t* ldx, const int32_t* n_s, const int32_t* degree,
+                             const double* lambda_cut, const double* lambda_max, void* work, size_t work_bytes);
+/* Rayleigh–Ritz of every problem with one shared workspace of
+ * sparc_rr_batched_workspace_bytes bytes; ritz_dev[p]: device, n_s[p] doubles. */
+size_t sparc_rr_batched_workspace_bytes(int32_t n_prob, sparc_ham* const* H, const int32_t* n_s);
+int rayleigh_ritz_batched(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H, void* const* X,
+                          const int64_t* ldx, const int32_t* n_s, sparc_gemm_mode mode,
+                          double* const* ritz_dev, void* work, size_t work_bytes);
+/* Stencil tile autotuning: when enabled, the first non-in-place stencil step of a new
+ * (grid, n_s, dtype, n_o) shape times every tile shape once (HIP events on the
+ * context's stream) and the fastest is cached for the process. */
+int sparc_ctx_set_autotune(sparc_ctx* ctx, int enable);
+
 /* Minimal self-consistent field (Sec. 2 SCF fixed point with mixing, Sec. 3.4
  * CheFSI schedule, Sec. 3.5 free energy) at the Gamma point in the reduced
  * model: V_eff = V_loc + V_H + V_x (Slater exchange), -Lap_h V_H =

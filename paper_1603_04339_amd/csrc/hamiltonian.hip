@@ -11,6 +11,9 @@
 // are x-fastest and coalesced; nodes outside the cell are fetched from their
 // periodic image with the Bloch factor e^{i k_s L_s w}.
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "devmath.hpp"
 
@@ -21,6 +24,7 @@ struct StepArgs {
   typedef typename elem<E>::real R;
   int n1, n2, n3;
   int tiles_x, zchunk;
+  int tiles, nz;     // tiles per plane, z chunks (batched launches)
   int64_t ldx, ldz, ldo;
   const E* __restrict__ x;
   const E* z;
@@ -53,20 +57,18 @@ __device__ __forceinline__ void bloch_factor(const double* kl, int wx, int wy, i
 }
 
 template <typename E, int TX, int TY, int NO>
-__global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
+__device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n, int zi,
+                                           E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
   typedef typename elem<E>::real R;
   constexpr int NT = TX * TY;
-  constexpr int PX = TX + 2 * NO, PY = TY + 2 * NO;
+  constexpr int PX = TX + 2 * NO;
   constexpr int HC = 2 * NO * (TX + TY);         // halo cells of one plane (no corners)
   constexpr int HM = (HC + NT - 1) / NT;         // halo cells per thread
-  __shared__ E plane[2][PY * PX];
 
   const int tid = threadIdx.x;
   const int hx = tid % TX, hy = tid / TX;
-  const int tile = blockIdx.x;
   const int x0 = (tile % A.tiles_x) * TX, y0 = (tile / A.tiles_x) * TY;
-  const int n = blockIdx.y;
-  const int zb = blockIdx.z * A.zchunk;
+  const int zb = zi * A.zchunk;
   const int ze = min(A.n3, zb + A.zchunk);
   const int n1 = A.n1, n2 = A.n2, n3 = A.n3;
   const int64_t plane_sz = (int64_t)n1 * n2;
@@ -200,6 +202,34 @@ __global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
   }
 }
 
+template <typename E, int TX, int TY, int NO>
+__global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
+  __shared__ E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
+  hstep_body<E, TX, TY, NO>(A, blockIdx.x, blockIdx.y, blockIdx.z, plane);
+}
+
+// Several (cell, k) problems in one launch: work-group b belongs to the problem p with
+// wg_off[p] <= b < wg_off[p+1]; inside it, (orbital, z chunk, tile) with tiles fastest.
+template <typename E, int TX, int TY, int NO>
+__global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>* __restrict__ probs,
+                                                               const int* __restrict__ wg_off, int n_probs) {
+  __shared__ E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
+  const int b = blockIdx.x;
+  int lo = 0, hi = n_probs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (wg_off[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const StepArgs<E> A = probs[lo];
+  const int local = b - wg_off[lo];
+  const int tile = local % A.tiles;
+  const int rest = local / A.tiles;
+  const int zi = rest % A.nz;
+  const int n = rest / A.nz;
+  hstep_body<E, TX, TY, NO>(A, tile, n, zi, plane);
+}
+
 // Non-local scatter: y(g, n) += a * sum_{entries e at g} gamma_p chi~_p(g) alpha[p][n] over the
 // nodes that carry projector support (point-major CSR).  One thread per node and
 // block of NB orbitals; alpha is projector-major with the orbitals contiguous
@@ -211,9 +241,11 @@ __global__ __launch_bounds__(256) void nl_scatter_kernel(int n_pts, const int32_
                                                          const int32_t* __restrict__ ent_proj,
                                                          const E* __restrict__ ent_coef,
                                                          const E* __restrict__ alpha, int lda, int n_s,
-                                                         typename elem<E>::real a, E* __restrict__ y, int64_t ldy) {
+                                                         typename elem<E>::real a, const double* a_dev,
+                                                         E* __restrict__ y, int64_t ldy) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pts) return;
+  if (a_dev) a = (typename elem<E>::real)(*a_dev);
   const int nb0 = blockIdx.y * NB;
   const int64_t g = pts[i];
   const int e0 = ptr[i], ne = ptr[i + 1] - e0;
@@ -335,32 +367,15 @@ int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alph
   return fail(SPARC_EINVAL, "nl_project: bad dtype");
 }
 
-template <typename E, int TX, int TY, int NO>
-static int launch_step(sparc_ham* H, StepArgs<E>& A, int32_t n_s) {
-  A.tiles_x = (A.n1 + TX - 1) / TX;
-  int tiles_y = (A.n2 + TY - 1) / TY;
-  // z chunks: enough work-groups to fill the chip, at least 4*NO planes per chunk
-  int64_t base = (int64_t)A.tiles_x * tiles_y * n_s;
-  int nz = 1;
-  int64_t want = 4 * (int64_t)H->ctx->n_cu * 2;
-  while (base * nz < want && A.n3 / (nz * 2) >= 4 * NO) nz *= 2;
-  A.zchunk = (A.n3 + nz - 1) / nz;
-  nz = (A.n3 + A.zchunk - 1) / A.zchunk;
-  dim3 grid((unsigned)(A.tiles_x * tiles_y), (unsigned)n_s, (unsigned)nz);
-  int t = timer_begin(H->ctx, "hstep");
-  hstep_kernel<E, TX, TY, NO><<<grid, TX * TY, 0, H->ctx->stream>>>(A);
-  timer_end(H->ctx, t);
-  return check_launch("hstep_kernel");
-}
-
-// Tile shapes (TX x TY threads).  The default picks the widest x extent that
-// divides n1 (no idle columns), else the one with the least waste; SPARC_HSTEP_TILE
-// (an index into this list) overrides the choice.
+// ------------------------------------------------------------ launch planning
+// Tile shapes (TX x TY threads).  Without autotuning the choice is the shape with
+// the least idle work (tiles that divide n1, n2) weighted by its halo overhead;
+// SPARC_HSTEP_TILE (an index into this list) overrides it.
 struct TileShape { int tx, ty; };
 static const TileShape kTiles[] = {{32, 8}, {32, 16}, {64, 4}, {64, 8}, {16, 16}, {24, 8}, {48, 8}, {32, 32}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
-static int pick_tile(int n1, int n2) {
+int heuristic_tile(int n1, int n2) {
   const char* env = getenv("SPARC_HSTEP_TILE");
   if (env) {
     int t = atoi(env);
@@ -379,18 +394,163 @@ static int pick_tile(int n1, int n2) {
   return best;
 }
 
-template <typename E, int NO>
-static int dispatch_tile(sparc_ham* H, StepArgs<E>& A, int32_t n_s) {
-  switch (pick_tile(A.n1, A.n2)) {
-    case 0: return launch_step<E, 32, 8, NO>(H, A, n_s);
-    case 1: return launch_step<E, 32, 16, NO>(H, A, n_s);
-    case 2: return launch_step<E, 64, 4, NO>(H, A, n_s);
-    case 3: return launch_step<E, 64, 8, NO>(H, A, n_s);
-    case 4: return launch_step<E, 16, 16, NO>(H, A, n_s);
-    case 5: return launch_step<E, 24, 8, NO>(H, A, n_s);
-    case 6: return launch_step<E, 48, 8, NO>(H, A, n_s);
-    default: return launch_step<E, 32, 32, NO>(H, A, n_s);
+// per-problem grid bookkeeping for a tile shape; returns the number of work-groups
+template <typename E>
+static int64_t plan_problem(StepArgs<E>& A, int tx, int ty, int no, int n_s, int n_cu) {
+  A.tiles_x = (A.n1 + tx - 1) / tx;
+  const int tiles_y = (A.n2 + ty - 1) / ty;
+  A.tiles = A.tiles_x * tiles_y;
+  // z chunks: enough work-groups to fill the chip, at least 4 n_o planes per chunk
+  const int64_t base = (int64_t)A.tiles * n_s;
+  int nz = 1;
+  const int64_t want = 8 * (int64_t)n_cu;
+  while (base * nz < want && A.n3 / (nz * 2) >= 4 * no) nz *= 2;
+  A.zchunk = (A.n3 + nz - 1) / nz;
+  A.nz = (A.n3 + A.zchunk - 1) / A.zchunk;
+  return (int64_t)A.tiles * A.nz * n_s;
+}
+
+template <typename E, int TX, int TY, int NO>
+static int launch_single_t(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s) {
+  plan_problem(A, TX, TY, NO, n_s, ctx->n_cu);
+  dim3 grid((unsigned)A.tiles, (unsigned)n_s, (unsigned)A.nz);
+  int t = timer_begin(ctx, "hstep");
+  hstep_kernel<E, TX, TY, NO><<<grid, TX * TY, 0, ctx->stream>>>(A);
+  timer_end(ctx, t);
+  return check_launch("hstep_kernel");
+}
+
+template <typename E, int TX, int TY, int NO>
+static int launch_batched_t(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total_wg) {
+  if (total_wg <= 0) return SPARC_OK;
+  if (total_wg > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "batched step: too many work-groups");
+  int t = timer_begin(ctx, "hstep");
+  hstep_batched_kernel<E, TX, TY, NO><<<(unsigned)total_wg, TX * TY, 0, ctx->stream>>>(
+      (const StepArgs<E>*)dprobs, dwg, n_probs);
+  timer_end(ctx, t);
+  return check_launch("hstep_batched_kernel");
+}
+
+// run `F::template run<TX, TY>()` for tile index t
+#define SPARC_TILE_SWITCH(t, CALL)        \
+  switch (t) {                            \
+    case 0: return CALL(32, 8);           \
+    case 1: return CALL(32, 16);          \
+    case 2: return CALL(64, 4);           \
+    case 3: return CALL(64, 8);           \
+    case 4: return CALL(16, 16);          \
+    case 5: return CALL(24, 8);           \
+    case 6: return CALL(48, 8);           \
+    default: return CALL(32, 32);         \
   }
+
+template <typename E, int NO>
+static int single_tile(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int t) {
+#define CALL(tx, ty) launch_single_t<E, tx, ty, NO>(ctx, A, n_s)
+  SPARC_TILE_SWITCH(t, CALL)
+#undef CALL
+}
+
+template <typename E>
+static int single_no(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int no, int t) {
+  switch (no) {
+    case 1: return single_tile<E, 1>(ctx, A, n_s, t);
+    case 2: return single_tile<E, 2>(ctx, A, n_s, t);
+    case 3: return single_tile<E, 3>(ctx, A, n_s, t);
+    case 4: return single_tile<E, 4>(ctx, A, n_s, t);
+    case 5: return single_tile<E, 5>(ctx, A, n_s, t);
+    case 6: return single_tile<E, 6>(ctx, A, n_s, t);
+    case 7: return single_tile<E, 7>(ctx, A, n_s, t);
+    case 8: return single_tile<E, 8>(ctx, A, n_s, t);
+  }
+  return fail(SPARC_EINVAL, "ham_step: n_o=%d unsupported", no);
+}
+
+template <typename E, int NO>
+static int batched_tile(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total, int t) {
+#define CALL(tx, ty) launch_batched_t<E, tx, ty, NO>(ctx, dprobs, dwg, n_probs, total)
+  SPARC_TILE_SWITCH(t, CALL)
+#undef CALL
+}
+
+// ------------------------------------------------------------ autotuner
+// The first non-in-place step for a new (grid, states, type, stencil) key times every
+// tile shape once (after one warm-up launch) with HIP events on the context's stream
+// and keeps the fastest; later steps with that key reuse the choice.
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int, int>, int> g_tune_cache;
+
+static bool tune_lookup(const std::tuple<int, int, int, int, int, int>& key, int* t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_cache.find(key);
+  if (it == g_tune_cache.end()) return false;
+  *t = it->second;
+  return true;
+}
+
+int tuned_tile(sparc_ham* H, int32_t n_s, int* t) {
+  return tune_lookup(std::make_tuple(H->grid.n[0], H->grid.n[1], H->grid.n[2], n_s, (int)H->dtype, H->grid.n_o), t)
+             ? 1 : 0;
+}
+
+template <typename E>
+static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best) {
+  sparc_ctx* ctx = H->ctx;
+  hipEvent_t e0, e1;
+  SPARC_HIP(hipEventCreate(&e0));
+  SPARC_HIP(hipEventCreate(&e1));
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  float best_ms = 1e30f;
+  *best = heuristic_tile(A.n1, A.n2);
+  int rc = SPARC_OK;
+  for (int t = 0; t < kNumTiles && rc == SPARC_OK; ++t) {
+    if (kTiles[t].tx * kTiles[t].ty > 1024) continue;
+    StepArgs<E> B = A;
+    rc = single_no<E>(ctx, B, n_s, H->grid.n_o, t);  // warm-up
+    if (rc != SPARC_OK) break;
+    hipEventRecord(e0, ctx->stream);
+    B = A;
+    rc = single_no<E>(ctx, B, n_s, H->grid.n_o, t);
+    hipEventRecord(e1, ctx->stream);
+    if (rc != SPARC_OK) break;
+    hipEventSynchronize(e1);
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best_ms) { best_ms = ms; *best = t; }
+  }
+  ctx->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SPARC_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[std::make_tuple(A.n1, A.n2, A.n3, n_s, (int)H->dtype, H->grid.n_o)] = *best;
+  return SPARC_OK;
+}
+
+template <typename E>
+static int nl_scatter_t(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out,
+                        int64_t ldo) {
+  typedef typename elem<E>::real R;
+  if (H->n_proj == 0 || H->n_nlpts == 0) return SPARC_OK;
+  constexpr int NB = 8;
+  dim3 grid((unsigned)((H->n_nlpts + 255) / 256), (unsigned)((n_s + NB - 1) / NB));
+  int t = timer_begin(H->ctx, "nl_scatter");
+  nl_scatter_kernel<E, NB><<<grid, 256, 0, H->ctx->stream>>>(
+      (int)H->n_nlpts, H->nl_pts, H->nl_ptr, H->ent_proj, (const E*)H->ent_coef, (const E*)alpha, alpha_ld(n_s), n_s,
+      (R)a, a_dev, (E*)out, ldo);
+  timer_end(H->ctx, t);
+  return check_launch("nl_scatter_kernel");
+}
+
+int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out, int64_t ldo) {
+  switch (H->dtype) {
+    case SPARC_R64: return nl_scatter_t<double>(H, alpha, n_s, a, a_dev, out, ldo);
+    case SPARC_R32: return nl_scatter_t<float>(H, alpha, n_s, a, a_dev, out, ldo);
+    case SPARC_C128: return nl_scatter_t<cd>(H, alpha, n_s, a, a_dev, out, ldo);
+    case SPARC_C64: return nl_scatter_t<cf>(H, alpha, n_s, a, a_dev, out, ldo);
+  }
+  return fail(SPARC_EINVAL, "nl_scatter: bad dtype");
 }
 
 template <typename E>
@@ -419,28 +579,98 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   A.vb = (R)b;
   A.zc = (R)c;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
-  int rc;
-  switch (H->grid.n_o) {
-    case 1: rc = dispatch_tile<E, 1>(H, A, n_s); break;
-    case 2: rc = dispatch_tile<E, 2>(H, A, n_s); break;
-    case 3: rc = dispatch_tile<E, 3>(H, A, n_s); break;
-    case 4: rc = dispatch_tile<E, 4>(H, A, n_s); break;
-    case 5: rc = dispatch_tile<E, 5>(H, A, n_s); break;
-    case 6: rc = dispatch_tile<E, 6>(H, A, n_s); break;
-    case 7: rc = dispatch_tile<E, 7>(H, A, n_s); break;
-    case 8: rc = dispatch_tile<E, 8>(H, A, n_s); break;
-    default: return fail(SPARC_EINVAL, "ham_step: n_o=%d unsupported", H->grid.n_o);
-  }
+  int t = heuristic_tile(A.n1, A.n2);
+  if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && z == nullptr && out != x) SPARC_TRY(autotune(H, A, n_s, &t));
+  int rc = single_no<E>(H->ctx, A, n_s, H->grid.n_o, t);
   if (rc != SPARC_OK || H->n_proj == 0 || H->n_nlpts == 0 || (flags & STEP_NO_NONLOCAL)) return rc;
   if (!alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
-  constexpr int NB = 8;
-  dim3 grid((unsigned)((H->n_nlpts + 255) / 256), (unsigned)((n_s + NB - 1) / NB));
-  int t = timer_begin(H->ctx, "nl_scatter");
-  nl_scatter_kernel<E, NB><<<grid, 256, 0, H->ctx->stream>>>(
-      (int)H->n_nlpts, H->nl_pts, H->nl_ptr, H->ent_proj, (const E*)H->ent_coef, (const E*)alpha, alpha_ld(n_s), n_s,
-      (R)a, (E*)out, ldo);
-  timer_end(H->ctx, t);
-  return check_launch("nl_scatter_kernel");
+  return nl_scatter(H, alpha, n_s, a, nullptr, out, ldo);
+}
+
+// ------------------------------------------------------------ batched step tables
+template <typename E>
+static void fill_args(sparc_ham* H, const StepDesc& d, StepArgs<E>& A) {
+  typedef typename elem<E>::real R;
+  A.n1 = H->grid.n[0];
+  A.n2 = H->grid.n[1];
+  A.n3 = H->grid.n[2];
+  A.ldx = d.ldx;
+  A.ldz = d.ldz;
+  A.ldo = d.ldo;
+  A.x = (const E*)d.x;
+  A.z = (const E*)d.z;
+  A.out = (E*)d.out;
+  if constexpr (sizeof(R) == 8) A.veff = (const R*)H->veff;
+  else A.veff = (const R*)H->veff32;
+  A.centre = (R)(d.a * H->centre);
+  for (int p = 0; p < 8; ++p) {
+    A.tx[p] = (R)(d.a * H->tap[0][p]);
+    A.ty[p] = (R)(d.a * H->tap[1][p]);
+    A.tz[p] = (R)(d.a * H->tap[2][p]);
+  }
+  A.va = (R)d.a;
+  A.vb = (R)d.b;
+  A.zc = (R)d.c;
+  for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
+}
+
+size_t step_args_bytes(sparc_dtype dt) {
+  switch (dt) {
+    case SPARC_R64: return sizeof(StepArgs<double>);
+    case SPARC_R32: return sizeof(StepArgs<float>);
+    case SPARC_C128: return sizeof(StepArgs<cd>);
+    case SPARC_C64: return sizeof(StepArgs<cf>);
+  }
+  return 0;
+}
+
+template <typename E>
+static int64_t build_t(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg) {
+  StepArgs<E>* T = (StepArgs<E>*)table;
+  int64_t total = 0;
+  for (int p = 0; p < n; ++p) {
+    fill_args<E>(H[p], d[p], T[p]);
+    wg[p] = (int)total;
+    total += plan_problem(T[p], kTiles[tile].tx, kTiles[tile].ty, H[p]->grid.n_o, d[p].n_s, H[p]->ctx->n_cu);
+  }
+  wg[n] = (int)total;
+  return total;
+}
+
+int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg) {
+  switch (H[0]->dtype) {
+    case SPARC_R64: return build_t<double>(H, d, n, tile, table, wg);
+    case SPARC_R32: return build_t<float>(H, d, n, tile, table, wg);
+    case SPARC_C128: return build_t<cd>(H, d, n, tile, table, wg);
+    case SPARC_C64: return build_t<cf>(H, d, n, tile, table, wg);
+  }
+  return -1;
+}
+
+template <typename E>
+static int launch_tab_t(sparc_ctx* ctx, int no, int tile, const void* table, const int* wg, int n, int64_t total) {
+  switch (no) {
+    case 1: return batched_tile<E, 1>(ctx, table, wg, n, total, tile);
+    case 2: return batched_tile<E, 2>(ctx, table, wg, n, total, tile);
+    case 3: return batched_tile<E, 3>(ctx, table, wg, n, total, tile);
+    case 4: return batched_tile<E, 4>(ctx, table, wg, n, total, tile);
+    case 5: return batched_tile<E, 5>(ctx, table, wg, n, total, tile);
+    case 6: return batched_tile<E, 6>(ctx, table, wg, n, total, tile);
+    case 7: return batched_tile<E, 7>(ctx, table, wg, n, total, tile);
+    case 8: return batched_tile<E, 8>(ctx, table, wg, n, total, tile);
+  }
+  return fail(SPARC_EINVAL, "batched step: n_o=%d unsupported", no);
+}
+
+int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
+                      int n, int64_t total) {
+  switch (dt) {
+    case SPARC_R64: return launch_tab_t<double>(ctx, no, tile, dev_table, dev_wg, n, total);
+    case SPARC_R32: return launch_tab_t<float>(ctx, no, tile, dev_table, dev_wg, n, total);
+    case SPARC_C128: return launch_tab_t<cd>(ctx, no, tile, dev_table, dev_wg, n, total);
+    case SPARC_C64: return launch_tab_t<cf>(ctx, no, tile, dev_table, dev_wg, n, total);
+  }
+  return fail(SPARC_EINVAL, "batched step: bad dtype");
 }
 
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,

@@ -63,6 +63,7 @@ struct sparc_ctx {
   hipStream_t stream;
   int n_cu;
   double* scalars;  // device scratch for scalar results (64 doubles), owned by the context
+  bool autotune = false;  // time the stencil tile shapes on first use of a problem shape
   // optional kernel timing: HIP events recorded around launches on `stream`
   bool timing = false;
   struct TimeRec {
@@ -134,6 +135,27 @@ enum { STEP_NO_VEFF = 1, STEP_NO_NONLOCAL = 2 };
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
              int32_t n_s, double a, double b, double c, const void* alpha, int flags = 0);
 int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha);
+//   out += a * V_nl-scatter(alpha); a from a device scalar when a_dev != nullptr
+int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out, int64_t ldo);
+int heuristic_tile(int n1, int n2);
+// batched stencil steps over several Hamiltonians (same dtype and n_o): a host table of
+// per-problem step arguments and work-group offsets is built, uploaded by the caller, and
+// launched as one kernel
+struct StepDesc {
+  const void* x;
+  int64_t ldx;
+  const void* z;
+  int64_t ldz;
+  void* out;
+  int64_t ldo;
+  int n_s;
+  double a, b, c;
+};
+size_t step_args_bytes(sparc_dtype dt);
+int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg);
+int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
+                      int n, int64_t total);
+int tuned_tile(sparc_ham* H, int32_t n_s, int* t);
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
 
 // GEMMs (gemm.hip)

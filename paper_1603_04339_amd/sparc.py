@@ -88,6 +88,21 @@ _SIGS = {
                                         C.c_int32, C.c_int, C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
     "sparc_fermi": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.c_double,
                               C.c_double, C.c_void_p, C.POINTER(C.c_double)]),
+    "sparc_filter_plan_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                                        C.POINTER(C.c_int32)]),
+    "sparc_filter_plan_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                                           C.c_void_p, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "sparc_filter_plan_run": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "sparc_filter_plan_destroy": (None, [C.c_void_p]),
+    "chebyshev_filter_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p, C.c_size_t]),
+    "sparc_rr_batched_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]),
+    "rayleigh_ritz_batched": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_void_p),
+                                        C.c_void_p, C.c_size_t]),
+    "sparc_ctx_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "sparc_scf_run": (C.c_int, [C.c_void_p, C.POINTER(sparc_grid), C.POINTER(sparc_atoms),
                                 C.POINTER(sparc_scf_params), C.POINTER(sparc_scf_result)]),
 }
@@ -303,6 +318,81 @@ def sparc_fermi(ctx: Context, lam, wk, n_elec: float, kT: float, occ_w=None):
     _check(load().sparc_fermi(ctx.handle, nk, ns, _ptr(lam), _dptr(w), float(n_elec), float(kT), _ptr(occ_w),
                               C.byref(mu)))
     return mu.value
+
+
+def _arr(ctype, vals):
+    return (ctype * len(vals))(*vals)
+
+
+def _batch_args(hams, Xs, n_s, degree=None):
+    H = _arr(C.c_void_p, [h.handle.value for h in hams])
+    X = _arr(C.c_void_p, [x.data_ptr() for x in Xs])
+    ld = _arr(C.c_int64, [x.stride(0) for x in Xs])
+    ns = _arr(C.c_int32, list(n_s))
+    dg = _arr(C.c_int32, list(degree)) if degree is not None else None
+    return H, X, ld, ns, dg
+
+
+class FilterPlan:
+    """Batched Chebyshev filter over several problems (sparc_filter_plan)."""
+
+    def __init__(self, ctx: Context, hams, Xs, degree, use_graph: bool = True):
+        lib = load()
+        for h, x in zip(hams, Xs):
+            _block(x, h)
+        n_s = [x.shape[0] for x in Xs]
+        self._args = _batch_args(hams, Xs, n_s, degree)
+        H, X, ld, ns, dg = self._args
+        nb = lib.sparc_filter_plan_workspace_bytes(len(hams), H, ns, dg)
+        self.work = torch.empty(max(int(nb), 256), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        h = C.c_void_p()
+        _check(lib.sparc_filter_plan_create(ctx.handle, len(hams), H, X, ld, ns, dg, int(use_graph),
+                                            _ptr(self.work), self.work.numel(), C.byref(h)))
+        self.handle = h
+        self.n = len(hams)
+        self._keep = (list(hams), list(Xs))   # the plan holds raw pointers into these
+
+    def run(self, lambda_cut, lambda_max):
+        lc = _arr(C.c_double, [float(v) for v in lambda_cut])
+        lm = _arr(C.c_double, [float(v) for v in lambda_max])
+        _check(load().sparc_filter_plan_run(self.handle, lc, lm))
+
+    def close(self):
+        if self.handle:
+            load().sparc_filter_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chebyshev_filter_batched(ctx: Context, hams, Xs, degree, lambda_cut, lambda_max):
+    lib = load()
+    n_s = [x.shape[0] for x in Xs]
+    H, X, ld, ns, dg = _batch_args(hams, Xs, n_s, degree)
+    nb = lib.sparc_filter_plan_workspace_bytes(len(hams), H, ns, dg)
+    work = torch.empty(max(int(nb), 256), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+    _check(lib.chebyshev_filter_batched(ctx.handle, len(hams), H, X, ld, ns, dg,
+                                        _arr(C.c_double, [float(v) for v in lambda_cut]),
+                                        _arr(C.c_double, [float(v) for v in lambda_max]), _ptr(work), work.numel()))
+
+
+def rayleigh_ritz_batched(ctx: Context, hams, Xs, ritz, mode: int = GEMM_NATIVE, work=None):
+    lib = load()
+    n_s = [x.shape[0] for x in Xs]
+    H, X, ld, ns, _ = _batch_args(hams, Xs, n_s)
+    if work is None:
+        nb = lib.sparc_rr_batched_workspace_bytes(len(hams), H, ns)
+        work = torch.empty(max(int(nb), 256), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+    R = _arr(C.c_void_p, [r.data_ptr() for r in ritz])
+    _check(lib.rayleigh_ritz_batched(ctx.handle, len(hams), H, X, ld, ns, int(mode), R, _ptr(work), work.numel()))
+
+
+def set_autotune(ctx: Context, enable: bool):
+    _check(load().sparc_ctx_set_autotune(ctx.handle, int(bool(enable))))
 
 
 def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=None, n_o: int = 6):
