@@ -380,13 +380,19 @@ def chebyshev_filter_batched(ctx: Context, hams, Xs, degree, lambda_cut, lambda_
                                         _arr(C.c_double, [float(v) for v in lambda_max]), _ptr(work), work.numel()))
 
 
+def rr_batched_workspace(ctx: Context, hams, Xs):
+    n_s = [x.shape[0] for x in Xs]
+    H, _, _, ns, _ = _batch_args(hams, Xs, n_s)
+    nb = load().sparc_rr_batched_workspace_bytes(len(hams), H, ns)
+    return torch.empty(max(int(nb), 256), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+
+
 def rayleigh_ritz_batched(ctx: Context, hams, Xs, ritz, mode: int = GEMM_NATIVE, work=None):
     lib = load()
     n_s = [x.shape[0] for x in Xs]
     H, X, ld, ns, _ = _batch_args(hams, Xs, n_s)
     if work is None:
-        nb = lib.sparc_rr_batched_workspace_bytes(len(hams), H, ns)
-        work = torch.empty(max(int(nb), 256), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        work = rr_batched_workspace(ctx, hams, Xs)
     R = _arr(C.c_void_p, [r.data_ptr() for r in ritz])
     _check(lib.rayleigh_ritz_batched(ctx.handle, len(hams), H, X, ld, ns, int(mode), R, _ptr(work), work.numel()))
 

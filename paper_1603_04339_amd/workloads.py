@@ -135,6 +135,27 @@ def uneven_batch(n_cells: int = 24, seed=(3, 0)):
     return [int(x) for x in rng.choice([32, 48, 64, 80], size=n_cells)]
 
 
+def mp2_kpoints(L):
+    """The 8 nodes of the shifted 2x2x2 Monkhorst-Pack grid, k_s = (2 pi / L_s)(+-1/4)
+    (bohr^-1, x fastest), each of weight 1/8."""
+    ks = [(2 * math.pi / L[0] * a, 2 * math.pi / L[1] * b, 2 * math.pi / L[2] * c)
+          for c in (-0.25, 0.25) for b in (-0.25, 0.25) for a in (-0.25, 0.25)]
+    return ks, [1.0 / 8.0] * 8
+
+
+def uneven_cells(n_cells: int = 24, h: float = 0.5, seed=(3, 0), with_orbitals: bool = True):
+    """The batch of independent uneven cells: grid n drawn from {32, 48, 64, 80}
+    (uneven_batch), spacing h, atoms / states / degree from UNEVEN_SIZES; cell i
+    seeded [3, 1 + i].  Returns a list of (cell, X0, rng)."""
+    out = []
+    for i, n in enumerate(uneven_batch(n_cells, seed)):
+        na, ns, deg = UNEVEN_SIZES[n]
+        cell, rng = draw_cell(3, 1 + i, n, n * h, na, (0,), 3.0, ns, deg, 1)
+        X0 = draw_orbitals(rng, cell.n_d, ns) if with_orbitals else None
+        out.append((cell, X0, rng))
+    return out
+
+
 def lanczos_start(rng, n_d: int, complex_: bool = False):
     """Random Lanczos start vector, N(0,1)."""
     v = rng.standard_normal(n_d)
