@@ -349,6 +349,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-scf", action="store_true")
     ap.add_argument("--cpu-orbitals", type=int, default=4)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design "
@@ -360,6 +362,16 @@ def main():
     from paper_1603_04339_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": a.numel() * 4, "calib_copy_bytes_written": b.numel() * 4,
+                          "launches": 3}), flush=True)
+        return
     sp.load()
     if args.config in ("c1", "c2"):
         result = run_gamma(args, sp, wl)

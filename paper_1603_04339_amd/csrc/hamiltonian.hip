@@ -24,7 +24,8 @@ struct StepArgs {
   typedef typename elem<E>::real R;
   int n1, n2, n3;
   int tiles_x, zchunk;
-  int tiles, nz;     // tiles per plane, z chunks (batched launches)
+  int tiles, nz;     // tiles per plane, z chunks
+  int ns;            // orbitals
   int64_t ldx, ldz, ldo;
   const E* __restrict__ x;
   const E* z;
@@ -202,19 +203,41 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
   }
 }
 
+// Work-groups are dispatched round-robin over the 8 XCDs, each with its own L2.  The
+// dispatch index is renumbered so that every XCD receives one contiguous range of the
+// logical order (tiles fastest, then orbitals, then z chunks): the tiles of one
+// (orbital, z chunk) then run side by side on one XCD and read each other's halo
+// columns from its L2, and the orbitals that follow reuse the same V_eff planes.
+__device__ __forceinline__ int64_t xcd_order(int64_t L, int64_t G) {
+  const int64_t q = G >> 3, r = G & 7;
+  const int64_t xcd = L & 7, slot = L >> 3;
+  return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+template <typename E, int TX, int TY, int NO>
+__device__ __forceinline__ void hstep_local(const StepArgs<E>& A, int64_t local,
+                                            E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
+  const int tile = (int)(local % A.tiles);
+  const int64_t rest = local / A.tiles;
+  const int n = (int)(rest % A.ns);
+  const int zi = (int)(rest / A.ns);
+  hstep_body<E, TX, TY, NO>(A, tile, n, zi, plane);
+}
+
 template <typename E, int TX, int TY, int NO>
 __global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
   __shared__ E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
-  hstep_body<E, TX, TY, NO>(A, blockIdx.x, blockIdx.y, blockIdx.z, plane);
+  hstep_local<E, TX, TY, NO>(A, xcd_order(blockIdx.x, gridDim.x), plane);
 }
 
-// Several (cell, k) problems in one launch: work-group b belongs to the problem p with
-// wg_off[p] <= b < wg_off[p+1]; inside it, (orbital, z chunk, tile) with tiles fastest.
+// Several (cell, k) problems in one launch: work-group b (in XCD order) belongs to the
+// problem p with wg_off[p] <= b < wg_off[p+1]; inside it, the logical order of a
+// single-problem launch.
 template <typename E, int TX, int TY, int NO>
 __global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>* __restrict__ probs,
                                                                const int* __restrict__ wg_off, int n_probs) {
   __shared__ E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
-  const int b = blockIdx.x;
+  const int b = (int)xcd_order(blockIdx.x, gridDim.x);
   int lo = 0, hi = n_probs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) / 2;
@@ -222,12 +245,7 @@ __global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>
     else hi = mid - 1;
   }
   const StepArgs<E> A = probs[lo];
-  const int local = b - wg_off[lo];
-  const int tile = local % A.tiles;
-  const int rest = local / A.tiles;
-  const int zi = rest % A.nz;
-  const int n = rest / A.nz;
-  hstep_body<E, TX, TY, NO>(A, tile, n, zi, plane);
+  hstep_local<E, TX, TY, NO>(A, b - wg_off[lo], plane);
 }
 
 // Non-local scatter: y(g, n) += a * sum_{entries e at g} gamma_p chi~_p(g) alpha[p][n] over the
@@ -407,15 +425,16 @@ static int64_t plan_problem(StepArgs<E>& A, int tx, int ty, int no, int n_s, int
   while (base * nz < want && A.n3 / (nz * 2) >= 4 * no) nz *= 2;
   A.zchunk = (A.n3 + nz - 1) / nz;
   A.nz = (A.n3 + A.zchunk - 1) / A.zchunk;
+  A.ns = n_s;
   return (int64_t)A.tiles * A.nz * n_s;
 }
 
 template <typename E, int TX, int TY, int NO>
 static int launch_single_t(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s) {
-  plan_problem(A, TX, TY, NO, n_s, ctx->n_cu);
-  dim3 grid((unsigned)A.tiles, (unsigned)n_s, (unsigned)A.nz);
+  const int64_t G = plan_problem(A, TX, TY, NO, n_s, ctx->n_cu);
+  if (G > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "stencil step: too many work-groups");
   int t = timer_begin(ctx, "hstep");
-  hstep_kernel<E, TX, TY, NO><<<grid, TX * TY, 0, ctx->stream>>>(A);
+  hstep_kernel<E, TX, TY, NO><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
   timer_end(ctx, t);
   return check_launch("hstep_kernel");
 }

@@ -115,14 +115,15 @@ def config_cell(name: str, cell_id: int = 0, with_orbitals: bool = True):
 
 
 def scf_cell(cell_id: int, n: int = 40, L: float = 20.0, split: str = "train"):
-    """A 40^3 SCF cell with 8-32 atoms; N_s = N_atoms + max(4, ceil(N_atoms/4))
-    rounded up to a multiple of 4.  Seeds [4, cell_id]; the test split uses
-    cell ids from 100000 on."""
+    """A 40^3 SCF cell with 8-32 atoms; N_s = N_atoms + 24 rounded up to a
+    multiple of 8 (the spectrum of these cells is dense near the Fermi level, so
+    the buffer of empty states must reach ~0.07 Ha = 7 kT above it for the SCF
+    to converge to 1e-6).  Seeds [4, cell_id]; the test split uses cell ids
+    from 100000 on."""
     cid = cell_id if split == "train" else 100000 + cell_id
     rng = np.random.default_rng([4, cid])
     n_atoms = int(rng.integers(8, 33))
-    n_s = n_atoms + max(4, math.ceil(0.25 * n_atoms))
-    n_s = 4 * math.ceil(n_s / 4)
+    n_s = 8 * math.ceil((n_atoms + 24) / 8)
     cell, rng = draw_cell(4, cid, n, L, n_atoms, (0,), 3.0, n_s, 20, 4, rng=rng)
     X0 = draw_orbitals(rng, cell.n_d, n_s)
     v0 = rng.standard_normal(cell.n_d)
