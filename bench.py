@@ -140,26 +140,42 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
     }
 
 
-def scf_leg(sp, ctx, precision, tol=1e-6):
-    """Plain SCF (Slater exchange, CG Poisson, Anderson mixing) on a 40^3 cell from
-    the atomic-superposition start: wall time, iterations, free energy."""
+def scf_leg(sp, ctx, precision, tol=1e-6, learned=False):
+    """Plain SCF (Slater exchange, CG Poisson, Anderson mixing) on a held-out 40^3
+    cell: wall time, iterations, free energy.  Started from the atomic superposition,
+    or (learned=True) from the trained density network's prediction, whose
+    inference time is included in the wall time."""
     import torch
     from paper_1603_04339_amd import workloads as wl
+    from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS, cell_dV
     cell, X0, v0 = wl.scf_cell(0, split="test")
+    rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    ritz = torch.zeros(cell.n_s, dtype=torch.float64, device="cuda:0")
+    net = None
+    if learned:
+        net = sp.DensityNet(ctx, cell.n, max_batch=1)
+        net.set_params(np.load(DEFAULT_WEIGHTS))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rho0, used = None, None
+    if net is not None:
+        sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+        sp.sad_density(ctx, cell, sad)
+        rho0 = torch.zeros_like(sad)
+        used = net.predict_density(sad, cell.n_elec, cell_dV(cell), rho0)
     prm = dict(n_s=cell.n_s, degree=20, n_first_passes=4, max_iter=200, lanczos_steps=20, mix_history=7, kT=0.01,
                mix=0.3, tol=tol, n_elec=cell.n_elec, poisson_tol=1e-10,
                filt=sp.R64 if precision == "f64" else sp.R32, rr=sp.GEMM_NATIVE, final_fp64_pass=1,
-               rho_init_dev=None, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda())
-    rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
-    ritz = torch.zeros(cell.n_s, dtype=torch.float64, device="cuda:0")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+               rho_init_dev=rho0, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda())
     out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return {"wall_s": wall, "iterations": out["iterations"], "converged": bool(out["converged"]),
-            "energy": out["energy"], "n_atoms": cell.n_atoms, "grid": list(cell.n), "n_s": cell.n_s,
-            "tol": tol}
+    r = {"wall_s": wall, "iterations": out["iterations"], "converged": bool(out["converged"]),
+         "energy": out["energy"], "n_atoms": cell.n_atoms, "grid": list(cell.n), "n_s": cell.n_s, "tol": tol}
+    if net is not None:
+        r["net_used"] = used
+        net.close()
+    return r
 
 
 def run_gamma(args, sp, wl):
@@ -197,11 +213,16 @@ def run_gamma(args, sp, wl):
                      f"from the same start after {args.warmup + args.steps} passes; {n_occ} occupied states"),
         }
     if not args.no_scf:
+        from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS
         s64 = scf_leg(sp, ctx, "f64")
         s32 = scf_leg(sp, ctx, "mixed")
         result["scf"] = {"f64": s64, "mixed": s32,
                          "mixed_energy_diff_per_atom": abs(s32["energy"] - s64["energy"]) / s64["n_atoms"],
                          "note": "40^3 SCF cell (held-out seed), atomic-superposition start, density residual tol"}
+        if os.path.exists(DEFAULT_WEIGHTS):
+            sl = scf_leg(sp, ctx, "f64", learned=True)
+            result["scf"]["learned_f64"] = sl
+            result["scf"]["learned_energy_diff_per_atom"] = abs(sl["energy"] - s64["energy"]) / s64["n_atoms"]
     if not args.no_cpu_baseline:
         k = args.cpu_orbitals
         log(f"[bench] cpu baseline: oracle filter on {k} orbitals ...")

@@ -258,6 +258,57 @@ typedef struct {
 int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
                   const sparc_scf_params* params, sparc_scf_result* result);
 
+/* Superposition of atomic densities, the SCF start density (Sec. 4): rho(x) =
+ * sum_J Z_J (2 pi w_J^2)^{-3/2} exp(-|x - R_J - L|^2 / (2 w_J^2)) over the images
+ * L within 10 w_J, with w_J = atoms->vloc_width[J] and Z_J = atoms->Z[J] (2 when
+ * Z is NULL), renormalised to h^3 sum rho = n_elec.  rho_dev: device, N_d doubles
+ * (x fastest).  Synchronous.  Errors: EINVAL, ESHAPE, ENAN (no charge), ENOMEM. */
+int sparc_sad_density(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms, double n_elec,
+                      double* rho_dev);
+
+/* ---- learned initial density ------------------------------------------------------
+ * Replaces the atomic-superposition start of the SCF (Sec. 4) by
+ *   rho_0 = renorm( relu(x + d - mean(d)) * rho_bar ),  x = rho_SAD / rho_bar,  d = f(x),
+ * rho_bar = n_elec / (N_d dV), f = four 3x3x3 periodic convolutions with channels
+ * 1 -> 16 -> 32 -> 32 -> 1 and ReLU after the first three (42849 parameters, FP32).
+ * Host parameter vector, layer by layer: W[c_out][c_in][kz][ky][kx] (tap (kz, ky,
+ * kx) reads the input at offset (kz-1, ky-1, kx-1)), then b[c_out].  Batches of
+ * cells are device arrays [batch][N_d] (x fastest) of FP32.  The net owns its
+ * parameters, Adam state and activations for up to max_batch cells (1..128);
+ * calls on one net are not concurrent. */
+typedef struct sparc_dnet sparc_dnet;
+int64_t sparc_dnet_num_params(void);
+/* n: grid points per direction (1..1024).  Parameters start at zero. */
+int sparc_dnet_create(sparc_ctx* ctx, const int32_t* n, int32_t max_batch, sparc_dnet** out);
+void sparc_dnet_destroy(sparc_dnet* net);
+/* Host parameter vector in/out (sparc_dnet_num_params floats).  Setting the
+ * parameters restarts Adam. */
+int sparc_dnet_set_params(sparc_dnet* net, const float* theta);
+int sparc_dnet_get_params(const sparc_dnet* net, float* theta);
+/* x_dev (FP32, N_d) = rho_dev / rho_bar: the network's input and target scaling. */
+int sparc_dnet_scale_density(sparc_dnet* net, const double* rho_dev, double n_elec, double dV, float* x_dev);
+/* Raw network output d = f(x) for `batch` cells (d_dev: batch * N_d floats). */
+int sparc_dnet_forward(sparc_dnet* net, const float* x_dev, int32_t batch, float* d_dev);
+/* Loss L = mean over cells and points of (relu(x + d - mean(d)) - y)^2 and its
+ * gradient (kept on the device for sparc_dnet_adam_step; also copied to grad_host,
+ * in the host parameter layout, when that is not NULL).  Synchronous.  ENAN for a
+ * non-finite loss. */
+int sparc_dnet_loss_grad(sparc_dnet* net, const float* x_dev, const float* y_dev, int32_t batch, double* loss,
+                         float* grad_host);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the last
+ * gradient. */
+int sparc_dnet_adam_step(sparc_dnet* net, double lr);
+/* loss_grad followed by adam_step. */
+int sparc_dnet_train_step(sparc_dnet* net, const float* x_dev, const float* y_dev, int32_t batch, double lr,
+                          double* loss);
+/* Learned start density of one cell from its atomic superposition (device FP64,
+ * N_d); rho_dev receives rho_0 (FP64, h^3 sum = n_elec).  Falls back to a copy
+ * of rho_sad_dev, with *used_net = 0, when any value is not finite or the charge
+ * before renormalisation differs from n_elec by more than charge_tol * n_elec.
+ * Synchronous. */
+int sparc_dnet_predict_density(sparc_dnet* net, const double* rho_sad_dev, double n_elec, double dV,
+                               double charge_tol, double* rho_dev, int32_t* used_net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -193,7 +193,7 @@ int sparc_filter_plan_create(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H
   int big = 0;
   for (int p = 1; p < n_prob; ++p)
     if ((double)H[p]->n_d * n_s[p] > (double)H[big]->n_d * n_s[big]) big = p;
-  P->tile = heuristic_tile(H[big]->grid.n[0], H[big]->grid.n[1]);
+  P->tile = heuristic_tile(H[big]->grid.n[0], H[big]->grid.n[1], elem_bytes(P->dt));
   if (ctx->autotune) {
     int t;
     if (!tuned_tile(H[big], n_s[big], &t)) {

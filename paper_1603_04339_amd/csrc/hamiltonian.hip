@@ -1,252 +1,16 @@
-// Application of the finite-difference Hamiltonian to a block of orbitals:
-// the fused stencil + local potential + non-local scatter step that every H*X,
-// Chebyshev recurrence step and Lanczos step runs, and the non-local gather
-// (projections of the orbitals onto the Kleinman-Bylander projectors).
-//
-// Stencil step (one work-group = one TX x TY column tile of one orbital, a
-// chunk of z planes): the tile streams along z.  Each thread keeps the 2*NO+1
-// values of its own (x, y) column around the current plane in registers
-// (z-direction taps); the current plane, with NO-wide x and y halos, is staged
-// in LDS (double-buffered, one barrier per plane) for the x and y taps.  Loads
-// are x-fastest and coalesced; nodes outside the cell are fetched from their
-// periodic image with the Bloch factor e^{i k_s L_s w}.
+// Application of the finite-difference Hamiltonian to a block of orbitals: the
+// non-local gather (projections of the orbitals onto the Kleinman-Bylander
+// projectors) and scatter kernels, the stencil-step launch logic (tile choice,
+// autotuner, batched step tables) and the H*X entry point.  The stencil step
+// kernels themselves are in hstep_impl.hpp.
 #include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
 
-#include "devmath.hpp"
+#include "hstep_api.hpp"
 
 namespace sparc {
-
-template <typename E>
-struct StepArgs {
-  typedef typename elem<E>::real R;
-  int n1, n2, n3;
-  int tiles_x, zchunk;
-  int tiles, nz;     // tiles per plane, z chunks
-  int ns;            // orbitals
-  int64_t ldx, ldz, ldo;
-  const E* __restrict__ x;
-  const E* z;
-  E* out;
-  const R* __restrict__ veff;
-  R centre;        // a * centre coefficient of -1/2 Lap_h
-  R tx[8], ty[8], tz[8];
-  R va, vb, zc;    // out = lap*a + (a V + b) x + zc z
-  double kl[3];    // k_s L_s
-};
-
-template <typename E>
-__device__ __forceinline__ void bloch_factor(const double* kl, int wx, int wy, int wz, typename elem<E>::real& c,
-                                             typename elem<E>::real& s) {
-  if constexpr (elem<E>::is_cplx) {
-    double th = kl[0] * wx + kl[1] * wy + kl[2] * wz;
-    if (th == 0.0) {
-      c = 1;
-      s = 0;
-    } else {
-      double sn, cs;
-      sincos(th, &sn, &cs);
-      c = (typename elem<E>::real)cs;
-      s = (typename elem<E>::real)sn;
-    }
-  } else {
-    c = 1;
-    s = 0;
-  }
-}
-
-template <typename E, int TX, int TY, int NO>
-__device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n, int zi,
-                                           E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
-  typedef typename elem<E>::real R;
-  constexpr int NT = TX * TY;
-  constexpr int PX = TX + 2 * NO;
-  constexpr int HC = 2 * NO * (TX + TY);         // halo cells of one plane (no corners)
-  constexpr int HM = (HC + NT - 1) / NT;         // halo cells per thread
-
-  const int tid = threadIdx.x;
-  const int hx = tid % TX, hy = tid / TX;
-  const int x0 = (tile % A.tiles_x) * TX, y0 = (tile / A.tiles_x) * TY;
-  const int zb = zi * A.zchunk;
-  const int ze = min(A.n3, zb + A.zchunk);
-  const int n1 = A.n1, n2 = A.n2, n3 = A.n3;
-  const int64_t plane_sz = (int64_t)n1 * n2;
-
-  const E* __restrict__ xc = A.x + (int64_t)n * A.ldx;
-  // own column: extended coordinates, periodic source and Bloch factor in x, y
-  const int ex = x0 + hx, ey = y0 + hy;
-  const int wx = floordiv_i(ex, n1), wy = floordiv_i(ey, n2);
-  const int col = (ex - wx * n1) + n1 * (ey - wy * n2);
-  const bool inside = (ex < n1) && (ey < n2);
-  R cxy = 1, sxy = 0;
-  bloch_factor<E>(A.kl, wx, wy, 0, cxy, sxy);
-  const int own = (hy + NO) * PX + hx + NO;
-
-  // halo cells owned by this thread: LDS slot, offset inside a plane, Bloch factor
-  int h_lds[HM], h_off[HM];
-  R h_c[HM], h_s[HM];
-#pragma unroll
-  for (int u = 0; u < HM; ++u) {
-    const int c = tid + u * NT;
-    h_lds[u] = -1;
-    h_off[u] = 0;
-    h_c[u] = 1;
-    h_s[u] = 0;
-    if (c < HC) {
-      int cx, cy;
-      if (c < 2 * NO * TY) {  // x strips
-        const int r = c / (2 * NO), k = c % (2 * NO);
-        cy = r;
-        cx = (k < NO) ? (k - NO) : (TX + k - NO);
-      } else {  // y strips
-        const int c2 = c - 2 * NO * TY;
-        const int r = c2 / TX, k = c2 % TX;
-        cx = k;
-        cy = (r < NO) ? (r - NO) : (TY + r - NO);
-      }
-      const int gx = x0 + cx, gy = y0 + cy;
-      const int hwx = floordiv_i(gx, n1), hwy = floordiv_i(gy, n2);
-      h_off[u] = (gx - hwx * n1) + n1 * (gy - hwy * n2);
-      h_lds[u] = (cy + NO) * PX + cx + NO;
-      bloch_factor<E>(A.kl, hwx, hwy, 0, h_c[u], h_s[u]);
-    }
-  }
-
-  // z-direction register queue q[d] = x(column, z - NO + d); the plane index of the
-  // next load and its number of cell wraps are advanced without divisions
-  int zl = zb - NO;
-  int wz = floordiv_i(zl, n3);
-  int sz = zl - wz * n3;
-  auto load_next = [&]() -> E {
-    E v = xc[col + plane_sz * sz];
-    if constexpr (elem<E>::is_cplx) {
-      if (wz != 0 || cxy != 1 || sxy != 0) {
-        R c = cxy, s = sxy;
-        if (wz != 0) {
-          R cz, szn;
-          bloch_factor<E>(A.kl, wx, wy, wz, cz, szn);
-          c = cz;
-          s = szn;
-        }
-        v = rot(v, c, s);
-      }
-    }
-    if (++sz == n3) {
-      sz = 0;
-      ++wz;
-    }
-    return v;
-  };
-
-  E q[2 * NO + 1];
-#pragma unroll
-  for (int d = 0; d < 2 * NO; ++d) q[d] = load_next();
-
-  // software pipeline: the column value and halo cells of plane z+1 are loaded while
-  // plane z is computed (their latency is hidden behind one plane of work)
-  const E* __restrict__ pz = xc + plane_sz * zb;
-  E qn = load_next();
-  E hn[HM];
-#pragma unroll
-  for (int u = 0; u < HM; ++u) {
-    hn[u] = zero<E>();
-    if (h_lds[u] >= 0 && zb < ze) hn[u] = pz[h_off[u]];
-  }
-  int64_t g = col + plane_sz * zb;
-  const R* __restrict__ vp = A.veff;
-  const E* __restrict__ zp = A.z ? A.z + (int64_t)n * A.ldz : nullptr;
-  E* __restrict__ op = A.out + (int64_t)n * A.ldo;
-  int step = 0;
-  for (int z = zb; z < ze; ++z, ++step, g += plane_sz) {
-    q[2 * NO] = qn;
-    E* __restrict__ pl = plane[step & 1];
-    pl[own] = q[NO];
-#pragma unroll
-    for (int u = 0; u < HM; ++u) {
-      if (h_lds[u] >= 0) {
-        E v = hn[u];
-        if constexpr (elem<E>::is_cplx) v = rot(v, h_c[u], h_s[u]);
-        pl[h_lds[u]] = v;
-      }
-    }
-    // issue the loads of the next plane and of this plane's point data
-    pz += plane_sz;
-    if (z + 1 < ze) {
-      qn = load_next();
-#pragma unroll
-      for (int u = 0; u < HM; ++u)
-        if (h_lds[u] >= 0) hn[u] = pz[h_off[u]];
-    }
-    R v = 0;
-    E zv = zero<E>();
-    if (inside) {
-      v = vp[g];
-      if (zp) zv = nt_load(zp + g);
-    }
-    __syncthreads();
-    if (inside) {
-      E lap = scale(A.centre, q[NO]);
-#pragma unroll
-      for (int p = 1; p <= NO; ++p) {
-        lap = fmar(lap, A.tz[p - 1], q[NO + p] + q[NO - p]);
-        lap = fmar(lap, A.tx[p - 1], pl[own + p] + pl[own - p]);
-        lap = fmar(lap, A.ty[p - 1], pl[own + p * PX] + pl[own - p * PX]);
-      }
-      E r = fmar(lap, (R)(A.va * v + A.vb), q[NO]);
-      if (zp) r = fmar(r, A.zc, zv);
-      nt_store(r, op + g);
-    }
-#pragma unroll
-    for (int d = 0; d < 2 * NO; ++d) q[d] = q[d + 1];
-  }
-}
-
-// Work-groups are dispatched round-robin over the 8 XCDs, each with its own L2.  The
-// dispatch index is renumbered so that every XCD receives one contiguous range of the
-// logical order (tiles fastest, then orbitals, then z chunks): the tiles of one
-// (orbital, z chunk) then run side by side on one XCD and read each other's halo
-// columns from its L2, and the orbitals that follow reuse the same V_eff planes.
-__device__ __forceinline__ int64_t xcd_order(int64_t L, int64_t G) {
-  const int64_t q = G >> 3, r = G & 7;
-  const int64_t xcd = L & 7, slot = L >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + slot;
-}
-
-template <typename E, int TX, int TY, int NO>
-__device__ __forceinline__ void hstep_local(const StepArgs<E>& A, int64_t local,
-                                            E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
-  const int tile = (int)(local % A.tiles);
-  const int64_t rest = local / A.tiles;
-  const int n = (int)(rest % A.ns);
-  const int zi = (int)(rest / A.ns);
-  hstep_body<E, TX, TY, NO>(A, tile, n, zi, plane);
-}
-
-template <typename E, int TX, int TY, int NO>
-__global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
-  __shared__ E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
-  hstep_local<E, TX, TY, NO>(A, xcd_order(blockIdx.x, gridDim.x), plane);
-}
-
-// Several (cell, k) problems in one launch: work-group b (in XCD order) belongs to the
-// problem p with wg_off[p] <= b < wg_off[p+1]; inside it, the logical order of a
-// single-problem launch.
-template <typename E, int TX, int TY, int NO>
-__global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>* __restrict__ probs,
-                                                               const int* __restrict__ wg_off, int n_probs) {
-  __shared__ E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
-  const int b = (int)xcd_order(blockIdx.x, gridDim.x);
-  int lo = 0, hi = n_probs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) / 2;
-    if (wg_off[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  const StepArgs<E> A = probs[lo];
-  hstep_local<E, TX, TY, NO>(A, b - wg_off[lo], plane);
-}
 
 // Non-local scatter: y(g, n) += a * sum_{entries e at g} gamma_p chi~_p(g) alpha[p][n] over the
 // nodes that carry projector support (point-major CSR).  One thread per node and
@@ -385,15 +149,7 @@ int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alph
   return fail(SPARC_EINVAL, "nl_project: bad dtype");
 }
 
-// ------------------------------------------------------------ launch planning
-// Tile shapes (TX x TY threads).  Without autotuning the choice is the shape with
-// the least idle work (tiles that divide n1, n2) weighted by its halo overhead;
-// SPARC_HSTEP_TILE (an index into this list) overrides it.
-struct TileShape { int tx, ty; };
-static const TileShape kTiles[] = {{32, 8}, {32, 16}, {64, 4}, {64, 8}, {16, 16}, {24, 8}, {48, 8}, {32, 32}};
-constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
-
-int heuristic_tile(int n1, int n2) {
+int heuristic_tile(int n1, int n2, size_t /*elem_size*/) {
   const char* env = getenv("SPARC_HSTEP_TILE");
   if (env) {
     int t = atoi(env);
@@ -410,86 +166,6 @@ int heuristic_tile(int n1, int n2) {
     if (cost < best_cost - 1e-12) { best_cost = cost; best = t; }
   }
   return best;
-}
-
-// per-problem grid bookkeeping for a tile shape; returns the number of work-groups
-template <typename E>
-static int64_t plan_problem(StepArgs<E>& A, int tx, int ty, int no, int n_s, int n_cu) {
-  A.tiles_x = (A.n1 + tx - 1) / tx;
-  const int tiles_y = (A.n2 + ty - 1) / ty;
-  A.tiles = A.tiles_x * tiles_y;
-  // z chunks: enough work-groups to fill the chip, at least 4 n_o planes per chunk
-  const int64_t base = (int64_t)A.tiles * n_s;
-  int nz = 1;
-  const int64_t want = 8 * (int64_t)n_cu;
-  while (base * nz < want && A.n3 / (nz * 2) >= 4 * no) nz *= 2;
-  A.zchunk = (A.n3 + nz - 1) / nz;
-  A.nz = (A.n3 + A.zchunk - 1) / A.zchunk;
-  A.ns = n_s;
-  return (int64_t)A.tiles * A.nz * n_s;
-}
-
-template <typename E, int TX, int TY, int NO>
-static int launch_single_t(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s) {
-  const int64_t G = plan_problem(A, TX, TY, NO, n_s, ctx->n_cu);
-  if (G > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "stencil step: too many work-groups");
-  int t = timer_begin(ctx, "hstep");
-  hstep_kernel<E, TX, TY, NO><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
-  timer_end(ctx, t);
-  return check_launch("hstep_kernel");
-}
-
-template <typename E, int TX, int TY, int NO>
-static int launch_batched_t(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total_wg) {
-  if (total_wg <= 0) return SPARC_OK;
-  if (total_wg > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "batched step: too many work-groups");
-  int t = timer_begin(ctx, "hstep");
-  hstep_batched_kernel<E, TX, TY, NO><<<(unsigned)total_wg, TX * TY, 0, ctx->stream>>>(
-      (const StepArgs<E>*)dprobs, dwg, n_probs);
-  timer_end(ctx, t);
-  return check_launch("hstep_batched_kernel");
-}
-
-// run `F::template run<TX, TY>()` for tile index t
-#define SPARC_TILE_SWITCH(t, CALL)        \
-  switch (t) {                            \
-    case 0: return CALL(32, 8);           \
-    case 1: return CALL(32, 16);          \
-    case 2: return CALL(64, 4);           \
-    case 3: return CALL(64, 8);           \
-    case 4: return CALL(16, 16);          \
-    case 5: return CALL(24, 8);           \
-    case 6: return CALL(48, 8);           \
-    default: return CALL(32, 32);         \
-  }
-
-template <typename E, int NO>
-static int single_tile(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int t) {
-#define CALL(tx, ty) launch_single_t<E, tx, ty, NO>(ctx, A, n_s)
-  SPARC_TILE_SWITCH(t, CALL)
-#undef CALL
-}
-
-template <typename E>
-static int single_no(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int no, int t) {
-  switch (no) {
-    case 1: return single_tile<E, 1>(ctx, A, n_s, t);
-    case 2: return single_tile<E, 2>(ctx, A, n_s, t);
-    case 3: return single_tile<E, 3>(ctx, A, n_s, t);
-    case 4: return single_tile<E, 4>(ctx, A, n_s, t);
-    case 5: return single_tile<E, 5>(ctx, A, n_s, t);
-    case 6: return single_tile<E, 6>(ctx, A, n_s, t);
-    case 7: return single_tile<E, 7>(ctx, A, n_s, t);
-    case 8: return single_tile<E, 8>(ctx, A, n_s, t);
-  }
-  return fail(SPARC_EINVAL, "ham_step: n_o=%d unsupported", no);
-}
-
-template <typename E, int NO>
-static int batched_tile(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total, int t) {
-#define CALL(tx, ty) launch_batched_t<E, tx, ty, NO>(ctx, dprobs, dwg, n_probs, total)
-  SPARC_TILE_SWITCH(t, CALL)
-#undef CALL
 }
 
 // ------------------------------------------------------------ autotuner
@@ -521,16 +197,16 @@ static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best) {
   const bool timing = ctx->timing;
   ctx->timing = false;
   float best_ms = 1e30f;
-  *best = heuristic_tile(A.n1, A.n2);
+  *best = heuristic_tile(A.n1, A.n2, sizeof(E));
   int rc = SPARC_OK;
   for (int t = 0; t < kNumTiles && rc == SPARC_OK; ++t) {
     if (kTiles[t].tx * kTiles[t].ty > 1024) continue;
     StepArgs<E> B = A;
-    rc = single_no<E>(ctx, B, n_s, H->grid.n_o, t);  // warm-up
+    rc = hstep_single<E>(ctx, B, n_s, H->grid.n_o, t);  // warm-up
     if (rc != SPARC_OK) break;
     hipEventRecord(e0, ctx->stream);
     B = A;
-    rc = single_no<E>(ctx, B, n_s, H->grid.n_o, t);
+    rc = hstep_single<E>(ctx, B, n_s, H->grid.n_o, t);
     hipEventRecord(e1, ctx->stream);
     if (rc != SPARC_OK) break;
     hipEventSynchronize(e1);
@@ -598,9 +274,9 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   A.vb = (R)b;
   A.zc = (R)c;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
-  int t = heuristic_tile(A.n1, A.n2);
+  int t = heuristic_tile(A.n1, A.n2, sizeof(E));
   if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && z == nullptr && out != x) SPARC_TRY(autotune(H, A, n_s, &t));
-  int rc = single_no<E>(H->ctx, A, n_s, H->grid.n_o, t);
+  int rc = hstep_single<E>(H->ctx, A, n_s, H->grid.n_o, t);
   if (rc != SPARC_OK || H->n_proj == 0 || H->n_nlpts == 0 || (flags & STEP_NO_NONLOCAL)) return rc;
   if (!alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
   return nl_scatter(H, alpha, n_s, a, nullptr, out, ldo);
@@ -666,28 +342,13 @@ int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile
   return -1;
 }
 
-template <typename E>
-static int launch_tab_t(sparc_ctx* ctx, int no, int tile, const void* table, const int* wg, int n, int64_t total) {
-  switch (no) {
-    case 1: return batched_tile<E, 1>(ctx, table, wg, n, total, tile);
-    case 2: return batched_tile<E, 2>(ctx, table, wg, n, total, tile);
-    case 3: return batched_tile<E, 3>(ctx, table, wg, n, total, tile);
-    case 4: return batched_tile<E, 4>(ctx, table, wg, n, total, tile);
-    case 5: return batched_tile<E, 5>(ctx, table, wg, n, total, tile);
-    case 6: return batched_tile<E, 6>(ctx, table, wg, n, total, tile);
-    case 7: return batched_tile<E, 7>(ctx, table, wg, n, total, tile);
-    case 8: return batched_tile<E, 8>(ctx, table, wg, n, total, tile);
-  }
-  return fail(SPARC_EINVAL, "batched step: n_o=%d unsupported", no);
-}
-
 int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
                       int n, int64_t total) {
   switch (dt) {
-    case SPARC_R64: return launch_tab_t<double>(ctx, no, tile, dev_table, dev_wg, n, total);
-    case SPARC_R32: return launch_tab_t<float>(ctx, no, tile, dev_table, dev_wg, n, total);
-    case SPARC_C128: return launch_tab_t<cd>(ctx, no, tile, dev_table, dev_wg, n, total);
-    case SPARC_C64: return launch_tab_t<cf>(ctx, no, tile, dev_table, dev_wg, n, total);
+    case SPARC_R64: return hstep_batched<double>(ctx, dev_table, dev_wg, n, total, no, tile);
+    case SPARC_R32: return hstep_batched<float>(ctx, dev_table, dev_wg, n, total, no, tile);
+    case SPARC_C128: return hstep_batched<cd>(ctx, dev_table, dev_wg, n, total, no, tile);
+    case SPARC_C64: return hstep_batched<cf>(ctx, dev_table, dev_wg, n, total, no, tile);
   }
   return fail(SPARC_EINVAL, "batched step: bad dtype");
 }

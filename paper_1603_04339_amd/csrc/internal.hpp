@@ -137,7 +137,7 @@ int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ld
 int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha);
 //   out += a * V_nl-scatter(alpha); a from a device scalar when a_dev != nullptr
 int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out, int64_t ldo);
-int heuristic_tile(int n1, int n2);
+int heuristic_tile(int n1, int n2, size_t elem_size);
 // batched stencil steps over several Hamiltonians (same dtype and n_o): a host table of
 // per-problem step arguments and work-group offsets is built, uploaded by the caller, and
 // launched as one kernel

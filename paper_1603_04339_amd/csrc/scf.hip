@@ -358,9 +358,61 @@ static double host_scalar(hipStream_t s, const double* d) {
   return h;
 }
 
+// Superposition of atomic densities (the SCF start of Sec. 4), renormalised so that
+// h^3 sum rho = n_elec; part: RED_BLOCKS doubles, sc: 8 doubles of scratch.
+// Synchronous (the renormalisation factor is read back to the host).
+static int sad_fill(hipStream_t s, Buffers& B, const sparc_grid* grid, const sparc_atoms* atoms, double n_elec,
+                    double* rho_in, double* part, double* sc) {
+  const int64_t n = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+  const double h1 = grid->L[0] / grid->n[0], h2 = grid->L[1] / grid->n[1], h3 = grid->L[2] / grid->n[2];
+  const double dV = h1 * h2 * h3;
+  std::vector<double> R(3 * atoms->n_atoms), W(atoms->n_atoms), Z(atoms->n_atoms);
+  for (int a = 0; a < atoms->n_atoms; ++a) {
+    for (int c = 0; c < 3; ++c) R[3 * a + c] = atoms->R[3 * a + c];
+    W[a] = atoms->vloc_width[a];
+    Z[a] = atoms->Z ? atoms->Z[a] : 2.0;
+  }
+  double *dR, *dW, *dZ;
+  SPARC_TRY(B.alloc(&dR, R.size()));
+  SPARC_TRY(B.alloc(&dW, W.size()));
+  SPARC_TRY(B.alloc(&dZ, Z.size()));
+  SPARC_HIP(hipMemcpyAsync(dR, R.data(), R.size() * 8, hipMemcpyHostToDevice, s));
+  SPARC_HIP(hipMemcpyAsync(dW, W.data(), W.size() * 8, hipMemcpyHostToDevice, s));
+  SPARC_HIP(hipMemcpyAsync(dZ, Z.data(), Z.size() * 8, hipMemcpyHostToDevice, s));
+  sad_kernel<<<GRID1(n)>>>(grid->n[0], grid->n[1], grid->n[2], h1, h2, h3, grid->L[0], grid->L[1], grid->L[2],
+                           atoms->n_atoms, dR, dW, dZ, rho_in);
+  SPARC_TRY(check_launch("sad_kernel"));
+  SPARC_TRY(reduce(s, n, rho_in, nullptr, RED_SUM, part, sc + 5));
+  // rho *= N_e / (dV * sum rho)
+  double tot = host_scalar(s, sc + 5);   // synchronises the stream (the host vectors stay valid)
+  if (!(tot > 0)) return fail(SPARC_ENAN, "atomic superposition has no charge");
+  double f = n_elec / (dV * tot);
+  std::vector<double> one{f, 1.0};
+  SPARC_HIP(hipMemcpyAsync(sc + 6, one.data(), 16, hipMemcpyHostToDevice, s));
+  scale_ratio_kernel<<<GRID1(n)>>>(n, rho_in, sc + 6, sc + 7, 1.0);
+  SPARC_HIP(hipStreamSynchronize(s));
+  return check_launch("scale_ratio_kernel");
+}
+
 }  // namespace sparc
 
 using namespace sparc;
+
+extern "C" int sparc_sad_density(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms, double n_elec,
+                                 double* rho_dev) {
+  if (!ctx || !grid || !atoms || !rho_dev) return fail(SPARC_EINVAL, "sparc_sad_density: null argument");
+  if (atoms->n_atoms < 1 || !atoms->R || !atoms->vloc_width)
+    return fail(SPARC_EINVAL, "sparc_sad_density: needs at least one atom with positions and widths");
+  for (int s3 = 0; s3 < 3; ++s3)
+    if (grid->n[s3] < 1 || !(grid->L[s3] > 0)) return fail(SPARC_ESHAPE, "sparc_sad_density: bad grid");
+  if (!(n_elec > 0)) return fail(SPARC_EINVAL, "sparc_sad_density: n_elec must be positive");
+  Buffers B;
+  double *part, *sc;
+  SPARC_TRY(B.alloc(&part, RED_BLOCKS));
+  SPARC_TRY(B.alloc(&sc, 16));
+  hipStream_t s = ctx->stream;
+  return sad_fill(s, B, grid, atoms, n_elec, rho_dev, part, sc);
+}
 
 extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
                              const sparc_scf_params* P, sparc_scf_result* res) {
@@ -439,32 +491,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
   if (P->rho_init_dev) {
     SPARC_HIP(hipMemcpyAsync(rho_in, P->rho_init_dev, n * 8, hipMemcpyDeviceToDevice, s));
   } else {
-    std::vector<double> R(3 * atoms->n_atoms), W(atoms->n_atoms), Z(atoms->n_atoms);
-    for (int a = 0; a < atoms->n_atoms; ++a) {
-      for (int c = 0; c < 3; ++c) R[3 * a + c] = atoms->R[3 * a + c];
-      W[a] = atoms->vloc_width[a];
-      Z[a] = atoms->Z ? atoms->Z[a] : 2.0;
-    }
-    double *dR, *dW, *dZ;
-    SPARC_TRY(B.alloc(&dR, R.size()));
-    SPARC_TRY(B.alloc(&dW, W.size()));
-    SPARC_TRY(B.alloc(&dZ, Z.size()));
-    SPARC_HIP(hipMemcpy(dR, R.data(), R.size() * 8, hipMemcpyHostToDevice));
-    SPARC_HIP(hipMemcpy(dW, W.data(), W.size() * 8, hipMemcpyHostToDevice));
-    SPARC_HIP(hipMemcpy(dZ, Z.data(), Z.size() * 8, hipMemcpyHostToDevice));
-    sad_kernel<<<GRID1(n)>>>(grid->n[0], grid->n[1], grid->n[2], H64->h[0], H64->h[1], H64->h[2], grid->L[0],
-                             grid->L[1], grid->L[2], atoms->n_atoms, dR, dW, dZ, rho_in);
-    SPARC_TRY(check_launch("sad_kernel"));
-    SPARC_TRY(reduce(s, n, rho_in, nullptr, RED_SUM, part, sc + 5));
-    // rho *= N_e / (dV * sum rho)
-    double tot = host_scalar(s, sc + 5);
-    if (!(tot > 0)) return fail(SPARC_ENAN, "sparc_scf_run: atomic superposition has no charge");
-    double f = P->n_elec / (dV * tot);
-    std::vector<double> one(1, f);
-    SPARC_HIP(hipMemcpy(sc + 6, one.data(), 8, hipMemcpyHostToDevice));
-    one[0] = 1.0;
-    SPARC_HIP(hipMemcpy(sc + 7, one.data(), 8, hipMemcpyHostToDevice));
-    scale_ratio_kernel<<<GRID1(n)>>>(n, rho_in, sc + 6, sc + 7, 1.0);
+    SPARC_TRY(sad_fill(s, B, grid, atoms, P->n_elec, rho_in, part, sc));
   }
   SPARC_HIP(hipMemcpyAsync(X, P->x0_dev, (size_t)n * ns * 8, hipMemcpyDeviceToDevice, s));
   SPARC_HIP(hipMemsetAsync(vh, 0, n * 8, s));

@@ -103,6 +103,21 @@ _SIGS = {
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int, C.POINTER(C.c_void_p),
                                         C.c_void_p, C.c_size_t]),
     "sparc_ctx_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
+    "sparc_sad_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "sparc_dnet_num_params": (C.c_int64, []),
+    "sparc_dnet_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_void_p)]),
+    "sparc_dnet_destroy": (None, [C.c_void_p]),
+    "sparc_dnet_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sparc_dnet_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sparc_dnet_scale_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
+    "sparc_dnet_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "sparc_dnet_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                       C.c_void_p]),
+    "sparc_dnet_adam_step": (C.c_int, [C.c_void_p, C.c_double]),
+    "sparc_dnet_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                                        C.POINTER(C.c_double)]),
+    "sparc_dnet_predict_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                             C.POINTER(C.c_int32)]),
     "sparc_scf_run": (C.c_int, [C.c_void_p, C.POINTER(sparc_grid), C.POINTER(sparc_atoms),
                                 C.POINTER(sparc_scf_params), C.POINTER(sparc_scf_result)]),
 }
@@ -424,3 +439,80 @@ def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=Non
     if st not in (OK, ENOCONV):
         _check(st)
     return out
+
+
+def sad_density(ctx: Context, cell, rho_out, n_o: int = 6):
+    """Atomic-superposition density of a cell into rho_out (device FP64, N_d)."""
+    grid = make_grid(cell.n, cell.L, n_o)
+    atoms = _Atoms(cell)
+    _check(load().sparc_sad_density(ctx.handle, C.byref(grid), C.byref(atoms.struct), float(cell.n_elec),
+                                    _ptr(rho_out)))
+    return rho_out
+
+
+class DensityNet:
+    """Learned initial density (sparc_dnet): FP32 3-D conv net on one grid shape."""
+
+    def __init__(self, ctx: Context, n, max_batch: int = 1):
+        lib = load()
+        self.ctx = ctx
+        self.n = tuple(int(v) for v in n)
+        self.n_d = self.n[0] * self.n[1] * self.n[2]
+        self.num_params = int(lib.sparc_dnet_num_params())
+        h = C.c_void_p()
+        _check(lib.sparc_dnet_create(ctx.handle, (C.c_int32 * 3)(*self.n), int(max_batch), C.byref(h)))
+        self.handle = h
+
+    def set_params(self, theta):
+        t = np.ascontiguousarray(theta, dtype=np.float32)
+        if t.size != self.num_params:
+            raise ValueError(f"expected {self.num_params} parameters, got {t.size}")
+        _check(load().sparc_dnet_set_params(self.handle, t.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self):
+        t = np.zeros(self.num_params, dtype=np.float32)
+        _check(load().sparc_dnet_get_params(self.handle, t.ctypes.data_as(C.c_void_p)))
+        return t
+
+    def scale_density(self, rho, n_elec: float, dV: float, x_out):
+        _check(load().sparc_dnet_scale_density(self.handle, _ptr(rho), float(n_elec), float(dV), _ptr(x_out)))
+        return x_out
+
+    def forward(self, x, d_out):
+        B = x.numel() // self.n_d
+        _check(load().sparc_dnet_forward(self.handle, _ptr(x), B, _ptr(d_out)))
+        return d_out
+
+    def loss_grad(self, x, y, want_grad: bool = True):
+        B = x.numel() // self.n_d
+        loss = C.c_double()
+        g = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
+        _check(load().sparc_dnet_loss_grad(self.handle, _ptr(x), _ptr(y), B, C.byref(loss),
+                                           g.ctypes.data_as(C.c_void_p) if want_grad else None))
+        return loss.value, g
+
+    def adam_step(self, lr: float):
+        _check(load().sparc_dnet_adam_step(self.handle, float(lr)))
+
+    def train_step(self, x, y, lr: float):
+        B = x.numel() // self.n_d
+        loss = C.c_double()
+        _check(load().sparc_dnet_train_step(self.handle, _ptr(x), _ptr(y), B, float(lr), C.byref(loss)))
+        return loss.value
+
+    def predict_density(self, rho_sad, n_elec: float, dV: float, rho_out, charge_tol: float = 1e-2):
+        used = C.c_int32()
+        _check(load().sparc_dnet_predict_density(self.handle, _ptr(rho_sad), float(n_elec), float(dV),
+                                                 float(charge_tol), _ptr(rho_out), C.byref(used)))
+        return bool(used.value)
+
+    def close(self):
+        if self.handle:
+            load().sparc_dnet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,176 @@
+"""GPU learned-density kernels (sparc_dnet_*, sparc_sad_density) against the
+FP64 oracle: atomic superposition (1e-12), network output (FP32 vs FP64,
+2e-5 of the output scale), loss (1e-5 relative) and gradient (2e-4 of the
+largest component), the first Adam step, the prediction with its charge
+renormalisation and SAD fallback, and a short training run that must lower
+the loss.  The effect of the trained network on the SCF is tested in
+test_gpu_learned_start.py."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import density_net as dn
+from oracle.fd import Grid
+from oracle.scf import sad_density
+from paper_1603_04339_amd import sparc as sp
+from paper_1603_04339_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+N = (10, 12, 14)      # (n1, n2, n3): x fastest; oracle arrays are (n3, n2, n1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+def _theta(seed):
+    rng = np.random.default_rng(seed)
+    th = dn.init_params(rng)
+    th += 0.02 * rng.standard_normal(th.size)
+    return th.astype(np.float32).astype(np.float64)   # exactly representable on both sides
+
+
+def _fields(seed, B):
+    rng = np.random.default_rng(seed)
+    xs = [np.abs(rng.standard_normal((N[2], N[1], N[0]))) * 1.5 for _ in range(B)]
+    ys = [np.maximum(x + 0.3 * rng.standard_normal(x.shape), 0.0) for x in xs]
+    xs = [x.astype(np.float32).astype(np.float64) for x in xs]
+    ys = [y.astype(np.float32).astype(np.float64) for y in ys]
+    return xs, ys
+
+
+def _dev(arrs):
+    return torch.from_numpy(np.stack(arrs).astype(np.float32).reshape(-1)).cuda()
+
+
+def test_sad_density_matches_oracle(ctx):
+    cell, _, _ = wl.scf_cell(3, n=24, L=12.0)
+    rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    sp.sad_density(ctx, cell, rho)
+    grid = Grid(n=cell.n, L=cell.L)
+    ref = sad_density(grid, cell.positions, cell.width, cell.Z, cell.n_elec)
+    np.testing.assert_allclose(rho.cpu().numpy(), ref, rtol=1e-12, atol=1e-14 * ref.max())
+
+
+def test_forward_matches_oracle(ctx):
+    th = _theta(1)
+    xs, _ = _fields(2, 2)
+    net = sp.DensityNet(ctx, N, max_batch=2)
+    net.set_params(th)
+    np.testing.assert_array_equal(net.get_params(), th.astype(np.float32))
+    d = torch.zeros(2 * np.prod(N), dtype=torch.float32, device="cuda:0")
+    net.forward(_dev(xs), d)
+    got = d.cpu().numpy().reshape(2, N[2], N[1], N[0])
+    for b in range(2):
+        _, (_, a, _) = dn.forward(th, xs[b])
+        ref = a[-1][0]
+        err = np.abs(got[b] - ref).max() / np.abs(ref).max()
+        print(f"forward cell {b}: max rel err {err:.2e}")
+        assert err < 2e-5
+
+
+def test_loss_grad_matches_oracle(ctx):
+    th = _theta(3)
+    xs, ys = _fields(4, 2)
+    net = sp.DensityNet(ctx, N, max_batch=2)
+    net.set_params(th)
+    loss, g = net.loss_grad(_dev(xs), _dev(ys))
+    lref, gref = dn.loss_and_grad(th, xs, ys)
+    print(f"loss gpu {loss:.8e} oracle {lref:.8e}; grad max err {np.abs(g - gref).max() / np.abs(gref).max():.2e}")
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert np.abs(g - gref).max() <= 2e-4 * np.abs(gref).max()
+    # per layer too (the small last layer must not hide behind the large ones)
+    o = 0
+    for ws, bs in dn.layer_shapes():
+        k = int(np.prod(ws)) + bs[0]
+        assert np.abs(g[o:o + k] - gref[o:o + k]).max() <= 5e-4 * np.abs(gref[o:o + k]).max() + 1e-12
+        o += k
+
+
+def test_adam_first_step(ctx):
+    th = _theta(5)
+    xs, ys = _fields(6, 1)
+    net = sp.DensityNet(ctx, N, max_batch=1)
+    net.set_params(th)
+    _, g = net.loss_grad(_dev(xs), _dev(ys))
+    lr = 1e-3
+    net.adam_step(lr)
+    new = net.get_params().astype(np.float64)
+    _, gref = dn.loss_and_grad(th, xs, ys)
+    ref, _, _ = dn.adam_step(th, gref, np.zeros_like(th), np.zeros_like(th), 1, lr)
+    big = np.abs(gref) > 1e-2 * np.abs(gref).max()
+    np.testing.assert_allclose(new[big], ref[big], atol=2e-6 * lr + 1e-6 * np.abs(ref[big]).max())
+    assert np.all(np.abs(new - th) <= lr * 1.001 + 1e-6)
+
+
+def test_predict_density(ctx):
+    cell, _, _ = wl.scf_cell(7, n=16, L=8.0)
+    n = cell.n
+    grid = Grid(n=cell.n, L=cell.L)
+    dV = grid.h[0] * grid.h[1] * grid.h[2]
+    rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    sp.sad_density(ctx, cell, rho_sad)
+    sad = rho_sad.cpu().numpy()
+    net = sp.DensityNet(ctx, n, max_batch=1)
+    out = torch.zeros_like(rho_sad)
+    # zero correction: the SAD density itself (through FP32 scaling)
+    th = np.zeros(dn.num_params())
+    th[-1] = 2.0
+    net.set_params(th)
+    assert net.predict_density(rho_sad, cell.n_elec, dV, out)
+    np.testing.assert_allclose(out.cpu().numpy(), sad, rtol=2e-7, atol=1e-7 * sad.max())
+    # a trained-looking net against the oracle prediction
+    th = _theta(8) * 0.2
+    net.set_params(th)
+    used = net.predict_density(rho_sad, cell.n_elec, dV, out, charge_tol=0.5)
+    ref, uref = dn.predict_density(th, sad.reshape(n[2], n[1], n[0]), cell.n_elec, dV, charge_tol=0.5)
+    assert used and uref
+    np.testing.assert_allclose(out.cpu().numpy(), ref.reshape(-1), atol=2e-5 * ref.max())
+    assert abs(out.sum().item() * dV - cell.n_elec) < 1e-9 * cell.n_elec
+    # fallbacks: a NaN parameter, and a correction whose clipping moves the charge
+    bad = th.copy()
+    bad[100] = np.nan
+    net.set_params(bad)
+    assert not net.predict_density(rho_sad, cell.n_elec, dV, out)
+    assert torch.equal(out, rho_sad)
+    L = dn.unpack(np.zeros(dn.num_params()))
+    for l in range(3):
+        L[l][0][0, 0, 1, 1, 1] = 1.0
+    L[3][0][0, 0, 1, 1, 1] = -2.0
+    net.set_params(dn.pack(L))
+    ref, uref = dn.predict_density(dn.pack(L), sad.reshape(n[2], n[1], n[0]), cell.n_elec, dV, charge_tol=1e-2)
+    assert not uref
+    out.zero_()
+    assert not net.predict_density(rho_sad, cell.n_elec, dV, out, charge_tol=1e-2)
+    assert torch.equal(out, rho_sad)
+
+
+def test_training_lowers_loss(ctx):
+    th = _theta(9)
+    xs, ys = _fields(10, 4)
+    net = sp.DensityNet(ctx, N, max_batch=4)
+    net.set_params(th)
+    x, y = _dev(xs), _dev(ys)
+    first = net.train_step(x, y, 2e-3)
+    for _ in range(40):
+        last = net.train_step(x, y, 2e-3)
+    print(f"loss {first:.4e} -> {last:.4e}")
+    assert last < 0.8 * first
+
+
+def test_error_paths(ctx):
+    with pytest.raises(sp.SparcError) as e:
+        sp.DensityNet(ctx, (0, 4, 4))
+    assert e.value.status == sp.ESHAPE
+    net = sp.DensityNet(ctx, N, max_batch=1)
+    x = torch.zeros(2 * int(np.prod(N)), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(sp.SparcError) as e:
+        net.forward(x, x.clone())
+    assert e.value.status == sp.ESHAPE

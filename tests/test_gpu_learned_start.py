@@ -1,0 +1,55 @@
+"""Effect of the trained density network on the plain SCF (parity unpinned:
+no oracle value exists for it).  On held-out 40^3 cells (test split, never
+seen in training) the SCF started from the learned density must reach the
+same fixed point as the one started from the atomic superposition (free
+energy within 1e-5 Ha/atom, both converged to a 1e-6 density residual) in
+fewer iterations on average.  The weights are those written by
+paper_1603_04339_amd.train_density_net."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1603_04339_amd import sparc as sp
+from paper_1603_04339_amd import workloads as wl
+from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS, cell_dV, solve
+
+pytestmark = pytest.mark.gpu
+
+HELD_OUT = [0, 1, 2, 3, 4, 5]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.skipif(not os.path.exists(DEFAULT_WEIGHTS), reason="no trained weights file")
+def test_learned_start_saves_iterations(ctx):
+    theta = np.load(DEFAULT_WEIGHTS)
+    net = sp.DensityNet(ctx, (40, 40, 40), max_batch=1)
+    net.set_params(theta)
+    its_sad, its_net = [], []
+    for cid in HELD_OUT:
+        cell, X0, v0 = wl.scf_cell(cid, split="test")
+        rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+        sp.sad_density(ctx, cell, rho_sad)
+        rho0 = torch.zeros_like(rho_sad)
+        used = net.predict_density(rho_sad, cell.n_elec, cell_dV(cell), rho0)
+        a, _ = solve(ctx, cell, X0, v0)
+        b, _ = solve(ctx, cell, X0, v0, rho_init=rho0)
+        de = abs(a["energy"] - b["energy"]) / cell.n_atoms
+        print(f"cell {cid} ({cell.n_atoms} atoms): SAD {a['iterations']} it, learned {b['iterations']} it "
+              f"(net used: {used}), |dF|/atom {de:.1e}")
+        assert a["converged"] and b["converged"]
+        assert de < 1e-5
+        its_sad.append(a["iterations"])
+        its_net.append(b["iterations"])
+    print(f"mean iterations: SAD {np.mean(its_sad):.1f}, learned {np.mean(its_net):.1f}")
+    assert np.mean(its_net) < np.mean(its_sad)
