@@ -147,7 +147,7 @@ def scf_leg(sp, ctx, precision, tol=1e-6, learned=False):
     inference time is included in the wall time."""
     import torch
     from paper_1603_04339_amd import workloads as wl
-    from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS, cell_dV
+    from paper_1603_04339_amd.train_density_net import CHARGE_TOL, DEFAULT_WEIGHTS, FIRST_PASSES, cell_dV, cell_start
     cell, X0, v0 = wl.scf_cell(0, split="test")
     rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
     ritz = torch.zeros(cell.n_s, dtype=torch.float64, device="cuda:0")
@@ -159,12 +159,11 @@ def scf_leg(sp, ctx, precision, tol=1e-6, learned=False):
     t0 = time.perf_counter()
     rho0, used = None, None
     if net is not None:
-        sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
-        sp.sad_density(ctx, cell, sad)
+        sad, vloc = cell_start(ctx, cell)
         rho0 = torch.zeros_like(sad)
-        used = net.predict_density(sad, cell.n_elec, cell_dV(cell), rho0)
-    prm = dict(n_s=cell.n_s, degree=20, n_first_passes=4, max_iter=200, lanczos_steps=20, mix_history=7, kT=0.01,
-               mix=0.3, tol=tol, n_elec=cell.n_elec, poisson_tol=1e-10,
+        used = net.predict_density(sad, vloc, cell.n_elec, cell_dV(cell), rho0, charge_tol=CHARGE_TOL)
+    prm = dict(n_s=cell.n_s, degree=20, n_first_passes=FIRST_PASSES, max_iter=200, lanczos_steps=20, mix_history=7,
+               kT=0.01, mix=0.3, tol=tol, n_elec=cell.n_elec, poisson_tol=1e-10,
                filt=sp.R64 if precision == "f64" else sp.R32, rr=sp.GEMM_NATIVE, final_fp64_pass=1,
                rho_init_dev=rho0, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda())
     out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz)

@@ -268,46 +268,52 @@ int sparc_sad_density(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms*
 
 /* ---- learned initial density ------------------------------------------------------
  * Replaces the atomic-superposition start of the SCF (Sec. 4) by
- *   rho_0 = renorm( relu(x + d - mean(d)) * rho_bar ),  x = rho_SAD / rho_bar,  d = f(x),
- * rho_bar = n_elec / (N_d dV), f = four 3x3x3 periodic convolutions with channels
- * 1 -> 16 -> 32 -> 32 -> 1 and ReLU after the first three (42849 parameters, FP32).
- * Host parameter vector, layer by layer: W[c_out][c_in][kz][ky][kx] (tap (kz, ky,
- * kx) reads the input at offset (kz-1, ky-1, kx-1)), then b[c_out].  Batches of
- * cells are device arrays [batch][N_d] (x fastest) of FP32.  The net owns its
+ *   rho_0 = renorm( relu(x + d - mean(d)) * rho_bar ),  x = rho_SAD / rho_bar,
+ *   d = f(x, u),  u = -V_loc (Ha),  rho_bar = n_elec / (N_d dV),
+ * f = four 3x3x3 periodic convolutions with dilations 1, 2, 4, 8, channels
+ * 2 -> 16 -> 32 -> 32 -> 1 and ReLU after the first three (43281 parameters, FP32).
+ * Host parameter vector, layer by layer: W[c_out][c_in][kz][ky][kx] (with dilation
+ * q, tap (kz, ky, kx) reads the input at offset q (kz-1, ky-1, kx-1)), then
+ * b[c_out].  Network inputs are device FP32 arrays [batch][N_d][2] (x fastest,
+ * channels (x, u) innermost); targets and outputs [batch][N_d].  The net owns its
  * parameters, Adam state and activations for up to max_batch cells (1..128);
  * calls on one net are not concurrent. */
 typedef struct sparc_dnet sparc_dnet;
 int64_t sparc_dnet_num_params(void);
-/* n: grid points per direction (1..1024).  Parameters start at zero. */
+/* n: grid points per direction (9..1024).  Parameters start at zero. */
 int sparc_dnet_create(sparc_ctx* ctx, const int32_t* n, int32_t max_batch, sparc_dnet** out);
 void sparc_dnet_destroy(sparc_dnet* net);
 /* Host parameter vector in/out (sparc_dnet_num_params floats).  Setting the
  * parameters restarts Adam. */
 int sparc_dnet_set_params(sparc_dnet* net, const float* theta);
 int sparc_dnet_get_params(const sparc_dnet* net, float* theta);
-/* x_dev (FP32, N_d) = rho_dev / rho_bar: the network's input and target scaling. */
+/* x_dev (FP32, N_d) = rho_dev / rho_bar: the scaling of the training targets. */
 int sparc_dnet_scale_density(sparc_dnet* net, const double* rho_dev, double n_elec, double dV, float* x_dev);
-/* Raw network output d = f(x) for `batch` cells (d_dev: batch * N_d floats). */
-int sparc_dnet_forward(sparc_dnet* net, const float* x_dev, int32_t batch, float* d_dev);
-/* Loss L = mean over cells and points of (relu(x + d - mean(d)) - y)^2 and its
+/* in_dev (FP32, N_d x 2) = (rho_dev / rho_bar, -vloc_dev): one cell's network input
+ * from its atomic superposition and local potential (device FP64). */
+int sparc_dnet_prepare_input(sparc_dnet* net, const double* rho_dev, const double* vloc_dev, double n_elec, double dV,
+                             float* in_dev);
+/* Raw network output d = f(x, u) for `batch` cells (d_dev: batch * N_d floats). */
+int sparc_dnet_forward(sparc_dnet* net, const float* in_dev, int32_t batch, float* d_dev);
+/* Loss L = mean over cells and points of (x + d - mean(d) - y)^2 and its
  * gradient (kept on the device for sparc_dnet_adam_step; also copied to grad_host,
  * in the host parameter layout, when that is not NULL).  Synchronous.  ENAN for a
  * non-finite loss. */
-int sparc_dnet_loss_grad(sparc_dnet* net, const float* x_dev, const float* y_dev, int32_t batch, double* loss,
+int sparc_dnet_loss_grad(sparc_dnet* net, const float* in_dev, const float* y_dev, int32_t batch, double* loss,
                          float* grad_host);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the last
  * gradient. */
 int sparc_dnet_adam_step(sparc_dnet* net, double lr);
 /* loss_grad followed by adam_step. */
-int sparc_dnet_train_step(sparc_dnet* net, const float* x_dev, const float* y_dev, int32_t batch, double lr,
+int sparc_dnet_train_step(sparc_dnet* net, const float* in_dev, const float* y_dev, int32_t batch, double lr,
                           double* loss);
-/* Learned start density of one cell from its atomic superposition (device FP64,
- * N_d); rho_dev receives rho_0 (FP64, h^3 sum = n_elec).  Falls back to a copy
- * of rho_sad_dev, with *used_net = 0, when any value is not finite or the charge
- * before renormalisation differs from n_elec by more than charge_tol * n_elec.
- * Synchronous. */
-int sparc_dnet_predict_density(sparc_dnet* net, const double* rho_sad_dev, double n_elec, double dV,
-                               double charge_tol, double* rho_dev, int32_t* used_net);
+/* Learned start density of one cell from its atomic superposition and local
+ * potential (device FP64, N_d each); rho_dev receives rho_0 (FP64, h^3 sum =
+ * n_elec).  Falls back to a copy of rho_sad_dev, with *used_net = 0, when any value
+ * is not finite or the charge before renormalisation differs from n_elec by more
+ * than charge_tol * n_elec.  Synchronous. */
+int sparc_dnet_predict_density(sparc_dnet* net, const double* rho_sad_dev, const double* vloc_dev, double n_elec,
+                               double dV, double charge_tol, double* rho_dev, int32_t* used_net);
 
 #ifdef __cplusplus
 }

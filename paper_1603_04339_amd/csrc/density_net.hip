@@ -3,13 +3,16 @@
 // it, trained on converged plain-SCF densities; forward, backward and Adam are
 // the kernels below (FP32 storage and arithmetic, FP64 reductions).
 //
-//   x = rho_SAD / rho_bar,  d = f_theta(x),  rho_0 = renorm(relu(x + d - mean(d)) * rho_bar)
-//   f_theta: four 3x3x3 periodic convolutions, channels 1 -> 16 -> 32 -> 32 -> 1, ReLU
-//   after the first three.
+//   x = rho_SAD / rho_bar,  u = -V_loc,  d = f_theta(x, u),
+//   rho_0 = renorm(relu(x + d - mean(d)) * rho_bar)
+//   f_theta: four 3x3x3 periodic convolutions with dilations 1, 2, 4, 8, channels
+//   2 -> 16 -> 32 -> 32 -> 1, ReLU after the first three.  The local potential is the
+//   second input channel: the atomic superposition does not see the well depths.
 //
 // Layout: a field of C channels for a batch of B cells is [B][N_d][C] (channels
 // fastest, voxel index i + n1 (j + n2 k)).  Weights are stored per layer as
-// W[tap][C_in][C_out] (tap = 9 kz + 3 ky + kx reads offset (kz-1, ky-1, kx-1)),
+// W[tap][C_in][C_out] (tap = 9 kz + 3 ky + kx reads offset q (kz-1, ky-1, kx-1) for
+// dilation q),
 // then b[C_out]; the host-side parameter vector uses W[C_out][C_in][kz][ky][kx]
 // and is transposed on set/get.
 //
@@ -29,7 +32,8 @@
 namespace sparc {
 
 static constexpr int kLayers = 4;
-static constexpr int kCh[kLayers + 1] = {1, 16, 32, 32, 1};
+static constexpr int kCh[kLayers + 1] = {2, 16, 32, 32, 1};
+static constexpr int kDil[kLayers] = {1, 2, 4, 8};
 static constexpr int kGroups = 64;   // weight-gradient partial groups
 static constexpr int kChunk = 64;    // voxels staged per weight-gradient iteration
 static constexpr int kRedBlocks = 256;
@@ -46,7 +50,7 @@ __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >
 
 // MODE 0: out = conv + bias; 1: out = relu(conv + bias); 2: out = conv * (mask > 0)
 template <int CI, int CO, int MODE>
-__global__ __launch_bounds__(256) void conv_kernel(int n1, int n2, int n3, const float* __restrict__ in,
+__global__ __launch_bounds__(256) void conv_kernel(int n1, int n2, int n3, int q, const float* __restrict__ in,
                                                    const float* __restrict__ W, const float* __restrict__ bias,
                                                    const float* __restrict__ mask, float* __restrict__ out) {
   const int64_t V = (int64_t)n1 * n2 * n3;
@@ -59,12 +63,12 @@ __global__ __launch_bounds__(256) void conv_kernel(int n1, int n2, int n3, const
 #pragma unroll
   for (int co = 0; co < CO; ++co) acc[co] = (MODE != 2) ? bias[co] : 0.0f;
   for (int kz = 0; kz < 3; ++kz) {
-    const int kk = wrapi(k + kz - 1, n3);
+    const int kk = wrapi(k + q * (kz - 1), n3);
     for (int ky = 0; ky < 3; ++ky) {
-      const int jj = wrapi(j + ky - 1, n2);
+      const int jj = wrapi(j + q * (ky - 1), n2);
 #pragma unroll
       for (int kx = 0; kx < 3; ++kx) {
-        const int ii = wrapi(i + kx - 1, n1);
+        const int ii = wrapi(i + q * (kx - 1), n1);
         const float* __restrict__ src = inb + (((int64_t)kk * n2 + jj) * n1 + ii) * CI;
         const float* __restrict__ w = W + ((kz * 3 + ky) * 3 + kx) * CI * CO;
         if constexpr (CI % 4 == 0) {
@@ -118,14 +122,14 @@ __global__ void transpose_w_kernel(int ci_n, int co_n, const float* __restrict__
 // partial weight gradients: part[g][t][ci*CO + co] = sum over the voxels of group g of
 // a(v + offset_t)[ci] * gz(v)[co]
 template <int CI, int CO>
-__global__ __launch_bounds__(256) void wgrad_kernel(int n1, int n2, int n3, int B, const float* __restrict__ a,
+__global__ __launch_bounds__(256) void wgrad_kernel(int n1, int n2, int n3, int q, int B, const float* __restrict__ a,
                                                     const float* __restrict__ gz, float* __restrict__ part) {
   constexpr int P = CI * CO;
   constexpr int PPT = (P + 255) / 256;
   __shared__ float xs[kChunk][CI + 1];
   __shared__ float gs[kChunk][CO];
   const int t = blockIdx.x, g = blockIdx.y;
-  const int oz = t / 9 - 1, oy = (t / 3) % 3 - 1, ox = t % 3 - 1;
+  const int oz = q * (t / 9 - 1), oy = q * ((t / 3) % 3 - 1), ox = q * (t % 3 - 1);
   const int64_t V = (int64_t)n1 * n2 * n3, total = V * B;
   const int64_t nchunks = (total + kChunk - 1) / kChunk;
   float acc[PPT];
@@ -244,19 +248,18 @@ __global__ void sample_sums_final_kernel(int B, int nblk, const double* __restri
   sums[idx] = s;
 }
 
-// loss head: s = x + d - mean_b(d), yhat = relu(s), r = yhat - y;
-// g = 2 r / (B V) [s > 0]; writes g and r^2 (for the loss sum)
-__global__ void head_loss_kernel(int64_t V, int B, const float* __restrict__ x, const float* __restrict__ d,
+// loss head: s = x + d - mean_b(d), r = s - y (before the ReLU of the prediction, so
+// that negative s is penalised); g = 2 r / (B V); writes g and r^2 (for the loss sum)
+__global__ void head_loss_kernel(int64_t V, int B, const float* __restrict__ in, const float* __restrict__ d,
                                  const double* __restrict__ dsum, const float* __restrict__ y, float* __restrict__ g,
                                  float* __restrict__ r2) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= V * B) return;
   const int64_t b = idx / V;
   const float mean = (float)(dsum[2 * b] / (double)V);
-  const float s = x[idx] + (d[idx] - mean);
-  const float yh = s < 0.0f ? 0.0f : s;
-  const float r = yh - y[idx];
-  g[idx] = s > 0.0f ? 2.0f * r / (float)((double)B * V) : 0.0f;
+  const float s = in[idx * 2] + (d[idx] - mean);   // channel 0 of the input: x
+  const float r = s - y[idx];
+  g[idx] = 2.0f * r / (float)((double)B * V);
   r2[idx] = r * r;
 }
 
@@ -268,12 +271,12 @@ __global__ void center_kernel(int64_t V, int B, float* __restrict__ g, const dou
 }
 
 // prediction head (one cell): s = x + d - mean(d); rho = relu(s) * rho_bar (FP64)
-__global__ void head_predict_kernel(int64_t V, const float* __restrict__ x, const float* __restrict__ d,
+__global__ void head_predict_kernel(int64_t V, const float* __restrict__ in, const float* __restrict__ d,
                                     const double* __restrict__ dsum, double rho_bar, double* __restrict__ rho,
                                     float* __restrict__ yh, float* __restrict__ sv) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  const float s = x[v] + (d[v] - (float)(dsum[0] / (double)V));
+  const float s = in[v * 2] + (d[v] - (float)(dsum[0] / (double)V));
   const float y = s < 0.0f ? 0.0f : s;
   yh[v] = y;
   sv[v] = s;   // summed separately so that a NaN anywhere reaches the host check
@@ -290,6 +293,16 @@ __global__ void to_scaled_f32_kernel(int64_t n, const double* __restrict__ rho, 
   if (i < n) x[i] = (float)(rho[i] * inv);
 }
 
+// network input [v][2] = (rho / rho_bar, -V_loc)
+__global__ void input_kernel(int64_t n, const double* __restrict__ rho, double inv, const double* __restrict__ vloc,
+                             float* __restrict__ in) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    in[2 * i] = (float)(rho[i] * inv);
+    in[2 * i + 1] = (float)(-vloc[i]);
+  }
+}
+
 // Adam (Kingma & Ba) with bias corrections c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t)
 __global__ void adam_kernel(int64_t n, float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
                             float* __restrict__ v, float lr, float b1, float b2, float c1, float c2, float eps) {
@@ -304,18 +317,18 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ th, const float* __re
 }
 
 template <int CI, int CO, int MODE>
-static int launch_conv(hipStream_t s, int n1, int n2, int n3, int B, const float* in, const float* W, const float* bias,
-                       const float* mask, float* out) {
+static int launch_conv(hipStream_t s, int n1, int n2, int n3, int q, int B, const float* in, const float* W,
+                       const float* bias, const float* mask, float* out) {
   const int64_t V = (int64_t)n1 * n2 * n3;
   dim3 grid((unsigned)((V + 255) / 256), (unsigned)B);
-  conv_kernel<CI, CO, MODE><<<grid, 256, 0, s>>>(n1, n2, n3, in, W, bias, mask, out);
+  conv_kernel<CI, CO, MODE><<<grid, 256, 0, s>>>(n1, n2, n3, q, in, W, bias, mask, out);
   return check_launch("conv_kernel");
 }
 
 template <int CI, int CO>
-static int launch_wgrad(hipStream_t s, int n1, int n2, int n3, int B, const float* a, const float* gz, float* part,
-                        double* bpart, float* gW, float* gb) {
-  wgrad_kernel<CI, CO><<<dim3(27, kGroups), 256, 0, s>>>(n1, n2, n3, B, a, gz, part);
+static int launch_wgrad(hipStream_t s, int n1, int n2, int n3, int q, int B, const float* a, const float* gz,
+                        float* part, double* bpart, float* gW, float* gb) {
+  wgrad_kernel<CI, CO><<<dim3(27, kGroups), 256, 0, s>>>(n1, n2, n3, q, B, a, gz, part);
   SPARC_TRY(check_launch("wgrad_kernel"));
   const int np = 27 * CI * CO;
   wgrad_reduce_kernel<<<(np + 255) / 256, 256, 0, s>>>(np, kGroups, part, gW);
@@ -363,11 +376,15 @@ static float* bl(sparc_dnet* N, float* base, int l) { return base + layer_off(l)
 static int dnet_forward(sparc_dnet* N, const float* x, int B) {
   hipStream_t s = N->ctx->stream;
   const int n1 = N->n[0], n2 = N->n[1], n3 = N->n[2];
-  SPARC_HIP(hipMemcpyAsync(N->a[0], x, (size_t)B * N->V * sizeof(float), hipMemcpyDeviceToDevice, s));
-  SPARC_TRY((launch_conv<1, 16, 1>(s, n1, n2, n3, B, N->a[0], Wl(N, N->theta, 0), bl(N, N->theta, 0), nullptr, N->a[1])));
-  SPARC_TRY((launch_conv<16, 32, 1>(s, n1, n2, n3, B, N->a[1], Wl(N, N->theta, 1), bl(N, N->theta, 1), nullptr, N->a[2])));
-  SPARC_TRY((launch_conv<32, 32, 1>(s, n1, n2, n3, B, N->a[2], Wl(N, N->theta, 2), bl(N, N->theta, 2), nullptr, N->a[3])));
-  SPARC_TRY((launch_conv<32, 1, 0>(s, n1, n2, n3, B, N->a[3], Wl(N, N->theta, 3), bl(N, N->theta, 3), nullptr, N->a[4])));
+  SPARC_HIP(hipMemcpyAsync(N->a[0], x, (size_t)B * N->V * kCh[0] * sizeof(float), hipMemcpyDeviceToDevice, s));
+  SPARC_TRY((launch_conv<2, 16, 1>(s, n1, n2, n3, kDil[0], B, N->a[0], Wl(N, N->theta, 0), bl(N, N->theta, 0), nullptr,
+                                   N->a[1])));
+  SPARC_TRY((launch_conv<16, 32, 1>(s, n1, n2, n3, kDil[1], B, N->a[1], Wl(N, N->theta, 1), bl(N, N->theta, 1), nullptr,
+                                    N->a[2])));
+  SPARC_TRY((launch_conv<32, 32, 1>(s, n1, n2, n3, kDil[2], B, N->a[2], Wl(N, N->theta, 2), bl(N, N->theta, 2), nullptr,
+                                    N->a[3])));
+  SPARC_TRY((launch_conv<32, 1, 0>(s, n1, n2, n3, kDil[3], B, N->a[3], Wl(N, N->theta, 3), bl(N, N->theta, 3), nullptr,
+                                   N->a[4])));
   return SPARC_OK;
 }
 
@@ -389,16 +406,20 @@ static int dnet_backward(sparc_dnet* N, int B) {
     return check_launch("transpose_w_kernel");
   };
   // layer 3 (linear): gz[3] is the head gradient
-  SPARC_TRY((launch_wgrad<32, 1>(s, n1, n2, n3, B, N->a[3], N->gz[3], N->part, N->bpart, Wl(N, N->grad, 3), bl(N, N->grad, 3))));
+  SPARC_TRY((launch_wgrad<32, 1>(s, n1, n2, n3, kDil[3], B, N->a[3], N->gz[3], N->part, N->bpart, Wl(N, N->grad, 3),
+                                  bl(N, N->grad, 3))));
   SPARC_TRY(transpose(3));
-  SPARC_TRY((launch_conv<1, 32, 2>(s, n1, n2, n3, B, N->gz[3], N->wt, nullptr, N->a[3], N->gz[2])));
-  SPARC_TRY((launch_wgrad<32, 32>(s, n1, n2, n3, B, N->a[2], N->gz[2], N->part, N->bpart, Wl(N, N->grad, 2), bl(N, N->grad, 2))));
+  SPARC_TRY((launch_conv<1, 32, 2>(s, n1, n2, n3, kDil[3], B, N->gz[3], N->wt, nullptr, N->a[3], N->gz[2])));
+  SPARC_TRY((launch_wgrad<32, 32>(s, n1, n2, n3, kDil[2], B, N->a[2], N->gz[2], N->part, N->bpart, Wl(N, N->grad, 2),
+                                   bl(N, N->grad, 2))));
   SPARC_TRY(transpose(2));
-  SPARC_TRY((launch_conv<32, 32, 2>(s, n1, n2, n3, B, N->gz[2], N->wt, nullptr, N->a[2], N->gz[1])));
-  SPARC_TRY((launch_wgrad<16, 32>(s, n1, n2, n3, B, N->a[1], N->gz[1], N->part, N->bpart, Wl(N, N->grad, 1), bl(N, N->grad, 1))));
+  SPARC_TRY((launch_conv<32, 32, 2>(s, n1, n2, n3, kDil[2], B, N->gz[2], N->wt, nullptr, N->a[2], N->gz[1])));
+  SPARC_TRY((launch_wgrad<16, 32>(s, n1, n2, n3, kDil[1], B, N->a[1], N->gz[1], N->part, N->bpart, Wl(N, N->grad, 1),
+                                   bl(N, N->grad, 1))));
   SPARC_TRY(transpose(1));
-  SPARC_TRY((launch_conv<32, 16, 2>(s, n1, n2, n3, B, N->gz[1], N->wt, nullptr, N->a[1], N->gz[0])));
-  SPARC_TRY((launch_wgrad<1, 16>(s, n1, n2, n3, B, N->a[0], N->gz[0], N->part, N->bpart, Wl(N, N->grad, 0), bl(N, N->grad, 0))));
+  SPARC_TRY((launch_conv<32, 16, 2>(s, n1, n2, n3, kDil[1], B, N->gz[1], N->wt, nullptr, N->a[1], N->gz[0])));
+  SPARC_TRY((launch_wgrad<2, 16>(s, n1, n2, n3, kDil[0], B, N->a[0], N->gz[0], N->part, N->bpart, Wl(N, N->grad, 0),
+                                  bl(N, N->grad, 0))));
   return SPARC_OK;
 }
 
@@ -441,7 +462,8 @@ int sparc_dnet_create(sparc_ctx* ctx, const int32_t* n, int32_t max_batch, sparc
   if (!ctx || !n || !out) return fail(SPARC_EINVAL, "sparc_dnet_create: null argument");
   *out = nullptr;
   for (int s3 = 0; s3 < 3; ++s3)
-    if (n[s3] < 1 || n[s3] > 1024) return fail(SPARC_ESHAPE, "sparc_dnet_create: grid size outside 1..1024");
+    if (n[s3] <= kDil[kLayers - 1] || n[s3] > 1024)
+      return fail(SPARC_ESHAPE, "sparc_dnet_create: grid size outside %d..1024", kDil[kLayers - 1] + 1);
   if (max_batch < 1 || max_batch > 128) return fail(SPARC_ESHAPE, "sparc_dnet_create: max_batch outside 1..128");
   sparc_dnet* N = new sparc_dnet();
   N->ctx = ctx;
@@ -519,6 +541,15 @@ int sparc_dnet_scale_density(sparc_dnet* N, const double* rho_dev, double n_elec
   return check_launch("to_scaled_f32_kernel");
 }
 
+int sparc_dnet_prepare_input(sparc_dnet* N, const double* rho_dev, const double* vloc_dev, double n_elec, double dV,
+                             float* in_dev) {
+  if (!N || !rho_dev || !vloc_dev || !in_dev) return fail(SPARC_EINVAL, "sparc_dnet_prepare_input: null argument");
+  if (!(n_elec > 0) || !(dV > 0)) return fail(SPARC_EINVAL, "sparc_dnet_prepare_input: n_elec, dV must be positive");
+  const double rho_bar = n_elec / ((double)N->V * dV);
+  input_kernel<<<(unsigned)((N->V + 255) / 256), 256, 0, N->ctx->stream>>>(N->V, rho_dev, 1.0 / rho_bar, vloc_dev, in_dev);
+  return check_launch("input_kernel");
+}
+
 int sparc_dnet_forward(sparc_dnet* N, const float* x_dev, int32_t B, float* d_dev) {
   SPARC_TRY(check_batch(N, B));
   if (!x_dev || !d_dev) return fail(SPARC_EINVAL, "sparc_dnet_forward: null argument");
@@ -574,17 +605,18 @@ int sparc_dnet_train_step(sparc_dnet* N, const float* x_dev, const float* y_dev,
   return sparc_dnet_adam_step(N, lr);
 }
 
-int sparc_dnet_predict_density(sparc_dnet* N, const double* rho_sad_dev, double n_elec, double dV, double charge_tol,
-                               double* rho_dev, int32_t* used_net) {
-  if (!N || !rho_sad_dev || !rho_dev || !used_net) return fail(SPARC_EINVAL, "sparc_dnet_predict_density: null argument");
+int sparc_dnet_predict_density(sparc_dnet* N, const double* rho_sad_dev, const double* vloc_dev, double n_elec,
+                               double dV, double charge_tol, double* rho_dev, int32_t* used_net) {
+  if (!N || !rho_sad_dev || !vloc_dev || !rho_dev || !used_net)
+    return fail(SPARC_EINVAL, "sparc_dnet_predict_density: null argument");
   if (!(n_elec > 0) || !(dV > 0) || !(charge_tol > 0))
     return fail(SPARC_EINVAL, "sparc_dnet_predict_density: n_elec, dV and charge_tol must be positive");
   hipStream_t s = N->ctx->stream;
   const int64_t V = N->V;
   const double rho_bar = n_elec / ((double)V * dV);
-  float* x = N->gz[3];   // scratch: one cell
-  SPARC_TRY(sparc_dnet_scale_density(N, rho_sad_dev, n_elec, dV, x));
-  SPARC_TRY(dnet_forward(N, x, 1));
+  float* in = N->gz[1];   // scratch: one cell, two channels
+  SPARC_TRY(sparc_dnet_prepare_input(N, rho_sad_dev, vloc_dev, n_elec, dV, in));
+  SPARC_TRY(dnet_forward(N, in, 1));
   SPARC_TRY(dnet_sample_sums(N, 1, N->a[4], nullptr));
   float* yh = N->r2;
   float* sv = N->gz[2];

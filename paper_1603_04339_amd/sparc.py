@@ -110,14 +110,15 @@ _SIGS = {
     "sparc_dnet_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sparc_dnet_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sparc_dnet_scale_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
+    "sparc_dnet_prepare_input": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
     "sparc_dnet_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "sparc_dnet_loss_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                                        C.c_void_p]),
     "sparc_dnet_adam_step": (C.c_int, [C.c_void_p, C.c_double]),
     "sparc_dnet_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
                                         C.POINTER(C.c_double)]),
-    "sparc_dnet_predict_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p,
-                                             C.POINTER(C.c_int32)]),
+    "sparc_dnet_predict_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                                             C.c_void_p, C.POINTER(C.c_int32)]),
     "sparc_scf_run": (C.c_int, [C.c_void_p, C.POINTER(sparc_grid), C.POINTER(sparc_atoms),
                                 C.POINTER(sparc_scf_params), C.POINTER(sparc_scf_result)]),
 }
@@ -478,13 +479,19 @@ class DensityNet:
         _check(load().sparc_dnet_scale_density(self.handle, _ptr(rho), float(n_elec), float(dV), _ptr(x_out)))
         return x_out
 
+    def prepare_input(self, rho_sad, vloc, n_elec: float, dV: float, in_out):
+        """in_out (FP32, N_d x 2) = (rho_sad / rho_bar, -vloc)."""
+        _check(load().sparc_dnet_prepare_input(self.handle, _ptr(rho_sad), _ptr(vloc), float(n_elec), float(dV),
+                                               _ptr(in_out)))
+        return in_out
+
     def forward(self, x, d_out):
-        B = x.numel() // self.n_d
+        B = x.numel() // (2 * self.n_d)
         _check(load().sparc_dnet_forward(self.handle, _ptr(x), B, _ptr(d_out)))
         return d_out
 
     def loss_grad(self, x, y, want_grad: bool = True):
-        B = x.numel() // self.n_d
+        B = y.numel() // self.n_d
         loss = C.c_double()
         g = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
         _check(load().sparc_dnet_loss_grad(self.handle, _ptr(x), _ptr(y), B, C.byref(loss),
@@ -495,14 +502,14 @@ class DensityNet:
         _check(load().sparc_dnet_adam_step(self.handle, float(lr)))
 
     def train_step(self, x, y, lr: float):
-        B = x.numel() // self.n_d
+        B = y.numel() // self.n_d
         loss = C.c_double()
         _check(load().sparc_dnet_train_step(self.handle, _ptr(x), _ptr(y), B, float(lr), C.byref(loss)))
         return loss.value
 
-    def predict_density(self, rho_sad, n_elec: float, dV: float, rho_out, charge_tol: float = 1e-2):
+    def predict_density(self, rho_sad, vloc, n_elec: float, dV: float, rho_out, charge_tol: float = 1e-2):
         used = C.c_int32()
-        _check(load().sparc_dnet_predict_density(self.handle, _ptr(rho_sad), float(n_elec), float(dV),
+        _check(load().sparc_dnet_predict_density(self.handle, _ptr(rho_sad), _ptr(vloc), float(n_elec), float(dV),
                                                  float(charge_tol), _ptr(rho_out), C.byref(used)))
         return bool(used.value)
 

@@ -7,9 +7,10 @@ evaluate it on held-out cells.
 
 Data: the 40^3 SCF cells of workloads.scf_cell (8-32 atoms, seeded; training
 ids 0..n_train-1, held-out ids from the test split).  For every cell the
-library computes the atomic superposition (sparc_sad_density) and runs the
+library computes the atomic superposition (sparc_sad_density) and the local
+potential (the network's two input channels) and runs the
 plain FP64 SCF from it (sparc_scf_run, Anderson mixing, density residual
-1e-6); the pair (SAD, converged density), both divided by the mean density,
+1e-5; unconverged cells are left out); the pair (SAD, converged density), both divided by the mean density,
 is one training sample.  Several cells run concurrently, one context and
 stream per worker thread.  Training: Adam (sparc_dnet_train_step) on shuffled
 mini-batches, cosine learning-rate decay.  Evaluation: every held-out cell is
@@ -36,14 +37,24 @@ from . import sparc as sp
 from . import workloads as wl
 
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "density_net_40.npy")
+# fallback threshold of the prediction: relative charge change made by the final ReLU
+# (clipping only adds charge; renormalisation removes it); beyond this the output is
+# treated as unusable and the atomic superposition is used instead
+CHARGE_TOL = 0.1
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# CheFSI passes of the first SCF iteration: enough to bring the random start subspace
+# close to the eigenspace of the start potential, so that the SCF iteration count
+# measures the quality of the start density rather than the subspace convergence
+FIRST_PASSES = 16
+
+
 def scf_params(cell, X0, v0, rho_init=None, tol=1e-6, max_iter=200):
-    return dict(n_s=cell.n_s, degree=20, n_first_passes=4, max_iter=max_iter, lanczos_steps=20, mix_history=7,
+    return dict(n_s=cell.n_s, degree=20, n_first_passes=FIRST_PASSES, max_iter=max_iter, lanczos_steps=20, mix_history=7,
                 kT=0.01, mix=0.3, tol=tol, n_elec=cell.n_elec, poisson_tol=1e-10, filt=sp.R64, rr=sp.GEMM_NATIVE,
                 final_fp64_pass=1, rho_init_dev=rho_init, x0_dev=torch.from_numpy(X0).cuda(),
                 lanczos_v0_dev=torch.from_numpy(v0).cuda())
@@ -51,6 +62,17 @@ def scf_params(cell, X0, v0, rho_init=None, tol=1e-6, max_iter=200):
 
 def cell_dV(cell):
     return (cell.L[0] / cell.n[0]) * (cell.L[1] / cell.n[1]) * (cell.L[2] / cell.n[2])
+
+
+def cell_start(ctx, cell):
+    """Atomic superposition and local potential of a cell (device FP64)."""
+    rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    sp.sad_density(ctx, cell, rho_sad)
+    vloc = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    ham.get_vloc(vloc)
+    ham.close()
+    return rho_sad, vloc
 
 
 class Worker:
@@ -70,38 +92,38 @@ class Worker:
         return w
 
 
-def solve(ctx, cell, X0, v0, rho_init=None):
+def solve(ctx, cell, X0, v0, rho_init=None, tol=1e-6):
     rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
     ritz = torch.zeros(cell.n_s, dtype=torch.float64, device="cuda:0")
     t0 = time.perf_counter()
-    out = sp.sparc_scf_run(ctx, cell, scf_params(cell, X0, v0, rho_init), rho, ritz)
+    out = sp.sparc_scf_run(ctx, cell, scf_params(cell, X0, v0, rho_init, tol=tol), rho, ritz)
     out["wall_s"] = time.perf_counter() - t0
     return out, rho
 
 
-def make_sample(cell_id, split, n):
-    """SAD and converged density of one cell, scaled, FP32 on the device."""
+def make_sample(cell_id, split, n, tol):
+    """Network input (SAD, -V_loc) and converged density of one cell, scaled, FP32 on
+    the device."""
     w = Worker.get(n)
     with torch.cuda.stream(w.stream):
         cell, X0, v0 = wl.scf_cell(cell_id, split=split)
-        rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
-        sp.sad_density(w.ctx, cell, rho_sad)
-        out, rho = solve(w.ctx, cell, X0, v0)
+        rho_sad, vloc = cell_start(w.ctx, cell)
+        out, rho = solve(w.ctx, cell, X0, v0, tol=tol)
         dV = cell_dV(cell)
-        x = torch.empty(cell.n_d, dtype=torch.float32, device="cuda:0")
+        x = torch.empty(2 * cell.n_d, dtype=torch.float32, device="cuda:0")
         y = torch.empty(cell.n_d, dtype=torch.float32, device="cuda:0")
-        w.net.scale_density(rho_sad, cell.n_elec, dV, x)
+        w.net.prepare_input(rho_sad, vloc, cell.n_elec, dV, x)
         w.net.scale_density(rho, cell.n_elec, dV, y)
         w.stream.synchronize()
     return dict(id=cell_id, x=x, y=y, iterations=out["iterations"], energy=out["energy"],
                 converged=out["converged"], n_atoms=cell.n_atoms, wall_s=out["wall_s"])
 
 
-def generate(ids, split, threads, n):
+def generate(ids, split, threads, n, tol):
     t0 = time.perf_counter()
     done = []
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        futs = [ex.submit(make_sample, i, split, n) for i in ids]
+        futs = [ex.submit(make_sample, i, split, n, tol) for i in ids]
         for k, f in enumerate(futs):
             done.append(f.result())
             if (k + 1) % 50 == 0 or k + 1 == len(futs):
@@ -110,14 +132,14 @@ def generate(ids, split, threads, n):
 
 
 def train(net, data, epochs, batch, lr, seed=0):
-    n_d = data[0]["x"].numel()
+    n_d = data[0]["y"].numel()
     X = torch.stack([d["x"] for d in data])
     Y = torch.stack([d["y"] for d in data])
     rng = np.random.default_rng(seed)
     steps = epochs * math.ceil(len(data) / batch)
     step = 0
     curve = []
-    xb = torch.empty(batch * n_d, dtype=torch.float32, device="cuda:0")
+    xb = torch.empty(2 * batch * n_d, dtype=torch.float32, device="cuda:0")
     yb = torch.empty(batch * n_d, dtype=torch.float32, device="cuda:0")
     t0 = time.perf_counter()
     for ep in range(epochs):
@@ -126,10 +148,10 @@ def train(net, data, epochs, batch, lr, seed=0):
         for s in range(0, len(perm), batch):
             idx = torch.from_numpy(perm[s:s + batch]).cuda()
             B = idx.numel()
-            xb[:B * n_d].copy_(X.index_select(0, idx).reshape(-1))
+            xb[:2 * B * n_d].copy_(X.index_select(0, idx).reshape(-1))
             yb[:B * n_d].copy_(Y.index_select(0, idx).reshape(-1))
             lr_t = lr * (0.05 + 0.95 * 0.5 * (1 + math.cos(math.pi * step / max(1, steps - 1))))
-            loss = net.train_step(xb[:B * n_d], yb[:B * n_d], lr_t)
+            loss = net.train_step(xb[:2 * B * n_d], yb[:B * n_d], lr_t)
             tot += loss * B
             cnt += B
             step += 1
@@ -138,15 +160,14 @@ def train(net, data, epochs, batch, lr, seed=0):
     return curve
 
 
-def evaluate_cell(theta, sample, n, charge_tol):
+def evaluate_cell(theta, sample, n, charge_tol=CHARGE_TOL):
     w = Worker.get(n)
     with torch.cuda.stream(w.stream):
         w.net.set_params(theta)
         cell, X0, v0 = wl.scf_cell(sample["id"], split="test")
-        rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
-        sp.sad_density(w.ctx, cell, rho_sad)
+        rho_sad, vloc = cell_start(w.ctx, cell)
         rho0 = torch.zeros_like(rho_sad)
-        used = w.net.predict_density(rho_sad, cell.n_elec, cell_dV(cell), rho0, charge_tol=charge_tol)
+        used = w.net.predict_density(rho_sad, vloc, cell.n_elec, cell_dV(cell), rho0, charge_tol=charge_tol)
         out, _ = solve(w.ctx, cell, X0, v0, rho_init=rho0)
         w.stream.synchronize()
     return dict(id=sample["id"], n_atoms=cell.n_atoms, used_net=used,
@@ -163,7 +184,9 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--threads", type=int, default=8)
-    ap.add_argument("--charge-tol", type=float, default=1e-2)
+    ap.add_argument("--charge-tol", type=float, default=CHARGE_TOL)
+    ap.add_argument("--train-tol", type=float, default=1e-5,
+                    help="SCF density-residual tolerance of the training targets (held-out cells: 1e-6)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--report", default=None)
@@ -172,8 +195,9 @@ def main():
     sp.load()
     n = (40, 40, 40)
     t0 = time.perf_counter()
-    train_data = generate(range(args.n_train), "train", args.threads, n)
-    test_data = generate(range(args.n_test), "test", args.threads, n)
+    train_all = generate(range(args.n_train), "train", args.threads, n, args.train_tol)
+    train_data = [d for d in train_all if d["converged"]]   # unconverged targets are left out
+    test_data = generate(range(args.n_test), "test", args.threads, n, 1e-6)
     t_data = time.perf_counter() - t0
     ctx = sp.Context(0)
     net = sp.DensityNet(ctx, n, max_batch=args.batch)
@@ -195,7 +219,7 @@ def main():
     report = {
         "n_train": args.n_train, "n_test": args.n_test, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
         "params": int(net.num_params), "loss_curve": curve,
-        "train_converged": int(sum(d["converged"] for d in train_data)),
+        "train_converged": len(train_data), "train_tol": args.train_tol,
         "test": {
             "mean_iterations_sad": float(it_sad.mean()), "mean_iterations_learned": float(it_net.mean()),
             "median_iterations_sad": float(np.median(it_sad)), "median_iterations_learned": float(np.median(it_net)),
@@ -219,7 +243,7 @@ def main():
 def init_params(rng, count):
     """He-normal weights (std sqrt(2 / (27 c_in))) in the host layout, zero biases; the
     last layer scaled by 0.1 so that the untrained correction is small."""
-    ch = (1, 16, 32, 32, 1)
+    ch = (2, 16, 32, 32, 1)
     parts = []
     for l, (ci, co) in enumerate(zip(ch[:-1], ch[1:])):
         std = math.sqrt(2.0 / (27 * ci)) * (0.1 if l == len(ch) - 2 else 1.0)

@@ -40,14 +40,20 @@ def _theta(seed):
 def _fields(seed, B):
     rng = np.random.default_rng(seed)
     xs = [np.abs(rng.standard_normal((N[2], N[1], N[0]))) * 1.5 for _ in range(B)]
+    us = [np.abs(rng.standard_normal((N[2], N[1], N[0]))) * 2.0 for _ in range(B)]
     ys = [np.maximum(x + 0.3 * rng.standard_normal(x.shape), 0.0) for x in xs]
-    xs = [x.astype(np.float32).astype(np.float64) for x in xs]
-    ys = [y.astype(np.float32).astype(np.float64) for y in ys]
-    return xs, ys
+    rt = lambda a: a.astype(np.float32).astype(np.float64)
+    return [rt(x) for x in xs], [rt(u) for u in us], [rt(y) for y in ys]
 
 
 def _dev(arrs):
     return torch.from_numpy(np.stack(arrs).astype(np.float32).reshape(-1)).cuda()
+
+
+def _dev_in(xs, us):
+    """Network input [cell][voxel][channel (x, u)]."""
+    return torch.from_numpy(np.stack([np.stack([x, u], axis=-1) for x, u in zip(xs, us)])
+                            .astype(np.float32).reshape(-1)).cuda()
 
 
 def test_sad_density_matches_oracle(ctx):
@@ -61,15 +67,15 @@ def test_sad_density_matches_oracle(ctx):
 
 def test_forward_matches_oracle(ctx):
     th = _theta(1)
-    xs, _ = _fields(2, 2)
+    xs, us, _ = _fields(2, 2)
     net = sp.DensityNet(ctx, N, max_batch=2)
     net.set_params(th)
     np.testing.assert_array_equal(net.get_params(), th.astype(np.float32))
     d = torch.zeros(2 * np.prod(N), dtype=torch.float32, device="cuda:0")
-    net.forward(_dev(xs), d)
+    net.forward(_dev_in(xs, us), d)
     got = d.cpu().numpy().reshape(2, N[2], N[1], N[0])
     for b in range(2):
-        _, (_, a, _) = dn.forward(th, xs[b])
+        _, (_, a, _) = dn.forward(th, xs[b], us[b])
         ref = a[-1][0]
         err = np.abs(got[b] - ref).max() / np.abs(ref).max()
         print(f"forward cell {b}: max rel err {err:.2e}")
@@ -78,11 +84,11 @@ def test_forward_matches_oracle(ctx):
 
 def test_loss_grad_matches_oracle(ctx):
     th = _theta(3)
-    xs, ys = _fields(4, 2)
+    xs, us, ys = _fields(4, 2)
     net = sp.DensityNet(ctx, N, max_batch=2)
     net.set_params(th)
-    loss, g = net.loss_grad(_dev(xs), _dev(ys))
-    lref, gref = dn.loss_and_grad(th, xs, ys)
+    loss, g = net.loss_grad(_dev_in(xs, us), _dev(ys))
+    lref, gref = dn.loss_and_grad(th, xs, us, ys)
     print(f"loss gpu {loss:.8e} oracle {lref:.8e}; grad max err {np.abs(g - gref).max() / np.abs(gref).max():.2e}")
     assert abs(loss - lref) <= 1e-5 * lref
     assert np.abs(g - gref).max() <= 2e-4 * np.abs(gref).max()
@@ -96,14 +102,14 @@ def test_loss_grad_matches_oracle(ctx):
 
 def test_adam_first_step(ctx):
     th = _theta(5)
-    xs, ys = _fields(6, 1)
+    xs, us, ys = _fields(6, 1)
     net = sp.DensityNet(ctx, N, max_batch=1)
     net.set_params(th)
-    _, g = net.loss_grad(_dev(xs), _dev(ys))
+    _, g = net.loss_grad(_dev_in(xs, us), _dev(ys))
     lr = 1e-3
     net.adam_step(lr)
     new = net.get_params().astype(np.float64)
-    _, gref = dn.loss_and_grad(th, xs, ys)
+    _, gref = dn.loss_and_grad(th, xs, us, ys)
     ref, _, _ = dn.adam_step(th, gref, np.zeros_like(th), np.zeros_like(th), 1, lr)
     big = np.abs(gref) > 1e-2 * np.abs(gref).max()
     np.testing.assert_allclose(new[big], ref[big], atol=2e-6 * lr + 1e-6 * np.abs(ref[big]).max())
@@ -118,19 +124,23 @@ def test_predict_density(ctx):
     rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
     sp.sad_density(ctx, cell, rho_sad)
     sad = rho_sad.cpu().numpy()
+    vl = torch.zeros_like(rho_sad)
+    sp.Hamiltonian(ctx, cell, sp.R64).get_vloc(vl)
+    vloc = vl.cpu().numpy()
     net = sp.DensityNet(ctx, n, max_batch=1)
     out = torch.zeros_like(rho_sad)
     # zero correction: the SAD density itself (through FP32 scaling)
     th = np.zeros(dn.num_params())
     th[-1] = 2.0
     net.set_params(th)
-    assert net.predict_density(rho_sad, cell.n_elec, dV, out)
+    assert net.predict_density(rho_sad, vl, cell.n_elec, dV, out)
     np.testing.assert_allclose(out.cpu().numpy(), sad, rtol=2e-7, atol=1e-7 * sad.max())
     # a trained-looking net against the oracle prediction
     th = _theta(8) * 0.2
     net.set_params(th)
-    used = net.predict_density(rho_sad, cell.n_elec, dV, out, charge_tol=0.5)
-    ref, uref = dn.predict_density(th, sad.reshape(n[2], n[1], n[0]), cell.n_elec, dV, charge_tol=0.5)
+    used = net.predict_density(rho_sad, vl, cell.n_elec, dV, out, charge_tol=0.5)
+    sh = (n[2], n[1], n[0])
+    ref, uref = dn.predict_density(th, sad.reshape(sh), vloc.reshape(sh), cell.n_elec, dV, charge_tol=0.5)
     assert used and uref
     np.testing.assert_allclose(out.cpu().numpy(), ref.reshape(-1), atol=2e-5 * ref.max())
     assert abs(out.sum().item() * dV - cell.n_elec) < 1e-9 * cell.n_elec
@@ -138,26 +148,26 @@ def test_predict_density(ctx):
     bad = th.copy()
     bad[100] = np.nan
     net.set_params(bad)
-    assert not net.predict_density(rho_sad, cell.n_elec, dV, out)
+    assert not net.predict_density(rho_sad, vl, cell.n_elec, dV, out)
     assert torch.equal(out, rho_sad)
     L = dn.unpack(np.zeros(dn.num_params()))
     for l in range(3):
         L[l][0][0, 0, 1, 1, 1] = 1.0
     L[3][0][0, 0, 1, 1, 1] = -2.0
     net.set_params(dn.pack(L))
-    ref, uref = dn.predict_density(dn.pack(L), sad.reshape(n[2], n[1], n[0]), cell.n_elec, dV, charge_tol=1e-2)
+    ref, uref = dn.predict_density(dn.pack(L), sad.reshape(sh), vloc.reshape(sh), cell.n_elec, dV, charge_tol=1e-2)
     assert not uref
     out.zero_()
-    assert not net.predict_density(rho_sad, cell.n_elec, dV, out, charge_tol=1e-2)
+    assert not net.predict_density(rho_sad, vl, cell.n_elec, dV, out, charge_tol=1e-2)
     assert torch.equal(out, rho_sad)
 
 
 def test_training_lowers_loss(ctx):
     th = _theta(9)
-    xs, ys = _fields(10, 4)
+    xs, us, ys = _fields(10, 4)
     net = sp.DensityNet(ctx, N, max_batch=4)
     net.set_params(th)
-    x, y = _dev(xs), _dev(ys)
+    x, y = _dev_in(xs, us), _dev(ys)
     first = net.train_step(x, y, 2e-3)
     for _ in range(40):
         last = net.train_step(x, y, 2e-3)
@@ -167,10 +177,10 @@ def test_training_lowers_loss(ctx):
 
 def test_error_paths(ctx):
     with pytest.raises(sp.SparcError) as e:
-        sp.DensityNet(ctx, (0, 4, 4))
+        sp.DensityNet(ctx, (8, 16, 16))
     assert e.value.status == sp.ESHAPE
     net = sp.DensityNet(ctx, N, max_batch=1)
-    x = torch.zeros(2 * int(np.prod(N)), dtype=torch.float32, device="cuda:0")
+    x = torch.zeros(4 * int(np.prod(N)), dtype=torch.float32, device="cuda:0")
     with pytest.raises(sp.SparcError) as e:
         net.forward(x, x.clone())
     assert e.value.status == sp.ESHAPE

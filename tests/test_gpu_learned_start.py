@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 
 from paper_1603_04339_amd import sparc as sp
 from paper_1603_04339_amd import workloads as wl
-from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS, cell_dV, solve
+from paper_1603_04339_amd.train_density_net import CHARGE_TOL, DEFAULT_WEIGHTS, cell_dV, cell_start, solve
 
 pytestmark = pytest.mark.gpu
 
@@ -38,10 +38,9 @@ def test_learned_start_saves_iterations(ctx):
     its_sad, its_net = [], []
     for cid in HELD_OUT:
         cell, X0, v0 = wl.scf_cell(cid, split="test")
-        rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
-        sp.sad_density(ctx, cell, rho_sad)
+        rho_sad, vloc = cell_start(ctx, cell)
         rho0 = torch.zeros_like(rho_sad)
-        used = net.predict_density(rho_sad, cell.n_elec, cell_dV(cell), rho0)
+        used = net.predict_density(rho_sad, vloc, cell.n_elec, cell_dV(cell), rho0, charge_tol=CHARGE_TOL)
         a, _ = solve(ctx, cell, X0, v0)
         b, _ = solve(ctx, cell, X0, v0, rho_init=rho0)
         de = abs(a["energy"] - b["energy"]) / cell.n_atoms

@@ -8,23 +8,24 @@ import pytest
 from oracle import density_net as dn
 
 
-def _fft_correlate(x, w):
-    """y[m] = sum_d w[d] x[m + d] for a 3x3x3 kernel on a periodic grid, via
-    the correlation theorem: y = ifft( fft(x) * conj(fft(K)) ) with K[d] = w[d]."""
+def _fft_correlate(x, w, q=1):
+    """y[m] = sum_d w[d] x[m + q d] for a 3x3x3 kernel with dilation q on a periodic
+    grid, via the correlation theorem: y = ifft( fft(x) * conj(fft(K)) ), K[q d] = w[d]."""
     K = np.zeros_like(x)
     for kz in range(3):
         for ky in range(3):
             for kx in range(3):
-                K[(kz - 1) % x.shape[0], (ky - 1) % x.shape[1], (kx - 1) % x.shape[2]] += w[kz, ky, kx]
+                K[(q * (kz - 1)) % x.shape[0], (q * (ky - 1)) % x.shape[1], (q * (kx - 1)) % x.shape[2]] += w[kz, ky, kx]
     return np.real(np.fft.ifftn(np.fft.fftn(x) * np.conj(np.fft.fftn(K))))
 
 
-def test_conv_single_channel_matches_fft():
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_conv_single_channel_matches_fft(q):
     rng = np.random.default_rng(0)
-    x = rng.standard_normal((5, 6, 7))
+    x = rng.standard_normal((9, 10, 11))
     w = rng.standard_normal((3, 3, 3))
-    y = dn.conv3d(x[None], w[None, None], np.array([0.25]))[0]
-    np.testing.assert_allclose(y, _fft_correlate(x, w) + 0.25, atol=1e-12)
+    y = dn.conv3d(x[None], w[None, None], np.array([0.25]), q)[0]
+    np.testing.assert_allclose(y, _fft_correlate(x, w, q) + 0.25, atol=1e-12)
 
 
 def test_conv_multichannel_is_sum_of_correlations():
@@ -32,9 +33,9 @@ def test_conv_multichannel_is_sum_of_correlations():
     x = rng.standard_normal((3, 4, 5, 6))
     W = rng.standard_normal((2, 3, 3, 3, 3))
     b = rng.standard_normal(2)
-    y = dn.conv3d(x, W, b)
+    y = dn.conv3d(x, W, b, 2)
     for co in range(2):
-        ref = b[co] + sum(_fft_correlate(x[ci], W[co, ci]) for ci in range(3))
+        ref = b[co] + sum(_fft_correlate(x[ci], W[co, ci], 2) for ci in range(3))
         np.testing.assert_allclose(y[co], ref, atol=1e-11)
 
 
@@ -45,17 +46,19 @@ def test_conv_shift_and_identity_taps():
     W[0, 0, 1, 1, 1] = 1.0
     np.testing.assert_array_equal(dn.conv3d(x, W, np.zeros(1)), x)
     W[:] = 0
-    W[0, 0, 2, 1, 0] = 1.0          # reads x at offset (+1, 0, -1)
-    y = dn.conv3d(x, W, np.zeros(1))
+    W[0, 0, 2, 1, 0] = 1.0          # reads x at offset q (+1, 0, -1)
     k, j, i = 1, 2, 3
+    y = dn.conv3d(x, W, np.zeros(1))
     assert y[0, k, j, i] == x[0, (k + 1) % 4, j, (i - 1) % 6]
+    y = dn.conv3d(x, W, np.zeros(1), 4)
+    assert y[0, k, j, i] == x[0, (k + 4) % 4, j, (i - 4) % 6]
 
 
 def test_param_count():
-    assert dn.num_params() == 448 + 13856 + 27680 + 865 == 42849
+    assert dn.num_params() == 880 + 13856 + 27680 + 865 == 43281
 
 
-def _small_net(rng, channels=(1, 3, 4, 2, 1)):
+def _small_net(rng, channels=(2, 3, 4, 2, 1)):
     theta = dn.init_params(rng, channels)
     theta += 0.05 * rng.standard_normal(theta.size)   # non-zero biases too
     return theta, channels
@@ -64,9 +67,11 @@ def _small_net(rng, channels=(1, 3, 4, 2, 1)):
 def test_loss_gradient_finite_differences():
     rng = np.random.default_rng(3)
     theta, ch = _small_net(rng)
-    xs = [np.abs(rng.standard_normal((4, 5, 3))) * 2 for _ in range(2)]
+    dil = (1, 2, 1, 2)
+    xs = [np.abs(rng.standard_normal((5, 6, 4))) * 2 for _ in range(2)]
+    us = [rng.standard_normal((5, 6, 4)) for _ in range(2)]
     ys = [x + 0.3 * rng.standard_normal(x.shape) for x in xs]
-    L0, g = dn.loss_and_grad(theta, xs, ys, ch)
+    L0, g = dn.loss_and_grad(theta, xs, us, ys, ch, dil)
     idx = rng.choice(theta.size, 40, replace=False)
     h = 1e-6
     for i in idx:
@@ -74,7 +79,7 @@ def test_loss_gradient_finite_differences():
         tp[i] += h
         tm = theta.copy()
         tm[i] -= h
-        fd = (dn.loss_and_grad(tp, xs, ys, ch)[0] - dn.loss_and_grad(tm, xs, ys, ch)[0]) / (2 * h)
+        fd = (dn.loss_and_grad(tp, xs, us, ys, ch, dil)[0] - dn.loss_and_grad(tm, xs, us, ys, ch, dil)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8, (i, fd, g[i])
 
 
@@ -83,8 +88,8 @@ def test_input_gradient_of_conv_finite_differences():
     x = rng.standard_normal((2, 3, 4, 5))
     W = rng.standard_normal((3, 2, 3, 3, 3))
     gy = rng.standard_normal((3, 3, 4, 5))
-    gx, gW, gb = dn.conv3d_backward(x, W, gy)
-    f = lambda xx: float((gy * dn.conv3d(xx, W, np.zeros(3))).sum())
+    gx, gW, gb = dn.conv3d_backward(x, W, gy, 2)
+    f = lambda xx: float((gy * dn.conv3d(xx, W, np.zeros(3), 2)).sum())
     for _ in range(10):
         c = tuple(rng.integers(0, s) for s in x.shape)
         xp = x.copy()
@@ -116,7 +121,7 @@ def test_predict_zero_correction_returns_sad():
     n_elec = float(rho.sum() * dV)
     theta = np.zeros(dn.num_params())
     theta[-1] = 3.0
-    out, used = dn.predict_density(theta, rho, n_elec, dV)
+    out, used = dn.predict_density(theta, rho, -rho, n_elec, dV)
     assert used
     np.testing.assert_allclose(out, rho, rtol=1e-12)
 
@@ -127,11 +132,12 @@ def test_predict_renormalises_and_falls_back():
     dV = 0.2
     n_elec = 10.0
     theta = dn.init_params(rng) * 0.01
-    out, used = dn.predict_density(theta, rho * (n_elec / (rho.sum() * dV)), n_elec, dV, charge_tol=0.5)
+    vloc = -np.abs(rng.standard_normal(rho.shape))
+    out, used = dn.predict_density(theta, rho * (n_elec / (rho.sum() * dV)), vloc, n_elec, dV, charge_tol=0.5)
     assert used and abs(out.sum() * dV - n_elec) < 1e-10 and np.all(out >= 0)
     bad = theta.copy()
     bad[5] = np.nan
-    out, used = dn.predict_density(bad, rho, n_elec, dV)
+    out, used = dn.predict_density(bad, rho, vloc, n_elec, dV)
     assert not used and np.array_equal(out, rho)
     # a correction that the final ReLU clips changes the charge: pass-through layers
     # give d = -2 x, so relu(x + d - mean(d)) = relu(2 - x) (x has mean 1) loses the
@@ -145,9 +151,9 @@ def test_predict_renormalises_and_falls_back():
     x = rho_n / (n_elec / (rho.size * dV))
     lost = np.maximum(x - 2.0, 0.0).sum() / x.sum()
     assert lost > 0.01
-    out, used = dn.predict_density(dn.pack(L), rho_n, n_elec, dV, charge_tol=1e-2)
+    out, used = dn.predict_density(dn.pack(L), rho_n, vloc, n_elec, dV, charge_tol=1e-2)
     assert not used and np.array_equal(out, rho_n)
-    out, used = dn.predict_density(dn.pack(L), rho_n, n_elec, dV, charge_tol=0.5)
+    out, used = dn.predict_density(dn.pack(L), rho_n, vloc, n_elec, dV, charge_tol=0.5)
     assert used
     np.testing.assert_allclose(out, np.maximum(2.0 - x, 0.0) * n_elec / (np.maximum(2.0 - x, 0.0).sum() * dV),
                                rtol=1e-12)
