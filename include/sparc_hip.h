@@ -50,10 +50,11 @@ typedef enum {
 typedef enum { SPARC_R64 = 0, SPARC_R32 = 1, SPARC_C128 = 2, SPARC_C64 = 3 } sparc_dtype;
 
 /* Precision of the N_d-long Rayleigh–Ritz contractions; the Cholesky factors,
- * the subspace eigensolve and all N_s x N_s work stay in FP64. */
+ * the subspace eigensolve and all N_s x N_s work stay in FP64.  One mode: the
+ * contractions run on MFMA in the element type of the orbitals (FP64 or FP32,
+ * FP32 accumulation for FP32); other values are rejected with EINVAL. */
 typedef enum {
-  SPARC_GEMM_NATIVE = 0, /* in the element type of the orbitals (FP64 or FP32)     */
-  SPARC_GEMM_BF16X3 = 1  /* FP32 orbitals split into bf16 hi + lo, 3 MFMA products  */
+  SPARC_GEMM_NATIVE = 0
 } sparc_gemm_mode;
 
 /* Uniform periodic grid on an axis-aligned cuboid (Sec. 3.1): n grid points and

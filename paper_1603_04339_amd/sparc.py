@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libsparc_hip.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, ENOTSPD, ENOCONV, EDEVICE, ENAN = 0, -1, -2, -3, -4, -5, -6, -7
 R64, R32, C128, C64 = 0, 1, 2, 3
-GEMM_NATIVE, GEMM_BF16X3 = 0, 1
+GEMM_NATIVE = 0
 OP_APPLY, OP_FILTER, OP_RR, OP_LANCZOS = 0, 1, 2, 3
 
 TORCH_DTYPE = {R64: torch.float64, R32: torch.float32, C128: torch.complex128, C64: torch.complex64}

@@ -263,6 +263,9 @@ def test_error_paths(ctx):
     # a zero column or a NaN cannot be orthonormalised
     ritz = torch.zeros(3, dtype=torch.float64, device="cuda:0")
     wr = sp.workspace(ham, 3, sp.OP_RR)
+    with pytest.raises(sp.SparcError) as e:
+        sp.rayleigh_ritz(ham, to_dev(rng.standard_normal((3, 1000))), ritz, wr, mode=1)
+    assert e.value.status == sp.EINVAL
     for bad in (0.0, float("nan")):
         Xd = to_dev(rng.standard_normal((3, 1000)))
         Xd[1] = bad
