@@ -34,6 +34,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "filtered grid-pt·states/s FP64 vs mixed; SCF wall time to 1e-5 Ha/atom"
+
+# HBM traffic of the FP64 c2 stencil-step launch, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hstep_c2_96cubed_f64.md);
+# valid only for the kernel source it was measured on (checked by hash, else null)
+HSTEP_TRAFFIC = {"bytes_per_launch": 1.804335e+10, "kernel_sources_sha256": "f43015aaa9f4b14c87044b62f3d3be618527f915653eff6bae422b1dd1fe9e10",
+                 "profile": "profiles/hstep_c2_96cubed_f64.md"}
 UNIT = "grid-pt·states/s"
 HBM_PEAK_GBS = 8000.0
 
@@ -67,11 +73,22 @@ def step_bytes(n_d, n_s, eb, degree):
     return n_d * n_s * eb * (2 + 3 * (degree - 1))
 
 
-def roofline_obj(kernel, total_bytes, ms, n):
+def roofline_obj(kernel, total_bytes, ms, n, traffic=None):
     achieved = (total_bytes / n) / (ms / n * 1e-3) / 1e9
     return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": ms / n, "launches": n,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_launch_ms": ms / n, "launches": n,
             "bytes_per_launch": total_bytes / n}
+
+
+def measured_traffic():
+    """Counter-measured bytes per c2 FP64 stencil launch, if the kernel sources are
+    the ones the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hstep_api.hpp", "hstep_impl.hpp"):
+        with open(os.path.join(ROOT, "paper_1603_04339_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return HSTEP_TRAFFIC["bytes_per_launch"] if h.hexdigest() == HSTEP_TRAFFIC["kernel_sources_sha256"] else None
 
 
 # ---------------------------------------------------------------------------------------------
@@ -135,7 +152,9 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
     return {
         "value": nd * ns / (t_total / steps), "ms_per_step": 1e3 * t_total / steps,
         "filter_ms": filt, "filter_throughput": nd * ns / (filt * 1e-3),
-        "roofline": roofline_obj("hstep (12th-order stencil + V_eff + recurrence, LDS-tiled)", total, hs_ms, hs_n),
+        "roofline": roofline_obj("hstep (12th-order stencil + V_eff + recurrence, LDS-tiled)", total, hs_ms, hs_n,
+                                 measured_traffic() if (dt == sp.R64 and tuple(cell.n) == (96, 96, 96)
+                                                        and cell.n_s == 512) else None),
         "ritz": ritz.cpu().numpy(), "bounds": (lmin, lmax), "n_proj": ham.n_proj,
     }
 
@@ -251,6 +270,7 @@ def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None):
     else:
         dt = sp.R64 if precision == "f64" else sp.R32
         tdt = torch.float64 if precision == "f64" else torch.float32
+    sp.set_autotune(ctx, True)   # the plan times every tile shape on the largest problem
     hams, Xs, bounds, ritz = [], [], [], []
     for cell, k, X0, v0, _ in probs:
         kk = k if k is not None else (0.0, 0.0, 0.0)

@@ -149,7 +149,7 @@ int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alph
   return fail(SPARC_EINVAL, "nl_project: bad dtype");
 }
 
-int heuristic_tile(int n1, int n2, size_t /*elem_size*/) {
+int heuristic_tile(int n1, int n2, size_t elem_size) {
   const char* env = getenv("SPARC_HSTEP_TILE");
   if (env) {
     int t = atoi(env);
@@ -162,7 +162,9 @@ int heuristic_tile(int n1, int n2, size_t /*elem_size*/) {
     if (tx * ty > 512) continue;
     const double waste = (double)((n1 + tx - 1) / tx * tx) / n1 * ((n2 + ty - 1) / ty * ty) / n2;
     const double halo = 1.0 + 12.0 * (tx + ty) / (double)(tx * ty) * 0.25;
-    const double cost = waste * halo;
+    // rows shorter than 128 bytes split the tile's loads into short segments
+    const double seg = (tx * elem_size < 128) ? 1.5 : 1.0;
+    const double cost = waste * halo * seg;
     if (cost < best_cost - 1e-12) { best_cost = cost; best = t; }
   }
   return best;
