@@ -3,7 +3,8 @@
 //   * column-scaled Cholesky factorisation and triangular inverse (the
 //     orthonormalising transform of a Cholesky-QR pass);
 //   * Hermitian eigensolver: Householder reduction to a real symmetric
-//     tridiagonal (one work-group, matrix resident in L2), eigenvalues by Sturm
+//     tridiagonal (blocked: one work-group per 32-column panel, the trailing
+//     update on many work-groups; matrix resident in L2), eigenvalues by Sturm
 //     bisection (one thread per eigenvalue), eigenvectors by inverse iteration
 //     with pivoted tridiagonal LU (one thread per cluster of close eigenvalues,
 //     Gram-Schmidt inside a cluster), and the back-transformation by the
@@ -477,6 +478,176 @@ __global__ __launch_bounds__(1024) void hetrd2_kernel(int n, T* __restrict__ A, 
   if (tid == 0) d[n - 1] = re_(A[(n - 1) + (int64_t)(n - 1) * n]);
 }
 
+// Blocked Householder tridiagonalisation (lower; panel / trailing-update split).
+// latrd_kernel reduces columns i0 .. i0+jb-1 with one work-group: column i is first
+// brought up to date with the panel's earlier reflectors (A(i:n, i) -= V W(i)^H +
+// W V(i)^H), its reflector is formed as in hetrd2_kernel, and the product with the
+// trailing block reads that block as it stood before the panel, corrected by
+// -V (W^H v) - W (V^H v).  The trailing block is read once per column instead of read
+// twice and written once.  trail_kernel then applies A -= V W^H + W V^H to the block
+// past the panel on many work-groups.  V, W: [jb][n] (vector k contiguous, zero above
+// its first row); storage of the reflectors in A, tau, d and e as hetrd2_kernel.
+template <typename T>
+__global__ __launch_bounds__(1024) void latrd_kernel(int n, int i0, int jb, T* __restrict__ A, double* __restrict__ d,
+                                                     double* __restrict__ e, T* __restrict__ tau, T* __restrict__ V,
+                                                     T* __restrict__ W) {
+  extern __shared__ char smem[];
+  T* v = (T*)smem;           // [n]
+  T* y = v + n;              // [n]
+  T* part = y + n;           // [16][n]
+  __shared__ T pq[2][64];    // pq[0][k] = W_k^H v, pq[1][k] = V_k^H v
+  __shared__ double red[16];
+  __shared__ T s_tau, s_scale;
+  __shared__ double s_beta;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+  for (int j = 0; j < jb; ++j) {
+    const int i = i0 + j, r0 = i + 1;
+    // (1) column i up to date with the panel's earlier reflectors
+    if (j > 0) {
+      for (int r = i + tid; r < n; r += nt) {
+        T a = A[r + (int64_t)i * n];
+        for (int k = 0; k < j; ++k) {
+          const int64_t o = (int64_t)k * n;
+          a = sub_(a, add_(mul_(V[o + r], conj_(W[o + i])), mul_(W[o + r], conj_(V[o + i]))));
+        }
+        A[r + (int64_t)i * n] = a;
+      }
+      __syncthreads();
+    }
+    // (2) reflector of A(i+2:n, i) (as hetrd2_kernel)
+    double xn = 0;
+    for (int r = i + 2 + tid; r < n; r += nt) {
+      T x = A[r + (int64_t)i * n];
+      xn += re_(mul_(conj_(x), x));
+    }
+    xn = block_sum(xn, red);
+    if (tid == 0) {
+      T alpha = A[i + 1 + (int64_t)i * n];
+      double ar = re_(alpha);
+      double ai = 0;
+      if constexpr (sizeof(T) == 16) ai = ((cd&)alpha).im;
+      if (xn == 0.0 && ai == 0.0) {
+        s_tau = mkT<T>(0.0, 0.0);
+        s_beta = ar;
+        s_scale = mkT<T>(0.0, 0.0);
+      } else {
+        double beta = -copysign(sqrt(ar * ar + ai * ai + xn), ar);
+        s_beta = beta;
+        s_tau = mkT<T>((beta - ar) / beta, -ai / beta);
+        double dr = ar - beta, di = ai, den = dr * dr + di * di;
+        s_scale = mkT<T>(dr / den, -di / den);
+      }
+      d[i] = re_(A[i + (int64_t)i * n]);
+    }
+    __syncthreads();
+    const T tau_i = s_tau;
+    const double beta = s_beta;
+    const bool trivial = re_(mul_(conj_(tau_i), tau_i)) == 0.0;
+    T* Vj = V + (int64_t)j * n;
+    T* Wj = W + (int64_t)j * n;
+    for (int r = tid; r < n; r += nt) {
+      T val = mkT<T>(0.0, 0.0);
+      if (r == r0) {
+        val = mkT<T>(1.0, 0.0);
+      } else if (r > r0) {
+        val = mul_(A[r + (int64_t)i * n], s_scale);
+        A[r + (int64_t)i * n] = val;
+      }
+      if (r >= r0) v[r] = val;
+      Vj[r] = val;
+    }
+    __syncthreads();
+    if (!trivial) {
+      // y = A_old(r0:n, r0:n) v: partial products over this wave's columns
+      for (int rb = r0; rb < n; rb += 64) {
+        const int r = rb + lane;
+        T acc = mkT<T>(0.0, 0.0);
+        if (r < n) {
+          int c = r0 + wave;
+#pragma unroll 4
+          for (; c < n; c += nwave) acc = add_(acc, mul_(A[r + (int64_t)c * n], v[c]));
+          part[wave * n + r] = acc;
+        }
+      }
+      // W_k^H v and V_k^H v for the panel's earlier reflectors: one wave per product
+      for (int task = wave; task < 2 * j; task += nwave) {
+        const int k = task >> 1;
+        const T* u = ((task & 1) ? V : W) + (int64_t)k * n;
+        double pr = 0, pi = 0;
+        for (int r = r0 + lane; r < n; r += 64) {
+          T t = mul_(conj_(u[r]), v[r]);
+          pr += re_(t);
+          if constexpr (sizeof(T) == 16) pi += ((cd&)t).im;
+        }
+        pr = wave_sum(pr);
+        if constexpr (sizeof(T) == 16) pi = wave_sum(pi);
+        if (lane == 0) pq[task & 1][k] = mkT<T>(pr, pi);
+      }
+      __syncthreads();
+      for (int r = r0 + tid; r < n; r += nt) {
+        T acc = mkT<T>(0.0, 0.0);
+        for (int q = 0; q < nwave; ++q) acc = add_(acc, part[q * n + r]);
+        for (int k = 0; k < j; ++k) {
+          const int64_t o = (int64_t)k * n;
+          acc = sub_(acc, add_(mul_(V[o + r], pq[0][k]), mul_(W[o + r], pq[1][k])));
+        }
+        y[r] = mul_(tau_i, acc);
+      }
+      __syncthreads();
+      double pr = 0, pi = 0;
+      for (int r = r0 + tid; r < n; r += nt) {
+        T t = mul_(conj_(y[r]), v[r]);
+        pr += re_(t);
+        if constexpr (sizeof(T) == 16) pi += ((cd&)t).im;
+      }
+      pr = block_sum(pr, red);
+      if constexpr (sizeof(T) == 16) pi = block_sum(pi, red);
+      const T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(pr, pi)));
+      for (int r = tid; r < n; r += nt) Wj[r] = (r >= r0) ? add_(y[r], mul_(a2, v[r])) : mkT<T>(0.0, 0.0);
+    } else {
+      for (int r = tid; r < n; r += nt) Wj[r] = mkT<T>(0.0, 0.0);
+    }
+    if (tid == 0) {
+      e[i] = beta;
+      tau[i] = tau_i;
+    }
+    __syncthreads();
+  }
+}
+
+// A(c0:n, c0:n) -= V W^H + W V^H over the jb panel reflectors; 16 x 16 tiles
+template <typename T>
+__global__ __launch_bounds__(256) void trail_kernel(int n, int c0, int jb, T* __restrict__ A, const T* __restrict__ V,
+                                                    const T* __restrict__ W) {
+  __shared__ T sVr[32][16], sWr[32][16], sVc[32][16], sWc[32][16];
+  const int tid = threadIdx.x;
+  const int r_base = c0 + blockIdx.x * 16, c_base = c0 + blockIdx.y * 16;
+  for (int idx = tid; idx < jb * 16; idx += 256) {
+    const int k = idx / 16, t = idx % 16;
+    const int r = r_base + t, c = c_base + t;
+    const int64_t o = (int64_t)k * n;
+    sVr[k][t] = r < n ? V[o + r] : mkT<T>(0.0, 0.0);
+    sWr[k][t] = r < n ? W[o + r] : mkT<T>(0.0, 0.0);
+    sVc[k][t] = c < n ? V[o + c] : mkT<T>(0.0, 0.0);
+    sWc[k][t] = c < n ? W[o + c] : mkT<T>(0.0, 0.0);
+  }
+  __syncthreads();
+  const int tx = tid % 16, ty = tid / 16;
+  const int r = r_base + tx, c = c_base + ty;
+  if (r < n && c < n) {
+    T acc = A[r + (int64_t)c * n];
+    for (int k = 0; k < jb; ++k)
+      acc = sub_(acc, add_(mul_(sVr[k][tx], conj_(sWc[k][ty])), mul_(sWr[k][tx], conj_(sVc[k][ty]))));
+    A[r + (int64_t)c * n] = acc;
+  }
+}
+
+template <typename T>
+__global__ void last_diag_kernel(int n, const T* __restrict__ A, double* __restrict__ d) {
+  if (threadIdx.x == 0) d[n - 1] = re_(A[(n - 1) + (int64_t)(n - 1) * n]);
+}
+
 // ------------------------------------------------------------ tridiagonal eigenvalues (bisection)
 __device__ int sturm_count(int n, const double* d, const double* e2, double x, double pivmin) {
   double q = d[0] - x;
@@ -687,7 +858,23 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
   double* scr = (double*)take((size_t)5 * n * n * 8);
   int* piv = (int*)take((size_t)n * n * 4);
   const size_t lds2 = (size_t)18 * n * sizeof(T);
-  if (n == 1) {
+  constexpr int NB = 32;   // panel width of the blocked reduction
+  if (n >= 64 && lds2 <= 150 * 1024) {
+    T* Vb = (T*)scr;       // [NB][n] each; the inverse-iteration scratch is free until then
+    T* Wb = Vb + (size_t)NB * n;
+    SPARC_HIP(hipFuncSetAttribute((const void*)latrd_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    for (int i0 = 0; i0 < n - 1; i0 += NB) {
+      const int jb = std::min(NB, n - 1 - i0);
+      latrd_kernel<T><<<1, 1024, lds2, s>>>(n, i0, jb, A, d, e, tau, Vb, Wb);
+      SPARC_TRY(check_launch("latrd_kernel"));
+      const int c0 = i0 + jb, m = n - c0;
+      if (m > 0) {
+        trail_kernel<T><<<dim3((m + 15) / 16, (m + 15) / 16), 256, 0, s>>>(n, c0, jb, A, Vb, Wb);
+        SPARC_TRY(check_launch("trail_kernel"));
+      }
+    }
+    last_diag_kernel<T><<<1, 64, 0, s>>>(n, A, d);
+  } else if (n == 1) {
     hetrd_kernel<T><<<1, 64, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
   } else if (lds2 <= 150 * 1024) {
     SPARC_HIP(hipFuncSetAttribute((const void*)hetrd2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
