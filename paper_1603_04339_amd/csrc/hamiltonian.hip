@@ -25,10 +25,12 @@ __global__ __launch_bounds__(256) void nl_scatter_kernel(int n_pts, const int32_
                                                          const E* __restrict__ alpha, int lda, int n_s,
                                                          typename elem<E>::real a, const double* a_dev,
                                                          E* __restrict__ y, int64_t ldy) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // orbital groups fastest in the grid: consecutive work-groups share the same nodes'
+  // entry lists (from L2)
+  const int i = blockIdx.y * blockDim.x + threadIdx.x;
   if (i >= n_pts) return;
   if (a_dev) a = (typename elem<E>::real)(*a_dev);
-  const int nb0 = blockIdx.y * NB;
+  const int nb0 = blockIdx.x * NB;
   const int64_t g = pts[i];
   const int e0 = ptr[i], ne = ptr[i + 1] - e0;
   E acc[NB];
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x,
 }
 
 // projections are stored [projector][orbital] with the orbital count padded to a multiple of 8
-static inline int alpha_ld(int32_t n_s) { return ((n_s + 7) / 8) * 8; }
+static inline int alpha_ld(int32_t n_s) { return ((n_s + 15) / 16) * 16; }
 
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s) {
   return (size_t)std::max(H->n_proj, 1) * (size_t)alpha_ld(n_s) * elem_bytes(H->dtype);
@@ -230,8 +232,9 @@ static int nl_scatter_t(sparc_ham* H, const void* alpha, int32_t n_s, double a, 
                         int64_t ldo) {
   typedef typename elem<E>::real R;
   if (H->n_proj == 0 || H->n_nlpts == 0) return SPARC_OK;
-  constexpr int NB = 8;
-  dim3 grid((unsigned)((H->n_nlpts + 255) / 256), (unsigned)((n_s + NB - 1) / NB));
+  constexpr int NB = 16;
+  if ((H->n_nlpts + 255) / 256 > 65535) return fail(SPARC_ESHAPE, "nl_scatter: too many projector nodes");
+  dim3 grid((unsigned)((n_s + NB - 1) / NB), (unsigned)((H->n_nlpts + 255) / 256));
   int t = timer_begin(H->ctx, "nl_scatter");
   nl_scatter_kernel<E, NB><<<grid, 256, 0, H->ctx->stream>>>(
       (int)H->n_nlpts, H->nl_pts, H->nl_ptr, H->ent_proj, (const E*)H->ent_coef, (const E*)alpha, alpha_ld(n_s), n_s,
