@@ -8,7 +8,7 @@
 //     bisection (one thread per eigenvalue), eigenvectors by inverse iteration
 //     with pivoted tridiagonal LU (one thread per cluster of close eigenvalues,
 //     Gram-Schmidt inside a cluster), and the back-transformation by the
-//     Householder reflectors (one work-group per block of columns).
+//     Householder reflectors (one wave per column).
 // Matrices are column-major with leading dimension n; complex matrices are
 // interleaved (re, im).
 #include <algorithm>
@@ -97,32 +97,33 @@ __global__ __launch_bounds__(256) void chol_scale_kernel(int n, const T* __restr
 template <typename T>
 __global__ __launch_bounds__(256) void chol_diag_kernel(int n, T* __restrict__ S, int k0, int kb,
                                                         T* __restrict__ Rinv, int* info) {
-  __shared__ T a[CB * CB];
-  __shared__ T r[CB * CB];
+  constexpr int LD = CB + 1;   // padded: column-strided accesses spread over the banks
+  __shared__ T a[CB * LD];
+  __shared__ T r[CB * LD];
   __shared__ int s_fail;
   if (*info != 0) return;
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
     int i = idx % kb, j = idx / kb;
-    a[idx] = (i <= j) ? S[(k0 + i) + (int64_t)(k0 + j) * n] : mkT<T>(0.0, 0.0);
+    a[i + j * LD] = (i <= j) ? S[(k0 + i) + (int64_t)(k0 + j) * n] : mkT<T>(0.0, 0.0);
   }
   if (tid == 0) s_fail = 0;
   __syncthreads();
   for (int k = 0; k < kb; ++k) {
     if (tid == 0) {
-      double akk = re_(a[k + k * kb]);
+      double akk = re_(a[k + k * LD]);
       if (!(akk > 1e-15) || !isfinite(akk)) s_fail = k0 + k + 1;  // unit-diagonal S: relative floor
-      else a[k + k * kb] = mkT<T>(sqrt(akk), 0.0);
+      else a[k + k * LD] = mkT<T>(sqrt(akk), 0.0);
     }
     __syncthreads();
     if (s_fail) break;
-    const double rinv = 1.0 / re_(a[k + k * kb]);
-    for (int j = k + 1 + tid; j < kb; j += blockDim.x) a[k + j * kb] = rscale(rinv, a[k + j * kb]);
+    const double rinv = 1.0 / re_(a[k + k * LD]);
+    for (int j = k + 1 + tid; j < kb; j += blockDim.x) a[k + j * LD] = rscale(rinv, a[k + j * LD]);
     __syncthreads();
     const int m = kb - k - 1;
     for (int idx = tid; idx < m * m; idx += blockDim.x) {
       int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (i <= j) a[i + j * kb] = sub_(a[i + j * kb], mul_(conj_(a[k + i * kb]), a[k + j * kb]));
+      if (i <= j) a[i + j * LD] = sub_(a[i + j * LD], mul_(conj_(a[k + i * LD]), a[k + j * LD]));
     }
     __syncthreads();
   }
@@ -130,24 +131,23 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(int n, T* __restrict__ S
     if (tid == 0) *info = s_fail;
     return;
   }
-  // R11^{-1}: column j by back substitution, one thread per column
-  if (tid < kb) {
-    const int j = tid;
-    for (int i = kb - 1; i >= 0; --i) {
+  // R11^{-1} row by row from the bottom; the columns of a row in parallel
+  for (int i = kb - 1; i >= 0; --i) {
+    for (int j = tid; j < kb; j += blockDim.x) {
       T x = mkT<T>(0.0, 0.0);
-      if (i <= j) {
-        T s = mkT<T>(i == j ? 1.0 : 0.0, 0.0);
-        for (int k = i + 1; k <= j; ++k) s = sub_(s, mul_(a[i + k * kb], r[k + j * kb]));
-        x = rscale(1.0 / re_(a[i + i * kb]), s);
+      if (j >= i) {
+        T sum = mkT<T>(i == j ? 1.0 : 0.0, 0.0);
+        for (int k = i + 1; k <= j; ++k) sum = sub_(sum, mul_(a[i + k * LD], r[k + j * LD]));
+        x = rscale(1.0 / re_(a[i + i * LD]), sum);
       }
-      r[i + j * kb] = x;
+      r[i + j * LD] = x;
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
     int i = idx % kb, j = idx / kb;
-    if (i <= j) S[(k0 + i) + (int64_t)(k0 + j) * n] = a[idx];
-    Rinv[idx] = r[idx];
+    if (i <= j) S[(k0 + i) + (int64_t)(k0 + j) * n] = a[i + j * LD];
+    Rinv[idx] = r[i + j * LD];
   }
 }
 
@@ -155,13 +155,13 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(int n, T* __restrict__ S
 template <typename T>
 __global__ __launch_bounds__(256) void chol_panel_kernel(int n, T* __restrict__ S, int k0, int kb,
                                                          const T* __restrict__ Rinv, const int* info) {
-  __shared__ T ri[CB * CB];
+  __shared__ T riT[CB * CB];   // riT[i + l kb] = Rinv[l + i kb]: threads of consecutive i read consecutive words
   __shared__ T col[CB * CB];
   if (*info != 0) return;
   const int c0 = k0 + kb + blockIdx.x * CB;
   const int nc = min(CB, n - c0);
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < kb * kb; idx += blockDim.x) ri[idx] = Rinv[idx];
+  for (int idx = tid; idx < kb * kb; idx += blockDim.x) riT[(idx / kb) + (idx % kb) * kb] = Rinv[idx];
   for (int idx = tid; idx < kb * nc; idx += blockDim.x) {
     int l = idx % kb, c = idx / kb;
     col[idx] = S[(k0 + l) + (int64_t)(c0 + c) * n];
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int n, T* __restrict__ 
   for (int idx = tid; idx < kb * nc; idx += blockDim.x) {
     int i = idx % kb, c = idx / kb;
     T acc = mkT<T>(0.0, 0.0);
-    for (int l = 0; l <= i; ++l) acc = add_(acc, mul_(conj_(ri[l + i * kb]), col[l + c * kb]));
+    for (int l = 0; l <= i; ++l) acc = add_(acc, mul_(conj_(riT[i + l * kb]), col[l + c * kb]));
     S[(k0 + i) + (int64_t)(c0 + c) * n] = acc;
   }
 }
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(int n, T* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(256) void chol_syrk_kernel(int n, T* __restrict__ S, int k0, int kb, int tiles,
                                                         const int* info) {
-  __shared__ T pa[CB * CB];
+  __shared__ T paT[CB * CB];   // paT[i + l CB]: threads of consecutive i read consecutive words
   __shared__ T pb[CB * CB];
   if (*info != 0) return;
   // upper-triangular tile enumeration
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(int n, T* __restrict__ S
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kb * CB; idx += blockDim.x) {
     int l = idx % kb, c = idx / kb;
-    pa[idx] = (c < ni) ? S[(k0 + l) + (int64_t)(i0 + c) * n] : mkT<T>(0.0, 0.0);
+    paT[c + l * CB] = (c < ni) ? S[(k0 + l) + (int64_t)(i0 + c) * n] : mkT<T>(0.0, 0.0);
     pb[idx] = (c < nj) ? S[(k0 + l) + (int64_t)(j0 + c) * n] : mkT<T>(0.0, 0.0);
   }
   __syncthreads();
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(int n, T* __restrict__ S
     int i = idx % CB, j = idx / CB;
     if (i >= ni || j >= nj || i0 + i > j0 + j) continue;
     T acc = mkT<T>(0.0, 0.0);
-    for (int l = 0; l < kb; ++l) acc = add_(acc, mul_(conj_(pa[l + i * kb]), pb[l + j * kb]));
+    for (int l = 0; l < kb; ++l) acc = add_(acc, mul_(conj_(paT[i + l * CB]), pb[l + j * kb]));
     T* sp = &S[(i0 + i) + (int64_t)(j0 + j) * n];
     *sp = sub_(*sp, acc);
   }
@@ -797,44 +797,33 @@ __global__ void inviter_kernel(int n, const double* __restrict__ d, const double
 template <typename T>
 __global__ __launch_bounds__(256) void ormtr_kernel(int n, const T* __restrict__ A, const T* __restrict__ tau,
                                                     const double* __restrict__ Y, T* __restrict__ Z) {
-  constexpr int NC = 16;
-  __shared__ double part_r[16][NC], part_i[16][NC];
-  __shared__ T s[NC];
-  const int c0 = blockIdx.x * NC;
-  const int tid = threadIdx.x, col = tid % NC, grp = tid / NC;
-  for (int idx = tid; idx < n * NC; idx += 256) {
-    int r = idx % n, c = c0 + idx / n;
-    if (c < n) Z[r + (int64_t)c * n] = mkT<T>(Y[r + (int64_t)c * n], 0.0);
-  }
-  __syncthreads();
+  // one wave per column z of Z: z = H_0 H_1 ... H_{n-2} y, the reflectors applied from
+  // the last one; row r is always handled by lane r % 64, so each lane only re-reads
+  // what it wrote itself and the wave needs no barrier
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;
+  T* __restrict__ z = Z + (int64_t)c * n;
+  for (int r = lane; r < n; r += 64) z[r] = mkT<T>(Y[r + (int64_t)c * n], 0.0);
   for (int i = n - 2; i >= 0; --i) {
-    const T ti = tau[i];
-    const int c = c0 + col;
+    const T* __restrict__ v = A + (int64_t)i * n;
+    const int rb = (i + 1) & ~63;
     double sr = 0, si = 0;
-    if (c < n) {
-      for (int r = i + 1 + grp; r < n; r += 16) {
-        T vr = (r == i + 1) ? mkT<T>(1.0, 0.0) : A[r + (int64_t)i * n];
-        T p = mul_(conj_(vr), Z[r + (int64_t)c * n]);
-        sr += re_(p);
-        if constexpr (sizeof(T) == 16) si += ((cd&)p).im;
-      }
+    for (int r = rb + lane; r < n; r += 64) {
+      if (r <= i) continue;
+      const T vr = (r == i + 1) ? mkT<T>(1.0, 0.0) : v[r];
+      const T p = mul_(conj_(vr), z[r]);
+      sr += re_(p);
+      if constexpr (sizeof(T) == 16) si += ((const cd&)p).im;
     }
-    part_r[grp][col] = sr;
-    part_i[grp][col] = si;
-    __syncthreads();
-    if (tid < NC) {
-      double a = 0, b = 0;
-      for (int g = 0; g < 16; ++g) { a += part_r[g][tid]; b += part_i[g][tid]; }
-      s[tid] = mul_(ti, mkT<T>(a, b));
+    sr = wave_sum(sr);
+    if constexpr (sizeof(T) == 16) si = wave_sum(si);
+    const T sc = mul_(tau[i], mkT<T>(sr, si));
+    for (int r = rb + lane; r < n; r += 64) {
+      if (r <= i) continue;
+      const T vr = (r == i + 1) ? mkT<T>(1.0, 0.0) : v[r];
+      z[r] = sub_(z[r], mul_(vr, sc));
     }
-    __syncthreads();
-    if (c < n) {
-      for (int r = i + 1 + grp; r < n; r += 16) {
-        T vr = (r == i + 1) ? mkT<T>(1.0, 0.0) : A[r + (int64_t)i * n];
-        Z[r + (int64_t)c * n] = sub_(Z[r + (int64_t)c * n], mul_(vr, s[col]));
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -889,7 +878,7 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
   SPARC_TRY(check_launch("bisect_kernel"));
   inviter_kernel<<<(n + 63) / 64, 64, 0, s>>>(n, d, e, w, tn, Y, scr, piv);
   SPARC_TRY(check_launch("inviter_kernel"));
-  ormtr_kernel<T><<<(n + 15) / 16, 256, 0, s>>>(n, A, tau, Y, Z);
+  ormtr_kernel<T><<<(n + 3) / 4, 256, 0, s>>>(n, A, tau, Y, Z);
   return check_launch("ormtr_kernel");
 }
 
