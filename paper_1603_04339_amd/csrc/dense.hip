@@ -661,136 +661,171 @@ __device__ int sturm_count(int n, const double* d, const double* e2, double x, d
   return cnt;
 }
 
-__global__ void bisect_kernel(int n, const double* __restrict__ d, const double* __restrict__ e,
-                              double* __restrict__ w, double* __restrict__ e2g) {
+// one wave per eigenvalue (4 per work-group): each round evaluates the Sturm count at 64
+// interior points of the current interval (one per lane) and keeps the sub-interval
+// where the count crosses j, so the interval shrinks 65-fold per round instead of 2-fold
+__global__ __launch_bounds__(256) void bisect_kernel(int n, const double* __restrict__ d, const double* __restrict__ e,
+                                                     double* __restrict__ w, double* __restrict__ e2g) {
   extern __shared__ double sm[];
   double* ds = sm;
   double* e2 = sm + n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  __shared__ double red[3][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < n; i += blockDim.x) {
     ds[i] = d[i];
     e2[i] = (i < n - 1) ? e[i] * e[i] : 0.0;
   }
   __syncthreads();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  // Gershgorin interval and pivot floor
-  double lo = ds[0], hi = ds[0], emax = 0;
-  for (int i = 0; i < n; ++i) {
+  // Gershgorin interval and pivot floor (block-wide min / max)
+  double lo = 1e300, hi = -1e300, emax = 0;
+  for (int i = tid; i < n; i += blockDim.x) {
     double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + (i < n - 1 ? sqrt(e2[i]) : 0.0);
     lo = fmin(lo, ds[i] - r);
     hi = fmax(hi, ds[i] + r);
     emax = fmax(emax, e2[i]);
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+    emax = fmax(emax, __shfl_xor(emax, o, 64));
+  }
+  if (lane == 0) {
+    red[0][wave] = lo;
+    red[1][wave] = hi;
+    red[2][wave] = emax;
+  }
+  __syncthreads();
+  lo = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
+  hi = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+  emax = fmax(fmax(red[2][0], red[2][1]), fmax(red[2][2], red[2][3]));
   const double pivmin = 1e-290 * fmax(1.0, emax);
-  double tnorm = fmax(fabs(lo), fabs(hi));
+  const double tnorm = fmax(fabs(lo), fabs(hi));
   lo -= 2.2e-16 * tnorm * n + 2 * pivmin;
   hi += 2.2e-16 * tnorm * n + 2 * pivmin;
+  const int j = blockIdx.x * 4 + wave;
   if (j >= n) return;
-  for (int it = 0; it < 200; ++it) {
-    double mid = 0.5 * (lo + hi);
+  for (int it = 0; it < 64; ++it) {
     if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + 2.2e-16 * tnorm + pivmin) break;
-    if (mid <= lo || mid >= hi) break;
-    if (sturm_count(n, ds, e2, mid, pivmin) > j) hi = mid;
-    else lo = mid;
+    const double step = (hi - lo) / 65.0;
+    const double x = lo + step * (lane + 1);
+    const unsigned long long above = __ballot(x < hi && sturm_count(n, ds, e2, x, pivmin) > j);
+    const int f = above ? __ffsll((long long)above) - 1 : 64;   // first point above lambda_j
+    const double nlo = (f == 0) ? lo : lo + step * f;
+    const double nhi = (f == 64) ? hi : lo + step * (f + 1);
+    if (!(nlo > lo) && !(nhi < hi)) break;   // no progress in floating point
+    lo = nlo;
+    hi = nhi;
   }
-  w[j] = 0.5 * (lo + hi);
-  if (j == 0) e2g[0] = tnorm;
+  if (lane == 0) w[j] = 0.5 * (lo + hi);
+  if (j == 0 && lane == 0) e2g[0] = tnorm;
 }
 
 // ------------------------------------------------------------ inverse iteration
-// One thread per cluster of eigenvalues (gap < gtol); Y (n x n, real) column j = eigenvector j of T.
-// Scratch per eigenvalue index j (column-strided): dl, dd, du, du2, b (n each) and ipiv.
-__global__ void inviter_kernel(int n, const double* __restrict__ d, const double* __restrict__ e,
-                               const double* __restrict__ w, const double* __restrict__ tnorm_p, double* __restrict__ Y,
-                               double* __restrict__ scratch, int* __restrict__ piv) {
-  const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j0 >= n) return;
+// One work-group (one wave) per cluster of eigenvalues (gap <= 1e-6 ||T||); Y (n x n, real)
+// column j = eigenvector j of T.  The pivoted LU of T - lambda I and the substitutions
+// are sequential and run on lane 0 with the factors in LDS (an LDS round trip per step
+// instead of an L2 one); start vector, Gram-Schmidt against the earlier vectors of the
+// cluster and normalisation use the whole wave.
+__global__ __launch_bounds__(64) void inviter_kernel(int n, const double* __restrict__ d,
+                                                     const double* __restrict__ e, const double* __restrict__ w,
+                                                     const double* __restrict__ tnorm_p, double* __restrict__ Y) {
+  extern __shared__ double sm[];
+  double* dl = sm;
+  double* dd = dl + n;
+  double* du = dd + n;
+  double* du2 = du + n;
+  double* b = du2 + n;
+  unsigned char* ip = (unsigned char*)(b + n);
+  const int j0 = blockIdx.x;
+  const int lane = threadIdx.x;
   const double tnorm = fmax(*tnorm_p, 1e-300);
   const double gtol = 1e-6 * tnorm;
-  if (j0 > 0 && w[j0] - w[j0 - 1] <= gtol) return;  // not the start of a cluster
+  if (j0 > 0 && w[j0] - w[j0 - 1] <= gtol) return;  // not the start of a cluster (uniform)
   int j1 = j0;
   while (j1 + 1 < n && w[j1 + 1] - w[j1] <= gtol) ++j1;
-  const int64_t S = n;  // stride between rows of one scratch vector (column-strided by j0)
-  double* dl = scratch + (int64_t)0 * n * n;
-  double* dd = scratch + (int64_t)1 * n * n;
-  double* du = scratch + (int64_t)2 * n * n;
-  double* du2 = scratch + (int64_t)3 * n * n;
-  double* b = scratch + (int64_t)4 * n * n;
-  int* ip = piv;
-#define AT(arr, i) arr[(int64_t)(i) * S + j0]
   const double eps = 2.2e-16;
   double prev = -1e300;
+  auto wave_dot = [&](const double* x, const double* y) {
+    double s = 0;
+    for (int i = lane; i < n; i += 64) s += x[i] * y[i];
+    return wave_sum(s);
+  };
   for (int j = j0; j <= j1; ++j) {
     double lam = w[j];
     if (lam - prev < 10.0 * eps * tnorm) lam = prev + 10.0 * eps * tnorm;
     prev = lam;
-    // LU with partial pivoting of T - lam I (general tridiagonal form)
-    for (int i = 0; i < n; ++i) {
-      AT(dd, i) = d[i] - lam;
-      if (i < n - 1) { AT(dl, i) = e[i]; AT(du, i) = e[i]; }
-    }
-    for (int i = 0; i < n - 1; ++i) {
-      double di = AT(dd, i), li = AT(dl, i);
-      if (fabs(di) >= fabs(li)) {
-        AT(ip, i) = 0;
-        if (di == 0.0) { di = eps * tnorm; AT(dd, i) = di; }
-        double f = li / di;
-        AT(dl, i) = f;
-        AT(dd, i + 1) = AT(dd, i + 1) - f * AT(du, i);
-        if (i < n - 2) AT(du2, i) = 0.0;
-      } else {
-        AT(ip, i) = 1;
-        double f = di / li;
-        AT(dd, i) = li;
-        AT(dl, i) = f;
-        double t = AT(du, i);
-        AT(du, i) = AT(dd, i + 1);
-        AT(dd, i + 1) = t - f * AT(dd, i + 1);
-        if (i < n - 2) {
-          AT(du2, i) = AT(du, i + 1);
-          AT(du, i + 1) = -f * AT(du, i + 1);
-        }
-      }
-    }
-    if (AT(dd, n - 1) == 0.0) AT(dd, n - 1) = eps * tnorm;
-    // deterministic start vector
-    double nrm = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = lane; i < n; i += 64) {
+      dd[i] = d[i] - lam;
+      if (i < n - 1) { dl[i] = e[i]; du[i] = e[i]; }
+      du2[i] = 0.0;
+      // deterministic start vector
       uint32_t h = (uint32_t)(i * 2654435761u) ^ (uint32_t)(j * 40503u + 0x9e3779b9u);
       h ^= h >> 16; h *= 0x7feb352du; h ^= h >> 15; h *= 0x846ca68bu; h ^= h >> 16;
-      double r = ((h & 0xffffff) / 16777216.0) - 0.5 + 1e-3;
-      AT(b, i) = r;
-      nrm += r * r;
+      b[i] = ((h & 0xffffff) / 16777216.0) - 0.5 + 1e-3;
     }
-    for (int it = 0; it < 4; ++it) {
-      // forward: apply row interchanges and multipliers
+    __syncthreads();
+    if (lane == 0) {
+      // LU with partial pivoting of T - lam I (general tridiagonal form)
       for (int i = 0; i < n - 1; ++i) {
-        if (AT(ip, i) == 0) AT(b, i + 1) = AT(b, i + 1) - AT(dl, i) * AT(b, i);
-        else {
-          double t = AT(b, i);
-          AT(b, i) = AT(b, i + 1);
-          AT(b, i + 1) = t - AT(dl, i) * AT(b, i);
+        double di = dd[i], li = dl[i];
+        if (fabs(di) >= fabs(li)) {
+          ip[i] = 0;
+          if (di == 0.0) { di = eps * tnorm; dd[i] = di; }
+          double f = li / di;
+          dl[i] = f;
+          dd[i + 1] = dd[i + 1] - f * du[i];
+          if (i < n - 2) du2[i] = 0.0;
+        } else {
+          ip[i] = 1;
+          double f = di / li;
+          dd[i] = li;
+          dl[i] = f;
+          double t = du[i];
+          du[i] = dd[i + 1];
+          dd[i + 1] = t - f * dd[i + 1];
+          if (i < n - 2) {
+            du2[i] = du[i + 1];
+            du[i + 1] = -f * du[i + 1];
+          }
         }
       }
-      // back substitution with U (diag dd, super du, super-2 du2)
-      AT(b, n - 1) = AT(b, n - 1) / AT(dd, n - 1);
-      if (n > 1) AT(b, n - 2) = (AT(b, n - 2) - AT(du, n - 2) * AT(b, n - 1)) / AT(dd, n - 2);
-      for (int i = n - 3; i >= 0; --i)
-        AT(b, i) = (AT(b, i) - AT(du, i) * AT(b, i + 1) - AT(du2, i) * AT(b, i + 2)) / AT(dd, i);
+      if (dd[n - 1] == 0.0) dd[n - 1] = eps * tnorm;
+    }
+    __syncthreads();
+    for (int it = 0; it < 4; ++it) {
+      if (lane == 0) {
+        // forward: row interchanges and multipliers
+        for (int i = 0; i < n - 1; ++i) {
+          if (ip[i] == 0) {
+            b[i + 1] = b[i + 1] - dl[i] * b[i];
+          } else {
+            double t = b[i];
+            b[i] = b[i + 1];
+            b[i + 1] = t - dl[i] * b[i];
+          }
+        }
+        // back substitution with U (diagonal dd, super du, super-2 du2)
+        b[n - 1] = b[n - 1] / dd[n - 1];
+        if (n > 1) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / dd[n - 2];
+        for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+      }
+      __syncthreads();
       // orthogonalise against the earlier vectors of the cluster (twice)
       for (int pass = 0; pass < 2; ++pass)
         for (int q = j0; q < j; ++q) {
-          double dot = 0;
-          for (int i = 0; i < n; ++i) dot += Y[i + (int64_t)q * n] * AT(b, i);
-          for (int i = 0; i < n; ++i) AT(b, i) = AT(b, i) - dot * Y[i + (int64_t)q * n];
+          const double* yq = Y + (int64_t)q * n;
+          const double dot = wave_dot(yq, b);
+          for (int i = lane; i < n; i += 64) b[i] = b[i] - dot * yq[i];
+          __syncthreads();
         }
-      nrm = 0;
-      for (int i = 0; i < n; ++i) nrm += AT(b, i) * AT(b, i);
-      double inv = 1.0 / sqrt(nrm);
-      for (int i = 0; i < n; ++i) AT(b, i) = AT(b, i) * inv;
+      const double inv = 1.0 / sqrt(wave_dot(b, b));
+      for (int i = lane; i < n; i += 64) b[i] = b[i] * inv;
+      __syncthreads();
     }
-    for (int i = 0; i < n; ++i) Y[i + (int64_t)j * n] = AT(b, i);
+    for (int i = lane; i < n; i += 64) Y[i + (int64_t)j * n] = b[i];
+    __syncthreads();   // the next vector of the cluster reads this column
   }
-#undef AT
 }
 
 // ------------------------------------------------------------ back-transformation Z = Q Y
@@ -845,7 +880,7 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
   T* tau = (T*)take(n * sizeof(T));
   double* Y = (double*)take((size_t)n * n * 8);
   double* scr = (double*)take((size_t)5 * n * n * 8);
-  int* piv = (int*)take((size_t)n * n * 4);
+  (void)take((size_t)n * n * 4);  // reserved (pivots are kept in LDS)
   const size_t lds2 = (size_t)18 * n * sizeof(T);
   constexpr int NB = 32;   // panel width of the blocked reduction
   if (n >= 64 && lds2 <= 150 * 1024) {
@@ -873,10 +908,12 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
     hetrd_kernel<T><<<1, nt, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
   }
   SPARC_TRY(check_launch("hetrd_kernel"));
-  int bt = 256;
-  bisect_kernel<<<(n + bt - 1) / bt, bt, 2 * n * 8, s>>>(n, d, e, w, tn);
+  SPARC_HIP(hipFuncSetAttribute((const void*)bisect_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * n * 8));
+  bisect_kernel<<<(n + 3) / 4, 256, 2 * n * 8, s>>>(n, d, e, w, tn);
   SPARC_TRY(check_launch("bisect_kernel"));
-  inviter_kernel<<<(n + 63) / 64, 64, 0, s>>>(n, d, e, w, tn, Y, scr, piv);
+  const size_t lds_inv = (size_t)n * (5 * 8 + 1);
+  SPARC_HIP(hipFuncSetAttribute((const void*)inviter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_inv));
+  inviter_kernel<<<n, 64, lds_inv, s>>>(n, d, e, w, tn, Y);
   SPARC_TRY(check_launch("inviter_kernel"));
   ormtr_kernel<T><<<(n + 3) / 4, 256, 0, s>>>(n, A, tau, Y, Z);
   return check_launch("ormtr_kernel");
