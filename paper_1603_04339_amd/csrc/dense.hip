@@ -65,31 +65,33 @@ template <typename T>
 __global__ __launch_bounds__(256) void chol_scale_kernel(int n, const T* __restrict__ M, T* __restrict__ S,
                                                          double* __restrict__ dinv, double shift, double min_rel_diag,
                                                          int* info) {
+  // one work-group per column j; every work-group checks the diagonal itself
   __shared__ int s_fail;
-  __shared__ double s_dmax;
-  if (threadIdx.x == 0) {
-    s_fail = 0x7fffffff;
-    double dm = 0;
-    for (int i = 0; i < n; ++i) dm = fmax(dm, re_(M[i + (int64_t)i * n]));
-    s_dmax = dm;
-    if (blockIdx.x == 0) *info = 0;
-  }
+  __shared__ double s_red[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j = blockIdx.x;
+  double dm = 0;
+  for (int i = tid; i < n; i += blockDim.x) dm = fmax(dm, re_(M[i + (int64_t)i * n]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  if (lane == 0) s_red[wv] = dm;
+  if (tid == 0) s_fail = 0x7fffffff;
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  const double dmax = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+  for (int i = tid; i < n; i += blockDim.x) {
     double d = re_(M[i + (int64_t)i * n]);
-    if (!(d > 0.0) || !isfinite(d) || d < min_rel_diag * s_dmax) atomicMin(&s_fail, i + 1);
-    dinv[i] = (d > 0.0) ? 1.0 / sqrt(d) : 0.0;
+    if (!(d > 0.0) || !isfinite(d) || d < min_rel_diag * dmax) atomicMin(&s_fail, i + 1);
+    if (j == 0) dinv[i] = (d > 0.0) ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
-  if (s_fail != 0x7fffffff) {
-    if (threadIdx.x == 0) *info = s_fail;
-    return;
-  }
-  for (int64_t idx = threadIdx.x; idx < (int64_t)n * n; idx += blockDim.x) {
-    int i = (int)(idx % n), j = (int)(idx / n);
-    T v = rscale(dinv[i] * dinv[j], M[idx]);
+  if (j == 0 && tid == 0) *info = (s_fail != 0x7fffffff) ? s_fail : 0;
+  if (s_fail != 0x7fffffff) return;
+  const double dj = 1.0 / sqrt(re_(M[j + (int64_t)j * n]));
+  for (int i = tid; i < n; i += blockDim.x) {
+    const double di = 1.0 / sqrt(re_(M[i + (int64_t)i * n]));
+    T v = rscale(di * dj, M[i + (int64_t)j * n]);
     if (i == j) v = mkT<T>(re_(v) + shift, 0.0);
-    S[idx] = v;
+    S[i + (int64_t)j * n] = v;
   }
 }
 
@@ -253,7 +255,7 @@ static int chol_orth_t(hipStream_t s, int n, const T* M, T* Tout, int* info, voi
   double* dinv = (double*)p;
   p += (((size_t)n * 8 + 255) / 256) * 256;
   T* Rinv = (T*)p;
-  chol_scale_kernel<T><<<1, 256, 0, s>>>(n, M, S, dinv, shift, min_rel_diag, info);
+  chol_scale_kernel<T><<<n, 256, 0, s>>>(n, M, S, dinv, shift, min_rel_diag, info);
   SPARC_TRY(check_launch("chol_scale_kernel"));
   for (int k0 = 0; k0 < n; k0 += CB) {
     const int kb = std::min(CB, n - k0);
