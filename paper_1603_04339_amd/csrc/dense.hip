@@ -138,9 +138,17 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(int n, T* __restrict__ S
     for (int j = tid; j < kb; j += blockDim.x) {
       T x = mkT<T>(0.0, 0.0);
       if (j >= i) {
-        T sum = mkT<T>(i == j ? 1.0 : 0.0, 0.0);
-        for (int k = i + 1; k <= j; ++k) sum = sub_(sum, mul_(a[i + k * LD], r[k + j * LD]));
-        x = rscale(1.0 / re_(a[i + i * LD]), sum);
+        // four independent partial sums: the LDS loads of one are in flight during the others
+        T s0 = mkT<T>(i == j ? 1.0 : 0.0, 0.0), s1 = mkT<T>(0.0, 0.0), s2 = s1, s3 = s1;
+        int k = i + 1;
+        for (; k + 3 <= j; k += 4) {
+          s0 = sub_(s0, mul_(a[i + k * LD], r[k + j * LD]));
+          s1 = sub_(s1, mul_(a[i + (k + 1) * LD], r[k + 1 + j * LD]));
+          s2 = sub_(s2, mul_(a[i + (k + 2) * LD], r[k + 2 + j * LD]));
+          s3 = sub_(s3, mul_(a[i + (k + 3) * LD], r[k + 3 + j * LD]));
+        }
+        for (; k <= j; ++k) s0 = sub_(s0, mul_(a[i + k * LD], r[k + j * LD]));
+        x = rscale(1.0 / re_(a[i + i * LD]), add_(add_(s0, s1), add_(s2, s3)));
       }
       r[i + j * LD] = x;
     }
