@@ -570,14 +570,46 @@ __global__ __launch_bounds__(1024) void latrd_kernel(int n, int i0, int jb, T* _
     __syncthreads();
     if (!trivial) {
       // y = A_old(r0:n, r0:n) v: partial products over this wave's columns
-      for (int rb = r0; rb < n; rb += 64) {
-        const int r = rb + lane;
-        T acc = mkT<T>(0.0, 0.0);
-        if (r < n) {
-          int c = r0 + wave;
-#pragma unroll 4
-          for (; c < n; c += nwave) acc = add_(acc, mul_(A[r + (int64_t)c * n], v[c]));
-          part[wave * n + r] = acc;
+      if constexpr (sizeof(T) == 8) {
+        if ((n & 1) == 0) {
+          // two rows per lane, 16-byte loads (rows paired from an even start)
+          for (int rb = r0 & ~1; rb < n; rb += 128) {
+            const int r = rb + 2 * lane;
+            if (r < n) {
+              double a0 = 0.0, a1 = 0.0;
+              int c = r0 + wave;
+#pragma unroll 8
+              for (; c < n; c += nwave) {
+                const double2 t = *(const double2*)&A[r + (int64_t)c * n];
+                a0 += t.x * v[c];
+                a1 += t.y * v[c];
+              }
+              if (r >= r0) part[wave * n + r] = a0;
+              if (r + 1 >= r0) part[wave * n + r + 1] = a1;
+            }
+          }
+        } else {
+          for (int rb = r0; rb < n; rb += 64) {
+            const int r = rb + lane;
+            if (r < n) {
+              double acc = 0.0;
+              int c = r0 + wave;
+#pragma unroll 8
+              for (; c < n; c += nwave) acc += A[r + (int64_t)c * n] * v[c];
+              part[wave * n + r] = acc;
+            }
+          }
+        }
+      } else {
+        for (int rb = r0; rb < n; rb += 64) {
+          const int r = rb + lane;
+          if (r < n) {
+            T acc = mkT<T>(0.0, 0.0);
+            int c = r0 + wave;
+#pragma unroll 8
+            for (; c < n; c += nwave) acc = add_(acc, mul_(A[r + (int64_t)c * n], v[c]));
+            part[wave * n + r] = acc;
+          }
         }
       }
       // W_k^H v and V_k^H v for the panel's earlier reflectors: one wave per product
