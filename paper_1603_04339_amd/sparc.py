@@ -276,6 +276,12 @@ def workspace(ham: Hamiltonian, n_s: int, op: int, device=None):
     return torch.empty(nb, dtype=torch.uint8, device=device or f"cuda:{ham.ctx.device}")
 
 
+def _ld(X):
+    """Leading dimension of an (n_s, ld) block; a single row's stride is
+    arbitrary in torch, its row length is what the library checks."""
+    return X.shape[1] if X.shape[0] == 1 else X.stride(0)
+
+
 def _block(X, ham):
     if X.dtype != TORCH_DTYPE[ham.dtype]:
         raise TypeError(f"block dtype {X.dtype} does not match the Hamiltonian's {TORCH_DTYPE[ham.dtype]}")
@@ -283,7 +289,7 @@ def _block(X, ham):
         return X, X.shape[0], 1
     if X.stride(1) != 1:
         raise ValueError("orbital blocks must be (n_s, ld) with unit stride along the grid")
-    return X, X.stride(0), X.shape[0]
+    return X, _ld(X), X.shape[0]
 
 
 def fd_hamiltonian_apply(ham: Hamiltonian, X, Y, work):
@@ -319,7 +325,7 @@ def lanczos_bounds(ham: Hamiltonian, v0, steps: int, work):
 def density_from_orbitals(ctx: Context, Xs, occ_w, dV: float, rho, dtype: int):
     nk = len(Xs)
     ptrs = (C.c_void_p * nk)(*[X.data_ptr() for X in Xs])
-    lds = (C.c_int64 * nk)(*[X.stride(0) for X in Xs])
+    lds = (C.c_int64 * nk)(*[_ld(X) for X in Xs])
     ns = Xs[0].shape[0]
     nd = Xs[0].shape[1]
     _check(load().density_from_orbitals(ctx.handle, nk, ptrs, lds, ns, dtype, _ptr(occ_w), nd, float(dV),
@@ -343,7 +349,7 @@ def _arr(ctype, vals):
 def _batch_args(hams, Xs, n_s, degree=None):
     H = _arr(C.c_void_p, [h.handle.value for h in hams])
     X = _arr(C.c_void_p, [x.data_ptr() for x in Xs])
-    ld = _arr(C.c_int64, [x.stride(0) for x in Xs])
+    ld = _arr(C.c_int64, [_ld(x) for x in Xs])
     ns = _arr(C.c_int32, list(n_s))
     dg = _arr(C.c_int32, list(degree)) if degree is not None else None
     return H, X, ld, ns, dg
