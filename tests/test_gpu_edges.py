@@ -3,7 +3,9 @@ states (real and complex), Rayleigh-Ritz on FP32 blocks (FP32 MFMA contractions,
 FP64 Cholesky and eigensolver), a 64-state block (the blocked tridiagonal
 reduction and the multisection eigenvalues on their smallest size), a filter
 plan holding a single problem of degree 1, and the Bloch factor at the zone
-boundary k = pi / L in FP32."""
+boundary k = pi / L in FP32, and every stencil tile shape (single and batched)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -115,3 +117,64 @@ def test_zone_boundary_bloch_fp32(ctx):
     sp.fd_hamiltonian_apply(ham, Xd, Y, sp.workspace(ham, 4, sp.OP_APPLY))
     ref = apply_H(X.T.astype(np.complex64).astype(np.complex128), grid, V, P)
     assert colnorm_err(block_to_oracle(Y).astype(np.complex128), ref) < 2e-5
+
+
+N_TILE_SHAPES = 6   # stencil tile shapes the library can launch (indices 0..5)
+
+
+@pytest.fixture
+def tile_env():
+    old = os.environ.get("SPARC_HSTEP_TILE")
+    yield
+    if old is None:
+        os.environ.pop("SPARC_HSTEP_TILE", None)
+    else:
+        os.environ["SPARC_HSTEP_TILE"] = old
+
+
+@pytest.mark.parametrize("dt", ["r64", "c128", "r32", "c64"])
+def test_every_tile_shape(ctx, tile_env, dt):
+    """Every tile shape on a grid that none of them
+    divides, with Bloch phases for the complex types, against the oracle."""
+    cplx = dt.startswith("c")
+    k = (0.21, -0.13, 0.3) if cplx else (0.0, 0.0, 0.0)
+    cell, rng = _cell(60, n=(37, 29, 21), L=(14.8, 11.6, 8.4))
+    grid, V, P = oracle_setup(cell, k)
+    X = rng.standard_normal((3, grid.n_d))
+    if cplx:
+        X = X + 1j * rng.standard_normal((3, grid.n_d))
+    single = dt in ("r32", "c64")
+    tdt = {"r64": torch.float64, "c128": torch.complex128, "r32": torch.float32, "c64": torch.complex64}[dt]
+    ham = sp.Hamiltonian(ctx, cell, {"r64": sp.R64, "c128": sp.C128, "r32": sp.R32, "c64": sp.C64}[dt], kpt=k)
+    Xd = to_dev(X, tdt)
+    Xr = block_to_oracle(Xd).astype(np.complex128 if cplx else np.float64)
+    ref = apply_H(Xr, grid, V, P)
+    w = sp.workspace(ham, 3, sp.OP_APPLY)
+    for t in range(N_TILE_SHAPES):
+        os.environ["SPARC_HSTEP_TILE"] = str(t)
+        Y = torch.zeros_like(Xd)
+        sp.fd_hamiltonian_apply(ham, Xd, Y, w)
+        err = colnorm_err(block_to_oracle(Y).astype(Xr.dtype), ref)
+        print(f"{dt} tile {t}: {err:.2e}")
+        assert err < (2e-5 if single else 1e-12)
+
+
+def test_every_tile_shape_batched(ctx, tile_env):
+    """Batched filter plans with every tile shape: two uneven real problems."""
+    probs = []
+    for s, (n, L) in enumerate([((37, 29, 21), (14.8, 11.6, 8.4)), ((24, 20, 18), (9.6, 8.0, 7.2))]):
+        cell, rng = _cell(70 + s, n=n, L=L)
+        grid, V, P = oracle_setup(cell)
+        probs.append((cell, grid, V, P, rng.standard_normal((4 + s, grid.n_d))))
+    for t in range(N_TILE_SHAPES):
+        os.environ["SPARC_HSTEP_TILE"] = str(t)
+        hams = [sp.Hamiltonian(ctx, p[0], sp.R64) for p in probs]
+        Xs = [to_dev(p[4]) for p in probs]
+        plan = sp.FilterPlan(ctx, hams, Xs, [4, 3], use_graph=False)
+        plan.run([2.0, 3.0], [60.0, 50.0])
+        for i, (p, Xd) in enumerate(zip(probs, Xs)):
+            ref = cheb_filter(p[4].T, p[1], p[2], p[3], [4, 3][i], [2.0, 3.0][i], [60.0, 50.0][i])
+            err = colnorm_err(block_to_oracle(Xd), ref)
+            print(f"batched tile {t} problem {i}: {err:.2e}")
+            assert err < 1e-12
+        plan.close()
