@@ -343,13 +343,13 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
   // pass 2 (implicit): T2 from the Gram matrix of X1 = X T1
   SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W1, N, w.M, n, w.gw, w.gw_bytes, mode, ncu));
   SPARC_TRY(chol_orth(s, cp, n, w.M, w.T2, w.info, w.cw, 0.0));
-  // H X1 and the projected matrix A1 = X1^H H X1
+  // H X1 and the projected matrix A1 = X1^H H X1 (Hermitian: its upper triangle, mirrored)
   SPARC_TRY(nl_project(H, w.W1, N, n, w.alpha));
   SPARC_TRY(ham_step(H, w.W1, N, nullptr, 0, w.W2, N, n, 1.0, 0.0, 0.0, w.alpha));
-  SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W2, N, w.A1, n, w.gw, w.gw_bytes, mode, ncu));
-  // H~ = T2^H A1 T2 (FP64), symmetrised
+  SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W2, N, w.A1, n, w.gw, w.gw_bytes, mode, ncu, true));
+  // H~ = T2^H A1 T2 (FP64, Hermitian by the same mirror), symmetrised
   SPARC_TRY(rotate(s, sdt, n, n, n, w.A1, n, w.T2, n, w.tmp, n, 1));
-  SPARC_TRY(gram(s, sdt, n, n, n, w.T2, n, w.tmp, n, w.A1, n, w.gw, w.gw_bytes, SPARC_GEMM_NATIVE, ncu));
+  SPARC_TRY(gram(s, sdt, n, n, n, w.T2, n, w.tmp, n, w.A1, n, w.gw, w.gw_bytes, SPARC_GEMM_NATIVE, ncu, true));
   herm_sym_kernel<<<(unsigned)(((int64_t)n * n + 255) / 256), 256, 0, s>>>(n, (double*)w.A1, cp ? 1 : 0);
   SPARC_TRY(check_launch("herm_sym_kernel"));
   SPARC_HIP(hipMemcpyAsync(&info, w.info, 4, hipMemcpyDeviceToHost, s));

@@ -277,8 +277,8 @@ size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt) {
 
 template <typename E>
 static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t lda, const E* B, int64_t ldb, void* C,
-                  int ldc, void* work, size_t work_bytes, int n_cu) {
-  const bool herm = (A == B) && (na == nb) && (lda == ldb);
+                  int ldc, void* work, size_t work_bytes, int n_cu, bool herm_result) {
+  const bool herm = (na == nb) && (herm_result || ((A == B) && (lda == ldb)));
   constexpr int T = gram_tile<E>::T;
   GramPlan p = gram_plan(N, na, nb, herm, n_cu, T);
   // persistent grid: two work-groups per CU (a multiple of 8), at most one per item
@@ -303,13 +303,14 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
 }
 
 int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t na, int32_t nb, const void* A, int64_t lda, const void* B,
-         int64_t ldb, void* C, int32_t ldc, void* work, size_t work_bytes, sparc_gemm_mode mode, int n_cu) {
+         int64_t ldb, void* C, int32_t ldc, void* work, size_t work_bytes, sparc_gemm_mode mode, int n_cu,
+         bool herm_result) {
   (void)mode;
   switch (dt) {
-    case SPARC_R64: return gram_t<double>(s, N, na, nb, (const double*)A, lda, (const double*)B, ldb, C, ldc, work, work_bytes, n_cu);
-    case SPARC_R32: return gram_t<float>(s, N, na, nb, (const float*)A, lda, (const float*)B, ldb, C, ldc, work, work_bytes, n_cu);
-    case SPARC_C128: return gram_t<cd>(s, N, na, nb, (const cd*)A, lda, (const cd*)B, ldb, C, ldc, work, work_bytes, n_cu);
-    case SPARC_C64: return gram_t<cf>(s, N, na, nb, (const cf*)A, lda, (const cf*)B, ldb, C, ldc, work, work_bytes, n_cu);
+    case SPARC_R64: return gram_t<double>(s, N, na, nb, (const double*)A, lda, (const double*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
+    case SPARC_R32: return gram_t<float>(s, N, na, nb, (const float*)A, lda, (const float*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
+    case SPARC_C128: return gram_t<cd>(s, N, na, nb, (const cd*)A, lda, (const cd*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
+    case SPARC_C64: return gram_t<cf>(s, N, na, nb, (const cf*)A, lda, (const cf*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
   }
   return fail(SPARC_EINVAL, "gram: bad dtype");
 }

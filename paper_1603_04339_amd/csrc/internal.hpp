@@ -161,10 +161,13 @@ size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
 // GEMMs (gemm.hip)
 //   gram:   C[n_a x n_b] (FP64 or complex FP64, column-major, ldc) = A^H B, A: N x n_a, B: N x n_b
 //           in the orbital element type; split over N with a deterministic reduction.
+//           herm_result: the caller knows C is Hermitian (A^H H A with H Hermitian): only
+//           the upper triangle is computed and the lower one is its conjugate mirror (this
+//           is automatic when A and B are the same block).
 size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt);
 int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_a, int32_t n_b, const void* A, int64_t lda,
          const void* B, int64_t ldb, void* C, int32_t ldc, void* work, size_t work_bytes,
-         sparc_gemm_mode mode, int n_cu);
+         sparc_gemm_mode mode, int n_cu, bool herm_result = false);
 //   rotate: Out[N x n_out] = A[N x n_in] * Q[n_in x n_out] (Q FP64 / complex FP64, column-major ldq)
 //   q_upper: Q is upper triangular (entries below the diagonal are not read).
 int rotate(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A, int64_t lda,
