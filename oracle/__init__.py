@@ -18,7 +18,9 @@ Modules
   cell     synthetic cell: local potential and Kleinman-Bylander projectors
   chefsi   Chebyshev filter (recurrence and direct), Rayleigh-Ritz, Lanczos
   scf      occupations, density, Poisson, Slater exchange, energy, SCF loop
-  convnet  3-D convolutional network forward/backward for the initial density
+  forces   atomic forces: local component, non-local component with the
+           gradient on the orbitals, FD gradient
+  density_net  3-D convolutional network forward/backward for the initial density
 
 Parity status: every function is pinned by a CPU test against closed forms,
 invariants or brute force (tests/test_oracle_*.py), except the effect of the
