@@ -129,7 +129,7 @@ int sparc_ham_get_vloc(const sparc_ham* ham, double* vloc_dev);
 int sparc_ham_info(const sparc_ham* ham, int64_t* n_d, int32_t* n_proj, int64_t* n_entries);
 
 /* Operation codes for sparc_workspace_bytes. */
-enum { SPARC_OP_APPLY = 0, SPARC_OP_FILTER = 1, SPARC_OP_RR = 2, SPARC_OP_LANCZOS = 3 };
+enum { SPARC_OP_APPLY = 0, SPARC_OP_FILTER = 1, SPARC_OP_RR = 2, SPARC_OP_LANCZOS = 3, SPARC_OP_FORCES = 4 };
 /* Bytes of device workspace an operation needs for n_s states (0 for none). */
 size_t sparc_workspace_bytes(const sparc_ham* ham, int32_t n_s, int32_t op);
 
@@ -266,6 +266,33 @@ int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* ato
  * (x fastest).  Synchronous.  Errors: EINVAL, ESHAPE, ENAN (no charge), ENOMEM. */
 int sparc_sad_density(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms, double n_elec,
                       double* rho_dev);
+
+/* ---- atomic forces ----------------------------------------------------------------
+ * f_J = -dF/dR_J (Sec. 2, atomic forces), split as in Sec. 3.6 into a local and a
+ * non-local component.  F_dev: device [n_atoms][3] FP64 (Ha/bohr, atoms in the order
+ * of sparc_atoms); both calls ADD to it (zero it first; call the non-local part once
+ * per k-point with that k-point's Hamiltonian).  Asynchronous on the context's stream.
+ *
+ * Local component.  The Gaussian wells are an external potential (jellium
+ * electrostatics, no pseudocharges, so no overlap correction), and the component is
+ * the exact derivative of the trapezoidal-rule local energy h1h2h3 sum_g rho_g V_loc(x_g):
+ *   f_J,loc = h1h2h3 sum_g rho_g sum_L D_J exp(-r^2/(2 w_J^2)) (x_g - R_J - L) / w_J^2,
+ * r = |x_g - R_J - L| <= 10 w_J.  rho_dev: device FP64 density [N_d] (h1h2h3 sum rho =
+ * N_e).  Errors: EINVAL. */
+int sparc_forces_local(sparc_ham* ham, const double* rho_dev, double* F_dev);
+
+/* Non-local component (Sec. 3.6, discrete non-local force with Y and W; Algorithm 3),
+ * the derivative moved from the projectors onto the orbitals and taken with the FD
+ * gradient of Sec. 3.1 (weights w~_p, Bloch-periodic index map):
+ *   f_J,nloc = -4 sum_n occ_n sum_{p of J} gamma_p Re[conj(alpha_pn) beta_pn] / h1h2h3,
+ *   alpha_pn = h1h2h3 sum_g conj(chi~_p(g)) X(g,n),
+ *   beta_pn  = h1h2h3 sum_g conj(chi~_p(g)) (grad_h X)(g,n),
+ * i.e. the paper's -4 sum w_b g_nb gamma Re[Y W] for Euclidean-orthonormal columns.
+ * X: device block (the Hamiltonian's dtype, column-major, ldx >= N_d); occ_dev: device
+ * FP64 [n_s] = w_b g_nb (states with zero weight are skipped); work: SPARC_OP_FORCES
+ * bytes.  Errors: EINVAL, ESHAPE, ENOMEM. */
+int sparc_forces_nonlocal(sparc_ham* ham, const void* X, int64_t ldx, int32_t n_s, const double* occ_dev,
+                          double* F_dev, void* work, size_t work_bytes);
 
 /* ---- learned initial density ------------------------------------------------------
  * Replaces the atomic-superposition start of the SCF (Sec. 4) by

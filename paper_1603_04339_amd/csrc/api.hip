@@ -380,6 +380,7 @@ size_t sparc_workspace_bytes(const sparc_ham* H, int32_t n_s, int32_t op) {
     case SPARC_OP_FILTER: return al(blk) + al(alpha_bytes(H, n_s));
     case SPARC_OP_RR: return rr_layout(H, n_s, nullptr, 0, nullptr);
     case SPARC_OP_LANCZOS: return lz_layout(H, n_s, nullptr, 0, nullptr);
+    case SPARC_OP_FORCES: return al(alpha_bytes(H, n_s)) + al(force_nl_part_bytes(H, n_s));
   }
   return 0;
 }

@@ -116,8 +116,6 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x,
 }
 
 // projections are stored [projector][orbital] with the orbital count padded to a multiple of 8
-static inline int alpha_ld(int32_t n_s) { return ((n_s + 15) / 16) * 16; }
-
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s) {
   return (size_t)std::max(H->n_proj, 1) * (size_t)alpha_ld(n_s) * elem_bytes(H->dtype);
 }

@@ -74,6 +74,9 @@ struct sparc_ctx {
   std::vector<hipEvent_t> pool;
 };
 
+// z-chunks of the local-force box per atom (partial sums reduced in a fixed order)
+constexpr int kForceChunks = 8;
+
 struct sparc_ham {
   sparc_ctx* ctx;
   sparc_grid grid;
@@ -108,6 +111,14 @@ struct sparc_ham {
   int32_t* nl_ptr;      // [n_nlpts+1] CSR: entries of each such node
   int32_t* ent_proj;    // [n_ent] projector of the entry
   void* ent_coef;       // [n_ent] gamma_p * chi~_p(g) (element type)
+  // atoms (device), kept for the atomic forces
+  int32_t n_atoms;
+  double* atom_R;       // [3 n_atoms]
+  double* atom_D;       // [n_atoms] well depths
+  double* atom_W;       // [n_atoms] well widths
+  double* force_part;   // [n_atoms * kForceChunks * 3] partial sums of the local force
+  int32_t* nl_atom;     // [n_atoms_nl] atom index of each projector-carrying atom
+  double gtap[3][8];    // FD gradient weights w~_p / h_s per direction, p = 1..n_o
 };
 
 namespace sparc {
@@ -157,6 +168,10 @@ int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const vo
                       int n, int64_t total);
 int tuned_tile(sparc_ham* H, int32_t n_s, int* t);
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
+// partial sums of the non-local force (forces.hip)
+size_t force_nl_part_bytes(const sparc_ham* H, int32_t n_s);
+// leading dimension (orbitals, padded to 16) of the projections alpha[projector][orbital]
+inline int alpha_ld(int32_t n_s) { return ((n_s + 15) / 16) * 16; }
 
 // GEMMs (gemm.hip)
 //   gram:   C[n_a x n_b] (FP64 or complex FP64, column-major, ldc) = A^H B, A: N x n_a, B: N x n_b

@@ -99,7 +99,7 @@ static int64_t floordiv(int64_t a, int64_t b) {
 
 // Host construction of the projector table for one cell.
 struct ProjTable {
-  std::vector<int32_t> sup_ptr, sup_idx, atom_pbeg;
+  std::vector<int32_t> sup_ptr, sup_idx, atom_pbeg, atom_id;
   std::vector<int64_t> proj_voff;
   std::vector<double> gamma;
   std::vector<double> vre, vim;  // values of chi~ (re, im)
@@ -187,6 +187,7 @@ static int build_projectors(const sparc_grid& G, const double h[3], double dV, c
       }
     }
     T.atom_pbeg.push_back(T.atom_pbeg.back() + nf);
+    T.atom_id.push_back(J);
   }
   return SPARC_OK;
 }
@@ -377,6 +378,11 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
     double kl = grid->kpt[s] * grid->L[s];
     H->ph_re[s] = std::cos(kl);
     H->ph_im[s] = std::sin(kl);
+    // FD gradient weights (Sec. 3.1): w~_p = (-1)^{p+1} (n_o!)^2 / (h p (n_o-p)! (n_o+p)!)
+    for (int p = 1; p <= 8; ++p)
+      H->gtap[s][p - 1] = (p <= no) ? ((p & 1) ? 1.0 : -1.0) * fact[no] * fact[no] /
+                                          (H->h[s] * p * fact[no - p] * fact[no + p])
+                                    : 0.0;
   }
 
   // local potential on the device
@@ -390,8 +396,18 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
                            atoms->vloc_depth ? atoms->vloc_depth + atoms->n_atoms : (const double*)nullptr);
     std::vector<double> Wp(atoms->vloc_width ? atoms->vloc_width : (const double*)nullptr,
                            atoms->vloc_width ? atoms->vloc_width + atoms->n_atoms : (const double*)nullptr);
-    if ((rc = upload(R, &dR)) || (rc = upload(Dp, &dD)) || (rc = upload(Wp, &dW))) {
-      delete H;
+    rc = upload(R, &dR);
+    if (!rc) rc = upload(Dp, &dD);
+    if (!rc) rc = upload(Wp, &dW);
+    H->n_atoms = atoms->n_atoms;
+    H->atom_R = dR;   // owned by the Hamiltonian from here on (atomic forces)
+    H->atom_D = dD;
+    H->atom_W = dW;
+    if (!rc && atoms->n_atoms > 0 &&
+        hipMalloc(&H->force_part, (size_t)atoms->n_atoms * kForceChunks * 3 * sizeof(double)) != hipSuccess)
+      rc = fail(SPARC_ENOMEM, "sparc_ham_create: force buffer allocation failed");
+    if (rc) {
+      sparc_ham_destroy(H);
       return rc;
     }
   }
@@ -463,6 +479,7 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
   std::vector<double> zeros(T.gamma.size(), 0.0);
   pack(dtype_single(dtype) ? SPARC_R32 : SPARC_R64, T.gamma, zeros, gm);
   if ((rc = upload(T.sup_ptr, &H->sup_ptr)) || (rc = upload(T.sup_idx, &H->sup_idx)) ||
+      (rc = upload(T.atom_id, &H->nl_atom)) ||
       (rc = upload(T.atom_pbeg, &H->atom_pbeg)) || (rc = upload(T.proj_voff, &H->proj_voff)) ||
       (rc = upload(pv, (char**)&H->pval)) || (rc = upload(gm, (char**)&H->gamma_d)) ||
       (rc = upload(nl_pts, &H->nl_pts)) || (rc = upload(nl_ptr, &H->nl_ptr)) || (rc = upload(ent_proj, &H->ent_proj)) ||
@@ -471,9 +488,6 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
     return rc;
   }
   hipError_t e = hipStreamSynchronize(st);
-  hipFree(dR);
-  hipFree(dD);
-  hipFree(dW);
   if (e != hipSuccess) {
     sparc_ham_destroy(H);
     return fail(SPARC_EDEVICE, "sparc_ham_create: %s", hipGetErrorString(e));
@@ -485,7 +499,8 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
 void sparc_ham_destroy(sparc_ham* H) {
   if (!H) return;
   void* ptrs[] = {H->vloc, H->veff, H->veff32, H->sup_ptr, H->sup_idx, H->atom_pbeg, H->proj_voff,
-                  H->pval, H->gamma_d, H->nl_pts, H->nl_ptr, H->ent_proj, H->ent_coef};
+                  H->pval, H->gamma_d, H->nl_pts, H->nl_ptr, H->ent_proj, H->ent_coef,
+                  H->atom_R, H->atom_D, H->atom_W, H->force_part, H->nl_atom};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete H;

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libsparc_hip.so")
 OK, EINVAL, ESHAPE, ENOMEM, ENOTSPD, ENOCONV, EDEVICE, ENAN = 0, -1, -2, -3, -4, -5, -6, -7
 R64, R32, C128, C64 = 0, 1, 2, 3
 GEMM_NATIVE = 0
-OP_APPLY, OP_FILTER, OP_RR, OP_LANCZOS = 0, 1, 2, 3
+OP_APPLY, OP_FILTER, OP_RR, OP_LANCZOS, OP_FORCES = 0, 1, 2, 3, 4
 
 TORCH_DTYPE = {R64: torch.float64, R32: torch.float32, C128: torch.complex128, C64: torch.complex64}
 
@@ -104,6 +104,9 @@ _SIGS = {
                                         C.c_void_p, C.c_size_t]),
     "sparc_ctx_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "sparc_sad_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "sparc_forces_local": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sparc_forces_nonlocal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_size_t]),
     "sparc_dnet_num_params": (C.c_int64, []),
     "sparc_dnet_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_void_p)]),
     "sparc_dnet_destroy": (None, [C.c_void_p]),
@@ -320,6 +323,22 @@ def lanczos_bounds(ham: Hamiltonian, v0, steps: int, work):
     _check(load().lanczos_bounds(ham.handle, _ptr(v0), int(steps), _ptr(work), work.numel(), C.byref(lo),
                                  C.byref(hi)))
     return lo.value, hi.value
+
+
+def forces_local(ham: Hamiltonian, rho, F):
+    """Adds the local force component (Ha/bohr) to F, a device FP64 tensor of shape
+    (n_atoms, 3); rho: device FP64 density [N_d]."""
+    _check(load().sparc_forces_local(ham.handle, _ptr(rho), _ptr(F)))
+    return F
+
+
+def forces_nonlocal(ham: Hamiltonian, X, occ_w, F, work):
+    """Adds the non-local force component of the block X (n_s, ld) with weights occ_w
+    (device FP64 [n_s], w_b g_nb) to F; work: workspace(ham, n_s, OP_FORCES)."""
+    X, ldx, ns = _block(X, ham)
+    _check(load().sparc_forces_nonlocal(ham.handle, _ptr(X), ldx, ns, _ptr(occ_w), _ptr(F), _ptr(work),
+                                        work.numel()))
+    return F
 
 
 def density_from_orbitals(ctx: Context, Xs, occ_w, dV: float, rho, dtype: int):
