@@ -144,6 +144,7 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
     t_total = time.perf_counter() - t_start
     hs_ms, hs_n = ctx.kernel_time("hstep")
     ctx.set_timing(False)
+    forces = forces_leg(sp, ctx, ham, cell, X, occ, rho) if dt == sp.R64 else None
     eb = 8 if dt == sp.R64 else 4
     # per pass: the filter's steps and the one H X of Rayleigh-Ritz (2 elements per point-state)
     total = steps * (step_bytes(nd, ns, eb, cell.degree) + 2 * nd * ns * eb)
@@ -155,8 +156,37 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
         "roofline": roofline_obj("hstep (12th-order stencil + V_eff + recurrence, LDS-tiled)", total, hs_ms, hs_n,
                                  measured_traffic() if (dt == sp.R64 and tuple(cell.n) == (96, 96, 96)
                                                         and cell.n_s == 512) else None),
-        "ritz": ritz.cpu().numpy(), "bounds": (lmin, lmax), "n_proj": ham.n_proj,
+        "ritz": ritz.cpu().numpy(), "bounds": (lmin, lmax), "n_proj": ham.n_proj, "forces": forces,
     }
+
+
+def forces_leg(sp, ctx, ham, cell, X, occ, rho, reps=3):
+    """Atomic forces on the state of the last step (local part on its density,
+    non-local part on its orbitals and occupations): kernel times (HIP events on
+    the context's stream), mean over reps after one warm-up."""
+    import torch
+    F = torch.zeros(len(cell.depth), 3, dtype=torch.float64, device="cuda:0")
+    wf = sp.workspace(ham, cell.n_s, sp.OP_FORCES)
+
+    def once():
+        F.zero_()
+        sp.forces_local(ham, rho, F)
+        sp.forces_nonlocal(ham, X, occ.view(-1), F, wf)
+
+    once()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(reps):
+        once()
+    loc_ms, loc_n = ctx.kernel_time("force_local")
+    nl_ms, nl_n = ctx.kernel_time("force_nl")
+    ctx.set_timing(False)
+    n_occ = int((occ.view(-1) != 0).sum())
+    return {"local_ms": loc_ms / loc_n, "nonlocal_ms": nl_ms / nl_n, "n_atoms": len(cell.depth),
+            "states_with_weight": n_occ, "max_abs_Ha_per_bohr": float(F.abs().max()),
+            "note": ("local component over every well image within 10 widths; non-local component (projections "
+                     "+ FD gradient of the orbitals at the projector supports) over the states with nonzero "
+                     "occupation")}
 
 
 def scf_leg(sp, ctx, precision, tol=1e-6, learned=False):
@@ -219,6 +249,8 @@ def run_gamma(args, sp, wl):
         "filter_ms": main["filter_ms"], "filter_throughput": main["filter_throughput"],
         "roofline": main["roofline"],
     }
+    if main["forces"] is not None:
+        result["forces"] = main["forces"]
     if args.precision == "f64" and not args.no_mixed:
         mx = gamma_leg(sp, ctx, cell, X0, v0, "mixed", args.steps, args.warmup, "mixed")
         n_occ = int(np.ceil(cell.n_elec / 2))
