@@ -20,6 +20,7 @@ Modules
   scf      occupations, density, Poisson, Slater exchange, energy, SCF loop
   forces   atomic forces: local component, non-local component with the
            gradient on the orbitals, FD gradient
+  bands    band structure at fixed potential (dense H(k)), density of states
   density_net  3-D convolutional network forward/backward for the initial density
 
 Parity status: every function is pinned by a CPU test against closed forms,
