@@ -294,6 +294,31 @@ int sparc_forces_local(sparc_ham* ham, const double* rho_dev, double* F_dev);
 int sparc_forces_nonlocal(sparc_ham* ham, const void* X, int64_t ldx, int32_t n_s, const double* occ_dev,
                           double* F_dev, void* work, size_t work_bytes);
 
+/* ---- band structure and density of states ----------------------------------------
+ * Band structure at the electronic ground state (Sec. 4): at every k-point the CheFSI
+ * steps of Sec. 3.4 are repeated, with the potential V_eff fixed, until the lowest
+ * n_bands Ritz values move by less than tol (Ha, max over the bands) between two
+ * passes.  All k-points are filtered together (one batched plan, HIP graph when
+ * use_graph) and Rayleigh–Ritz'd per k; filter bounds per k: lambda_max by Lanczos
+ * (20 steps from the first column of X[b]), lambda_cut the midpoint of the Lanczos
+ * interval for the first pass, then the largest Ritz value of the previous pass.
+ * grid: the cell (its kpt is ignored); kpts: host [3*n_k] (bohr^-1); veff_dev: device
+ * FP64 [N_d]; X: host array of n_k device complex128 blocks (N_d x n_s, ld = N_d): the
+ * start vectors (linearly independent), overwritten by the Ritz vectors.  eig_out:
+ * host [n_k*n_bands] ascending per k; passes_out: host [n_k] passes used (max_passes
+ * where not converged).  Synchronous; allocates its own Hamiltonians and workspace.
+ * Errors: ENOCONV (outputs hold the last pass), ENAN, ENOTSPD, EINVAL, ESHAPE, ENOMEM. */
+int sparc_band_structure(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms, const double* veff_dev,
+                         int32_t n_k, const double* kpts, void* const* X, int32_t n_s, int32_t n_bands,
+                         int32_t degree, int32_t max_passes, double tol, int32_t use_graph, double* eig_out,
+                         int32_t* passes_out);
+
+/* Density of states (Sec. 4): D(E) = 2 sum_b wk[b] sum_n g(E - eig[b*n_bands+n]) with g
+ * the normalised Gaussian of width sigma (the broadened delta function), at n_e
+ * energies.  Host arrays; host computation.  Errors: EINVAL, ESHAPE. */
+int sparc_dos(int32_t n_k, int32_t n_bands, const double* eig, const double* wk, int32_t n_e, const double* energies,
+              double sigma, double* dos_out);
+
 /* ---- learned initial density ------------------------------------------------------
  * Replaces the atomic-superposition start of the SCF (Sec. 4) by
  *   rho_0 = renorm( relu(x + d - mean(d)) * rho_bar ),  x = rho_SAD / rho_bar,

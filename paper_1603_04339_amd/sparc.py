@@ -105,6 +105,11 @@ _SIGS = {
     "sparc_ctx_set_autotune": (C.c_int, [C.c_void_p, C.c_int]),
     "sparc_sad_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
     "sparc_forces_local": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "sparc_band_structure": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                       C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                       C.c_void_p, C.c_void_p]),
+    "sparc_dos": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_double,
+                            C.c_void_p]),
     "sparc_forces_nonlocal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_size_t]),
     "sparc_dnet_num_params": (C.c_int64, []),
@@ -464,6 +469,45 @@ def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=Non
            "history": hist[:3 * max(res.iterations, 0)].reshape(-1, 3), "status": st}
     if st not in (OK, ENOCONV):
         _check(st)
+    return out
+
+
+def band_structure(ctx: Context, cell, veff, kpts, Xs, n_bands: int, degree: int = 20, max_passes: int = 50,
+                   tol: float = 1e-8, use_graph: bool = True, n_o: int = 6):
+    """Band structure at fixed potential (sparc_band_structure).  veff: device FP64
+    [N_d]; kpts: (n_k, 3); Xs: list of n_k device complex128 (n_s, N_d) start blocks,
+    overwritten by the Ritz vectors.  Returns (eig (n_k, n_bands), passes (n_k,),
+    status) where status is OK or ENOCONV."""
+    lib = load()
+    grid = make_grid(cell.n, cell.L, n_o)
+    atoms = _Atoms(cell)
+    k = np.ascontiguousarray(kpts, dtype=np.float64).reshape(-1, 3)
+    nk = k.shape[0]
+    if len(Xs) != nk:
+        raise ValueError("one start block per k-point")
+    for X in Xs:
+        if X.dtype != torch.complex128 or not X.is_contiguous() or X.shape[1] != cell.n_d:
+            raise ValueError("start blocks must be contiguous complex128 (n_s, N_d)")
+    ns = int(Xs[0].shape[0])
+    ptrs = (C.c_void_p * nk)(*[X.data_ptr() for X in Xs])
+    eig = np.zeros((nk, n_bands))
+    passes = np.zeros(nk, dtype=np.int32)
+    st = lib.sparc_band_structure(ctx.handle, C.byref(grid), C.byref(atoms.struct), _ptr(veff), nk, _dptr(k),
+                                  ptrs, ns, int(n_bands), int(degree), int(max_passes), float(tol),
+                                  1 if use_graph else 0, _dptr(eig), passes.ctypes.data_as(C.c_void_p))
+    if st not in (OK, ENOCONV):
+        _check(st)
+    return eig, passes, st
+
+
+def dos(eig, wk, energies, sigma: float):
+    """Density of states D(E) (sparc_dos, host computation)."""
+    eig = np.ascontiguousarray(eig, dtype=np.float64)
+    wk = np.ascontiguousarray(wk, dtype=np.float64)
+    E = np.ascontiguousarray(energies, dtype=np.float64)
+    out = np.zeros(E.shape[0])
+    _check(load().sparc_dos(eig.shape[0], eig.shape[1], _dptr(eig), _dptr(wk), E.shape[0], _dptr(E), float(sigma),
+                            _dptr(out)))
     return out
 
 
