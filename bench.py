@@ -425,8 +425,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a design "
-              "described in DESIGN.md, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the path over several "
+              "GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

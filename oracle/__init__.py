@@ -25,6 +25,6 @@ Modules
 
 Parity status: every function is pinned by a CPU test against closed forms,
 invariants or brute force (tests/test_oracle_*.py), except the effect of the
-learned initial density, which is "parity unpinned" (judged only by the SCF
+learned initial density, which is "parity unpinned" (assessed only by the SCF
 it seeds).
 """

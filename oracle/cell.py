@@ -4,7 +4,7 @@ the grid (Sec. 2 non-local energy and Sec. 3.1 discrete non-local operator).
 Test infrastructure (see oracle/__init__.py); never imported by the product path.
 
 The paper's Troullier-Martins pseudopotentials are not available, so the cell is
-synthetic (readings listed in the design doc):
+synthetic (readings of the paper where its data are not available):
   V_loc(x)  = - sum_J sum_L D_J exp(-|x - R_J - L|^2 / (2 w_J^2)), every image L
               with |x - R_J - L| <= 10 w_J;
   chi_s(r)  = c exp(-r^2/(2 sigma^2)) [r <= r_c],  sigma = r_c / 4;

@@ -24,7 +24,7 @@ they would add under the ReLU is what the fallback rule measures).  Prediction
 falls back to the SAD density when any value is not finite or when the charge
 before renormalisation is off by more than charge_tol * N_e.
 
-Parity of the network's *effect* is unpinned (it is judged by the SCF it
+Parity of the network's *effect* is unpinned (it is assessed by the SCF it
 starts); the functions here are pinned by the circular-correlation theorem
 (FFT), by finite differences of the loss, and by the closed form of Adam's
 first step.

@@ -4,7 +4,7 @@ Sec. 3.3-3.5), in the reduced form of the synthetic cell.
 
 Test infrastructure (see oracle/__init__.py); never imported by the product path.
 
-Reduced model (readings listed in the design doc):
+Reduced model (readings of the paper where it does not apply as written):
   * exchange only (Slater): eps_x = -(3/4)(3/pi)^{1/3} rho^{1/3}, V_x = (4/3) eps_x;
   * jellium electrostatics: the Gaussian local potential is external, the
     Hartree potential solves -Lap_h V_H = 4 pi (rho - mean(rho)) with zero mean;
