@@ -144,6 +144,20 @@ def mp2_kpoints(L):
     return ks, [1.0 / 8.0] * 8
 
 
+def band_path(L, corners=((-0.5, 0.5, 0.5), (0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (1.0, 1.0, 1.0)),
+              divisions=(10, 12, 17)):
+    """k-points of a piecewise-linear path through `corners` (reciprocal-lattice
+    coordinates, units of 2 pi / L_s) with the given divisions per segment, corners
+    included once: the L - Gamma - X - Gamma circuit with 10, 12 and 17 divisions of
+    the band-structure comparison of Sec. 4 (40 points).  Returns (n_k, 3) bohr^-1."""
+    c = np.asarray(corners, dtype=np.float64)
+    pts = [c[0]]
+    for s, nd in enumerate(divisions):
+        for t in range(1, nd + 1):
+            pts.append(c[s] + (c[s + 1] - c[s]) * t / nd)
+    return np.asarray(pts) * (2 * math.pi / np.asarray(L, dtype=np.float64))[None, :]
+
+
 def uneven_cells(n_cells: int = 24, h: float = 0.5, seed=(3, 0), with_orbitals: bool = True):
     """The batch of independent uneven cells: grid n drawn from {32, 48, 64, 80}
     (uneven_batch), spacing h, atoms / states / degree from UNEVEN_SIZES; cell i
