@@ -33,8 +33,9 @@ def _box_range(c: float, rcut: float, h: float, n: int):
 
 
 def _images(grid: Grid, rcut: float):
-    """Integer image multiples (a, b, c) that can bring a point within rcut."""
-    M = [int(math.ceil(rcut / grid.L[s])) + 1 for s in range(3)]
+    """Integer image multiples (a, b, c) that can bring a point within rcut; none
+    across a direction with zero Dirichlet conditions (the cell is not repeated)."""
+    M = [0 if grid.bc[s] == 1 else int(math.ceil(rcut / grid.L[s])) + 1 for s in range(3)]
     for c in range(-M[2], M[2] + 1):
         for b in range(-M[1], M[1] + 1):
             for a in range(-M[0], M[0] + 1):

@@ -11,6 +11,8 @@ Bloch form (reading of Sec. 2 "Electronic ground-state" with the periodic index
 map of Sec. 3.1): the operator acts on psi = e^{ik.x} u, and an index that leaves
 the cell is mapped to its periodic image with the Bloch factor
 psi(i + n_s) = e^{i k_s L_s} psi(i).  Then H = -1/2 Lap_h + V_eff + V_nl.
+A direction with zero Dirichlet conditions (slabs and wires, Sec. 3.1) sets every
+value at an index outside the grid to zero instead.
 """
 from __future__ import annotations
 
@@ -28,6 +30,7 @@ class Grid:
     L: tuple            # (L1, L2, L3) in bohr
     n_o: int = 6        # half-width of the stencil (12th order: n_o = 6, Sec. 4)
     k: tuple = (0.0, 0.0, 0.0)  # Bloch wavevector (bohr^-1)
+    bc: tuple = (0, 0, 0)       # per direction: 0 Bloch-periodic, 1 zero Dirichlet
 
     @property
     def h(self):
@@ -80,14 +83,19 @@ def gradient_weights(n_o: int, h: float):
                      for p in range(1, n_o + 1)])
 
 
-def bloch_shift(f3: np.ndarray, p: int, axis: int, n: int, kL: float):
+def bloch_shift(f3: np.ndarray, p: int, axis: int, n: int, kL: float, dirichlet: bool = False):
     """Return g with g(i) = f(i + p) along `axis` (length n), mapping an index
     outside 0..n-1 to its periodic image and multiplying by the Bloch factor
-    e^{i kL w}, w = floor((i+p)/n) the number of cell lengths crossed."""
+    e^{i kL w}, w = floor((i+p)/n) the number of cell lengths crossed; with a
+    zero Dirichlet condition such values are 0 (Sec. 3.1)."""
     idx = np.arange(n) + p
     wraps = np.floor_divide(idx, n)
     src = np.mod(idx, n)
     out = np.take(f3, src, axis=axis)
+    if dirichlet:
+        shape = [1, 1, 1]
+        shape[axis] = n
+        return out * (wraps == 0).reshape(shape)
     if kL != 0.0 and np.any(wraps != 0):
         fac = np.exp(1j * kL * wraps)
         shape = [1, 1, 1]
@@ -110,8 +118,8 @@ def minus_half_laplacian(f: np.ndarray, grid: Grid):
         kL = grid.k[s] * grid.L[s]
         lap = lap + 2.0 * w0 * f3
         for p in range(1, grid.n_o + 1):
-            lap = lap + w[p - 1] * (bloch_shift(f3, p, axes[s], grid.n[s], kL)
-                                    + bloch_shift(f3, -p, axes[s], grid.n[s], kL))
+            lap = lap + w[p - 1] * (bloch_shift(f3, p, axes[s], grid.n[s], kL, grid.bc[s] == 1)
+                                    + bloch_shift(f3, -p, axes[s], grid.n[s], kL, grid.bc[s] == 1))
     return (-0.5 * lap).reshape(-1)
 
 

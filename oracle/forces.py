@@ -59,8 +59,8 @@ def fd_gradient(f: np.ndarray, grid: Grid):
         kL = grid.k[s] * grid.L[s]
         acc = np.zeros(f3.shape, dtype=np.complex128 if (np.iscomplexobj(f3) or kL != 0.0) else np.float64)
         for p in range(1, grid.n_o + 1):
-            acc = acc + wt[p - 1] * (bloch_shift(f3, p, axes[s], grid.n[s], kL)
-                                     - bloch_shift(f3, -p, axes[s], grid.n[s], kL))
+            acc = acc + wt[p - 1] * (bloch_shift(f3, p, axes[s], grid.n[s], kL, grid.bc[s] == 1)
+                                     - bloch_shift(f3, -p, axes[s], grid.n[s], kL, grid.bc[s] == 1))
         out.append(acc.reshape(-1))
     return np.stack(out)
 
