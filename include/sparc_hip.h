@@ -57,14 +57,18 @@ typedef enum {
   SPARC_GEMM_NATIVE = 0
 } sparc_gemm_mode;
 
-/* Uniform periodic grid on an axis-aligned cuboid (Sec. 3.1): n grid points and
- * L lengths (bohr) per direction, stencil half-width n_o (12th order: 6), Bloch
- * wavevector kpt (bohr^-1). */
+/* Uniform grid on an axis-aligned cuboid (Sec. 3.1): n grid points and L lengths
+ * (bohr) per direction, stencil half-width n_o (12th order: 6), Bloch wavevector
+ * kpt (bohr^-1), and per direction the boundary condition bc: 0 Bloch-periodic,
+ * 1 zero Dirichlet (Sec. 3.1: every value at an index outside the grid is zero; the
+ * cell is not repeated across that direction, so atoms have no images there and kpt
+ * must be 0 in it).  Zero-initialise bc for a periodic cell. */
 typedef struct {
   int32_t n[3];
   double L[3];
   int32_t n_o;
   double kpt[3];
+  int32_t bc[3];
 } sparc_grid;
 
 /* Synthetic atoms (host pointers, read during sparc_ham_create only).
@@ -115,7 +119,8 @@ const char* sparc_status_string(int status);
  * sum_L e^{ik.L} chi_J(x - R_J - L) (Sec. 2, non-local operator; Sec. 3.1,
  * discrete form with the trapezoidal rule).  V_eff starts equal to V_loc.
  * dtype: SPARC_R64/SPARC_R32 need kpt = 0.  Synchronous.
- * Errors: EINVAL (null, n_o outside 1..8, l outside {0,1}, R64/R32 with k != 0),
+ * Errors: EINVAL (null, n_o outside 1..8, l outside {0,1}, R64/R32 with k != 0,
+ * bc outside {0,1}, k != 0 in a Dirichlet direction),
  * ESHAPE (n outside 1..4096, N_d >= 2^31). */
 int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
                      sparc_dtype dtype, sparc_ham** out);
@@ -254,8 +259,10 @@ typedef struct {
   double* history;     /* caller-provided host [3*max_iter]: (energy, rho_err, t_s) per iteration (may be NULL) */
 } sparc_scf_result;
 
-/* Runs the SCF; synchronous.  Errors: ENOCONV (max_iter reached; result holds
- * the last iterate), ENOTSPD, ENAN, EINVAL, ESHAPE, ENOMEM. */
+/* Runs the SCF; synchronous.  Periodic cells only (the jellium electrostatics have
+ * no Dirichlet form): a grid with a Dirichlet direction is rejected with EINVAL.
+ * Errors: ENOCONV (max_iter reached; result holds the last iterate), ENOTSPD, ENAN,
+ * EINVAL, ESHAPE, ENOMEM. */
 int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
                   const sparc_scf_params* params, sparc_scf_result* result);
 

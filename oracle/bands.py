@@ -21,14 +21,14 @@ from .fd import Grid, dense_H
 from .cell import projectors
 
 
-def bands(n, L, kpts, veff, atoms, n_bands: int, n_o: int = 6):
+def bands(n, L, kpts, veff, atoms, n_bands: int, n_o: int = 6, bc=(0, 0, 0)):
     """Lowest n_bands eigenvalues of H(k) (Sec. 2 Bloch Hamiltonian, Sec. 3.1
     discretisation) at every k of kpts (shape (n_k, 3), bohr^-1) with the
     potential veff fixed.  atoms = (R, chan_atom, chan_l, chan_gamma, chan_rc) for
     the projectors (rebuilt with the Bloch phases of each k).  Returns (n_k, n_bands)."""
     out = []
     for k in np.asarray(kpts, dtype=np.float64):
-        grid = Grid(n=tuple(n), L=tuple(L), n_o=n_o, k=tuple(k))
+        grid = Grid(n=tuple(n), L=tuple(L), n_o=n_o, k=tuple(k), bc=tuple(bc))
         P = projectors(grid, *atoms) if atoms is not None else ()
         H = dense_H(grid, veff, P)
         out.append(np.linalg.eigvalsh(0.5 * (H + H.conj().T))[:n_bands])

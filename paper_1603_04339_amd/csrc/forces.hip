@@ -14,7 +14,8 @@
 //             support node t as -4 sum_t sum_n occ_n Re[c_n(t) (grad_h u_n)(t)] with
 //             c_n(t) = sum_p gamma_p conj(alpha_pn chi~_p(t)), so a thread keeps three sums.
 //             One work-group per (atom, block of orbitals); the FD gradient (Sec. 3.1) is
-//             evaluated on the fly at the support nodes with the Bloch-periodic index map.
+//             evaluated on the fly at the support nodes with the Bloch-periodic index map
+//             (zero past a Dirichlet face).
 //             Orbitals with zero occupation are skipped.
 #include <algorithm>
 #include <cmath>
@@ -47,17 +48,23 @@ __device__ __forceinline__ int64_t floordiv_l(int64_t a, int64_t b) {
 
 // ---------------------------------------------------------------- local component
 __global__ __launch_bounds__(256) void force_local_kernel(int n1, int n2, int n3, double h1, double h2, double h3,
-                                                          const double* __restrict__ R, const double* __restrict__ D,
+                                                          int dmask, const double* __restrict__ R,
+                                                          const double* __restrict__ D,
                                                           const double* __restrict__ W,
                                                           const double* __restrict__ rho, double* __restrict__ part) {
   const int J = blockIdx.x, chunk = blockIdx.y;
   const double Rx = R[3 * J], Ry = R[3 * J + 1], Rz = R[3 * J + 2];
   const double w = W[J], rc = 10.0 * w, inv2w2 = 1.0 / (2.0 * w * w), amp = D[J] / (w * w);
   // box of unwrapped nodes within rc of the centre (each is one image point)
-  const int64_t i0 = (int64_t)ceil((Rx - rc) / h1), i1 = (int64_t)floor((Rx + rc) / h1);
-  const int64_t j0 = (int64_t)ceil((Ry - rc) / h2), j1 = (int64_t)floor((Ry + rc) / h2);
-  const int64_t k0 = (int64_t)ceil((Rz - rc) / h3), k1 = (int64_t)floor((Rz + rc) / h3);
-  const int64_t nx = i1 - i0 + 1, ny = j1 - j0 + 1, nz = k1 - k0 + 1;
+  int64_t i0 = (int64_t)ceil((Rx - rc) / h1), i1 = (int64_t)floor((Rx + rc) / h1);
+  int64_t j0 = (int64_t)ceil((Ry - rc) / h2), j1 = (int64_t)floor((Ry + rc) / h2);
+  int64_t k0 = (int64_t)ceil((Rz - rc) / h3), k1 = (int64_t)floor((Rz + rc) / h3);
+  // no images across a Dirichlet direction: keep the nodes inside the grid
+  if (dmask & 1) { i0 = max(i0, (int64_t)0); i1 = min(i1, (int64_t)n1 - 1); }
+  if (dmask & 2) { j0 = max(j0, (int64_t)0); j1 = min(j1, (int64_t)n2 - 1); }
+  if (dmask & 4) { k0 = max(k0, (int64_t)0); k1 = min(k1, (int64_t)n3 - 1); }
+  const int64_t nx = max(i1 - i0 + 1, (int64_t)0), ny = max(j1 - j0 + 1, (int64_t)0),
+                nz = max(k1 - k0 + 1, (int64_t)0);
   // this chunk's z planes
   const int64_t zc = (nz + gridDim.y - 1) / gridDim.y;
   const int64_t kb = k0 + chunk * zc, ke = std::min(k1 + 1, kb + zc);
@@ -89,7 +96,7 @@ __global__ void force_local_reduce(int n_atoms, int n_chunks, double dV, const d
 
 // ---------------------------------------------------------------- non-local component
 struct GradArgs {
-  int n1, n2, n3, no;
+  int n1, n2, n3, no, dmask;
   double w[3][8];    // w~_p / h_s
   double kl[3];      // k_s L_s
 };
@@ -183,12 +190,16 @@ __global__ __launch_bounds__(256) void force_nl_kernel(const E* __restrict__ x, 
           const int wp = floordiv_i(ip, nn), wm = floordiv_i(im, nn);
           const int64_t op = base + (int64_t)(ip - wp * nn) * stride, om = base + (int64_t)(im - wm * nn) * stride;
           const R wt = (R)G.w[d][p - 1];
+          // zero Dirichlet conditions: values past the face are zero
+          const bool zp = ((G.dmask >> d) & 1) && wp != 0, zm = ((G.dmask >> d) & 1) && wm != 0;
 #pragma unroll
           for (int j = 0; j < NB; ++j) {
             if (on[j] != 0.0) {
               const E* xn = x + (int64_t)(nb0 + j) * ldx;
-              const E vp = bloch_load(xn, op, wp, G.kl[d]);
-              const E vm = bloch_load(xn, om, wm, G.kl[d]);
+              E vp = bloch_load(xn, op, wp, G.kl[d]);
+              E vm = bloch_load(xn, om, wm, G.kl[d]);
+              if (zp) vp = zero<E>();
+              if (zm) vm = zero<E>();
               gs[j] = fmar(gs[j], wt, vp - vm);
             }
           }
@@ -229,6 +240,7 @@ static int force_nl_t(sparc_ham* H, const void* X, int64_t ldx, int32_t n_s, con
   G.n2 = H->grid.n[1];
   G.n3 = H->grid.n[2];
   G.no = H->grid.n_o;
+  G.dmask = dirichlet_mask(H->grid);
   for (int s = 0; s < 3; ++s) {
     for (int p = 0; p < 8; ++p) G.w[s][p] = H->gtap[s][p];
     G.kl[s] = H->grid.kpt[s] * H->grid.L[s];
@@ -267,8 +279,8 @@ int sparc_forces_local(sparc_ham* H, const double* rho_dev, double* F_dev) {
   hipStream_t st = H->ctx->stream;
   const int t = timer_begin(H->ctx, "force_local");
   force_local_kernel<<<dim3(H->n_atoms, kForceChunks), 256, 0, st>>>(
-      H->grid.n[0], H->grid.n[1], H->grid.n[2], H->h[0], H->h[1], H->h[2], H->atom_R, H->atom_D, H->atom_W, rho_dev,
-      H->force_part);
+      H->grid.n[0], H->grid.n[1], H->grid.n[2], H->h[0], H->h[1], H->h[2], dirichlet_mask(H->grid), H->atom_R,
+      H->atom_D, H->atom_W, rho_dev, H->force_part);
   timer_end(H->ctx, t);
   SPARC_TRY(check_launch("force_local_kernel"));
   const int nq = 3 * H->n_atoms;

@@ -277,6 +277,7 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   A.vb = (R)b;
   A.zc = (R)c;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
+  A.dmask = dirichlet_mask(H->grid);
   int t = heuristic_tile(A.n1, A.n2, sizeof(E));
   if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && z == nullptr && out != x) SPARC_TRY(autotune(H, A, n_s, &t));
   int rc = hstep_single<E>(H->ctx, A, n_s, H->grid.n_o, t);
@@ -310,6 +311,7 @@ static void fill_args(sparc_ham* H, const StepDesc& d, StepArgs<E>& A) {
   A.vb = (R)d.b;
   A.zc = (R)d.c;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
+  A.dmask = dirichlet_mask(H->grid);
 }
 
 size_t step_args_bytes(sparc_dtype dt) {

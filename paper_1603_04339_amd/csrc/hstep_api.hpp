@@ -23,6 +23,7 @@ struct StepArgs {
   R tx[8], ty[8], tz[8];
   R va, vb, zc;    // out = lap*a + (a V + b) x + zc z
   double kl[3];    // k_s L_s
+  int dmask;       // bit s: zero Dirichlet conditions along direction s
 };
 
 // ------------------------------------------------------------ launch planning

@@ -7,7 +7,8 @@
 // columns around the current plane in registers (z-direction taps); the current
 // plane, with NO-wide x and y halos, is staged in LDS (double-buffered, one barrier
 // per plane) for the x and y taps.  Loads are x-fastest and coalesced; nodes outside
-// the cell are fetched from their periodic image with the Bloch factor e^{i k_s L_s w}.
+// the cell are fetched from their periodic image with the Bloch factor e^{i k_s L_s w},
+// or are zero along a direction with Dirichlet conditions.
 #pragma once
 #include <algorithm>
 #include <cstdlib>
@@ -67,18 +68,23 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
   const int wx = floordiv_i(ex, n1), wy = floordiv_i(ey, n2);
   const int col = (ex - wx * n1) + n1 * (ey - wy * n2);
   const bool inside = (ex < n1) && (ey < n2);
+  // a column past a Dirichlet face holds zeros (it is read only as a halo)
+  const bool own_zero = ((A.dmask & 1) && wx != 0) || ((A.dmask & 2) && wy != 0);
+  const bool dz = (A.dmask & 4) != 0;
   R cxy = 1, sxy = 0;
   bloch_factor<E>(A.kl, wx, wy, 0, cxy, sxy);
   const int own = (hy + NO) * PX + hx + NO;
 
   // halo cells owned by this thread: LDS slot, offset inside a plane, Bloch factor
   int h_lds[HM], h_off[HM];
+  bool h_dz[HM];
   R h_c[HM], h_s[HM];
 #pragma unroll
   for (int u = 0; u < HM; ++u) {
     const int c = tid + u * NT;
     h_lds[u] = -1;
     h_off[u] = 0;
+    h_dz[u] = false;
     h_c[u] = 1;
     h_s[u] = 0;
     if (c < HC) {
@@ -98,27 +104,30 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
       h_off[u] = (gx - hwx * n1) + n1 * (gy - hwy * n2);
       h_lds[u] = (cy + NO) * PX + cx + NO;
       bloch_factor<E>(A.kl, hwx, hwy, 0, h_c[u], h_s[u]);
+      h_dz[u] = ((A.dmask & 1) && hwx != 0) || ((A.dmask & 2) && hwy != 0);   // Dirichlet: zero
     }
   }
 
   // z-direction register queue q[d] = x(column, z - NO + d); the plane index of the
-  // next load and its number of cell wraps are advanced without divisions
+  // next load and its number of cell wraps are advanced without divisions.  The Bloch
+  // rotation of a value from a wrapped plane is computed when the load is issued and
+  // applied where the value is consumed, so that issuing a prefetch never waits for its
+  // data; Dirichlet zeros replace the loads of planes past a z face and are applied at
+  // the LDS writes for x and y.
   int zl = zb - NO;
   int wz = floordiv_i(zl, n3);
   int sz = zl - wz * n3;
-  auto load_next = [&]() -> E {
-    E v = xc[col + plane_sz * sz];
+  R qc = cxy, qs = sxy;   // rotation of the pending column value
+  auto issue_next = [&]() -> E {
+    // a plane past a Dirichlet face in z is zero: the test is uniform over the
+    // work-group, so the load is branched around rather than its value selected
+    E v;
+    if (dz && wz != 0) v = zero<E>();
+    else v = xc[col + plane_sz * sz];
+    qc = cxy;
+    qs = sxy;
     if constexpr (elem<E>::is_cplx) {
-      if (wz != 0 || cxy != 1 || sxy != 0) {
-        R c = cxy, s = sxy;
-        if (wz != 0) {
-          R cz, szn;
-          bloch_factor<E>(A.kl, wx, wy, wz, cz, szn);
-          c = cz;
-          s = szn;
-        }
-        v = rot(v, c, s);
-      }
+      if (wz != 0) bloch_factor<E>(A.kl, wx, wy, wz, qc, qs);
     }
     if (++sz == n3) {
       sz = 0;
@@ -129,7 +138,11 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
 
   E q[2 * NO + 1];
 #pragma unroll
-  for (int d = 0; d < 2 * NO; ++d) q[d] = load_next();
+  for (int d = 0; d < 2 * NO; ++d) {
+    E v = issue_next();
+    if constexpr (elem<E>::is_cplx) v = rot(v, qc, qs);
+    q[d] = v;
+  }
 
   // software pipeline: the column value and halo cells of plane z+1 are loaded while
   // plane z is computed.  For 4-byte elements V_eff and the recurrence operand of plane
@@ -139,7 +152,7 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
   // number of resident waves, of the larger register queue down.
   constexpr bool PF = sizeof(E) <= 4;
   const E* __restrict__ pz = xc + plane_sz * zb;
-  E qn = load_next();
+  E qn = issue_next();
   E hn[HM];
 #pragma unroll
   for (int u = 0; u < HM; ++u) {
@@ -158,14 +171,16 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
   }
   int step = 0;
   for (int z = zb; z < ze; ++z, ++step, g += plane_sz) {
-    q[2 * NO] = qn;
+    if constexpr (elem<E>::is_cplx) q[2 * NO] = rot(qn, qc, qs);
+    else q[2 * NO] = qn;
     E* __restrict__ pl = plane[step & 1];
-    pl[own] = q[NO];
+    pl[own] = own_zero ? zero<E>() : q[NO];
 #pragma unroll
     for (int u = 0; u < HM; ++u) {
       if (h_lds[u] >= 0) {
         E v = hn[u];
         if constexpr (elem<E>::is_cplx) v = rot(v, h_c[u], h_s[u]);
+        if (h_dz[u]) v = zero<E>();
         pl[h_lds[u]] = v;
       }
     }
@@ -174,7 +189,7 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
     // issue the loads of the next plane (and, without prefetch, this plane's point data)
     pz += plane_sz;
     if (z + 1 < ze) {
-      qn = load_next();
+      qn = issue_next();
 #pragma unroll
       for (int u = 0; u < HM; ++u)
         if (h_lds[u] >= 0) hn[u] = pz[h_off[u]];

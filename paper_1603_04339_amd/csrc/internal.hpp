@@ -74,6 +74,9 @@ struct sparc_ctx {
   std::vector<hipEvent_t> pool;
 };
 
+// bit s set: zero Dirichlet conditions along direction s
+inline int dirichlet_mask(const sparc_grid& g) { return (g.bc[0] == 1 ? 1 : 0) | (g.bc[1] == 1 ? 2 : 0) | (g.bc[2] == 1 ? 4 : 0); }
+
 // z-chunks of the local-force box per atom (partial sums reduced in a fixed order)
 constexpr int kForceChunks = 8;
 

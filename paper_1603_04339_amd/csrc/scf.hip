@@ -63,7 +63,7 @@ static int reduce(hipStream_t s, int64_t n, const double* a, const double* b, in
 
 // atomic superposition: Z_J (2 pi w^2)^{-3/2} exp(-r^2/(2 w^2)), images within 10 w
 __global__ void sad_kernel(int n1, int n2, int n3, double h1, double h2, double h3, double L1, double L2, double L3,
-                           int n_atoms, const double* __restrict__ R, const double* __restrict__ W,
+                           int dmask, int n_atoms, const double* __restrict__ R, const double* __restrict__ W,
                            const double* __restrict__ Z, double* __restrict__ rho) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= (int64_t)n1 * n2 * n3) return;
@@ -72,9 +72,13 @@ __global__ void sad_kernel(int n1, int n2, int n3, double h1, double h2, double 
   for (int a = 0; a < n_atoms; ++a) {
     double w = W[a], rc = 10.0 * w, amp = Z[a] * pow(2.0 * M_PI * w * w, -1.5);
     double dx0 = x - R[3 * a], dy0 = y - R[3 * a + 1], dz0 = z - R[3 * a + 2];
-    for (int az = (int)ceil((dz0 - rc) / L3); az <= (int)floor((dz0 + rc) / L3); ++az)
-      for (int ay = (int)ceil((dy0 - rc) / L2); ay <= (int)floor((dy0 + rc) / L2); ++ay)
-        for (int ax = (int)ceil((dx0 - rc) / L1); ax <= (int)floor((dx0 + rc) / L1); ++ax) {
+    // images only along periodic directions
+    const int az0 = (dmask & 4) ? 0 : (int)ceil((dz0 - rc) / L3), az1 = (dmask & 4) ? 0 : (int)floor((dz0 + rc) / L3);
+    const int ay0 = (dmask & 2) ? 0 : (int)ceil((dy0 - rc) / L2), ay1 = (dmask & 2) ? 0 : (int)floor((dy0 + rc) / L2);
+    const int ax0 = (dmask & 1) ? 0 : (int)ceil((dx0 - rc) / L1), ax1 = (dmask & 1) ? 0 : (int)floor((dx0 + rc) / L1);
+    for (int az = az0; az <= az1; ++az)
+      for (int ay = ay0; ay <= ay1; ++ay)
+        for (int ax = ax0; ax <= ax1; ++ax) {
           double dx = dx0 - ax * L1, dy = dy0 - ay * L2, dz = dz0 - az * L3;
           double r2 = dx * dx + dy * dy + dz * dz;
           if (r2 <= rc * rc) acc += amp * exp(-r2 / (2.0 * w * w));
@@ -380,7 +384,7 @@ static int sad_fill(hipStream_t s, Buffers& B, const sparc_grid* grid, const spa
   SPARC_HIP(hipMemcpyAsync(dW, W.data(), W.size() * 8, hipMemcpyHostToDevice, s));
   SPARC_HIP(hipMemcpyAsync(dZ, Z.data(), Z.size() * 8, hipMemcpyHostToDevice, s));
   sad_kernel<<<GRID1(n)>>>(grid->n[0], grid->n[1], grid->n[2], h1, h2, h3, grid->L[0], grid->L[1], grid->L[2],
-                           atoms->n_atoms, dR, dW, dZ, rho_in);
+                           dirichlet_mask(*grid), atoms->n_atoms, dR, dW, dZ, rho_in);
   SPARC_TRY(check_launch("sad_kernel"));
   SPARC_TRY(reduce(s, n, rho_in, nullptr, RED_SUM, part, sc + 5));
   // rho *= N_e / (dV * sum rho)
@@ -417,6 +421,8 @@ extern "C" int sparc_sad_density(sparc_ctx* ctx, const sparc_grid* grid, const s
 extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms,
                              const sparc_scf_params* P, sparc_scf_result* res) {
   if (!ctx || !grid || !atoms || !P || !res) return fail(SPARC_EINVAL, "sparc_scf_run: null argument");
+  if (dirichlet_mask(*grid) != 0)
+    return fail(SPARC_EINVAL, "sparc_scf_run: periodic cells only (the jellium electrostatics have no Dirichlet form)");
   if (grid->kpt[0] != 0 || grid->kpt[1] != 0 || grid->kpt[2] != 0)
     return fail(SPARC_EINVAL, "sparc_scf_run: the SCF driver runs at the Gamma point");
   if (P->n_s < 1 || P->degree < 1 || P->max_iter < 1 || P->n_first_passes < 1 || P->lanczos_steps < 2)

@@ -25,9 +25,9 @@ int fail(int status, const char* fmt, ...) {
 }
 
 // Local potential: one thread per node, summing every atom image whose well
-// reaches the node (cut at 10 widths).
+// reaches the node (cut at 10 widths); images only along periodic directions.
 __global__ void vloc_kernel(int n1, int n2, int n3, double h1, double h2, double h3, double L1, double L2,
-                            double L3, int n_atoms, const double* __restrict__ R,
+                            double L3, int dmask, int n_atoms, const double* __restrict__ R,
                             const double* __restrict__ D, const double* __restrict__ W, double* __restrict__ v) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t nd = (int64_t)n1 * n2 * n3;
@@ -43,6 +43,10 @@ __global__ void vloc_kernel(int n1, int n2, int n3, double h1, double h2, double
     int ax0 = (int)ceil((dx0 - rc) / L1), ax1 = (int)floor((dx0 + rc) / L1);
     int ay0 = (int)ceil((dy0 - rc) / L2), ay1 = (int)floor((dy0 + rc) / L2);
     int az0 = (int)ceil((dz0 - rc) / L3), az1 = (int)floor((dz0 + rc) / L3);
+    // no images across a Dirichlet direction
+    if (dmask & 1) ax0 = ax1 = 0;
+    if (dmask & 2) ay0 = ay1 = 0;
+    if (dmask & 4) az0 = az1 = 0;
     for (int az = az0; az <= az1; ++az) {
       double dz = dz0 - az * L3;
       for (int ay = ay0; ay <= ay1; ++ay) {
@@ -134,6 +138,10 @@ static int build_projectors(const sparc_grid& G, const double h[3], double dV, c
     int64_t i0 = (int64_t)std::ceil((Rx - rmax) / h[0]), i1 = (int64_t)std::floor((Rx + rmax) / h[0]);
     int64_t j0 = (int64_t)std::ceil((Ry - rmax) / h[1]), j1 = (int64_t)std::floor((Ry + rmax) / h[1]);
     int64_t k0 = (int64_t)std::ceil((Rz - rmax) / h[2]), k1 = (int64_t)std::floor((Rz + rmax) / h[2]);
+    // a Dirichlet direction keeps the nodes inside the grid (no images, no wrap)
+    if (G.bc[0] == 1) { i0 = std::max<int64_t>(i0, 0); i1 = std::min<int64_t>(i1, n1 - 1); }
+    if (G.bc[1] == 1) { j0 = std::max<int64_t>(j0, 0); j1 = std::min<int64_t>(j1, n2 - 1); }
+    if (G.bc[2] == 1) { k0 = std::max<int64_t>(k0, 0); k1 = std::min<int64_t>(k1, n3 - 1); }
     for (int64_t k = k0; k <= k1; ++k)
       for (int64_t j = j0; j <= j1; ++j)
         for (int64_t i = i0; i <= i1; ++i) {
@@ -333,6 +341,12 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
     nd *= grid->n[s];
   }
   if (nd >= (int64_t(1) << 31)) return fail(SPARC_ESHAPE, "sparc_ham_create: N_d=%lld too large", (long long)nd);
+  for (int s = 0; s < 3; ++s) {
+    if (grid->bc[s] != 0 && grid->bc[s] != 1)
+      return fail(SPARC_EINVAL, "sparc_ham_create: bc[%d]=%d (0 periodic, 1 Dirichlet)", s, grid->bc[s]);
+    if (grid->bc[s] == 1 && grid->kpt[s] != 0.0)
+      return fail(SPARC_EINVAL, "sparc_ham_create: k[%d] must be 0 in a Dirichlet direction", s);
+  }
   bool gamma = grid->kpt[0] == 0.0 && grid->kpt[1] == 0.0 && grid->kpt[2] == 0.0;
   if (!dtype_complex(dtype) && !gamma)
     return fail(SPARC_EINVAL, "sparc_ham_create: real dtype needs the Gamma point");
@@ -421,7 +435,8 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
     int64_t nb = (nd + blk - 1) / blk;
     vloc_kernel<<<dim3((unsigned)nb), dim3(blk), 0, st>>>(grid->n[0], grid->n[1], grid->n[2], H->h[0], H->h[1],
                                                            H->h[2], grid->L[0], grid->L[1], grid->L[2],
-                                                           atoms->n_atoms, dR, dD, dW, H->vloc);
+                                                           dirichlet_mask(*grid), atoms->n_atoms, dR, dD, dW,
+                                                           H->vloc);
     if ((rc = check_launch("vloc_kernel"))) { sparc_ham_destroy(H); return rc; }
     hipMemcpyAsync(H->veff, H->vloc, nd * 8, hipMemcpyDeviceToDevice, st);
     d2f_kernel<<<dim3((unsigned)nb), dim3(blk), 0, st>>>(H->vloc, H->veff32, nd);

@@ -35,7 +35,8 @@ class SparcError(RuntimeError):
 
 
 class sparc_grid(C.Structure):
-    _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3), ("n_o", C.c_int32), ("kpt", C.c_double * 3)]
+    _fields_ = [("n", C.c_int32 * 3), ("L", C.c_double * 3), ("n_o", C.c_int32), ("kpt", C.c_double * 3),
+                ("bc", C.c_int32 * 3)]
 
 
 class sparc_atoms(C.Structure):
@@ -208,12 +209,14 @@ class Context:
             pass
 
 
-def make_grid(n, L, n_o=6, kpt=(0.0, 0.0, 0.0)):
+def make_grid(n, L, n_o=6, kpt=(0.0, 0.0, 0.0), bc=(0, 0, 0)):
+    """Grid struct; bc per direction: 0 Bloch-periodic, 1 zero Dirichlet."""
     g = sparc_grid()
     for s in range(3):
         g.n[s] = int(n[s])
         g.L[s] = float(L[s])
         g.kpt[s] = float(kpt[s])
+        g.bc[s] = int(bc[s])
     g.n_o = int(n_o)
     return g
 
@@ -246,7 +249,7 @@ class Hamiltonian:
         lib = load()
         self.ctx = ctx
         self.dtype = dtype
-        self.grid = make_grid(cell.n, cell.L, n_o, kpt)
+        self.grid = make_grid(cell.n, cell.L, n_o, kpt, getattr(cell, "bc", (0, 0, 0)))
         self._atoms = _Atoms(cell)
         h = C.c_void_p()
         _check(lib.sparc_ham_create(ctx.handle, C.byref(self.grid), C.byref(self._atoms.struct), dtype, C.byref(h)))
@@ -450,7 +453,7 @@ def set_autotune(ctx: Context, enable: bool):
 def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=None, n_o: int = 6):
     """Minimal SCF through the library; params keys follow sparc_scf_params."""
     lib = load()
-    grid = make_grid(cell.n, cell.L, n_o)
+    grid = make_grid(cell.n, cell.L, n_o, bc=getattr(cell, "bc", (0, 0, 0)))
     atoms = _Atoms(cell)
     p = sparc_scf_params()
     for k, v in params.items():
@@ -479,7 +482,7 @@ def band_structure(ctx: Context, cell, veff, kpts, Xs, n_bands: int, degree: int
     overwritten by the Ritz vectors.  Returns (eig (n_k, n_bands), passes (n_k,),
     status) where status is OK or ENOCONV."""
     lib = load()
-    grid = make_grid(cell.n, cell.L, n_o)
+    grid = make_grid(cell.n, cell.L, n_o, bc=getattr(cell, "bc", (0, 0, 0)))
     atoms = _Atoms(cell)
     k = np.ascontiguousarray(kpts, dtype=np.float64).reshape(-1, 3)
     nk = k.shape[0]
@@ -513,7 +516,7 @@ def dos(eig, wk, energies, sigma: float):
 
 def sad_density(ctx: Context, cell, rho_out, n_o: int = 6):
     """Atomic-superposition density of a cell into rho_out (device FP64, N_d)."""
-    grid = make_grid(cell.n, cell.L, n_o)
+    grid = make_grid(cell.n, cell.L, n_o, bc=getattr(cell, "bc", (0, 0, 0)))
     atoms = _Atoms(cell)
     _check(load().sparc_sad_density(ctx.handle, C.byref(grid), C.byref(atoms.struct), float(cell.n_elec),
                                     _ptr(rho_out)))

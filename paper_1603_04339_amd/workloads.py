@@ -56,6 +56,7 @@ class Cell:
     n_s: int = 0
     degree: int = 20
     passes: int = 1
+    bc: tuple = (0, 0, 0)           # per direction: 0 Bloch-periodic, 1 zero Dirichlet
     extra: dict = field(default_factory=dict)
 
     @property

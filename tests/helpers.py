@@ -6,7 +6,7 @@ from oracle.cell import local_potential, projectors
 
 
 def oracle_setup(cell, kpt=(0.0, 0.0, 0.0), n_o=6):
-    grid = Grid(n=tuple(cell.n), L=tuple(cell.L), n_o=n_o, k=tuple(kpt))
+    grid = Grid(n=tuple(cell.n), L=tuple(cell.L), n_o=n_o, k=tuple(kpt), bc=tuple(getattr(cell, "bc", (0, 0, 0))))
     V = local_potential(grid, cell.positions, cell.depth, cell.width)
     P = projectors(grid, cell.positions, cell.chan_atom, cell.chan_l, cell.chan_gamma, cell.chan_rc)
     return grid, V, P
