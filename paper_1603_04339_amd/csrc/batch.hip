@@ -23,6 +23,7 @@ struct sparc_filter_plan {
   sparc_ctx* ctx;
   sparc_dtype dt;
   int n_o, tile, n_prob, max_deg;
+  int dir;   // some problem has a Dirichlet direction
   std::vector<sparc_ham*> H;
   std::vector<void*> X, W, alpha;
   std::vector<int64_t> ldx;
@@ -60,7 +61,7 @@ static int plan_enqueue(sparc_filter_plan* P) {
       SPARC_TRY(nl_project(P->H[p], x, ld, P->n_s[p], P->alpha[p]));
     }
     SPARC_TRY(step_table_launch(P->ctx, P->dt, P->n_o, P->tile, P->dev_tables + P->table_off[j],
-                                P->dev_wg + P->wg_off[j], (int)mem.size(), P->total_wg[j]));
+                                P->dev_wg + P->wg_off[j], (int)mem.size(), P->total_wg[j], P->dir));
     for (int p : mem) {
       void* out = (j % 2 == 0) ? P->W[p] : P->X[p];
       const int64_t ldo = (j % 2 == 0) ? P->H[p]->n_d : P->ldx[p];
@@ -194,6 +195,8 @@ int sparc_filter_plan_create(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H
   for (int p = 1; p < n_prob; ++p)
     if ((double)H[p]->n_d * n_s[p] > (double)H[big]->n_d * n_s[big]) big = p;
   P->tile = heuristic_tile(H[big]->grid.n[0], H[big]->grid.n[1], elem_bytes(P->dt));
+  P->dir = 0;
+  for (int p = 0; p < n_prob; ++p) P->dir |= dirichlet_mask(H[p]->grid) != 0 ? 1 : 0;
   if (ctx->autotune) {
     int t;
     if (!tuned_tile(H[big], n_s[big], &t)) {

@@ -278,6 +278,7 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   A.zc = (R)c;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
   A.dmask = dirichlet_mask(H->grid);
+  A.zplane = (const E*)H->zplane;
   int t = heuristic_tile(A.n1, A.n2, sizeof(E));
   if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && z == nullptr && out != x) SPARC_TRY(autotune(H, A, n_s, &t));
   int rc = hstep_single<E>(H->ctx, A, n_s, H->grid.n_o, t);
@@ -312,6 +313,7 @@ static void fill_args(sparc_ham* H, const StepDesc& d, StepArgs<E>& A) {
   A.zc = (R)d.c;
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
   A.dmask = dirichlet_mask(H->grid);
+  A.zplane = (const E*)H->zplane;
 }
 
 size_t step_args_bytes(sparc_dtype dt) {
@@ -348,12 +350,12 @@ int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile
 }
 
 int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
-                      int n, int64_t total) {
+                      int n, int64_t total, int dir) {
   switch (dt) {
-    case SPARC_R64: return hstep_batched<double>(ctx, dev_table, dev_wg, n, total, no, tile);
-    case SPARC_R32: return hstep_batched<float>(ctx, dev_table, dev_wg, n, total, no, tile);
-    case SPARC_C128: return hstep_batched<cd>(ctx, dev_table, dev_wg, n, total, no, tile);
-    case SPARC_C64: return hstep_batched<cf>(ctx, dev_table, dev_wg, n, total, no, tile);
+    case SPARC_R64: return hstep_batched<double>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
+    case SPARC_R32: return hstep_batched<float>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
+    case SPARC_C128: return hstep_batched<cd>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
+    case SPARC_C64: return hstep_batched<cf>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
   }
   return fail(SPARC_EINVAL, "batched step: bad dtype");
 }

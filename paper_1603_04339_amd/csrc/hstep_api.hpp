@@ -24,6 +24,7 @@ struct StepArgs {
   R va, vb, zc;    // out = lap*a + (a V + b) x + zc z
   double kl[3];    // k_s L_s
   int dmask;       // bit s: zero Dirichlet conditions along direction s
+  const E* zplane; // one plane of zeros (read for planes past a Dirichlet z face)
 };
 
 // ------------------------------------------------------------ launch planning
@@ -54,8 +55,9 @@ inline int64_t plan_problem(StepArgs<E>& A, int tx, int ty, int no, int n_s, int
 // one stencil step launch (single problem) with stencil order no and tile shape t
 template <typename E>
 int hstep_single(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int no, int t);
-// one batched stencil step launch over a device table of n problems
+// one batched stencil step launch over a device table of n problems (dir: some problem
+// has a Dirichlet direction)
 template <typename E>
-int hstep_batched(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n, int64_t total, int no, int t);
+int hstep_batched(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n, int64_t total, int no, int t, int dir);
 
 }  // namespace sparc

@@ -45,7 +45,7 @@ __device__ __forceinline__ void bloch_factor(const double* kl, int wx, int wy, i
 // staged in LDS (double-buffered, one barrier per plane).  Threads whose column lies
 // past the grid edge (partial tiles) load the periodic image, with the Bloch factor,
 // so the LDS plane is always complete.
-template <typename E, int TX, int TY, int NO>
+template <typename E, int TX, int TY, int NO, bool DIR>
 __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n, int zi,
                                            E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
   typedef typename elem<E>::real R;
@@ -68,9 +68,10 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
   const int wx = floordiv_i(ex, n1), wy = floordiv_i(ey, n2);
   const int col = (ex - wx * n1) + n1 * (ey - wy * n2);
   const bool inside = (ex < n1) && (ey < n2);
-  // a column past a Dirichlet face holds zeros (it is read only as a halo)
-  const bool own_zero = ((A.dmask & 1) && wx != 0) || ((A.dmask & 2) && wy != 0);
-  const bool dz = (A.dmask & 4) != 0;
+  // a column past a Dirichlet face holds zeros (it is read only as a halo); DIR is
+  // false for launches without Dirichlet directions, which then compile without them
+  const bool own_zero = DIR && (((A.dmask & 1) && wx != 0) || ((A.dmask & 2) && wy != 0));
+  const bool dz = DIR && (A.dmask & 4) != 0;
   R cxy = 1, sxy = 0;
   bloch_factor<E>(A.kl, wx, wy, 0, cxy, sxy);
   const int own = (hy + NO) * PX + hx + NO;
@@ -104,7 +105,7 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
       h_off[u] = (gx - hwx * n1) + n1 * (gy - hwy * n2);
       h_lds[u] = (cy + NO) * PX + cx + NO;
       bloch_factor<E>(A.kl, hwx, hwy, 0, h_c[u], h_s[u]);
-      h_dz[u] = ((A.dmask & 1) && hwx != 0) || ((A.dmask & 2) && hwy != 0);   // Dirichlet: zero
+      h_dz[u] = DIR && (((A.dmask & 1) && hwx != 0) || ((A.dmask & 2) && hwy != 0));   // Dirichlet: zero
     }
   }
 
@@ -112,18 +113,20 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
   // next load and its number of cell wraps are advanced without divisions.  The Bloch
   // rotation of a value from a wrapped plane is computed when the load is issued and
   // applied where the value is consumed, so that issuing a prefetch never waits for its
-  // data; Dirichlet zeros replace the loads of planes past a z face and are applied at
-  // the LDS writes for x and y.
+  // data; planes past a Dirichlet z face are read from a plane of zeros, and the
+  // Dirichlet zeros in x and y are applied at the LDS writes.
   int zl = zb - NO;
   int wz = floordiv_i(zl, n3);
   int sz = zl - wz * n3;
   R qc = cxy, qs = sxy;   // rotation of the pending column value
   auto issue_next = [&]() -> E {
-    // a plane past a Dirichlet face in z is zero: the test is uniform over the
-    // work-group, so the load is branched around rather than its value selected
-    E v;
-    if (dz && wz != 0) v = zero<E>();
-    else v = xc[col + plane_sz * sz];
+    // a plane past a Dirichlet face in z is read from a plane of zeros: the choice is
+    // uniform over the work-group and made on the address, never on loaded data
+    const E* __restrict__ src = xc + plane_sz * sz;
+    if constexpr (DIR) {
+      if (dz && wz != 0) src = A.zplane;
+    }
+    E v = src[col];
     qc = cxy;
     qs = sxy;
     if constexpr (elem<E>::is_cplx) {
@@ -174,13 +177,16 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
     if constexpr (elem<E>::is_cplx) q[2 * NO] = rot(qn, qc, qs);
     else q[2 * NO] = qn;
     E* __restrict__ pl = plane[step & 1];
-    pl[own] = own_zero ? zero<E>() : q[NO];
+    if constexpr (DIR) pl[own] = own_zero ? zero<E>() : q[NO];
+    else pl[own] = q[NO];
 #pragma unroll
     for (int u = 0; u < HM; ++u) {
       if (h_lds[u] >= 0) {
         E v = hn[u];
         if constexpr (elem<E>::is_cplx) v = rot(v, h_c[u], h_s[u]);
-        if (h_dz[u]) v = zero<E>();
+        if constexpr (DIR) {
+          if (h_dz[u]) v = zero<E>();
+        }
         pl[h_lds[u]] = v;
       }
     }
@@ -231,7 +237,7 @@ __device__ __forceinline__ int64_t xcd_order(int64_t L, int64_t G) {
   return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
-template <typename E, int TX, int TY, int NO>
+template <typename E, int TX, int TY, int NO, bool DIR>
 __device__ __forceinline__ void hstep_local(const StepArgs<E>& A, int64_t local,
                                             E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
   // tiles fastest (neighbouring tiles share halo columns in L2), then orbitals, then z chunks
@@ -239,19 +245,19 @@ __device__ __forceinline__ void hstep_local(const StepArgs<E>& A, int64_t local,
   const int64_t rest = local / A.tiles;
   const int n = (int)(rest % A.ns);
   const int zi = (int)(rest / A.ns);
-  hstep_body<E, TX, TY, NO>(A, tile, n, zi, plane);
+  hstep_body<E, TX, TY, NO, DIR>(A, tile, n, zi, plane);
 }
 
-template <typename E, int TX, int TY, int NO>
+template <typename E, int TX, int TY, int NO, bool DIR>
 __global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
   __shared__ __align__(16) E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
-  hstep_local<E, TX, TY, NO>(A, xcd_order(blockIdx.x, gridDim.x), plane);
+  hstep_local<E, TX, TY, NO, DIR>(A, xcd_order(blockIdx.x, gridDim.x), plane);
 }
 
 // Several (cell, k) problems in one launch: work-group b (in XCD order) belongs to the
 // problem p with wg_off[p] <= b < wg_off[p+1]; inside it, the logical order of a
 // single-problem launch.
-template <typename E, int TX, int TY, int NO>
+template <typename E, int TX, int TY, int NO, bool DIR>
 __global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>* __restrict__ probs,
                                                                     const int* __restrict__ wg_off, int n_probs) {
   __shared__ __align__(16) E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
@@ -263,7 +269,7 @@ __global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>
     else hi = mid - 1;
   }
   const StepArgs<E> A = probs[lo];
-  hstep_local<E, TX, TY, NO>(A, b - wg_off[lo], plane);
+  hstep_local<E, TX, TY, NO, DIR>(A, b - wg_off[lo], plane);
 }
 
 template <typename E, int TX, int TY, int NO>
@@ -271,18 +277,24 @@ static int launch_single_t(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s) {
   const int64_t G = plan_problem(A, TX, TY, NO, n_s, ctx->n_cu);
   if (G > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "stencil step: too many work-groups");
   int t = timer_begin(ctx, "hstep");
-  hstep_kernel<E, TX, TY, NO><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
+  if (A.dmask) hstep_kernel<E, TX, TY, NO, true><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
+  else hstep_kernel<E, TX, TY, NO, false><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
   timer_end(ctx, t);
   return check_launch("hstep_kernel");
 }
 
 template <typename E, int TX, int TY, int NO>
-static int launch_batched_t(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total_wg) {
+static int launch_batched_t(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total_wg,
+                            int dir) {
   if (total_wg <= 0) return SPARC_OK;
   if (total_wg > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "batched step: too many work-groups");
   int t = timer_begin(ctx, "hstep");
-  hstep_batched_kernel<E, TX, TY, NO><<<(unsigned)total_wg, TX * TY, 0, ctx->stream>>>(
-      (const StepArgs<E>*)dprobs, dwg, n_probs);
+  if (dir)
+    hstep_batched_kernel<E, TX, TY, NO, true><<<(unsigned)total_wg, TX * TY, 0, ctx->stream>>>(
+        (const StepArgs<E>*)dprobs, dwg, n_probs);
+  else
+    hstep_batched_kernel<E, TX, TY, NO, false><<<(unsigned)total_wg, TX * TY, 0, ctx->stream>>>(
+        (const StepArgs<E>*)dprobs, dwg, n_probs);
   timer_end(ctx, t);
   return check_launch("hstep_batched_kernel");
 }
@@ -321,8 +333,9 @@ static int single_no(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int no, int t)
 }
 
 template <typename E, int NO>
-static int batched_tile(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total, int t) {
-#define CALL(tx, ty) launch_batched_t<E, tx, ty, NO>(ctx, dprobs, dwg, n_probs, total)
+static int batched_tile(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total, int t,
+                        int dir) {
+#define CALL(tx, ty) launch_batched_t<E, tx, ty, NO>(ctx, dprobs, dwg, n_probs, total, dir)
   SPARC_TILE_SWITCH(t, CALL)
 #undef CALL
 }
@@ -333,16 +346,16 @@ int hstep_single(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int no, int t) {
 }
 
 template <typename E>
-int hstep_batched(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n, int64_t total, int no, int t) {
+int hstep_batched(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n, int64_t total, int no, int t, int dir) {
   switch (no) {
-    case 1: return batched_tile<E, 1>(ctx, dprobs, dwg, n, total, t);
-    case 2: return batched_tile<E, 2>(ctx, dprobs, dwg, n, total, t);
-    case 3: return batched_tile<E, 3>(ctx, dprobs, dwg, n, total, t);
-    case 4: return batched_tile<E, 4>(ctx, dprobs, dwg, n, total, t);
-    case 5: return batched_tile<E, 5>(ctx, dprobs, dwg, n, total, t);
-    case 6: return batched_tile<E, 6>(ctx, dprobs, dwg, n, total, t);
-    case 7: return batched_tile<E, 7>(ctx, dprobs, dwg, n, total, t);
-    case 8: return batched_tile<E, 8>(ctx, dprobs, dwg, n, total, t);
+    case 1: return batched_tile<E, 1>(ctx, dprobs, dwg, n, total, t, dir);
+    case 2: return batched_tile<E, 2>(ctx, dprobs, dwg, n, total, t, dir);
+    case 3: return batched_tile<E, 3>(ctx, dprobs, dwg, n, total, t, dir);
+    case 4: return batched_tile<E, 4>(ctx, dprobs, dwg, n, total, t, dir);
+    case 5: return batched_tile<E, 5>(ctx, dprobs, dwg, n, total, t, dir);
+    case 6: return batched_tile<E, 6>(ctx, dprobs, dwg, n, total, t, dir);
+    case 7: return batched_tile<E, 7>(ctx, dprobs, dwg, n, total, t, dir);
+    case 8: return batched_tile<E, 8>(ctx, dprobs, dwg, n, total, t, dir);
   }
   return fail(SPARC_EINVAL, "batched step: n_o=%d unsupported", no);
 }

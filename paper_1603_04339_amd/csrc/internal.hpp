@@ -121,6 +121,7 @@ struct sparc_ham {
   double* atom_W;       // [n_atoms] well widths
   double* force_part;   // [n_atoms * kForceChunks * 3] partial sums of the local force
   int32_t* nl_atom;     // [n_atoms_nl] atom index of each projector-carrying atom
+  void* zplane;         // [n1 n2] zero elements (Dirichlet z only; read for planes past a face)
   double gtap[3][8];    // FD gradient weights w~_p / h_s per direction, p = 1..n_o
 };
 
@@ -168,7 +169,7 @@ struct StepDesc {
 size_t step_args_bytes(sparc_dtype dt);
 int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg);
 int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
-                      int n, int64_t total);
+                      int n, int64_t total, int dir);
 int tuned_tile(sparc_ham* H, int32_t n_s, int* t);
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
 // partial sums of the non-local force (forces.hip)

@@ -420,6 +420,11 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
     if (!rc && atoms->n_atoms > 0 &&
         hipMalloc(&H->force_part, (size_t)atoms->n_atoms * kForceChunks * 3 * sizeof(double)) != hipSuccess)
       rc = fail(SPARC_ENOMEM, "sparc_ham_create: force buffer allocation failed");
+    if (!rc && grid->bc[2] == 1) {   // plane of zeros (16 bytes per node covers every element type)
+      const size_t zb = (size_t)grid->n[0] * grid->n[1] * 16;
+      if (hipMalloc(&H->zplane, zb) != hipSuccess || hipMemsetAsync(H->zplane, 0, zb, ctx->stream) != hipSuccess)
+        rc = fail(SPARC_ENOMEM, "sparc_ham_create: zero-plane allocation failed");
+    }
     if (rc) {
       sparc_ham_destroy(H);
       return rc;
@@ -515,7 +520,7 @@ void sparc_ham_destroy(sparc_ham* H) {
   if (!H) return;
   void* ptrs[] = {H->vloc, H->veff, H->veff32, H->sup_ptr, H->sup_idx, H->atom_pbeg, H->proj_voff,
                   H->pval, H->gamma_d, H->nl_pts, H->nl_ptr, H->ent_proj, H->ent_coef,
-                  H->atom_R, H->atom_D, H->atom_W, H->force_part, H->nl_atom};
+                  H->atom_R, H->atom_D, H->atom_W, H->force_part, H->nl_atom, H->zplane};
   for (void* p : ptrs)
     if (p) hipFree(p);
   delete H;
