@@ -38,7 +38,7 @@ METRIC = "filtered grid-pt·states/s FP64 vs mixed; SCF wall time to 1e-5 Ha/ato
 # HBM traffic of the FP64 c2 stencil-step launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hstep_c2_96cubed_f64.md);
 # valid only for the kernel source it was measured on (checked by hash, else null)
-HSTEP_TRAFFIC = {"bytes_per_launch": 1.804335e+10, "kernel_sources_sha256": "f43015aaa9f4b14c87044b62f3d3be618527f915653eff6bae422b1dd1fe9e10",
+HSTEP_TRAFFIC = {"bytes_per_launch": 1.809424e+10, "kernel_sources_sha256": "f674b1518227c669e94f3c8ccd3cd7b245b4d22e0cc787519b3f6f7886b27b38",
                  "profile": "profiles/hstep_c2_96cubed_f64.md"}
 UNIT = "grid-pt·states/s"
 HBM_PEAK_GBS = 8000.0
