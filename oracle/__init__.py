@@ -21,6 +21,8 @@ Modules
   forces   atomic forces: local component, non-local component with the
            gradient on the orbitals, FD gradient
   bands    band structure at fixed potential (dense H(k)), density of states
+  pseudocharge  pseudocharge electrostatics: truncation radius, pseudocharge and
+           self energy, overlap correction, local and correction forces
   density_net  3-D convolutional network forward/backward for the initial density
 
 Parity status: every function is pinned by a CPU test against closed forms,

@@ -8,6 +8,9 @@ Reduced model (readings of the paper where it does not apply as written):
   * exchange only (Slater): eps_x = -(3/4)(3/pi)^{1/3} rho^{1/3}, V_x = (4/3) eps_x;
   * jellium electrostatics: the Gaussian local potential is external, the
     Hartree potential solves -Lap_h V_H = 4 pi (rho - mean(rho)) with zero mean;
+    or, with a pseudocharge b (oracle/pseudocharge.py), the paper's form: V_loc = 0,
+    phi solves -Lap_h phi = 4 pi (rho + b) (mean removed), and the free energy gains
+    1/2 h1h2h3 sum b phi - E_self^h + E_c^h (Sec. 3.5);
   * density mixing: linear rho_in <- rho_in + beta (rho_out - rho_in), or
     Anderson extrapolation (relaxation beta, history m) as named in Sec. 4;
   * Harris-Foulkes free energy at rho_in.
@@ -116,14 +119,17 @@ def entropy_term(g, wk, kT: float):
     return 2.0 * kT * float(np.sum(np.asarray(wk)[:, None] * (a + b)))
 
 
-def harris_foulkes(lam, g, wk, rho_in, vh_in, grid: Grid, kT: float):
+def harris_foulkes(lam, g, wk, rho_in, vh_in, grid: Grid, kT: float, b=None, e_const: float = 0.0):
     """Free energy of Sec. 3.5 in the reduced model, evaluated at the input
-    density: F = 2 sum w g lambda + dV sum [eps_x rho - V_x rho - 1/2 V_H rho]
-    + entropy (jellium: no pseudocharge, self-energy or overlap terms)."""
+    density: F = 2 sum w g lambda + dV sum [eps_x rho - V_x rho + 1/2 (b - rho) phi]
+    + entropy + e_const, where phi = vh_in.  Jellium: b = None and e_const = 0 (no
+    pseudocharge, self-energy or overlap terms); with pseudocharges
+    e_const = -E_self^h + E_c^h."""
     eps, vx = slater(rho_in)
     band = 2.0 * float(np.sum(np.asarray(wk)[:, None] * np.asarray(g) * np.asarray(lam)))
-    dc = grid.dV * float(np.sum(eps * rho_in - vx * rho_in - 0.5 * vh_in * rho_in))
-    return band + dc + entropy_term(g, wk, kT)
+    half_b = 0.0 if b is None else 0.5 * np.asarray(b)
+    dc = grid.dV * float(np.sum(eps * rho_in - vx * rho_in + (half_b - 0.5 * rho_in) * vh_in))
+    return band + dc + entropy_term(g, wk, kT) + e_const
 
 
 def sad_density(grid: Grid, R, width, Z, n_elec: float):
@@ -179,7 +185,8 @@ def anderson_update(x, f, hist_x, hist_f, beta: float, m: int):
 
 def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.01,
         mix: float = 0.3, tol: float = 1e-6, max_iter: int = 100, n_first_passes: int = 4,
-        rho_init=None, lanczos_v0=None, lanczos_steps: int = 20, callback=None, mix_history: int = 0):
+        rho_init=None, lanczos_v0=None, lanczos_steps: int = 20, callback=None, mix_history: int = 0,
+        psd=None):
     """Minimal SCF of Sec. 2 ("fixed-point iteration ... accelerated using
     mixing") with the CheFSI policy of Sec. 3.4: the first SCF step runs
     n_first_passes filter + Rayleigh-Ritz passes from the random X0 before the
@@ -191,12 +198,21 @@ def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.0
     Ritz value of the previous pass.
     Mixing: mix_history = 0 is linear density mixing rho_in + mix (rho_out - rho_in);
     mix_history > 0 is Anderson extrapolation with relaxation mix and that history.
+    Electrostatics: psd = None is the jellium form; psd = the dict of
+    oracle.pseudocharge.electrostatics_setup switches to pseudocharges (vloc must then
+    be zero: the electrons see phi).
     Returns dict(energy, mu, iterations, converged, rho, ritz, history).
     """
     hx, hf = [], []
     rho_in = np.asarray(rho_init, dtype=np.float64).copy()
     X = np.array(X0, copy=True)
-    vh = poisson(rho_in, grid)
+    bpsd = None if psd is None else psd["b"]
+    e_const = 0.0 if psd is None else psd["ec"] - psd["eself"]
+
+    def potential(r):
+        return poisson(r if bpsd is None else r + bpsd, grid)
+
+    vh = potential(rho_in)
     history = []
     lam = None
     lmin = lmax = None
@@ -214,7 +230,7 @@ def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.0
             lam, X = rayleigh_ritz(Xf, grid, veff, projs)
         mu = fermi_level(lam[None, :], np.array([1.0]), n_elec, kT)
         g = occupations(lam, mu, kT)
-        F = harris_foulkes(lam[None, :], g[None, :], np.array([1.0]), rho_in, vh, grid, kT)
+        F = harris_foulkes(lam[None, :], g[None, :], np.array([1.0]), rho_in, vh, grid, kT, bpsd, e_const)
         rho_out = density([X], g[None, :], grid.dV)
         err = float(np.linalg.norm(rho_out - rho_in) / np.linalg.norm(rho_in))
         history.append({"iter": it, "energy": F, "mu": mu, "rho_err": err})
@@ -224,6 +240,6 @@ def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.0
             converged = True
             break
         rho_in = anderson_update(rho_in, rho_out - rho_in, hx, hf, mix, mix_history)
-        vh = poisson(rho_in, grid)
+        vh = potential(rho_in)
     return {"energy": F, "mu": mu, "iterations": it, "converged": converged,
-            "rho": rho_in, "ritz": lam, "history": history, "X": X}
+            "rho": rho_in, "ritz": lam, "history": history, "X": X, "phi": vh, "occ": g}

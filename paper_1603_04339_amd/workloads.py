@@ -57,6 +57,8 @@ class Cell:
     degree: int = 20
     passes: int = 1
     bc: tuple = (0, 0, 0)           # per direction: 0 Bloch-periodic, 1 zero Dirichlet
+    psd_rc: np.ndarray = None       # (N,) cutoff of the Coulomb-tailed local pseudopotential (bohr)
+    psd_rc_ref: np.ndarray = None   # (N,) cutoff of its reference potential (bohr)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -89,7 +91,8 @@ def draw_cell(cfg_id: int, cell_id: int, n, L, n_atoms: int, ls=(0,), rc=3.0, n_
     cell = Cell(n=n, L=L, positions=pos, depth=depth, width=width,
                 chan_atom=chan_atom, chan_l=chan_l, chan_gamma=gam.reshape(-1),
                 chan_rc=np.full(n_atoms * len(ls), float(rc)),
-                Z=np.full(n_atoms, 2.0), n_s=n_s, degree=degree, passes=passes)
+                Z=np.full(n_atoms, 2.0), n_s=n_s, degree=degree, passes=passes,
+                psd_rc=2.0 * width, psd_rc_ref=1.0 * width)
     return cell, rng
 
 
