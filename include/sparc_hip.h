@@ -78,7 +78,10 @@ typedef struct {
  * x, y, z), energy chan_gamma[c] (Ha) and cutoff radius chan_rc[c] (bohr):
  * chi_s = c exp(-r^2/(2 s^2)), chi_p,m = c (r_m/s) exp(-r^2/(2 s^2)) for r <= rc,
  * s = rc/4, c normalising h1h2h3 * sum over the unwrapped grid of chi^2 to 1.
- * Z: valence charge per atom (used for the atomic-superposition density). */
+ * Z: valence charge per atom (used for the atomic-superposition density and the
+ * pseudocharges).  psd_rc / psd_rc_ref: cutoffs of the Coulomb-tailed local
+ * pseudopotential and of its reference potential, read only by the pseudocharge
+ * calls and the pseudocharge SCF (may be NULL otherwise; see sparc_pseudocharge). */
 typedef struct {
   int32_t n_atoms;
   const double* R;          /* [3*n_atoms], bohr                */
@@ -90,6 +93,8 @@ typedef struct {
   const double* chan_gamma; /* [n_chan]                         */
   const double* chan_rc;    /* [n_chan]                         */
   const double* Z;          /* [n_atoms]                        */
+  const double* psd_rc;     /* [n_atoms] rc_J, bohr, or NULL    */
+  const double* psd_rc_ref; /* [n_atoms] rc~_J, bohr, or NULL   */
 } sparc_atoms;
 
 typedef struct sparc_ctx sparc_ctx; /* device + stream                                    */
@@ -235,7 +240,15 @@ int sparc_ctx_set_autotune(sparc_ctx* ctx, int enable);
  * `mix_history`), Harris–Foulkes energy at the input density, stop when
  * ||rho_out - rho_in|| / ||rho_in|| < tol.  The first step runs n_first_passes
  * CheFSI passes from X0 before forming the density.
+ * electrostatics = SPARC_ELEC_PSEUDOCHARGE replaces the jellium form by the paper's
+ * (Sec. 2 electrostatic reformulation, Sec. 3.2, Sec. 3.5): the pseudocharge b, E_self^h
+ * and E_c^h are set up once (sparc_psd_boxes with eps_b, then sparc_pseudocharge),
+ * V_eff = phi + V_x with -Lap_h phi = 4 pi (rho + b) (mean removed, phi with zero mean),
+ * V_loc is not used, and the free energy is
+ *   2 sum g lambda + h^3 sum [eps_x rho - V_x rho + 1/2 (b - rho) phi] - E_self^h + E_c^h
+ *   + entropy.
  */
+enum { SPARC_ELEC_JELLIUM = 0, SPARC_ELEC_PSEUDOCHARGE = 1 };
 typedef struct {
   int32_t n_s, degree, n_first_passes, max_iter, lanczos_steps;
   int32_t mix_history;         /* 0: linear mixing; m > 0: Anderson extrapolation with m
@@ -248,6 +261,8 @@ typedef struct {
                                   atomic Gaussians of width w_J and charge Z_J)        */
   const double* x0_dev;        /* device [N_d*n_s] FP64 start orbitals (column-major) */
   const double* lanczos_v0_dev;/* device [N_d] FP64 Lanczos start vector              */
+  int32_t electrostatics;      /* SPARC_ELEC_JELLIUM (0) or SPARC_ELEC_PSEUDOCHARGE   */
+  double eps_b;                /* pseudocharge truncation tolerance (0: 1e-8)         */
 } sparc_scf_params;
 
 typedef struct {
@@ -257,6 +272,8 @@ typedef struct {
   double* ritz_dev;    /* caller-provided device [n_s]: final Ritz values (out)      */
   double* x_dev;       /* caller-provided device [N_d*n_s] FP64: final orbitals (out, may be NULL) */
   double* history;     /* caller-provided host [3*max_iter]: (energy, rho_err, t_s) per iteration (may be NULL) */
+  double* phi_dev;     /* caller-provided device [N_d]: V_H (jellium) or phi (pseudocharges) of the final
+                          input density (out, may be NULL)                                        */
 } sparc_scf_result;
 
 /* Runs the SCF; synchronous.  Periodic cells only (the jellium electrostatics have
@@ -325,6 +342,59 @@ int sparc_band_structure(sparc_ctx* ctx, const sparc_grid* grid, const sparc_ato
  * energies.  Host arrays; host computation.  Errors: EINVAL, ESHAPE. */
 int sparc_dos(int32_t n_k, int32_t n_bands, const double* eig, const double* wk, int32_t n_e, const double* energies,
               double sigma, double* dos_out);
+
+/* ---- pseudocharge electrostatics ---------------------------------------------------
+ * The paper's local electrostatics (Sec. 2, electrostatic reformulation: pseudocharges
+ * b_I = -Lap V_I / (4 pi), self energy, overlap correction E_c; Sec. 3.2, Algorithm 1;
+ * Appendix A).  Sign convention: electrons carry positive density rho, the pseudocharge
+ * is negative (h1h2h3 sum b = -N_e), and phi, the potential energy of an electron,
+ * solves -Lap_h phi = 4 pi (rho + b).
+ * Local pseudopotential of atom J, valence charge Z_J = atoms->Z[J] > 0, cutoff
+ * rc_J = atoms->psd_rc[J] > 0: the potential of the charge -Z 315/(64 pi rc^3)
+ * (1 - r^2/rc^2)^3 (zero beyond rc),
+ *   V_J(r) = -Z/r for r >= rc,  -(Z/rc)(315 - 420 s^2 + 378 s^4 - 180 s^6 + 35 s^8)/128,
+ *   s = r/rc, inside.
+ * Reference potential V~_J of the overlap correction: the same form with cutoff
+ * rc~_J = atoms->psd_rc_ref[J] > 0.  Atoms have images across periodic directions
+ * only.  All three calls are synchronous and allocate their own scratch.
+ *
+ * Truncation boxes (Sec. 3.2, the choice of r^b from eps_b): per atom and direction the
+ * box half-width r^b_s = m_s h_s, m_s = ceil(rc/h_s) + t, with t >= 0 the smallest
+ * step for which the discrete pseudocharge of all nodes x with |x_s - R_s| <= m_s h_s
+ * (on the unbounded grid, i.e. all images inside the cell) sums to within eps_b Z of -Z;
+ * at most 16 steps.  boxes: host int32 [n_atoms][6], (m1, m2, m3) for the pseudocharge
+ * then (m1, m2, m3) for the reference charge.  Errors: EINVAL (null, a value <= 0,
+ * eps_b outside (0,1), n_o outside 1..8, bc outside {0,1}), ESHAPE, ENOCONV (no box within
+ * 16 steps), ENAN, ENOMEM, EDEVICE. */
+int sparc_psd_boxes(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms, double eps_b, int32_t* boxes);
+
+/* Algorithm 1 and the discrete overlap correction (Appendix A, E_c^h), for the boxes
+ * of sparc_psd_boxes (host [n_atoms][6], each 0..1024).  For every image J' of every atom
+ * and every node x of its box, b_J'(x) = -(1/4pi) Lap_h V_J'(x) (the FD Laplacian of
+ * Sec. 3.1 applied to V_J' evaluated in closed form at x and its stencil neighbours);
+ * likewise b~_J' on the reference box, and V_c(x) = sum_J' (V~_J' - V_J')(x).
+ * Outputs: device FP64 [N_d] each (x fastest) b_dev = sum b_J', bref_dev = sum b~_J',
+ * vc_dev = V_c; host energies[3] = { E_self^h = 1/2 h^3 sum_J' sum_box b_J' V_J',
+ * E~_self^h (the same for the reference), E_c^h = 1/2 h^3 sum (b~ + b) V_c + E_self^h -
+ * E~_self^h }.  Errors: EINVAL, ESHAPE, ENAN, ENOMEM, EDEVICE. */
+int sparc_pseudocharge(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms, const int32_t* boxes,
+                       double* b_dev, double* bref_dev, double* vc_dev, double* energies);
+
+/* Local and overlap-correction components of the atomic forces with pseudocharges
+ * (Sec. 3.6, discrete local force; Appendix A, discrete correction force), for every
+ * atom J summed over its images J':
+ *   f_J,loc = h^3 sum_J' sum_{box of J'} grad_h b_J' (phi - V_J'),
+ *   f_J,c   = 1/2 h^3 sum_J' [ sum_{box~} (grad_h b~_J' (V_c - V~_J') - b~_J' grad_h V~_J')
+ *             + sum_{box} (grad_h b_J' (V_c + V_J') + b_J' grad_h V_J')
+ *             + sum_x grad_h (V~_J' - V_J') (b~ + b) ],
+ * with grad_h the FD gradient of Sec. 3.1 and b_J' at the stencil neighbours of a box
+ * node computed like inside the box.  phi_dev, b_dev, bref_dev, vc_dev: device FP64
+ * [N_d] (phi for the density at hand; the rest from sparc_pseudocharge with the same
+ * boxes).  Floc_dev, Fc_dev: device FP64 [n_atoms][3], ADDED to (either may be NULL).
+ * Errors: EINVAL, ESHAPE, ENAN, ENOMEM, EDEVICE. */
+int sparc_forces_psd(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* atoms, const int32_t* boxes,
+                     const double* phi_dev, const double* b_dev, const double* bref_dev, const double* vc_dev,
+                     double* Floc_dev, double* Fc_dev);
 
 /* ---- learned initial density ------------------------------------------------------
  * Replaces the atomic-superposition start of the SCF (Sec. 4) by

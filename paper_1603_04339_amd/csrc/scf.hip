@@ -127,9 +127,11 @@ __global__ void residual_kernel(int64_t n, const double* __restrict__ b, double*
   if (i < n) r[i] = b[i] - r[i];
 }
 
-// Slater exchange and the effective potential; e_dc = eps*rho - vx*rho - 1/2 vh*rho
+// Slater exchange and the effective potential; e_dc = eps*rho - vx*rho + 1/2 (b - rho) vh
+// (b = 0 for jellium: bpsd == nullptr)
 __global__ void xc_veff_kernel(int64_t n, const double* __restrict__ rho, const double* __restrict__ vloc,
-                               const double* __restrict__ vh, double* __restrict__ veff, double* __restrict__ edc) {
+                               const double* __restrict__ vh, const double* __restrict__ bpsd,
+                               double* __restrict__ veff, double* __restrict__ edc) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double r = fmax(rho[i], 0.0);
@@ -137,7 +139,14 @@ __global__ void xc_veff_kernel(int64_t n, const double* __restrict__ rho, const 
   const double eps = -0.75 * cbrt(3.0 / M_PI) * r13;
   const double vx = -cbrt(3.0 / M_PI) * r13;
   veff[i] = vloc[i] + vh[i] + vx;
-  edc[i] = eps * r - vx * r - 0.5 * vh[i] * r;
+  const double hb = bpsd ? 0.5 * bpsd[i] : 0.0;
+  edc[i] = eps * r - vx * r + (hb - 0.5 * r) * vh[i];
+}
+
+__global__ void add_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ out) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
 }
 
 __global__ void mix_kernel(int64_t n, double* __restrict__ rin, const double* __restrict__ rout, double beta) {
@@ -422,7 +431,11 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
                              const sparc_scf_params* P, sparc_scf_result* res) {
   if (!ctx || !grid || !atoms || !P || !res) return fail(SPARC_EINVAL, "sparc_scf_run: null argument");
   if (dirichlet_mask(*grid) != 0)
-    return fail(SPARC_EINVAL, "sparc_scf_run: periodic cells only (the jellium electrostatics have no Dirichlet form)");
+    return fail(SPARC_EINVAL, "sparc_scf_run: periodic cells only (its Poisson solve is periodic)");
+  if (P->electrostatics != SPARC_ELEC_JELLIUM && P->electrostatics != SPARC_ELEC_PSEUDOCHARGE)
+    return fail(SPARC_EINVAL, "sparc_scf_run: electrostatics must be SPARC_ELEC_JELLIUM or SPARC_ELEC_PSEUDOCHARGE");
+  const bool psd = P->electrostatics == SPARC_ELEC_PSEUDOCHARGE;
+  if (psd && (P->eps_b < 0.0 || P->eps_b >= 1.0)) return fail(SPARC_EINVAL, "sparc_scf_run: eps_b outside [0, 1)");
   if (grid->kpt[0] != 0 || grid->kpt[1] != 0 || grid->kpt[2] != 0)
     return fail(SPARC_EINVAL, "sparc_scf_run: the SCF driver runs at the Gamma point");
   if (P->n_s < 1 || P->degree < 1 || P->max_iter < 1 || P->n_first_passes < 1 || P->lanczos_steps < 2)
@@ -505,9 +518,33 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
   SPARC_TRY(B.alloc(&vloc, n));
   SPARC_TRY(sparc_ham_get_vloc(H64, vloc));
 
+  // pseudocharge electrostatics: b, E_self^h and E_c^h once; the electrons see phi, not V_loc
+  double *bpsd = nullptr, *rhob = nullptr;
+  double e_psd = 0.0;
+  if (psd) {
+    std::vector<int32_t> boxes(6 * (size_t)atoms->n_atoms);
+    SPARC_TRY(sparc_psd_boxes(ctx, grid, atoms, P->eps_b > 0 ? P->eps_b : 1e-8, boxes.data()));
+    double *bref, *vc;
+    SPARC_TRY(B.alloc(&bpsd, n));
+    SPARC_TRY(B.alloc(&bref, n));
+    SPARC_TRY(B.alloc(&vc, n));
+    SPARC_TRY(B.alloc(&rhob, n));
+    double en[3];
+    SPARC_TRY(sparc_pseudocharge(ctx, grid, atoms, boxes.data(), bpsd, bref, vc, en));
+    e_psd = en[2] - en[0];
+    SPARC_HIP(hipMemsetAsync(vloc, 0, n * 8, s));
+  }
+
   Poisson PS{H64, n, pb, pr, pp, pAp, part, sc};
   const double ptol = P->poisson_tol > 0 ? P->poisson_tol : 1e-10;
-  SPARC_TRY(PS.solve(s, rho_in, vh, ptol, 20000));
+  // phi (or V_H) of the current input density
+  auto solve_potential = [&]() -> int {
+    if (!psd) return PS.solve(s, rho_in, vh, ptol, 20000);
+    add_kernel<<<GRID1(n)>>>(n, rho_in, bpsd, rhob);
+    SPARC_TRY(check_launch("add_kernel"));
+    return PS.solve(s, rhob, vh, ptol, 20000);
+  };
+  SPARC_TRY(solve_potential());
 
   double lmin = 0, lmax = 0, lcut = 0;
   bool have_ritz = false;
@@ -520,7 +557,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
   int it = 1;
   int converged = 0;
   for (; it <= P->max_iter; ++it) {
-    xc_veff_kernel<<<GRID1(n)>>>(n, rho_in, vloc, vh, veff, edc);
+    xc_veff_kernel<<<GRID1(n)>>>(n, rho_in, vloc, vh, bpsd, veff, edc);
     SPARC_TRY(check_launch("xc_veff_kernel"));
     SPARC_TRY(sparc_ham_set_veff(H64, veff));
     if (mixed) SPARC_TRY(sparc_ham_set_veff(H32, veff));
@@ -545,7 +582,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
     double be[3];
     SPARC_HIP(hipMemcpyAsync(be, sc + 8, 3 * 8, hipMemcpyDeviceToHost, s));
     SPARC_HIP(hipStreamSynchronize(s));
-    F = be[0] + dV * be[2] + be[1];
+    F = be[0] + dV * be[2] + be[1] + e_psd;
     if (!std::isfinite(F)) return fail(SPARC_ENAN, "sparc_scf_run: non-finite energy at iteration %d", it);
     // output density from the current block
     const void* xs[1] = {use32 ? (const void*)X32 : (const void*)X};
@@ -605,7 +642,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
       }
     }
     SPARC_TRY(check_launch("density mixing"));
-    SPARC_TRY(PS.solve(s, rho_in, vh, ptol, 20000));
+    SPARC_TRY(solve_potential());
   }
   res->energy = F;
   res->mu = mu;
@@ -613,6 +650,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
   res->converged = converged;
   SPARC_HIP(hipMemcpyAsync(res->rho_dev, rho_in, n * 8, hipMemcpyDeviceToDevice, s));
   SPARC_HIP(hipMemcpyAsync(res->ritz_dev, ritz, ns * 8, hipMemcpyDeviceToDevice, s));
+  if (res->phi_dev) SPARC_HIP(hipMemcpyAsync(res->phi_dev, vh, n * 8, hipMemcpyDeviceToDevice, s));
   if (res->x_dev) {
     if (use32) f2d_block_kernel<<<GRID1((int64_t)n * ns)>>>((int64_t)n * ns, X32, X);
     SPARC_HIP(hipMemcpyAsync(res->x_dev, X, (size_t)n * ns * 8, hipMemcpyDeviceToDevice, s));

@@ -24,6 +24,7 @@ OK, EINVAL, ESHAPE, ENOMEM, ENOTSPD, ENOCONV, EDEVICE, ENAN = 0, -1, -2, -3, -4,
 R64, R32, C128, C64 = 0, 1, 2, 3
 GEMM_NATIVE = 0
 OP_APPLY, OP_FILTER, OP_RR, OP_LANCZOS, OP_FORCES = 0, 1, 2, 3, 4
+ELEC_JELLIUM, ELEC_PSEUDOCHARGE = 0, 1
 
 TORCH_DTYPE = {R64: torch.float64, R32: torch.float32, C128: torch.complex128, C64: torch.complex64}
 
@@ -44,7 +45,8 @@ class sparc_atoms(C.Structure):
                 ("vloc_width", C.POINTER(C.c_double)), ("n_chan", C.c_int32),
                 ("chan_atom", C.POINTER(C.c_int32)), ("chan_l", C.POINTER(C.c_int32)),
                 ("chan_gamma", C.POINTER(C.c_double)), ("chan_rc", C.POINTER(C.c_double)),
-                ("Z", C.POINTER(C.c_double))]
+                ("Z", C.POINTER(C.c_double)), ("psd_rc", C.POINTER(C.c_double)),
+                ("psd_rc_ref", C.POINTER(C.c_double))]
 
 
 class sparc_scf_params(C.Structure):
@@ -52,13 +54,14 @@ class sparc_scf_params(C.Structure):
                 ("max_iter", C.c_int32), ("lanczos_steps", C.c_int32), ("mix_history", C.c_int32),
                 ("kT", C.c_double), ("mix", C.c_double), ("tol", C.c_double), ("n_elec", C.c_double),
                 ("poisson_tol", C.c_double), ("filt", C.c_int), ("rr", C.c_int), ("final_fp64_pass", C.c_int32),
-                ("rho_init_dev", C.c_void_p), ("x0_dev", C.c_void_p), ("lanczos_v0_dev", C.c_void_p)]
+                ("rho_init_dev", C.c_void_p), ("x0_dev", C.c_void_p), ("lanczos_v0_dev", C.c_void_p),
+                ("electrostatics", C.c_int32), ("eps_b", C.c_double)]
 
 
 class sparc_scf_result(C.Structure):
     _fields_ = [("energy", C.c_double), ("mu", C.c_double), ("iterations", C.c_int32), ("converged", C.c_int32),
                 ("rho_dev", C.c_void_p), ("ritz_dev", C.c_void_p), ("x_dev", C.c_void_p),
-                ("history", C.POINTER(C.c_double))]
+                ("history", C.POINTER(C.c_double)), ("phi_dev", C.c_void_p)]
 
 
 # entry points: name -> (restype, argtypes)
@@ -113,6 +116,11 @@ _SIGS = {
                             C.c_void_p]),
     "sparc_forces_nonlocal": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_size_t]),
+    "sparc_psd_boxes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p]),
+    "sparc_pseudocharge": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "sparc_forces_psd": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "sparc_dnet_num_params": (C.c_int64, []),
     "sparc_dnet_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_void_p)]),
     "sparc_dnet_destroy": (None, [C.c_void_p]),
@@ -233,12 +241,19 @@ class _Atoms:
         self.cg = np.ascontiguousarray(cell.chan_gamma, dtype=np.float64)
         self.cr = np.ascontiguousarray(cell.chan_rc, dtype=np.float64)
         self.Z = np.ascontiguousarray(cell.Z, dtype=np.float64)
+        prc, prr = getattr(cell, "psd_rc", None), getattr(cell, "psd_rc_ref", None)
+        self.prc = None if prc is None else np.ascontiguousarray(prc, dtype=np.float64)
+        self.prr = None if prr is None else np.ascontiguousarray(prr, dtype=np.float64)
         a = sparc_atoms()
         a.n_atoms = len(self.D)
         a.R, a.vloc_depth, a.vloc_width = _dptr(self.R), _dptr(self.D), _dptr(self.W)
         a.n_chan = len(self.ca)
         a.chan_atom, a.chan_l = _iptr(self.ca), _iptr(self.cl)
         a.chan_gamma, a.chan_rc, a.Z = _dptr(self.cg), _dptr(self.cr), _dptr(self.Z)
+        if self.prc is not None:
+            a.psd_rc = _dptr(self.prc)
+        if self.prr is not None:
+            a.psd_rc_ref = _dptr(self.prr)
         self.struct = a
 
 
@@ -450,8 +465,9 @@ def set_autotune(ctx: Context, enable: bool):
     _check(load().sparc_ctx_set_autotune(ctx.handle, int(bool(enable))))
 
 
-def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=None, n_o: int = 6):
-    """Minimal SCF through the library; params keys follow sparc_scf_params."""
+def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=None, n_o: int = 6, phi_out=None):
+    """Minimal SCF through the library; params keys follow sparc_scf_params.
+    phi_out (optional device FP64 [N_d]) receives V_H or phi of the final density."""
     lib = load()
     grid = make_grid(cell.n, cell.L, n_o, bc=getattr(cell, "bc", (0, 0, 0)))
     atoms = _Atoms(cell)
@@ -465,6 +481,7 @@ def sparc_scf_run(ctx: Context, cell, params: dict, rho_out, ritz_out, x_out=Non
     res.rho_dev = C.c_void_p(rho_out.data_ptr())
     res.ritz_dev = C.c_void_p(ritz_out.data_ptr())
     res.x_dev = C.c_void_p(x_out.data_ptr()) if x_out is not None else None
+    res.phi_dev = C.c_void_p(phi_out.data_ptr()) if phi_out is not None else None
     hist = np.zeros(3 * max(1, params.get("max_iter", 1)))
     res.history = _dptr(hist)
     st = lib.sparc_scf_run(ctx.handle, C.byref(grid), C.byref(atoms.struct), C.byref(p), C.byref(res))
@@ -512,6 +529,42 @@ def dos(eig, wk, energies, sigma: float):
     _check(load().sparc_dos(eig.shape[0], eig.shape[1], _dptr(eig), _dptr(wk), E.shape[0], _dptr(E), float(sigma),
                             _dptr(out)))
     return out
+
+
+def psd_boxes(ctx: Context, cell, eps_b: float = 1e-8, n_o: int = 6):
+    """Truncation boxes of the pseudocharges (sparc_psd_boxes): int32 (n_atoms, 6),
+    half-widths in nodes (pseudocharge x, y, z, then reference x, y, z)."""
+    grid = make_grid(cell.n, cell.L, n_o, bc=getattr(cell, "bc", (0, 0, 0)))
+    atoms = _Atoms(cell)
+    out = np.zeros((cell.n_atoms, 6), dtype=np.int32)
+    _check(load().sparc_psd_boxes(ctx.handle, C.byref(grid), C.byref(atoms.struct), float(eps_b),
+                                  out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def pseudocharge(ctx: Context, cell, boxes, n_o: int = 6):
+    """Algorithm 1 and E_c (sparc_pseudocharge).  Returns dict(b, bref, vc: device FP64
+    [N_d]; eself, eself_ref, ec: floats)."""
+    grid = make_grid(cell.n, cell.L, n_o, bc=getattr(cell, "bc", (0, 0, 0)))
+    atoms = _Atoms(cell)
+    bx = np.ascontiguousarray(boxes, dtype=np.int32)
+    out = {k: torch.zeros(cell.n_d, dtype=torch.float64, device=f"cuda:{ctx.device}") for k in ("b", "bref", "vc")}
+    en = np.zeros(3)
+    _check(load().sparc_pseudocharge(ctx.handle, C.byref(grid), C.byref(atoms.struct), bx.ctypes.data_as(C.c_void_p),
+                                     _ptr(out["b"]), _ptr(out["bref"]), _ptr(out["vc"]), _dptr(en)))
+    out.update(eself=float(en[0]), eself_ref=float(en[1]), ec=float(en[2]))
+    return out
+
+
+def forces_psd(ctx: Context, cell, boxes, phi, st, Floc=None, Fc=None, n_o: int = 6):
+    """Adds the local and overlap-correction force components with pseudocharges
+    (sparc_forces_psd) to Floc and Fc (device FP64 (n_atoms, 3), either may be None);
+    st: the dict of pseudocharge() for the same boxes."""
+    grid = make_grid(cell.n, cell.L, n_o, bc=getattr(cell, "bc", (0, 0, 0)))
+    atoms = _Atoms(cell)
+    bx = np.ascontiguousarray(boxes, dtype=np.int32)
+    _check(load().sparc_forces_psd(ctx.handle, C.byref(grid), C.byref(atoms.struct), bx.ctypes.data_as(C.c_void_p),
+                                   _ptr(phi), _ptr(st["b"]), _ptr(st["bref"]), _ptr(st["vc"]), _ptr(Floc), _ptr(Fc)))
 
 
 def sad_density(ctx: Context, cell, rho_out, n_o: int = 6):

@@ -1,0 +1,198 @@
+"""GPU pseudocharge electrostatics (sparc_psd_boxes, sparc_pseudocharge,
+sparc_forces_psd, and sparc_scf_run with SPARC_ELEC_PSEUDOCHARGE) against the FP64
+oracle (Sec. 2 electrostatic reformulation; Sec. 3.2 Algorithm 1 and the choice of
+r^b; Appendix A E_c and f_c; Sec. 3.6 local force):
+  * truncation boxes bit-exact (integer decisions taken in FP64 on both sides);
+  * b, b~, V_c element by element within 1e-12 of max|b|, E_self^h, E~_self^h, E_c^h
+    within 1e-11 relative, on periodic and slab cells with ragged tiles;
+  * f_loc and f_c within 1e-11 of the largest component;
+  * the pseudocharge SCF energy within 1e-6 Ha/atom of the oracle SCF, and its forces
+    (local + correction + non-local) within 2e-3 Ha/bohr of central differences of its
+    free energy;
+  * error paths."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import pseudocharge as pc
+from oracle.forces import nonlocal_force
+from oracle.scf import occupations, sad_density, scf as oracle_scf
+from paper_1603_04339_amd import sparc as sp
+from paper_1603_04339_amd import workloads as wl
+from tests.helpers import oracle_setup, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = sp.Context(0)
+    yield c
+    c.close()
+
+
+def _cells():
+    """(name, cell): overlapping pseudocharges in a cube; a drawn cell with ragged tiles;
+    the drawn cell as a slab (zero Dirichlet along z); one atom near a corner."""
+    out = []
+    c1 = wl.Cell(n=(24, 24, 24), L=(9.0, 9.0, 9.0),
+                 positions=np.array([[1.1, 2.3, 3.7], [3.9, 3.2, 4.6], [6.0, 6.9, 1.5]]),
+                 depth=np.zeros(3), width=np.ones(3), chan_atom=np.zeros(0, np.int32), chan_l=np.zeros(0, np.int32),
+                 chan_gamma=np.zeros(0), chan_rc=np.zeros(0), Z=np.array([2.0, 3.0, 1.0]),
+                 psd_rc=np.array([2.2, 2.4, 1.8]), psd_rc_ref=np.array([1.0, 1.1, 0.9]))
+    out.append(("cube3", c1))
+    c2, _ = wl.draw_cell(96, 0, (21, 18, 23), (8.4, 7.2, 9.2), 4, (0, 1), 2.6, 0)
+    out.append(("drawn4", c2))
+    c3 = wl.Cell(**{**c2.__dict__, "bc": (0, 0, 1)})
+    out.append(("slab4", c3))
+    c4 = wl.Cell(**{**c1.__dict__, "positions": np.array([[0.05, 8.93, 0.11]]), "Z": np.array([2.0]),
+                    "depth": np.zeros(1), "width": np.ones(1), "psd_rc": np.array([2.5]),
+                    "psd_rc_ref": np.array([1.2])})
+    out.append(("corner1", c4))
+    return out
+
+
+def _oracle(cell, eps_b=1e-8):
+    grid, _, _ = oracle_setup(cell)
+    bx = pc.truncation_boxes(grid, cell.positions, cell.Z, cell.psd_rc, eps_b)
+    bxr = pc.truncation_boxes(grid, cell.positions, cell.Z, cell.psd_rc_ref, eps_b)
+    st = pc.electrostatics_setup(grid, cell.positions, cell.Z, cell.psd_rc, cell.psd_rc_ref, bx, bxr)
+    return grid, bx, bxr, st
+
+
+@pytest.mark.parametrize("name,cell", _cells(), ids=[c[0] for c in _cells()])
+def test_boxes_and_pseudocharge_match_oracle(ctx, name, cell):
+    grid, bx, bxr, st = _oracle(cell)
+    boxes = sp.psd_boxes(ctx, cell, 1e-8)
+    np.testing.assert_array_equal(boxes[:, :3], np.array(bx))
+    np.testing.assert_array_equal(boxes[:, 3:], np.array(bxr))
+    got = sp.pseudocharge(ctx, cell, boxes)
+    scale = np.abs(st["b"]).max()
+    for k in ("b", "bref", "vc"):
+        err = np.abs(got[k].cpu().numpy() - st[k]).max()
+        print(f"{name} {k}: max |ref| {np.abs(st[k]).max():.3e} err {err:.2e}")
+        assert err <= 1e-12 * max(scale, np.abs(st[k]).max())
+    for k in ("eself", "eself_ref", "ec"):
+        print(f"{name} {k}: {got[k]:.15e} oracle {st[k]:.15e}")
+        assert abs(got[k] - st[k]) <= 1e-11 * max(1.0, abs(st["eself"]))
+    if grid.bc == (0, 0, 0):
+        assert abs(grid.dV * float(got["b"].sum()) + cell.Z.sum()) < 1e-8 * cell.Z.sum()
+
+
+@pytest.mark.parametrize("name,cell", _cells()[:3], ids=[c[0] for c in _cells()[:3]])
+def test_psd_forces_match_oracle(ctx, name, cell):
+    grid, bx, bxr, st = _oracle(cell)
+    rng = np.random.default_rng(7)
+    phi = rng.uniform(-1.0, 1.0, grid.n_d)
+    boxes = np.concatenate([np.array(bx), np.array(bxr)], axis=1).astype(np.int32)
+    dev = {k: to_dev(st[k]) for k in ("b", "bref", "vc")}
+    Fl = torch.zeros(cell.n_atoms, 3, dtype=torch.float64, device="cuda:0")
+    Fc = torch.zeros_like(Fl)
+    sp.forces_psd(ctx, cell, boxes, to_dev(phi), dev, Fl, Fc)
+    rl = pc.local_force(grid, cell.positions, cell.Z, cell.psd_rc, bx, phi)
+    rc = pc.correction_force(grid, cell.positions, cell.Z, cell.psd_rc, cell.psd_rc_ref, bx, bxr, st)
+    el = np.abs(Fl.cpu().numpy() - rl).max() / np.abs(rl).max()
+    ec = np.abs(Fc.cpu().numpy() - rc).max() / np.abs(rc).max()
+    print(f"{name}: |f_loc| {np.abs(rl).max():.3e} rel err {el:.2e}; |f_c| {np.abs(rc).max():.3e} rel err {ec:.2e}")
+    assert el < 1e-11 and ec < 1e-10
+    # accumulation into only one output
+    sp.forces_psd(ctx, cell, boxes, to_dev(phi), dev, Fl, None)
+    np.testing.assert_allclose(Fl.cpu().numpy(), 2 * rl, rtol=0, atol=2e-11 * np.abs(rl).max())
+
+
+def _scf_cell():
+    base, rng = wl.draw_cell(95, 0, 20, 7.0, 2, (0,), 2.4, 8)
+    X0 = wl.draw_orbitals(rng, base.n_d, 8)
+    v0 = wl.lanczos_start(rng, base.n_d)
+    return base, X0, v0
+
+
+def _gpu_scf(ctx, cell, X0, v0, tol=1e-10):
+    prm = dict(n_s=8, degree=16, n_first_passes=6, max_iter=200, lanczos_steps=20, mix_history=7, kT=0.01,
+               mix=0.3, tol=tol, n_elec=cell.n_elec, poisson_tol=1e-13, filt=sp.R64, rr=sp.GEMM_NATIVE,
+               final_fp64_pass=1, rho_init_dev=None, x0_dev=torch.from_numpy(X0).cuda(),
+               lanczos_v0_dev=torch.from_numpy(v0).cuda(), electrostatics=sp.ELEC_PSEUDOCHARGE, eps_b=1e-8)
+    rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    ritz = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+    X = torch.zeros(8, cell.n_d, dtype=torch.float64, device="cuda:0")
+    phi = torch.zeros_like(rho)
+    out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz, X, phi_out=phi)
+    assert out["converged"]
+    return out, rho, ritz, X, phi
+
+
+def test_scf_pseudocharge_matches_oracle(ctx):
+    cell, X0, v0 = _scf_cell()
+    out, rho, ritz, X, phi = _gpu_scf(ctx, cell, X0, v0, tol=1e-9)
+    grid, V, P = oracle_setup(cell)
+    _, bx, bxr, st = _oracle(cell)
+    rho0 = sad_density(grid, cell.positions, cell.width, cell.Z, cell.n_elec)
+    ref = oracle_scf(grid, np.zeros(grid.n_d), P, X0.T, cell.n_elec, 16, kT=0.01, mix=0.3, tol=1e-9, max_iter=200,
+                     n_first_passes=6, rho_init=rho0, lanczos_v0=v0, mix_history=7, psd=st)
+    print(f"gpu: {out['iterations']} it F={out['energy']:.10f}; oracle {ref['iterations']} it F={ref['energy']:.10f}")
+    assert ref["converged"]
+    assert abs(out["energy"] - ref["energy"]) / cell.n_atoms < 1e-6
+    np.testing.assert_allclose(rho.cpu().numpy(), ref["rho"], atol=1e-6 * np.abs(ref["rho"]).max())
+    np.testing.assert_allclose(ritz.cpu().numpy(), ref["ritz"], atol=1e-6)
+    np.testing.assert_allclose(phi.cpu().numpy(), ref["phi"], atol=1e-6 * np.abs(ref["phi"]).max())
+
+
+def test_scf_pseudocharge_forces_match_energy_differences(ctx):
+    """Total force (f_loc + f_c from sparc_forces_psd on the SCF's phi, f_nloc from
+    sparc_forces_nonlocal on its orbitals) against central differences of the GPU SCF
+    free energy; the bound, 2e-3 Ha/bohr, is the one of the jellium forces (the
+    FD-gradient error next to the projector cut-off spheres)."""
+    base, X0, v0 = _scf_cell()
+    out, rho, ritz, X, phi = _gpu_scf(ctx, base, X0, v0)
+    boxes = sp.psd_boxes(ctx, base, 1e-8)
+    st = sp.pseudocharge(ctx, base, boxes)
+    F = torch.zeros(base.n_atoms, 3, dtype=torch.float64, device="cuda:0")
+    sp.forces_psd(ctx, base, boxes, phi, st, F, F)
+    g = occupations(ritz.cpu().numpy(), out["mu"], 0.01)
+    ham = sp.Hamiltonian(ctx, base, sp.R64)
+    sp.forces_nonlocal(ham, X, to_dev(g), F, sp.workspace(ham, 8, sp.OP_FORCES))
+    got = F.cpu().numpy()
+    grid, V, P = oracle_setup(base)
+    _, bx, bxr, ost = _oracle(base)
+    ref = (pc.local_force(grid, base.positions, base.Z, base.psd_rc, bx, phi.cpu().numpy())
+           + pc.correction_force(grid, base.positions, base.Z, base.psd_rc, base.psd_rc_ref, bx, bxr, ost)
+           + nonlocal_force([grid], [P], [X.cpu().numpy().T], g[None, :], 2))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    assert np.abs(got.sum(axis=0)).max() < 1e-4          # no net force on the cell
+    d = 2e-3
+    for J, s in [(0, 0), (1, 1), (0, 2)]:
+        e = []
+        for sign in (1, -1):
+            c = wl.Cell(**{**base.__dict__, "positions": base.positions.copy()})
+            c.positions[J, s] += sign * d
+            e.append(_gpu_scf(ctx, c, X0, v0)[0]["energy"])
+        fd = -(e[0] - e[1]) / (2 * d)
+        print(f"atom {J} dir {s}: force {got[J, s]:+.6e}  -dF/dR {fd:+.6e}")
+        assert abs(got[J, s] - fd) < 2e-3
+
+
+def test_pseudocharge_error_paths(ctx):
+    name, cell = _cells()[0]
+    bad = wl.Cell(**{**cell.__dict__, "psd_rc": None})
+    with pytest.raises(sp.SparcError) as e:
+        sp.psd_boxes(ctx, bad, 1e-8)
+    assert e.value.status == sp.EINVAL
+    with pytest.raises(sp.SparcError) as e:
+        sp.psd_boxes(ctx, cell, 0.0)
+    assert e.value.status == sp.EINVAL
+    with pytest.raises(sp.SparcError) as e:       # beyond the rounding floor of the charge sum
+        sp.psd_boxes(ctx, cell, 1e-17)
+    assert e.value.status == sp.ENOCONV
+    boxes = sp.psd_boxes(ctx, cell, 1e-8)
+    neg = boxes.copy()
+    neg[0, 0] = -1
+    with pytest.raises(sp.SparcError) as e:
+        sp.pseudocharge(ctx, cell, neg)
+    assert e.value.status == sp.EINVAL
+    bz = wl.Cell(**{**cell.__dict__, "Z": np.array([2.0, 0.0, 1.0])})
+    with pytest.raises(sp.SparcError) as e:
+        sp.pseudocharge(ctx, bz, boxes)
+    assert e.value.status == sp.EINVAL
