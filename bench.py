@@ -145,6 +145,7 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
     hs_ms, hs_n = ctx.kernel_time("hstep")
     ctx.set_timing(False)
     forces = forces_leg(sp, ctx, ham, cell, X, occ, rho) if dt == sp.R64 else None
+    psd = pseudocharge_leg(sp, ctx, cell, rho) if dt == sp.R64 else None
     eb = 8 if dt == sp.R64 else 4
     # per pass: the filter's steps and the one H X of Rayleigh-Ritz (2 elements per point-state)
     total = steps * (step_bytes(nd, ns, eb, cell.degree) + 2 * nd * ns * eb)
@@ -157,6 +158,7 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
                                  measured_traffic() if (dt == sp.R64 and tuple(cell.n) == (96, 96, 96)
                                                         and cell.n_s == 512) else None),
         "ritz": ritz.cpu().numpy(), "bounds": (lmin, lmax), "n_proj": ham.n_proj, "forces": forces,
+        "pseudocharge": psd,
     }
 
 
@@ -187,6 +189,37 @@ def forces_leg(sp, ctx, ham, cell, X, occ, rho, reps=3):
             "note": ("local component over every well image within 10 widths; non-local component (projections "
                      "+ FD gradient of the orbitals at the projector supports) over the states with nonzero "
                      "occupation")}
+
+
+def pseudocharge_leg(sp, ctx, cell, rho, reps=3):
+    """Pseudocharge electrostatics of the cell (truncation boxes, Algorithm 1 with the
+    reference charge and V_c, local and correction forces on the potential of the
+    given density): kernel times (HIP events on the context's stream), mean over reps
+    after one warm-up; the boxes call is timed on the host clock."""
+    import torch
+    t0 = time.perf_counter()
+    boxes = sp.psd_boxes(ctx, cell, 1e-8)
+    boxes_ms = 1e3 * (time.perf_counter() - t0)
+    st = sp.pseudocharge(ctx, cell, boxes)
+    # the force kernel's cost does not depend on the values of phi: V_c stands in for it
+    phi = st["vc"]
+    F = torch.zeros(cell.n_atoms, 3, dtype=torch.float64, device="cuda:0")
+    sp.forces_psd(ctx, cell, boxes, phi, st, F, F)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    for _ in range(reps):
+        st = sp.pseudocharge(ctx, cell, boxes)
+        sp.forces_psd(ctx, cell, boxes, phi, st, F, F)
+    g_ms, g_n = ctx.kernel_time("psd_grid")
+    f_ms, f_n = ctx.kernel_time("psd_force")
+    ctx.set_timing(False)
+    return {"boxes_ms_host_clock": boxes_ms, "pseudocharge_ms": g_ms / g_n, "forces_ms": f_ms / f_n,
+            "n_atoms": cell.n_atoms, "box_half_widths": [int(boxes[:, :3].min()), int(boxes[:, :3].max())],
+            "eself": st["eself"], "ec": st["ec"],
+            "charge_error": float(cell.Z.sum() + float(st["b"].sum()) * float(np.prod(np.asarray(cell.L) / np.asarray(cell.n)))),
+            "note": ("closed-form Coulomb-tailed pseudopotentials with cutoffs 2 w_J (reference w_J), eps_b 1e-8; "
+                     "the pseudocharge kernel evaluates b, b~, V_c and the energy integrands node by node, the "
+                     "force kernel the FD gradients of b and b~ at every node of every image box")}
 
 
 def scf_leg(sp, ctx, precision, tol=1e-6, learned=False):
@@ -251,6 +284,8 @@ def run_gamma(args, sp, wl):
     }
     if main["forces"] is not None:
         result["forces"] = main["forces"]
+    if main["pseudocharge"] is not None:
+        result["pseudocharge"] = main["pseudocharge"]
     if args.precision == "f64" and not args.no_mixed:
         mx = gamma_leg(sp, ctx, cell, X0, v0, "mixed", args.steps, args.warmup, "mixed")
         n_occ = int(np.ceil(cell.n_elec / 2))

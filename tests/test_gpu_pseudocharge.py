@@ -196,3 +196,35 @@ def test_pseudocharge_error_paths(ctx):
     with pytest.raises(sp.SparcError) as e:
         sp.pseudocharge(ctx, bz, boxes)
     assert e.value.status == sp.EINVAL
+
+
+def test_full_size_cell(ctx):
+    """The 96^3 cell with 64 atoms (the large Gamma-point workload): boxes exact, b, b~,
+    V_c element by element and the energies as above; f_loc and f_c of four sampled
+    atoms (the oracle sums over those atoms' images only)."""
+    cell, _, _ = wl.config_cell("c2", with_orbitals=False)
+    grid, bx, bxr, st = _oracle(cell)
+    boxes = sp.psd_boxes(ctx, cell, 1e-8)
+    np.testing.assert_array_equal(boxes[:, :3], np.array(bx))
+    np.testing.assert_array_equal(boxes[:, 3:], np.array(bxr))
+    got = sp.pseudocharge(ctx, cell, boxes)
+    scale = np.abs(st["b"]).max()
+    for k in ("b", "bref", "vc"):
+        err = np.abs(got[k].cpu().numpy() - st[k]).max()
+        print(f"c2 {k}: max |ref| {np.abs(st[k]).max():.3e} err {err:.2e}")
+        assert err <= 1e-12 * max(scale, np.abs(st[k]).max())
+    for k in ("eself", "eself_ref", "ec"):
+        print(f"c2 {k}: {got[k]:.15e} oracle {st[k]:.15e}")
+        assert abs(got[k] - st[k]) <= 1e-11 * abs(st["eself"])
+    phi = np.random.default_rng(11).uniform(-1.0, 1.0, grid.n_d)
+    Fl = torch.zeros(cell.n_atoms, 3, dtype=torch.float64, device="cuda:0")
+    Fc = torch.zeros_like(Fl)
+    sp.forces_psd(ctx, cell, boxes, to_dev(phi), got, Fl, Fc)
+    smp = [0, 17, 38, 63]
+    rl = pc.local_force(grid, cell.positions[smp], cell.Z[smp], cell.psd_rc[smp], [bx[j] for j in smp], phi)
+    rc = pc.correction_force(grid, cell.positions[smp], cell.Z[smp], cell.psd_rc[smp], cell.psd_rc_ref[smp],
+                             [bx[j] for j in smp], [bxr[j] for j in smp], st)
+    el = np.abs(Fl.cpu().numpy()[smp] - rl).max() / np.abs(rl).max()
+    ec = np.abs(Fc.cpu().numpy()[smp] - rc).max() / np.abs(rc).max()
+    print(f"c2 sampled atoms: f_loc rel err {el:.2e}, f_c rel err {ec:.2e}")
+    assert el < 1e-11 and ec < 1e-10
