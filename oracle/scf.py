@@ -50,11 +50,14 @@ def fermi_level(lam, wk, n_elec: float, kT: float, rel_tol: float = 1e-13):
         raise ValueError("not enough states for the electron count")
     for _ in range(400):
         mid = 0.5 * (lo + hi)
-        if count(mid) < n_elec:
+        c = count(mid)
+        if abs(c - n_elec) < rel_tol * n_elec:
+            return mid              # the constraint holds here (inside a gap, anywhere on the plateau)
+        if c < n_elec:
             lo = mid
         else:
             hi = mid
-        if abs(count(mid) - n_elec) < rel_tol * n_elec or hi - lo < 1e-15 * max(1.0, abs(mid)):
+        if hi - lo < 1e-15 * max(1.0, abs(mid)):
             break
     return 0.5 * (lo + hi)
 

@@ -30,6 +30,16 @@ def test_fermi_charge_and_monotone():
     np.testing.assert_allclose(occupations(x, 0.0, 0.01), 1.0 / (1.0 + np.exp(x / 0.01)), rtol=0, atol=1e-15)
 
 
+def test_fermi_level_meets_the_charge_in_a_gap():
+    """Sec. 3.4 electron-count constraint at the returned mu, also where a gap makes
+    the count flat (every mu inside the gap is a root)."""
+    lam = np.array([[-1.0, -0.9, 0.8, 0.9, 1.0, 1.5]])
+    for kT in (0.001, 0.01, 0.2):
+        mu = fermi_level(lam, np.array([1.0]), 4.0, kT)
+        assert 2 * np.sum(occupations(lam, mu, kT)) == pytest.approx(4.0, rel=1e-12)
+    assert -0.9 < fermi_level(lam, np.array([1.0]), 4.0, 0.001) < 0.8
+
+
 def test_density_conservation_and_uniform_shell():
     """dV sum rho = N_e, rho >= 0, and a fully occupied closed shell of plane
     waves (any unitary mix inside the shell) gives a uniform density."""
