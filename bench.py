@@ -222,11 +222,12 @@ def pseudocharge_leg(sp, ctx, cell, rho, reps=3):
                      "force kernel the FD gradients of b and b~ at every node of every image box")}
 
 
-def scf_leg(sp, ctx, precision, tol=1e-6, learned=False):
+def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False):
     """Plain SCF (Slater exchange, CG Poisson, Anderson mixing) on a held-out 40^3
     cell: wall time, iterations, free energy.  Started from the atomic superposition,
     or (learned=True) from the trained density network's prediction, whose
-    inference time is included in the wall time."""
+    inference time is included in the wall time.  pseudocharge=True runs the
+    pseudocharge electrostatics (set-up included in the wall time) instead of jellium."""
     import torch
     from paper_1603_04339_amd import workloads as wl
     from paper_1603_04339_amd.train_density_net import CHARGE_TOL, DEFAULT_WEIGHTS, FIRST_PASSES, cell_dV, cell_start
@@ -247,7 +248,8 @@ def scf_leg(sp, ctx, precision, tol=1e-6, learned=False):
     prm = dict(n_s=cell.n_s, degree=20, n_first_passes=FIRST_PASSES, max_iter=200, lanczos_steps=20, mix_history=7,
                kT=0.01, mix=0.3, tol=tol, n_elec=cell.n_elec, poisson_tol=1e-10,
                filt=sp.R64 if precision == "f64" else sp.R32, rr=sp.GEMM_NATIVE, final_fp64_pass=1,
-               rho_init_dev=rho0, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda())
+               rho_init_dev=rho0, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda(),
+               electrostatics=sp.ELEC_PSEUDOCHARGE if pseudocharge else sp.ELEC_JELLIUM, eps_b=1e-8)
     out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -304,6 +306,7 @@ def run_gamma(args, sp, wl):
         result["scf"] = {"f64": s64, "mixed": s32,
                          "mixed_energy_diff_per_atom": abs(s32["energy"] - s64["energy"]) / s64["n_atoms"],
                          "note": "40^3 SCF cell (held-out seed), atomic-superposition start, density residual tol"}
+        result["scf"]["pseudocharge_f64"] = scf_leg(sp, ctx, "f64", pseudocharge=True)
         if os.path.exists(DEFAULT_WEIGHTS):
             sl = scf_leg(sp, ctx, "f64", learned=True)
             result["scf"]["learned_f64"] = sl

@@ -190,8 +190,10 @@ int density_from_orbitals(sparc_ctx* ctx, int32_t n_k, const void* const* X, con
                           double dV, double* rho_dev);
 
 /* Fermi level and occupations (Sec. 3.4 electron-count constraint; Sec. 2
- * Fermi-Dirac occupations): mu with 2 sum_b w_b sum_n g_nb = n_elec by
- * bisection to 1e-13 relative charge, g = (1 - tanh((lambda - mu)/(2 kT)))/2.
+ * Fermi-Dirac occupations): mu with 2 sum_b w_b sum_n g_nb = n_elec by Brent's
+ * method (the paper's Fermi-level solver, Sec. 4) on the bracket
+ * [min lambda - 40 kT - 1, max lambda + 40 kT + 1], to 1e-13 relative charge,
+ * g = (1 - tanh((lambda - mu)/(2 kT)))/2.
  * lambda_dev: device [n_k*n_s]; wk host [n_k]; occ_w_dev (out, device, may be
  * NULL): w_b g_nb; mu (host out).  Synchronous. */
 int sparc_fermi(sparc_ctx* ctx, int32_t n_k, int32_t n_s, const double* lambda_dev, const double* wk,

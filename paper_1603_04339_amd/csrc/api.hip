@@ -161,14 +161,43 @@ __global__ __launch_bounds__(256) void fermi_kernel(int nk, int ns, const double
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
     return s;
   };
-  for (int it = 0; it < 400; ++it) {
-    double mid = 0.5 * (lo + hi);
-    double c = count(mid);
-    if (c < ne) lo = mid;
-    else hi = mid;
-    if (fabs(c - ne) < 1e-13 * ne || hi - lo < 1e-15 * fmax(1.0, fabs(mid))) break;
+  // Brent's method (inverse quadratic interpolation or secant inside a bracket, with
+  // bisection whenever the interpolated step is not safely inside it or shrinks too
+  // slowly) on f(mu) = count(mu) - ne, which increases with mu; f(lo) < 0 < f(hi).
+  // Every thread runs the same scalar iteration on the block-reduced counts.
+  double a = lo, b = hi, fa = count(lo) - ne, fb = count(hi) - ne;
+  if (fabs(fa) < fabs(fb)) { double t = a; a = b; b = t; t = fa; fa = fb; fb = t; }
+  double c = a, fc = fa, d = a;
+  bool bisected = true;
+  for (int it = 0; it < 200; ++it) {
+    if (fabs(fb) < 1e-13 * ne || fabs(b - a) < 1e-15 * fmax(1.0, fabs(b))) break;
+    double s;
+    if (fa != fc && fb != fc) {  // inverse quadratic interpolation through (a, fa), (b, fb), (c, fc)
+      s = a * fb * fc / ((fa - fb) * (fa - fc)) + b * fa * fc / ((fb - fa) * (fb - fc)) +
+          c * fa * fb / ((fc - fa) * (fc - fb));
+    } else {  // secant through (a, fa), (b, fb)
+      s = b - fb * (b - a) / (fb - fa);
+    }
+    const double q = 0.25 * (3.0 * a + b);
+    const double tol = 1e-15 * fmax(1.0, fabs(b));
+    const bool outside = !((s > fmin(q, b)) && (s < fmax(q, b)));
+    const bool slow = bisected ? (fabs(s - b) >= 0.5 * fabs(b - c) || fabs(b - c) < tol)
+                               : (fabs(s - b) >= 0.5 * fabs(c - d) || fabs(c - d) < tol);
+    if (outside || slow || !isfinite(s)) {
+      s = 0.5 * (a + b);
+      bisected = true;
+    } else {
+      bisected = false;
+    }
+    const double fs = count(s) - ne;
+    d = c;
+    c = b;
+    fc = fb;
+    if ((fa < 0.0) != (fs < 0.0)) { b = s; fb = fs; }
+    else { a = s; fa = fs; }
+    if (fabs(fa) < fabs(fb)) { double t = a; a = b; b = t; t = fa; fa = fb; fb = t; }
   }
-  double mu = 0.5 * (lo + hi);
+  double mu = b;
   if (tid == 0) *mu_out = mu;
   if (occ_w)
     for (int i = tid; i < tot; i += blockDim.x) {

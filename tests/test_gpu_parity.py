@@ -245,6 +245,23 @@ def test_fermi_parity(ctx):
     np.testing.assert_allclose(occ.cpu().numpy(), wk[:, None] * occupations(lam, mu_ref, 0.01), atol=1e-11)
 
 
+@pytest.mark.parametrize("kT", [0.001, 0.01, 0.2])
+def test_fermi_brent_cases(ctx, kT):
+    """Brent's method against the oracle's bisection: degenerate levels, a fractional
+    filling inside a degenerate shell, and a gapped spectrum where every mu inside the gap
+    meets the charge (mu is then not unique: compare the occupations and the count)."""
+    shell = np.repeat(np.array([[-0.5, -0.2, -0.2, -0.2, 0.1, 0.4]]), 2, axis=0)
+    gapped = np.array([[-1.0, -0.9, 0.8, 0.9, 1.0, 1.5]])
+    for lam, ne in ((shell, 5.0), (shell, 7.3), (gapped, 4.0)):
+        wk = np.full(lam.shape[0], 1.0 / lam.shape[0])
+        mu_ref = fermi_level(lam, wk, ne, kT)
+        occ = torch.zeros(lam.shape, dtype=torch.float64, device="cuda:0")
+        mu = sp.sparc_fermi(ctx, to_dev(lam), wk, ne, kT, occ)
+        g = occ.cpu().numpy()
+        assert abs(2.0 * g.sum() - ne) < 1e-12 * ne
+        np.testing.assert_allclose(g, wk[:, None] * occupations(lam, mu_ref, kT), atol=1e-10)
+
+
 def test_error_paths(ctx):
     cell, rng = _cell((10, 10, 10), (5.0, 5.0, 5.0), 2, (0,), 2.0, 1)
     ham = sp.Hamiltonian(ctx, cell, sp.R64)
