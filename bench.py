@@ -95,7 +95,7 @@ def measured_traffic():
 # one Gamma cell (c1, c2)
 
 
-def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
+def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label, rr_mode=0):
     import torch
     dt = sp.R64 if precision == "f64" else sp.R32
     tdt = torch.float64 if precision == "f64" else torch.float32
@@ -123,7 +123,7 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
         sp.chebyshev_filter(ham, X, cell.degree, state["lcut"], lmax, wf)
         if timed:
             ev[1].record()
-        sp.rayleigh_ritz(ham, X, ritz, wr)
+        sp.rayleigh_ritz(ham, X, ritz, wr, rr_mode)
         sp.sparc_fermi(ctx, ritz.view(1, ns), [1.0], n_elec, 0.01, occ)
         sp.density_from_orbitals(ctx, [X], occ, ham.dV, rho, dt)
         if timed:
@@ -143,6 +143,7 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     hs_ms, hs_n = ctx.kernel_time("hstep")
+    gm_ms, gm_n = ctx.kernel_time("gram")
     ctx.set_timing(False)
     forces = forces_leg(sp, ctx, ham, cell, X, occ, rho) if dt == sp.R64 else None
     psd = pseudocharge_leg(sp, ctx, cell, rho) if dt == sp.R64 else None
@@ -158,7 +159,7 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label):
                                  measured_traffic() if (dt == sp.R64 and tuple(cell.n) == (96, 96, 96)
                                                         and cell.n_s == 512) else None),
         "ritz": ritz.cpu().numpy(), "bounds": (lmin, lmax), "n_proj": ham.n_proj, "forces": forces,
-        "pseudocharge": psd,
+        "pseudocharge": psd, "gram_ms_per_step": gm_ms / steps,
     }
 
 
@@ -296,9 +297,17 @@ def run_gamma(args, sp, wl):
             "value": mx["value"], "ms_per_step": mx["ms_per_step"], "filter_ms": mx["filter_ms"],
             "speedup_vs_f64": mx["value"] / main["value"], "roofline": mx["roofline"],
             "ritz_max_abs_diff_vs_f64_occupied": float(d.max()),
+            "gram_ms_per_step": mx["gram_ms_per_step"],
             "note": (f"FP32 filter and FP32 MFMA Gram/rotation with FP64 Cholesky-QR and eigensolve; both forms "
                      f"from the same start after {args.warmup + args.steps} passes; {n_occ} occupied states"),
         }
+        for nm, md in (("bf16x3", sp.GEMM_BF16X3), ("bf16x6", sp.GEMM_BF16X6)):
+            sx = gamma_leg(sp, ctx, cell, X0, v0, "mixed", args.steps, args.warmup, "mixed-" + nm, rr_mode=md)
+            d = np.abs(sx["ritz"][:n_occ] - main["ritz"][:n_occ])
+            result["mixed"]["grams_" + nm] = {
+                "value": sx["value"], "ms_per_step": sx["ms_per_step"], "gram_ms_per_step": sx["gram_ms_per_step"],
+                "ritz_max_abs_diff_vs_f64_occupied": float(d.max()),
+                "note": f"the mixed form with the Rayleigh-Ritz Grams on split-BF16 MFMA ({nm})"}
     if not args.no_scf:
         from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS
         s64 = scf_leg(sp, ctx, "f64")
@@ -398,6 +407,7 @@ def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None):
     eager.run([b[0] for b in bounds], [b[1] for b in bounds])
     torch.cuda.synchronize()
     hs_ms, hs_n = ctx.kernel_time("hstep")
+    gm_ms, gm_n = ctx.kernel_time("gram")
     ctx.set_timing(False)
     eager.close()
     plan.close()

@@ -50,11 +50,19 @@ typedef enum {
 typedef enum { SPARC_R64 = 0, SPARC_R32 = 1, SPARC_C128 = 2, SPARC_C64 = 3 } sparc_dtype;
 
 /* Precision of the N_d-long Rayleigh–Ritz contractions; the Cholesky factors,
- * the subspace eigensolve and all N_s x N_s work stay in FP64.  One mode: the
- * contractions run on MFMA in the element type of the orbitals (FP64 or FP32,
- * FP32 accumulation for FP32); other values are rejected with EINVAL. */
+ * the subspace eigensolve and all N_s x N_s work stay in FP64.
+ * NATIVE: the contractions run on MFMA in the element type of the orbitals (FP64 or
+ * FP32, FP32 accumulation for FP32).
+ * BF16X3 / BF16X6 (FP32 and complex64 blocks only, else EINVAL): the Gram contractions
+ * X^H X and X^H (H X) split every FP32 operand into 2 (x3) or 3 (x6) bfloat16 pieces,
+ * x = x_0 + x_1 (+ x_2) with each piece the round-to-nearest bf16 of the remainder, and
+ * sum the piece products x_p y_q with p + q < 2 (three products: about 16 significant
+ * bits) or p + q < 3 (six products: FP32 accuracy) on bf16 MFMA with FP32 accumulation;
+ * the rotations stay FP32 MFMA.  Other values: EINVAL. */
 typedef enum {
-  SPARC_GEMM_NATIVE = 0
+  SPARC_GEMM_NATIVE = 0,
+  SPARC_GEMM_BF16X3 = 1,
+  SPARC_GEMM_BF16X6 = 2
 } sparc_gemm_mode;
 
 /* Uniform grid on an axis-aligned cuboid (Sec. 3.1): n grid points and L lengths

@@ -446,7 +446,10 @@ int rayleigh_ritz(sparc_ham* H, void* X, int64_t ldx, int32_t n_s, sparc_gemm_mo
   SPARC_TRY(check_ham(H, "rayleigh_ritz"));
   SPARC_TRY(check_block(H, X, ldx, n_s, "rayleigh_ritz"));
   if (!ritz_dev) return fail(SPARC_EINVAL, "rayleigh_ritz: ritz_dev is NULL");
-  if (mode != SPARC_GEMM_NATIVE) return fail(SPARC_EINVAL, "rayleigh_ritz: unknown GEMM mode %d", (int)mode);
+  if (mode != SPARC_GEMM_NATIVE && mode != SPARC_GEMM_BF16X3 && mode != SPARC_GEMM_BF16X6)
+    return fail(SPARC_EINVAL, "rayleigh_ritz: unknown GEMM mode %d", (int)mode);
+  if (mode != SPARC_GEMM_NATIVE && !dtype_single(H->dtype))
+    return fail(SPARC_EINVAL, "rayleigh_ritz: split-BF16 modes take FP32 / complex64 blocks");
   if (n_s > 2048) return fail(SPARC_ESHAPE, "rayleigh_ritz: n_s=%d above 2048", n_s);
   if (n_s > H->n_d) return fail(SPARC_ESHAPE, "rayleigh_ritz: n_s=%d exceeds N_d", n_s);
   RRWork w;

@@ -219,6 +219,175 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t N, int na, int nb, co
   }
 }
 
+// ---------------------------------------------------------------- gram, split-BF16 operands
+// FP32 operands split into P bfloat16 pieces, x = x_0 + x_1 (+ x_2), each piece the
+// round-to-nearest bf16 of what the previous pieces leave (exact differences).  A
+// product of two elements is the sum of the piece products x_p y_q with p + q < P
+// (P = 2: three products; P = 3: six), each exact in v_mfma_f32_16x16x16_bf16 with FP32
+// accumulation.  The pieces are formed when a chunk is written to LDS (hardware
+// round-to-nearest conversion), stored k-contiguous per column, so one 8-byte LDS read
+// gives a lane the four k values of its MFMA operand.  Lane layout of the bf16 MFMA:
+// A[i][k] in lane i + 16 (k / 4), element k % 4; B[k][j] likewise with j; result as for
+// v_mfma_f32_16x16x4f32.
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+template <int P>
+__device__ __forceinline__ void bf16_pieces(float x, unsigned short out[P]) {
+  float r = x;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const __bf16 h = (__bf16)r;
+    out[q] = __builtin_bit_cast(unsigned short, h);
+    if (q + 1 < P) r = r - (float)h;
+  }
+}
+
+__device__ __forceinline__ v4s neg_bf16(v4s v) {
+  return v ^ (v4s){(short)0x8000, (short)0x8000, (short)0x8000, (short)0x8000};
+}
+
+template <typename E, int T, int KC, int P>
+__global__ __launch_bounds__(256) void gram_split_kernel(int64_t N, int na, int nb, const E* __restrict__ A,
+                                                         int64_t lda, const E* __restrict__ B, int64_t ldb,
+                                                         int n_slab, int64_t slab_len, int tiles_a, int n_tiles,
+                                                         int herm, double* __restrict__ part, int xcd_remap,
+                                                         int vec) {
+  static_assert(sizeof(typename elem<E>::real) == 4, "split-BF16 products take FP32 operands");
+  constexpr bool CPX = elem<E>::is_cplx;
+  constexpr int NCP = CPX ? 2 : 1;
+  constexpr int WB = T / 32;
+  constexpr int KP = KC + 4;  // padded row: 8-byte aligned, rows spread over the banks
+  typedef mfma_t<float> M;
+  typedef PairLoader<E, T, KC> LD;
+  __shared__ __attribute__((aligned(16))) unsigned short As[NCP][P][T][KP];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[NCP][P][T][KP];
+
+  const int total = n_slab * n_tiles;
+  const int G = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = (wv & 1) * (T / 2), wj = (wv >> 1) * (T / 2);
+  for (int round = 0;; ++round) {
+    const int bid = xcd_remap ? round * G + (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8)
+                              : round * G + (int)blockIdx.x;
+    if (bid >= total) break;
+    const int slab = bid / n_tiles;
+    const int tile = bid % n_tiles;
+    int ti, tj;
+    if (herm) {
+      tj = 0;
+      while ((tj + 1) * (tj + 2) / 2 <= tile) ++tj;
+      ti = tile - tj * (tj + 1) / 2;
+    } else {
+      ti = tile % tiles_a;
+      tj = tile / tiles_a;
+    }
+    const int i0 = ti * T, j0 = tj * T;
+    const int64_t k_beg = (int64_t)slab * slab_len;
+    const int64_t k_end = min(N, k_beg + slab_len);
+
+    typename M::acc acc_r[WB][WB], acc_i[WB][WB];
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+      for (int b = 0; b < WB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; if constexpr (CPX) acc_i[a][b][v] = 0; }
+
+    LD la, lb;
+    la.fetch(A, lda, i0, na, k_beg, k_end, vec);
+    lb.fetch(B, ldb, j0, nb, k_beg, k_end, vec);
+    for (int64_t k0 = k_beg; k0 < k_end; k0 += KC) {
+#pragma unroll
+      for (int u = 0; u < LD::PAIRS; ++u) {
+        const int q = tid + 256 * u;
+        const int c = q / (KC / 2), kk = (q % (KC / 2)) * 2;
+        float r0, im0, r1, im1;
+        unsigned short p0[P], p1[P];
+        split<E>(la.v0[u], r0, im0);
+        split<E>(la.v1[u], r1, im1);
+        bf16_pieces<P>(r0, p0);
+        bf16_pieces<P>(r1, p1);
+#pragma unroll
+        for (int t = 0; t < P; ++t) *(unsigned*)&As[0][t][c][kk] = (unsigned)p0[t] | ((unsigned)p1[t] << 16);
+        if constexpr (CPX) {
+          bf16_pieces<P>(im0, p0);
+          bf16_pieces<P>(im1, p1);
+#pragma unroll
+          for (int t = 0; t < P; ++t) *(unsigned*)&As[1][t][c][kk] = (unsigned)p0[t] | ((unsigned)p1[t] << 16);
+        }
+        split<E>(lb.v0[u], r0, im0);
+        split<E>(lb.v1[u], r1, im1);
+        bf16_pieces<P>(r0, p0);
+        bf16_pieces<P>(r1, p1);
+#pragma unroll
+        for (int t = 0; t < P; ++t) *(unsigned*)&Bs[0][t][c][kk] = (unsigned)p0[t] | ((unsigned)p1[t] << 16);
+        if constexpr (CPX) {
+          bf16_pieces<P>(im0, p0);
+          bf16_pieces<P>(im1, p1);
+#pragma unroll
+          for (int t = 0; t < P; ++t) *(unsigned*)&Bs[1][t][c][kk] = (unsigned)p0[t] | ((unsigned)p1[t] << 16);
+        }
+      }
+      __syncthreads();
+      if (k0 + KC < k_end) {
+        la.fetch(A, lda, i0, na, k0 + KC, k_end, vec);
+        lb.fetch(B, ldb, j0, nb, k0 + KC, k_end, vec);
+      }
+      // one 16-wide k step at a time keeps the three-piece operands within two waves per SIMD
+#pragma unroll(P == 2 ? KC / 16 : 1)
+      for (int kk = 0; kk < KC; kk += 16) {
+        const int kq = kk + 4 * (lane >> 4), r16 = lane & 15;
+        v4s a_[NCP][P][WB], b_[NCP][P][WB];
+#pragma unroll
+        for (int cp = 0; cp < NCP; ++cp)
+#pragma unroll
+          for (int t = 0; t < P; ++t)
+#pragma unroll
+            for (int a = 0; a < WB; ++a) {
+              a_[cp][t][a] = *(const v4s*)&As[cp][t][wi + 16 * a + r16][kq];
+              b_[cp][t][a] = *(const v4s*)&Bs[cp][t][wj + 16 * a + r16][kq];
+            }
+#pragma unroll
+        for (int a = 0; a < WB; ++a)
+#pragma unroll
+          for (int b = 0; b < WB; ++b)
+#pragma unroll
+            for (int ta = P - 1; ta >= 0; --ta)
+#pragma unroll
+              for (int tb = P - 1 - ta; tb >= 0; --tb) {
+                acc_r[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_[0][ta][a], b_[0][tb][b], acc_r[a][b], 0, 0, 0);
+                if constexpr (CPX) {
+                  // conj(A)^T B: re += ar br + ai bi ; im += ar bi - ai br
+                  acc_r[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_[1][ta][a], b_[1][tb][b], acc_r[a][b], 0, 0, 0);
+                  acc_i[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_[0][ta][a], b_[1][tb][b], acc_i[a][b], 0, 0, 0);
+                  acc_i[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(neg_bf16(a_[1][ta][a]), b_[0][tb][b], acc_i[a][b], 0, 0, 0);
+                }
+              }
+      }
+      __syncthreads();
+    }
+    const int64_t mat = (int64_t)na * nb * NCP;
+    double* Pp = part + (int64_t)slab * mat;
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+      for (int b = 0; b < WB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          int i = i0 + wi + 16 * a + M::row(lane, v);
+          int j = j0 + wj + 16 * b + (lane & 15);
+          if (i < na && j < nb) {
+            if constexpr (CPX) {
+              Pp[2 * (i + (int64_t)j * na)] = (double)acc_r[a][b][v];
+              Pp[2 * (i + (int64_t)j * na) + 1] = (double)acc_i[a][b][v];
+            } else {
+              Pp[i + (int64_t)j * na] = (double)acc_r[a][b][v];
+            }
+          }
+        }
+  }
+}
+
 // C = sum over slabs; herm: only tiles with ti <= tj were computed, fill the
 // lower triangle by conjugate symmetry and make the diagonal real.
 __global__ void gram_reduce_kernel(int na, int nb, int n_slab, const double* __restrict__ part, double* __restrict__ C,
@@ -277,7 +446,8 @@ size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt) {
 
 template <typename E>
 static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t lda, const E* B, int64_t ldb, void* C,
-                  int ldc, void* work, size_t work_bytes, int n_cu, bool herm_result) {
+                  int ldc, void* work, size_t work_bytes, int n_cu, bool herm_result,
+                  sparc_gemm_mode mode = SPARC_GEMM_NATIVE) {
   const bool herm = (na == nb) && (herm_result || ((A == B) && (lda == ldb)));
   constexpr int T = gram_tile<E>::T;
   GramPlan p = gram_plan(N, na, nb, herm, n_cu, T);
@@ -292,8 +462,21 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
   int remap = (grid % 8 == 0) ? 1 : 0;
   int tmr = timer_begin(g_timer_ctx, "gram");
   const int vec = (lda % 2 == 0 && ldb % 2 == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0) ? 1 : 0;
-  gram_kernel<E, T, 16><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
-                                              herm ? 1 : 0, part, remap, vec);
+  if constexpr (sizeof(typename elem<E>::real) == 4) {
+    if (mode == SPARC_GEMM_BF16X3)
+      gram_split_kernel<E, T, 32, 2><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
+                                                           p.n_tiles, herm ? 1 : 0, part, remap, vec);
+    else if (mode == SPARC_GEMM_BF16X6)
+      gram_split_kernel<E, T, 32, 3><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
+                                                           p.n_tiles, herm ? 1 : 0, part, remap, vec);
+    else
+      gram_kernel<E, T, 16><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
+                                                  p.n_tiles, herm ? 1 : 0, part, remap, vec);
+  } else {
+    if (mode != SPARC_GEMM_NATIVE) return fail(SPARC_EINVAL, "gram: split-BF16 modes take FP32 blocks");
+    gram_kernel<E, T, 16><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
+                                                herm ? 1 : 0, part, remap, vec);
+  }
   timer_end(g_timer_ctx, tmr);
   SPARC_TRY(check_launch("gram_kernel"));
   int64_t ne = (int64_t)na * nb;
@@ -305,12 +488,11 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
 int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t na, int32_t nb, const void* A, int64_t lda, const void* B,
          int64_t ldb, void* C, int32_t ldc, void* work, size_t work_bytes, sparc_gemm_mode mode, int n_cu,
          bool herm_result) {
-  (void)mode;
   switch (dt) {
-    case SPARC_R64: return gram_t<double>(s, N, na, nb, (const double*)A, lda, (const double*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
-    case SPARC_R32: return gram_t<float>(s, N, na, nb, (const float*)A, lda, (const float*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
-    case SPARC_C128: return gram_t<cd>(s, N, na, nb, (const cd*)A, lda, (const cd*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
-    case SPARC_C64: return gram_t<cf>(s, N, na, nb, (const cf*)A, lda, (const cf*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result);
+    case SPARC_R64: return gram_t<double>(s, N, na, nb, (const double*)A, lda, (const double*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
+    case SPARC_R32: return gram_t<float>(s, N, na, nb, (const float*)A, lda, (const float*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
+    case SPARC_C128: return gram_t<cd>(s, N, na, nb, (const cd*)A, lda, (const cd*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
+    case SPARC_C64: return gram_t<cf>(s, N, na, nb, (const cf*)A, lda, (const cf*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
   }
   return fail(SPARC_EINVAL, "gram: bad dtype");
 }

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libsparc_hip.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, ENOTSPD, ENOCONV, EDEVICE, ENAN = 0, -1, -2, -3, -4, -5, -6, -7
 R64, R32, C128, C64 = 0, 1, 2, 3
-GEMM_NATIVE = 0
+GEMM_NATIVE, GEMM_BF16X3, GEMM_BF16X6 = 0, 1, 2
 OP_APPLY, OP_FILTER, OP_RR, OP_LANCZOS, OP_FORCES = 0, 1, 2, 3, 4
 ELEC_JELLIUM, ELEC_PSEUDOCHARGE = 0, 1
 
