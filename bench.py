@@ -144,6 +144,9 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label, rr_mode=0)
     t_total = time.perf_counter() - t_start
     hs_ms, hs_n = ctx.kernel_time("hstep")
     gm_ms, gm_n = ctx.kernel_time("gram")
+    ro_ms, ro_n = ctx.kernel_time("rotate")
+    ga_ms, ga_n = ctx.kernel_time("nl_gather")
+    sc_ms, sc_n = ctx.kernel_time("nl_scatter")
     ctx.set_timing(False)
     forces = forces_leg(sp, ctx, ham, cell, X, occ, rho) if dt == sp.R64 else None
     psd = pseudocharge_leg(sp, ctx, cell, rho) if dt == sp.R64 else None
@@ -160,6 +163,9 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label, rr_mode=0)
                                                         and cell.n_s == 512) else None),
         "ritz": ritz.cpu().numpy(), "bounds": (lmin, lmax), "n_proj": ham.n_proj, "forces": forces,
         "pseudocharge": psd, "gram_ms_per_step": gm_ms / steps,
+        "step_breakdown_ms": {"stencil": hs_ms / steps, "projector_gather": ga_ms / steps,
+                              "projector_scatter": sc_ms / steps, "grams": gm_ms / steps,
+                              "rotations": ro_ms / steps},
     }
 
 
@@ -283,7 +289,7 @@ def run_gamma(args, sp, wl):
             "n_d": nd, "n_s": ns, "degree": cell.degree, "n_k": 1,
         },
         "filter_ms": main["filter_ms"], "filter_throughput": main["filter_throughput"],
-        "roofline": main["roofline"],
+        "roofline": main["roofline"], "step_breakdown_ms": main["step_breakdown_ms"],
     }
     if main["forces"] is not None:
         result["forces"] = main["forces"]
@@ -408,6 +414,9 @@ def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None):
     torch.cuda.synchronize()
     hs_ms, hs_n = ctx.kernel_time("hstep")
     gm_ms, gm_n = ctx.kernel_time("gram")
+    ro_ms, ro_n = ctx.kernel_time("rotate")
+    ga_ms, ga_n = ctx.kernel_time("nl_gather")
+    sc_ms, sc_n = ctx.kernel_time("nl_scatter")
     ctx.set_timing(False)
     eager.close()
     plan.close()
