@@ -174,9 +174,11 @@ int chebyshev_filter(sparc_ham* ham, void* X, int64_t ldx, int32_t n_s, int32_t 
  * on the GPU (Householder tridiagonalisation, bisection, inverse iteration),
  * and X is overwritten with the rotated orbitals (Euclidean-orthonormal Ritz
  * vectors).  ritz_dev: device, n_s doubles, ascending.  mode: precision of the
- * N_d-long contractions.  info (host, may be NULL): failing column + 1 on
+ * N_d-long contractions (sparc_gemm_mode; the split-BF16 modes only with SPARC_R32 /
+ * SPARC_C64 Hamiltonians).  info (host, may be NULL): failing column + 1 on
  * ENOTSPD.  work: SPARC_OP_RR bytes.  Errors: ENOTSPD (rank-deficient block),
- * EINVAL, ESHAPE, ENOMEM.  Synchronous (reads back the Cholesky status). */
+ * EINVAL (also an unknown mode, or a split mode with an FP64 dtype), ESHAPE, ENOMEM.
+ * Synchronous (reads back the Cholesky status). */
 int rayleigh_ritz(sparc_ham* ham, void* X, int64_t ldx, int32_t n_s, sparc_gemm_mode mode,
                   double* ritz_dev, void* work, size_t work_bytes, int32_t* info);
 

@@ -140,6 +140,23 @@ def test_scf_pseudocharge_matches_oracle(ctx):
     np.testing.assert_allclose(phi.cpu().numpy(), ref["phi"], atol=1e-6 * np.abs(ref["phi"]).max())
 
 
+def test_scf_pseudocharge_mixed_precision(ctx):
+    """The pseudocharge SCF with FP32 filter passes (split-BF16 x3 Grams) and the FP64
+    hand-over reaches the FP64 pseudocharge SCF's free energy within 1e-6 Ha/atom."""
+    cell, X0, v0 = _scf_cell()
+    ref = _gpu_scf(ctx, cell, X0, v0, tol=1e-9)[0]
+    prm = dict(n_s=8, degree=16, n_first_passes=6, max_iter=200, lanczos_steps=20, mix_history=7, kT=0.01,
+               mix=0.3, tol=1e-9, n_elec=cell.n_elec, poisson_tol=1e-13, filt=sp.R32, rr=sp.GEMM_BF16X3,
+               final_fp64_pass=1, rho_init_dev=None, x0_dev=torch.from_numpy(X0).cuda(),
+               lanczos_v0_dev=torch.from_numpy(v0).cuda(), electrostatics=sp.ELEC_PSEUDOCHARGE, eps_b=1e-8)
+    rho = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    ritz = torch.zeros(8, dtype=torch.float64, device="cuda:0")
+    out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz)
+    err = abs(out["energy"] - ref["energy"]) / cell.n_atoms
+    print(f"pseudocharge mixed: {out['iterations']} it (FP64 {ref['iterations']}), |dF|/atom = {err:.2e}")
+    assert out["converged"] and err < 1e-6
+
+
 def test_scf_pseudocharge_forces_match_energy_differences(ctx):
     """Total force (f_loc + f_c from sparc_forces_psd on the SCF's phi, f_nloc from
     sparc_forces_nonlocal on its orbitals) against central differences of the GPU SCF

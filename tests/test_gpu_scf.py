@@ -69,11 +69,14 @@ def test_scf_matches_oracle(ctx, oracle_ref):
     np.testing.assert_allclose(ritz.cpu().numpy(), ref["ritz"], atol=1e-6)
 
 
-def test_scf_mixed_precision(ctx, oracle_ref):
+@pytest.mark.parametrize("rr", [sp.GEMM_NATIVE, sp.GEMM_BF16X6, sp.GEMM_BF16X3], ids=["fp32", "bf16x6", "bf16x3"])
+def test_scf_mixed_precision(ctx, oracle_ref, rr):
+    """FP32 filter passes with FP32, split-BF16 x6 or x3 Rayleigh-Ritz Grams, then the FP64
+    hand-over: the converged free energy within 1e-6 Ha/atom of the FP64 oracle."""
     cell, X0, v0, ref = oracle_ref
-    out, rho, ritz = _run(ctx, cell, _params(cell, X0, v0, filt=sp.R32))
+    out, rho, ritz = _run(ctx, cell, {**_params(cell, X0, v0, filt=sp.R32), "rr": rr})
     err = abs(out["energy"] - ref["energy"]) / cell.n_atoms
-    print(f"mixed: {out['iterations']} it, F={out['energy']:.10f}, |dF|/atom = {err:.2e}")
+    print(f"mixed (rr mode {rr}): {out['iterations']} it, F={out['energy']:.10f}, |dF|/atom = {err:.2e}")
     assert out["converged"]
     assert err < 1e-6
 
