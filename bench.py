@@ -304,6 +304,7 @@ def run_gamma(args, sp, wl):
             "speedup_vs_f64": mx["value"] / main["value"], "roofline": mx["roofline"],
             "ritz_max_abs_diff_vs_f64_occupied": float(d.max()),
             "gram_ms_per_step": mx["gram_ms_per_step"],
+            "rotation_ms_per_step": mx["step_breakdown_ms"]["rotations"],
             "note": (f"FP32 filter and FP32 MFMA Gram/rotation with FP64 Cholesky-QR and eigensolve; both forms "
                      f"from the same start after {args.warmup + args.steps} passes; {n_occ} occupied states"),
         }
@@ -312,8 +313,10 @@ def run_gamma(args, sp, wl):
             d = np.abs(sx["ritz"][:n_occ] - main["ritz"][:n_occ])
             result["mixed"]["grams_" + nm] = {
                 "value": sx["value"], "ms_per_step": sx["ms_per_step"], "gram_ms_per_step": sx["gram_ms_per_step"],
+                "rotation_ms_per_step": sx["step_breakdown_ms"]["rotations"],
                 "ritz_max_abs_diff_vs_f64_occupied": float(d.max()),
-                "note": f"the mixed form with the Rayleigh-Ritz Grams on split-BF16 MFMA ({nm})"}
+                "note": (f"the mixed form with the Rayleigh-Ritz Grams on split-BF16 MFMA ({nm})"
+                         + ("; the rotations too, from pre-split pieces" if nm == "bf16x3" else ""))}
     if not args.no_scf:
         from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS
         s64 = scf_leg(sp, ctx, "f64")

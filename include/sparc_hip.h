@@ -57,7 +57,9 @@ typedef enum { SPARC_R64 = 0, SPARC_R32 = 1, SPARC_C128 = 2, SPARC_C64 = 3 } spa
  * X^H X and X^H (H X) split every FP32 operand into 2 (x3) or 3 (x6) bfloat16 pieces,
  * x = x_0 + x_1 (+ x_2) with each piece the round-to-nearest bf16 of the remainder, and
  * sum the piece products x_p y_q with p + q < 2 (three products: about 16 significant
- * bits) or p + q < 3 (six products: FP32 accuracy) on bf16 MFMA with FP32 accumulation;
+ * bits) or p + q < 3 (six products: FP32 accuracy) on bf16 MFMA with FP32 accumulation.
+ * With BF16X3 and n_s a multiple of 16 the two N_d-long rotations X Q use three split
+ * products too (the block is split once into the Rayleigh–Ritz workspace); otherwise
  * the rotations stay FP32 MFMA.  Other values: EINVAL. */
 typedef enum {
   SPARC_GEMM_NATIVE = 0,

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void fermi_kernel(int nk, int ns, const double
 
 // ------------------------------------------------------------ Rayleigh-Ritz workspace
 struct RRWork {
-  void *W1, *W2, *alpha, *M, *T1, *T2, *A1, *tmp, *Z, *Qf, *gw, *cw, *hw;
+  void *W1, *W2, *alpha, *M, *T1, *T2, *A1, *tmp, *Z, *Qf, *qp, *gw, *cw, *hw;
   int* info;
   size_t gw_bytes;
 };
@@ -233,7 +233,7 @@ static size_t rr_layout(const sparc_ham* H, int32_t n_s, void* base, size_t byte
     w->tmp = c.take(sm);
     w->Z = c.take(sm);
     w->Qf = c.take(sm);
-    c.take(sm);
+    w->qp = c.take(sm);
     w->gw = c.take(gwb);
     w->gw_bytes = gwb;
     w->cw = c.take(chol_orth_work_bytes(n_s, cp));
@@ -328,6 +328,17 @@ int filter_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n_s, int32_t degree,
   return SPARC_OK;
 }
 
+// Out = A Q for the N_d-long rotations of Rayleigh-Ritz: split-BF16 (x3) products from
+// pieces made in W2 (free at every rotation) when the mode asks for them and n is a
+// multiple of 16, else the element type's MFMA
+static int rr_rotate(sparc_ham* H, sparc_gemm_mode mode, int32_t n, const void* A, int64_t lda, const void* Q,
+                     void* Out, int64_t ldo, int q_upper, RRWork& w) {
+  hipStream_t s = H->ctx->stream;
+  if (mode == SPARC_GEMM_BF16X3 && dtype_single(H->dtype) && n % 16 == 0)
+    return rotate_split_x3(s, H->dtype, H->n_d, n, n, A, lda, Q, n, Out, ldo, q_upper, w.W2, w.qp);
+  return rotate(s, H->dtype, H->n_d, n, n, A, lda, Q, n, Out, ldo, q_upper);
+}
+
 int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode, double* ritz, RRWork& w,
             int32_t* info_out) {
   hipStream_t s = H->ctx->stream;
@@ -355,7 +366,7 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
     }
     shifted = true;
   }
-  SPARC_TRY(rotate(s, dt, N, n, n, X, ldx, w.T1, n, w.W1, N, 1));
+  SPARC_TRY(rr_rotate(H, mode, n, X, ldx, w.T1, w.W1, N, 1, w));
   if (shifted) {  // one more explicit pass after a shifted factorisation
     SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W1, N, w.M, n, w.gw, w.gw_bytes, mode, ncu));
     SPARC_TRY(chol_orth(s, cp, n, w.M, w.T1, w.info, w.cw, 0.0));
@@ -365,7 +376,7 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
       if (info_out) *info_out = info;
       return fail(SPARC_ENOTSPD, "rayleigh_ritz: Gram matrix not positive definite at column %d", info);
     }
-    SPARC_TRY(rotate(s, dt, N, n, n, w.W1, N, w.T1, n, X, ldx, 1));
+    SPARC_TRY(rr_rotate(H, mode, n, w.W1, N, w.T1, X, ldx, 1, w));
     SPARC_HIP(hipMemcpy2DAsync(w.W1, N * elem_bytes(dt), X, ldx * elem_bytes(dt), N * elem_bytes(dt), n,
                                hipMemcpyDeviceToDevice, s));
   }
@@ -390,7 +401,7 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
   SPARC_TRY(heev(s, cp, n, w.A1, ritz, w.Z, w.hw));
   // U = X1 (T2 Z)
   SPARC_TRY(rotate(s, sdt, n, n, n, w.T2, n, w.Z, n, w.Qf, n, 0));
-  SPARC_TRY(rotate(s, dt, N, n, n, w.W1, N, w.Qf, n, X, ldx, 0));
+  SPARC_TRY(rr_rotate(H, mode, n, w.W1, N, w.Qf, X, ldx, 0, w));
   if (info_out) *info_out = 0;
   return SPARC_OK;
 }

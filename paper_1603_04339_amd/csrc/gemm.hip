@@ -679,6 +679,176 @@ static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, i
   return check_launch("rotate_kernel");
 }
 
+// ---------------------------------------------------------------- rotate, split-BF16 (x3) from pre-split pieces
+// The FP32 block is split once into two bf16 pieces laid out for the B operand of
+// v_mfma_f32_16x16x16_bf16: pieces[t][c][k/4][m][k%4] (t piece, c real/imaginary part,
+// k column of A, m row), so a lane's four k values of row m are one 8-byte load; Q
+// (FP64, rounded to FP32) likewise as Qp[t][c][k/4][j][k%4].  The rotation then
+// reads its operands straight from global memory (L2) in MFMA layout, without LDS, and
+// sums the three piece products with p + q < 2.  n_in must be a multiple of 16.
+template <typename E>
+__global__ __launch_bounds__(256) void split_block_kernel(int64_t N, int n, const E* __restrict__ A, int64_t lda,
+                                                          unsigned short* __restrict__ out) {
+  constexpr int NCP = elem<E>::is_cplx ? 2 : 1;
+  const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int kb = blockIdx.y, KB = gridDim.y;
+  if (m >= N) return;
+  unsigned short pc[2][NCP][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = 4 * kb + q;
+    float vr = 0.0f, vi = 0.0f;
+    if (k < n) split<E>(A[m + (int64_t)k * lda], vr, vi);
+    unsigned short t2[2];
+    bf16_pieces<2>(vr, t2);
+    pc[0][0][q] = t2[0];
+    pc[1][0][q] = t2[1];
+    if constexpr (NCP == 2) {
+      bf16_pieces<2>(vi, t2);
+      pc[0][1][q] = t2[0];
+      pc[1][1][q] = t2[1];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NCP; ++c) {
+      v4s v = {(short)pc[t][c][0], (short)pc[t][c][1], (short)pc[t][c][2], (short)pc[t][c][3]};
+      *(v4s*)&out[((((int64_t)t * NCP + c) * KB + kb) * N + m) * 4] = v;
+    }
+}
+
+template <bool CPX>
+__global__ void split_q_kernel(int n_in, int n_out, const double* __restrict__ Q, int ldq,
+                               unsigned short* __restrict__ out) {
+  constexpr int NCP = CPX ? 2 : 1;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)n_in * n_out) return;
+  const int k = (int)(i % n_in), j = (int)(i / n_in);
+#pragma unroll
+  for (int c = 0; c < NCP; ++c) {
+    const double q = CPX ? Q[2 * (k + (int64_t)j * ldq) + c] : Q[k + (int64_t)j * ldq];
+    unsigned short t2[2];
+    bf16_pieces<2>((float)q, t2);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) out[((((int64_t)t * NCP + c) * (n_in / 4) + k / 4) * n_out + j) * 4 + k % 4] = t2[t];
+  }
+}
+
+template <typename E, int T>
+__global__ __launch_bounds__(256) void rotate_pieces_kernel(int64_t N, int n_in, int n_out,
+                                                            const unsigned short* __restrict__ Ap,
+                                                            const unsigned short* __restrict__ Qp,
+                                                            E* __restrict__ Out, int64_t ldo, int tiles_n,
+                                                            int xcd_remap, int64_t total, int q_upper) {
+  constexpr bool CPX = elem<E>::is_cplx;
+  constexpr int NCP = CPX ? 2 : 1;
+  constexpr int WB = T / 32;
+  typedef mfma_t<float> M;
+  int64_t bid = blockIdx.x;
+  if (xcd_remap) bid = (bid % 8) * (total / 8) + bid / 8;
+  const int tn = (int)(bid % tiles_n);
+  const int64_t m0 = (bid / tiles_n) * T;
+  const int j0 = tn * T;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wj = (wv & 1) * (T / 2), wm = (wv >> 1) * (T / 2);
+  const int r16 = lane & 15;
+  const int KB = n_in / 4;
+  typename M::acc acc_r[WB][WB], acc_i[WB][WB];
+#pragma unroll
+  for (int a = 0; a < WB; ++a)
+#pragma unroll
+    for (int b = 0; b < WB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { acc_r[a][b][v] = 0; if constexpr (CPX) acc_i[a][b][v] = 0; }
+  const int k_stop = q_upper ? min(n_in, j0 + T) : n_in;  // a multiple of 16
+  const v4s zero4 = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < k_stop; k0 += 16) {
+    const int kq = k0 + 4 * (lane >> 4);
+    v4s q_[NCP][2][WB], a_[NCP][2][WB];
+#pragma unroll
+    for (int c = 0; c < NCP; ++c)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int a = 0; a < WB; ++a) {
+          const int j = j0 + wj + 16 * a + r16;
+          const int64_t m = m0 + wm + 16 * a + r16;
+          q_[c][t][a] = j < n_out ? *(const v4s*)&Qp[((((int64_t)t * NCP + c) * KB + kq / 4) * n_out + j) * 4] : zero4;
+          a_[c][t][a] = m < N ? *(const v4s*)&Ap[((((int64_t)t * NCP + c) * KB + kq / 4) * N + m) * 4] : zero4;
+        }
+#pragma unroll
+    for (int a = 0; a < WB; ++a)
+#pragma unroll
+      for (int b = 0; b < WB; ++b)
+#pragma unroll
+        for (int tq = 1; tq >= 0; --tq)
+#pragma unroll
+          for (int ta = 1 - tq; ta >= 0; --ta) {
+            acc_r[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(q_[0][tq][a], a_[0][ta][b], acc_r[a][b], 0, 0, 0);
+            if constexpr (CPX) {
+              // (A Q): re = Ar Qr - Ai Qi ; im = Ar Qi + Ai Qr
+              acc_r[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(neg_bf16(q_[1][tq][a]), a_[1][ta][b], acc_r[a][b], 0, 0, 0);
+              acc_i[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(q_[1][tq][a], a_[0][ta][b], acc_i[a][b], 0, 0, 0);
+              acc_i[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(q_[0][tq][a], a_[1][ta][b], acc_i[a][b], 0, 0, 0);
+            }
+          }
+  }
+#pragma unroll
+  for (int a = 0; a < WB; ++a)
+#pragma unroll
+    for (int b = 0; b < WB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int j = j0 + wj + 16 * a + M::row(lane, v);
+        int64_t m = m0 + wm + 16 * b + (lane & 15);
+        if (j < n_out && m < N) {
+          if constexpr (CPX) {
+            E o;
+            o.re = acc_r[a][b][v];
+            o.im = acc_i[a][b][v];
+            Out[m + (int64_t)j * ldo] = o;
+          } else {
+            Out[m + (int64_t)j * ldo] = acc_r[a][b][v];
+          }
+        }
+      }
+}
+
+template <typename E>
+static int rotate_x3_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, int64_t lda, const double* Q,
+                       int ldq, E* Out, int64_t ldo, int q_upper, void* a_pieces, void* q_pieces) {
+  constexpr int T = gram_tile<E>::T;
+  constexpr bool CPX = elem<E>::is_cplx;
+  int tmr = timer_begin(g_timer_ctx, "rotate");
+  split_block_kernel<E><<<dim3((unsigned)((N + 255) / 256), (unsigned)(n_in / 4)), 256, 0, s>>>(
+      N, n_in, A, lda, (unsigned short*)a_pieces);
+  split_q_kernel<CPX><<<(unsigned)(((int64_t)n_in * n_out + 255) / 256), 256, 0, s>>>(n_in, n_out, Q, ldq,
+                                                                                     (unsigned short*)q_pieces);
+  const int tiles_n = (n_out + T - 1) / T;
+  const int64_t total = ((N + T - 1) / T) * tiles_n;
+  if (total > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "rotate: too many tiles");
+  const int remap = (total % 8 == 0) ? 1 : 0;
+  rotate_pieces_kernel<E, T><<<(unsigned)total, 256, 0, s>>>(N, n_in, n_out, (const unsigned short*)a_pieces,
+                                                              (const unsigned short*)q_pieces, Out, ldo, tiles_n,
+                                                              remap, total, q_upper);
+  timer_end(g_timer_ctx, tmr);
+  return check_launch("rotate_pieces_kernel");
+}
+
+int rotate_split_x3(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A,
+                    int64_t lda, const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper, void* a_pieces,
+                    void* q_pieces) {
+  if (n_in % 16 != 0) return fail(SPARC_EINVAL, "rotate_split_x3: n_in=%d is not a multiple of 16", n_in);
+  if (n_in / 4 > 65535) return fail(SPARC_ESHAPE, "rotate_split_x3: n_in=%d too large", n_in);
+  switch (dt) {
+    case SPARC_R32: return rotate_x3_t<float>(s, N, n_in, n_out, (const float*)A, lda, (const double*)Q, ldq, (float*)Out, ldo, q_upper, a_pieces, q_pieces);
+    case SPARC_C64: return rotate_x3_t<cf>(s, N, n_in, n_out, (const cf*)A, lda, (const double*)Q, ldq, (cf*)Out, ldo, q_upper, a_pieces, q_pieces);
+    default: break;
+  }
+  return fail(SPARC_EINVAL, "rotate_split_x3: FP32 / complex64 blocks only");
+}
+
 int rotate(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A, int64_t lda,
            const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper) {
   switch (dt) {

@@ -191,6 +191,13 @@ int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_a, int32_t n_b, con
 //   q_upper: Q is upper triangular (entries below the diagonal are not read).
 int rotate(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A, int64_t lda,
            const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper = 0);
+// Out = A Q with split-BF16 (x3) products from pre-split operands (FP32 / complex64
+// blocks, n_in a multiple of 16): a_pieces holds N * n_in * 2 pieces of 2 bytes per
+// real part (the size of one FP32 / complex64 N x n_in block), q_pieces 2 * n_in * n_out
+// pieces per real part.
+int rotate_split_x3(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A,
+                    int64_t lda, const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper, void* a_pieces,
+                    void* q_pieces);
 
 // Dense N_s x N_s FP64 linear algebra (dense.hip); complex when cplx = true.
 //   scaled Cholesky: M = D S D with D = diag(M)^{1/2}; S = R^H R; T = D^{-1} R^{-1} (upper)

@@ -3,7 +3,8 @@
 FP32 filtered block (real at Gamma and complex at a Bloch k), reference = the oracle's
 Rayleigh-Ritz of the same rounded block in FP64.  Six products reach the accuracy of
 the native FP32 contractions; three products keep about 16 significant bits of each
-product.  The modes are refused for FP64 blocks."""
+product (x3 also rotates with split products when n_s is a multiple of 16).  The modes
+are refused for FP64 blocks."""
 import numpy as np
 import pytest
 
@@ -26,16 +27,14 @@ def ctx():
     c.close()
 
 
-def _case(cplx):
+def _case(cplx, ns):
     """A filtered block in FP64 (oracle), rounded to single precision."""
     if cplx:
         k = (0.21, -0.13, 0.3)
         cell, rng = wl.draw_cell(97, 1, (22, 20, 24), (11.0, 10.0, 12.0), 6, (0, 1), 2.6, 0)
-        ns = 40
     else:
         k = (0.0, 0.0, 0.0)
         cell, X0, rng = wl.config_cell("c1")
-        ns = 32
     grid, V, P = oracle_setup(cell, k)
     X = rng.standard_normal((grid.n_d, ns))
     if cplx:
@@ -49,9 +48,12 @@ def _case(cplx):
     return cell, k, X32, lam_ref, lmax - lmin
 
 
-@pytest.mark.parametrize("cplx", [False, True], ids=["r32", "c64"])
-def test_split_bf16_ritz_values(ctx, cplx):
-    cell, k, X32, lam_ref, width = _case(cplx)
+@pytest.mark.parametrize("cplx,ns", [(False, 32), (True, 48), (False, 40), (True, 40)],
+                         ids=["r32", "c64", "r32-ns40", "c64-ns40"])
+def test_split_bf16_ritz_values(ctx, cplx, ns):
+    """n_s a multiple of 16: the x3 mode also rotates with split-BF16 products from
+    pre-split pieces; n_s = 40: its rotations fall back to FP32 MFMA."""
+    cell, k, X32, lam_ref, width = _case(cplx, ns)
     dt = sp.C64 if cplx else sp.R32
     ham = sp.Hamiltonian(ctx, cell, dt, kpt=k)
     ns = X32.shape[1]
@@ -64,7 +66,7 @@ def test_split_bf16_ritz_values(ctx, cplx):
         err[name] = float(np.abs(lam - lam_ref).max() / width)
         Xo = block_to_oracle(X).astype(np.complex128 if cplx else np.float64)
         orth[name] = float(np.abs(Xo.conj().T @ Xo - np.eye(ns)).max())
-        print(f"{'c64' if cplx else 'r32'} {name}: max |dritz| / spectral width {err[name]:.2e}, "
+        print(f"{'c64' if cplx else 'r32'} n_s={ns} {name}: max |dritz| / spectral width {err[name]:.2e}, "
               f"orthonormality {orth[name]:.2e}")
     assert err["native"] < 1e-5
     assert err["x6"] < 3 * err["native"] + 1e-7
