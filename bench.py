@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "filtered grid-pt·states/s FP64 vs mixed; SCF wall time to 1e-5 Ha/atom"
+RR_MODES = {"native": 0, "bf16x3": 1, "bf16x6": 2}
 
 # HBM traffic of the FP64 c2 stencil-step launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hstep_c2_96cubed_f64.md);
@@ -274,7 +275,8 @@ def run_gamma(args, sp, wl):
     v0 = wl.lanczos_start(rng, cell.n_d)
     log(f"[bench] {args.config}: n={cell.n} N_s={cell.n_s} m={cell.degree}")
     ctx = sp.Context(0)
-    main = gamma_leg(sp, ctx, cell, X0, v0, args.precision, args.steps, args.warmup, args.precision)
+    main = gamma_leg(sp, ctx, cell, X0, v0, args.precision, args.steps, args.warmup, args.precision,
+                     rr_mode=RR_MODES[args.rr])
     nd, ns = cell.n_d, cell.n_s
     result = {
         "metric": METRIC, "value": main["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -347,7 +349,7 @@ def run_gamma(args, sp, wl):
 # batched problems (c3: k-points of one cell; c4: uneven independent cells)
 
 
-def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None):
+def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None, rr_mode=0):
     """probs: list of (cell, kpt, X0, v0, weight).  Step = batched graph filter +
     Rayleigh-Ritz of every problem + (k-point batch) Fermi level and density."""
     import torch
@@ -389,7 +391,7 @@ def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None):
         plan.run([b[0] for b in bounds], [b[1] for b in bounds])
         if timed:
             ev[1].record()
-        sp.rayleigh_ritz_batched(ctx, hams, Xs, ritz, sp.GEMM_NATIVE, wr)
+        sp.rayleigh_ritz_batched(ctx, hams, Xs, ritz, rr_mode, wr)
         if kb:
             lam = torch.stack(ritz)
             sp.sparc_fermi(ctx, lam, wk, n_elec_k, 0.01, occ)
@@ -450,8 +452,9 @@ def run_batched(args, sp, wl):
                 f"in one batched stencil launch per step, HIP-graph-captured; step = filter + Rayleigh-Ritz per "
                 f"k-point + Fermi + density")
         n_elec = cell.n_elec
-        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, n_elec)
-        cfg = {"workload": desc, "n_d": cell.n_d, "n_s": cell.n_s, "degree": cell.degree, "n_k": 8}
+        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, n_elec, RR_MODES[args.rr])
+        cfg = {"workload": desc, "n_d": cell.n_d, "n_s": cell.n_s, "degree": cell.degree, "n_k": 8,
+               "rr_contractions": args.rr}
     else:
         cells = wl.uneven_cells(24)
         probs = [(c, None, X, wl.lanczos_start(r, c.n_d), 1.0) for c, X, r in cells]
@@ -459,8 +462,8 @@ def run_batched(args, sp, wl):
         desc = (f"c4: 24 independent periodic cells, grids {sorted(set(sizes))}^3 (h=0.5 bohr), atoms 8-48, "
                 f"N_s 32-256, degree 16-24 by size; every cell in one batched stencil launch per step, "
                 f"HIP-graph-captured; step = filter + Rayleigh-Ritz of every cell")
-        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, None)
-        cfg = {"workload": desc, "n_cells": 24, "grid_sizes": sizes,
+        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, None, RR_MODES[args.rr])
+        cfg = {"workload": desc, "n_cells": 24, "grid_sizes": sizes, "rr_contractions": args.rr,
                "total_point_states": int(sum(c.n_d * c.n_s for c, _, _ in cells))}
     ctx.close()
     return {"metric": METRIC, "value": res["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -520,11 +523,16 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--rr", default="native", choices=list(RR_MODES),
+                    help="Rayleigh-Ritz contractions of the --precision mixed form: FP32 MFMA or split-BF16")
     ap.add_argument("--no-scf", action="store_true")
     ap.add_argument("--cpu-orbitals", type=int, default=4)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
+    if args.rr != "native" and args.precision != "mixed":
+        print("--rr applies to --precision mixed only (FP64 blocks use FP64 MFMA)", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding the path over several "
               "GPUs is not implemented.", file=sys.stderr)
