@@ -36,7 +36,8 @@ def ctx():
 
 def _cells():
     """(name, cell): overlapping pseudocharges in a cube; a drawn cell with ragged tiles;
-    the drawn cell as a slab (zero Dirichlet along z); one atom near a corner."""
+    the drawn cell as a slab (zero Dirichlet along z) and as a wire (along x and y); one
+    atom near a corner."""
     out = []
     c1 = wl.Cell(n=(24, 24, 24), L=(9.0, 9.0, 9.0),
                  positions=np.array([[1.1, 2.3, 3.7], [3.9, 3.2, 4.6], [6.0, 6.9, 1.5]]),
@@ -48,6 +49,7 @@ def _cells():
     out.append(("drawn4", c2))
     c3 = wl.Cell(**{**c2.__dict__, "bc": (0, 0, 1)})
     out.append(("slab4", c3))
+    out.append(("wire4", wl.Cell(**{**c2.__dict__, "bc": (1, 1, 0)})))
     c4 = wl.Cell(**{**c1.__dict__, "positions": np.array([[0.05, 8.93, 0.11]]), "Z": np.array([2.0]),
                     "depth": np.zeros(1), "width": np.ones(1), "psd_rc": np.array([2.5]),
                     "psd_rc_ref": np.array([1.2])})
@@ -82,7 +84,7 @@ def test_boxes_and_pseudocharge_match_oracle(ctx, name, cell):
         assert abs(grid.dV * float(got["b"].sum()) + cell.Z.sum()) < 1e-8 * cell.Z.sum()
 
 
-@pytest.mark.parametrize("name,cell", _cells()[:3], ids=[c[0] for c in _cells()[:3]])
+@pytest.mark.parametrize("name,cell", _cells()[:4], ids=[c[0] for c in _cells()[:4]])
 def test_psd_forces_match_oracle(ctx, name, cell):
     grid, bx, bxr, st = _oracle(cell)
     rng = np.random.default_rng(7)
