@@ -349,7 +349,7 @@ def run_gamma(args, sp, wl):
 # batched problems (c3: k-points of one cell; c4: uneven independent cells)
 
 
-def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None, rr_mode=0):
+def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None, rr_mode=0, autotune=True):
     """probs: list of (cell, kpt, X0, v0, weight).  Step = batched graph filter +
     Rayleigh-Ritz of every problem + (k-point batch) Fermi level and density."""
     import torch
@@ -360,7 +360,7 @@ def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None, rr_mode
     else:
         dt = sp.R64 if precision == "f64" else sp.R32
         tdt = torch.float64 if precision == "f64" else torch.float32
-    sp.set_autotune(ctx, True)   # the plan times every tile shape on the largest problem
+    sp.set_autotune(ctx, autotune)   # the plan times every tile shape on the largest problem
     hams, Xs, bounds, ritz = [], [], [], []
     for cell, k, X0, v0, _ in probs:
         kk = k if k is not None else (0.0, 0.0, 0.0)
@@ -452,7 +452,8 @@ def run_batched(args, sp, wl):
                 f"in one batched stencil launch per step, HIP-graph-captured; step = filter + Rayleigh-Ritz per "
                 f"k-point + Fermi + density")
         n_elec = cell.n_elec
-        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, n_elec, RR_MODES[args.rr])
+        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, n_elec, RR_MODES[args.rr],
+                          not args.no_autotune)
         cfg = {"workload": desc, "n_d": cell.n_d, "n_s": cell.n_s, "degree": cell.degree, "n_k": 8,
                "rr_contractions": args.rr}
     else:
@@ -462,7 +463,8 @@ def run_batched(args, sp, wl):
         desc = (f"c4: 24 independent periodic cells, grids {sorted(set(sizes))}^3 (h=0.5 bohr), atoms 8-48, "
                 f"N_s 32-256, degree 16-24 by size; every cell in one batched stencil launch per step, "
                 f"HIP-graph-captured; step = filter + Rayleigh-Ritz of every cell")
-        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, None, RR_MODES[args.rr])
+        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, None, RR_MODES[args.rr],
+                          not args.no_autotune)
         cfg = {"workload": desc, "n_cells": 24, "grid_sizes": sizes, "rr_contractions": args.rr,
                "total_point_states": int(sum(c.n_d * c.n_s for c, _, _ in cells))}
     ctx.close()
@@ -523,6 +525,8 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched configs: keep the heuristic stencil tile instead of timing every shape")
     ap.add_argument("--rr", default="native", choices=list(RR_MODES),
                     help="Rayleigh-Ritz contractions of the --precision mixed form: FP32 MFMA or split-BF16")
     ap.add_argument("--no-scf", action="store_true")
