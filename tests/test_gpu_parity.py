@@ -51,6 +51,11 @@ CASES = [
     ("multiwrap", (5, 6, 9), (2.5, 3.0, 4.5), 6, (0.9, 0.4, -0.7), sp.C128, (0,), 1.2, 2, 3, 1),
     ("no1_single", (16, 16, 16), (8.0, 8.0, 8.0), 1, (0, 0, 0), sp.R64, (0,), 2.5, 2, 1, 0),
     ("wide48_k", (48, 40, 33), (24.0, 20.0, 16.5), 6, (0.1, 0.05, -0.08), sp.C128, (0, 1), 3.0, 5, 7, 0),
+    # long z with few states: the launch splits z into 4 chunks of 25, 25, 25, 23 planes
+    # (n_o = 6), so chunk edges, the z halo across them and the Bloch wraps of the first
+    # and last chunk are all exercised
+    ("zchunk_no6_k", (16, 16, 98), (8.0, 8.0, 49.0), 6, (0.1, -0.2, 0.35), sp.C128, (0, 1), 2.5, 3, 3, 0),
+    ("zchunk_no6_r", (16, 16, 98), (8.0, 8.0, 49.0), 6, (0, 0, 0), sp.R64, (0, 1), 2.5, 3, 3, 2),
 ]
 
 
@@ -119,6 +124,23 @@ def test_filter_parity_bloch(ctx, degree):
     sp.chebyshev_filter(ham, X, degree, 1.0, 60.0, sp.workspace(ham, 4, sp.OP_FILTER))
     Yref = cheb_filter(Xh.T, grid, V, P, degree, 1.0, 60.0)
     assert colnorm_err(block_to_oracle(X), Yref) < 1e-11
+
+
+@pytest.mark.parametrize("dt", [sp.C128, sp.R64])
+def test_filter_parity_zchunked(ctx, dt):
+    """Filter of degree 6 on the z-chunked n_o = 6 grid (4 z chunks per orbital)."""
+    cplx = dt == sp.C128
+    k = (0.1, -0.2, 0.35) if cplx else (0.0, 0.0, 0.0)
+    cell, rng = _cell((16, 16, 98), (8.0, 8.0, 49.0), 3, (0, 1), 2.5, 6)
+    grid, V, P = oracle_setup(cell, k)
+    Xh = _xblock(rng, grid.n_d, 3, cplx)
+    ham = sp.Hamiltonian(ctx, cell, dt, kpt=k)
+    X = to_dev(Xh)
+    sp.chebyshev_filter(ham, X, 6, 2.0, 60.0, sp.workspace(ham, 3, sp.OP_FILTER))
+    Yref = cheb_filter(Xh.T, grid, V, P, 6, 2.0, 60.0)
+    err = colnorm_err(block_to_oracle(X), Yref)
+    print(f"z-chunked filter dtype={dt}: colnorm err {err:.2e}")
+    assert err < 1e-11
 
 
 def test_lanczos_parity_c1(ctx):

@@ -90,7 +90,9 @@ def test_split_modes_refused_for_fp64(ctx):
 def test_batched_split_x3_matches_native(ctx):
     """rayleigh_ritz_batched over three Bloch k-points of one complex64 cell (n_s = 48,
     so the x3 rotations use pre-split pieces): Ritz values with x3 contractions within
-    1e-3 of the spectral width of the native FP32 ones, each k against its own."""
+    1e-4 of the spectral width of the native FP32 ones (about 16 significant bits per
+    product; a dropped cross term costs about 2^-8), each k against its own, and
+    orthonormal within 1e-4."""
     cell, rng = wl.draw_cell(97, 2, (20, 22, 18), (10.0, 11.0, 9.0), 5, (0, 1), 2.6, 0)
     ks = [(0.1, -0.2, 0.15), (0.0, 0.3, -0.1), (-0.25, 0.05, 0.2)]
     ns = 48
@@ -107,8 +109,8 @@ def test_batched_split_x3_matches_native(ctx):
         out[name] = np.stack([r.cpu().numpy() for r in ritz])
         for X in Xs:
             Xo = block_to_oracle(X).astype(np.complex128)
-            assert np.abs(Xo.conj().T @ Xo - np.eye(ns)).max() < 1e-3
+            assert np.abs(Xo.conj().T @ Xo - np.eye(ns)).max() < 1e-4
     width = np.ptp(out["native"], axis=1).max()
     err = np.abs(out["x3"] - out["native"]).max() / width
     print(f"batched c64 x3 vs native: max |dritz| / width {err:.2e}")
-    assert err < 1e-3
+    assert err < 1e-4

@@ -9,7 +9,7 @@ import pytest
 
 from oracle.fd import Grid, minus_half_laplacian
 from oracle.scf import (occupations, fermi_level, density, poisson, slater, entropy_term,
-                        harris_foulkes, sad_density, scf)
+                        harris_foulkes, sad_density, anderson_update, scf)
 from oracle.chefsi import rayleigh_ritz
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -146,6 +146,94 @@ def test_sad_normalisation():
     rho = sad_density(grid, R, [0.9, 1.2], [2.0, 2.0], 4.0)
     assert grid.dV * rho.sum() == pytest.approx(4.0, rel=1e-13)
     assert np.all(rho >= 0)
+
+
+def test_sad_brute_force_image_sum():
+    """The superposition of atomic densities at sampled nodes against a brute-force
+    sum over 7^3 periodic images of the closed-form normalised Gaussian
+    Z (2 pi w^2)^{-3/2} exp(-r^2 / (2 w^2)), no cutoff.  The widths are resolved by
+    the grid (w/h >= 1.8), so the node sum of each image-summed Gaussian is Z to
+    e^{-2 pi^2 w^2 / h^2} < 1e-25 (Poisson summation), and the renormalisation to N_e
+    is the factor N_e / sum Z.  Atoms at a corner and on faces make the images count;
+    a wrong width convention, a dropped image or a per-atom amplitude error fails."""
+    grid = Grid(n=(18, 16, 20), L=(9.0, 8.0, 10.0))
+    R = np.array([[0.1, 0.2, 9.8], [4.5, 7.9, 5.0], [8.8, 3.0, 0.05]])
+    w = np.array([0.9, 1.2, 1.4])
+    Z = np.array([2.0, 3.0, 1.0])
+    ne = 7.5
+    rho = sad_density(grid, R, w, Z, ne)
+    rng = np.random.default_rng(12)
+    nodes = np.concatenate([rng.integers(0, grid.n_d, 40), [0, grid.n_d - 1]])
+    X = grid.coords()[nodes]
+    ref = np.zeros(len(nodes))
+    for J in range(3):
+        for a in range(-3, 4):
+            for b in range(-3, 4):
+                for c in range(-3, 4):
+                    d = X - R[J] - np.array([a * 9.0, b * 8.0, c * 10.0])
+                    r2 = np.sum(d * d, axis=1)
+                    ref += Z[J] * (2 * math.pi * w[J] ** 2) ** -1.5 * np.exp(-r2 / (2 * w[J] ** 2))
+    ref *= ne / Z.sum()
+    np.testing.assert_allclose(rho[nodes], ref, rtol=1e-12, atol=1e-14 * ref.max())
+
+
+def test_anderson_linear_map_terminates():
+    """For a linear fixed-point map x -> M x + c, Anderson extrapolation with a
+    history at least the dimension minimises the residual over the affine span of
+    all iterates, which is the Krylov space of GMRES (Walker and Ni, 2011): the
+    iterate reaches the fixed point after d + 1 residual evaluations, for any
+    relaxation.  A sign error, a dropped dX gamma term or a misaligned history
+    breaks the finite termination."""
+    rng = np.random.default_rng(1)
+    d = 6
+    M = rng.standard_normal((d, d))
+    M *= 0.9 / np.max(np.abs(np.linalg.eigvals(M)))
+    c = rng.standard_normal(d)
+    xs = np.linalg.solve(np.eye(d) - M, c)
+    for beta in (0.3, 1.0):
+        x = np.zeros(d)
+        hx, hf = [], []
+        errs = []
+        for _ in range(d + 1):
+            x = anderson_update(x, M @ x + c - x, hx, hf, beta, d)
+            errs.append(np.linalg.norm(x - xs))
+        assert errs[-1] < 1e-10 * np.linalg.norm(xs)
+        assert errs[-2] > 1e-6
+    # m = 0 is plain linear mixing
+    x = rng.standard_normal(d)
+    f = M @ x + c - x
+    np.testing.assert_array_equal(anderson_update(x, f, [], [], 0.3, 0), x + 0.3 * f)
+
+
+def test_anderson_constrained_form():
+    """Anderson's original form: the extrapolated point is sum_i a_i x_i over the
+    last m + 1 iterates with sum_i a_i = 1 and a minimising ||sum_i a_i f_i||, then
+    relaxed by beta times that residual combination.  Solved here through its
+    KKT system on a nonlinear map, step by step with history m = 3 (so the window
+    slides), against anderson_update."""
+    rng = np.random.default_rng(4)
+    d, m, beta = 8, 3, 0.4
+    A = rng.standard_normal((d, d)) / 3.0
+    c = rng.standard_normal(d)
+    g = lambda x: np.tanh(A @ x) + c
+    x = rng.standard_normal(d)
+    hx, hf, xs, fs = [], [], [], []
+    for step in range(8):
+        f = g(x) - x
+        xs.append(x.copy())
+        fs.append(f.copy())
+        Xw, Fw = np.array(xs[-(m + 1):]).T, np.array(fs[-(m + 1):]).T
+        k = Xw.shape[1]
+        K = np.zeros((k + 1, k + 1))
+        K[:k, :k] = 2.0 * Fw.T @ Fw
+        K[:k, k] = 1.0
+        K[k, :k] = 1.0
+        rhs = np.zeros(k + 1)
+        rhs[k] = 1.0
+        a = np.linalg.lstsq(K, rhs, rcond=None)[0][:k]
+        ref = Xw @ a + beta * (Fw @ a)
+        x = anderson_update(x, f, hx, hf, beta, m)
+        np.testing.assert_allclose(x, ref, rtol=1e-9, atol=1e-11)
 
 
 @pytest.mark.slow
