@@ -49,22 +49,98 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cell, X0, degree, lcut, lmax, n_orb, kpt=(0.0, 0.0, 0.0)):
-    """The oracle's filter on a bounded sample (n_orb orbitals), single thread."""
+def cpu_cores():
+    """Host cores for the oracle timing: the process's CPU affinity, capped at 16 (the
+    CPU share of one GPU on the box)."""
+    return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+_CPU = {}   # the oracle's inputs, inherited by the forked worker processes of cpu_baseline
+
+
+def _cpu_filter_cols(ab):
+    """Worker: the oracle's filter on orbitals a..b-1, one orbital at a time."""
+    from threadpoolctl import threadpool_limits
+    from oracle.chefsi import cheb_filter
+    d = _CPU
+    with threadpool_limits(1):
+        for c in range(ab[0], ab[1]):
+            cheb_filter(np.ascontiguousarray(d["X0"][c:c + 1].T), d["grid"], d["V"], d["P"], d["degree"],
+                        d["lcut"], d["lmax"])
+    return ab
+
+
+def _cpu_apply_cols(ab):
+    """Worker: the oracle's H on columns a..b-1 of the shared block Q."""
+    from threadpoolctl import threadpool_limits
+    from oracle.fd import apply_H
+    d = _CPU
+    Q = np.frombuffer(d["q_shm"].buf, dtype=np.float64).reshape(d["shape"])
+    Y = np.frombuffer(d["y_shm"].buf, dtype=np.float64).reshape(d["shape"])
+    with threadpool_limits(1):
+        for c in range(ab[0], ab[1]):
+            Y[:, c] = apply_H(np.ascontiguousarray(Q[:, c:c + 1]), d["grid"], d["V"], d["P"])[:, 0]
+    return ab
+
+
+def cpu_baseline(cell, X0, v0, cols=32):
+    """One CheFSI pass of the oracle on the host cores, on a bounded sample of the block.
+
+    Runs before the process touches the GPU, so that its worker processes can be forked
+    (one per core, numpy single-threaded in each).  Bounds: the oracle's Lanczos from
+    the same start vector.  Filter: `cols` orbitals split over the workers, one orbital
+    per oracle call, timed; orbitals are independent, so the full-block filter time is
+    that time scaled by N_s / cols.  Rayleigh-Ritz: the oracle's Householder QR and
+    eigh (BLAS on all cores) with H Q applied column by column by the workers, timed in
+    full on the whole N_d x N_s block."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
     from threadpoolctl import threadpool_limits
     from oracle.fd import Grid
     from oracle.cell import local_potential, projectors
-    from oracle.chefsi import cheb_filter
+    from oracle.chefsi import lanczos_bounds, rayleigh_ritz
 
-    with threadpool_limits(1):
-        grid = Grid(n=cell.n, L=cell.L, k=tuple(kpt))
-        V = local_potential(grid, cell.positions, cell.depth, cell.width)
-        P = projectors(grid, cell.positions, cell.chan_atom, cell.chan_l, cell.chan_gamma, cell.chan_rc)
-        X = np.ascontiguousarray(X0[:n_orb].T)
-        t0 = time.perf_counter()
-        cheb_filter(X, grid, V, P, degree, lcut, lmax)
-        dt = time.perf_counter() - t0
-    return dt
+    cores = cpu_cores()
+    grid = Grid(n=cell.n, L=cell.L)
+    V = local_potential(grid, cell.positions, cell.depth, cell.width)
+    P = projectors(grid, cell.positions, cell.chan_atom, cell.chan_l, cell.chan_gamma, cell.chan_rc)
+    ns, nd = X0.shape
+    t0 = time.perf_counter()
+    lmin, lmax = lanczos_bounds(grid, V, P, v0, 20)
+    t_lz = time.perf_counter() - t0
+    _CPU.update(grid=grid, V=V, P=P, X0=X0, degree=cell.degree, lcut=0.5 * (lmin + lmax), lmax=lmax)
+
+    def parts(a, b):
+        e = [a + round(i * (b - a) / cores) for i in range(cores + 1)]
+        return [(e[i], e[i + 1]) for i in range(cores) if e[i + 1] > e[i]]
+
+    shm = [shared_memory.SharedMemory(create=True, size=nd * ns * 8) for _ in range(2)]
+    try:
+        _CPU.update(q_shm=shm[0], y_shm=shm[1], shape=(nd, ns))
+        with mp.get_context("fork").Pool(cores) as pool:
+            t0 = time.perf_counter()
+            pool.map(_cpu_filter_cols, parts(0, cols))
+            t_f = time.perf_counter() - t0
+            log(f"[bench] cpu baseline: filter of {cols} orbitals on {cores} cores: {t_f:.1f} s")
+
+            def apply(Q):
+                np.frombuffer(shm[0].buf, dtype=np.float64).reshape(nd, ns)[:] = Q
+                pool.map(_cpu_apply_cols, parts(0, Q.shape[1]))
+                return np.frombuffer(shm[1].buf, dtype=np.float64).reshape(nd, ns).copy()
+
+            Xf = np.ascontiguousarray(X0.T)
+            with threadpool_limits(cores):
+                t0 = time.perf_counter()
+                rayleigh_ritz(Xf, grid, V, P, apply=apply)
+                t_rr = time.perf_counter() - t0
+            log(f"[bench] cpu baseline: Rayleigh-Ritz of the {nd} x {ns} block: {t_rr:.1f} s")
+    finally:
+        _CPU.clear()
+        for m in shm:
+            m.close()
+            m.unlink()
+    return {"cores": cores, "filter_s_sample": t_f, "filter_cols": cols, "rr_s": t_rr, "lanczos_s": t_lz,
+            "pass_s": t_f * ns / cols + t_rr}
 
 
 def step_bytes(n_d, n_s, eb, degree):
@@ -170,6 +246,46 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label, rr_mode=0)
     }
 
 
+def mixed_job_leg(sp, ctx, cell, X0, v0, steps, warmup, rr_mode=0):
+    """The mixed-precision form as a whole job with its FP64 correction: from the same
+    start as the FP64 form, warmup + steps passes, of which the timed part is steps - 1
+    passes with the FP32 filter and FP32 (or split-BF16) Rayleigh-Ritz contractions,
+    then the orbitals promoted to FP64 and one FP64 filter + Rayleigh-Ritz pass (every
+    pass followed by the Fermi level and the density)."""
+    import torch
+    h32 = sp.Hamiltonian(ctx, cell, sp.R32)
+    h64 = sp.Hamiltonian(ctx, cell, sp.R64)
+    ns, nd = cell.n_s, cell.n_d
+    X32 = torch.from_numpy(X0).to("cuda:0").to(torch.float32)
+    X64 = torch.empty(X0.shape, dtype=torch.float64, device="cuda:0")
+    w = {d: (sp.workspace(h, ns, sp.OP_FILTER), sp.workspace(h, ns, sp.OP_RR)) for d, h in ((32, h32), (64, h64))}
+    ritz = torch.zeros(ns, dtype=torch.float64, device="cuda:0")
+    occ = torch.zeros(1, ns, dtype=torch.float64, device="cuda:0")
+    rho = torch.zeros(nd, dtype=torch.float64, device="cuda:0")
+    lmin, lmax = sp.lanczos_bounds(h64, torch.from_numpy(v0).to("cuda:0"), 20, sp.workspace(h64, 20, sp.OP_LANCZOS))
+    state = {"lcut": 0.5 * (lmin + lmax)}
+
+    def one_pass(h, X, dt, ws, mode):
+        sp.chebyshev_filter(h, X, cell.degree, state["lcut"], lmax, ws[0])
+        sp.rayleigh_ritz(h, X, ritz, ws[1], mode)
+        sp.sparc_fermi(ctx, ritz.view(1, ns), [1.0], float(cell.n_elec), 0.01, occ)
+        sp.density_from_orbitals(ctx, [X], occ, h.dV, rho, dt)
+        state["lcut"] = float(ritz[-1])
+
+    for _ in range(warmup):
+        one_pass(h32, X32, sp.R32, w[32], rr_mode)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps - 1):
+        one_pass(h32, X32, sp.R32, w[32], rr_mode)
+    X64.copy_(X32)
+    one_pass(h64, X64, sp.R64, w[64], sp.GEMM_NATIVE)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    log(f"[bench] mixed job ({steps - 1} mixed passes + 1 FP64 pass): {1e3 * t:.1f} ms")
+    return {"job_ms": 1e3 * t, "passes": steps, "value": nd * ns * steps / t, "ritz": ritz.cpu().numpy()}
+
+
 def forces_leg(sp, ctx, ham, cell, X, occ, rho, reps=3):
     """Atomic forces on the state of the last step (local part on its density,
     non-local part on its orbitals and occupations): kernel times (HIP events on
@@ -230,12 +346,15 @@ def pseudocharge_leg(sp, ctx, cell, rho, reps=3):
                      "force kernel the FD gradients of b and b~ at every node of every image box")}
 
 
-def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False):
+def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False, e_ref=None):
     """Plain SCF (Slater exchange, CG Poisson, Anderson mixing) on a held-out 40^3
     cell: wall time, iterations, free energy.  Started from the atomic superposition,
     or (learned=True) from the trained density network's prediction, whose
     inference time is included in the wall time.  pseudocharge=True runs the
-    pseudocharge electrostatics (set-up included in the wall time) instead of jellium."""
+    pseudocharge electrostatics (set-up included in the wall time) instead of jellium.
+    With e_ref (a reference free energy), also the wall time to 1e-5 Ha/atom: the time
+    stamp of the first iteration from which every later Harris-Foulkes free energy stays
+    within 1e-5 Ha/atom of e_ref (per-iteration stamps of the library's history)."""
     import torch
     from paper_1603_04339_amd import workloads as wl
     from paper_1603_04339_amd.train_density_net import CHARGE_TOL, DEFAULT_WEIGHTS, FIRST_PASSES, cell_dV, cell_start
@@ -258,21 +377,32 @@ def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False):
                filt=sp.R64 if precision == "f64" else sp.R32, rr=sp.GEMM_NATIVE, final_fp64_pass=1,
                rho_init_dev=rho0, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda(),
                electrostatics=sp.ELEC_PSEUDOCHARGE if pseudocharge else sp.ELEC_JELLIUM, eps_b=1e-8)
+    torch.cuda.synchronize()
+    t_call = time.perf_counter() - t0
     out = sp.sparc_scf_run(ctx, cell, prm, rho, ritz)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     r = {"wall_s": wall, "iterations": out["iterations"], "converged": bool(out["converged"]),
          "energy": out["energy"], "n_atoms": cell.n_atoms, "grid": list(cell.n), "n_s": cell.n_s, "tol": tol}
+    hist = out["history"]
+    if e_ref is not None and len(hist):
+        ok = np.abs(hist[:, 0] - e_ref) <= 1e-5 * cell.n_atoms
+        bad = np.nonzero(~ok)[0]
+        i = int(bad[-1]) + 1 if len(bad) else 0
+        if i < len(hist):
+            r["wall_s_to_1e-5_Ha_per_atom"] = t_call + float(hist[i, 2])
+            r["iterations_to_1e-5_Ha_per_atom"] = i + 1
+        else:
+            r["wall_s_to_1e-5_Ha_per_atom"] = None
+            r["iterations_to_1e-5_Ha_per_atom"] = None
     if net is not None:
         r["net_used"] = used
         net.close()
     return r
 
 
-def run_gamma(args, sp, wl):
+def run_gamma(args, sp, wl, cell, X0, v0, cpu=None):
     import torch
-    cell, X0, rng = wl.config_cell(args.config)
-    v0 = wl.lanczos_start(rng, cell.n_d)
     log(f"[bench] {args.config}: n={cell.n} N_s={cell.n_s} m={cell.degree}")
     ctx = sp.Context(0)
     main = gamma_leg(sp, ctx, cell, X0, v0, args.precision, args.steps, args.warmup, args.precision,
@@ -310,6 +440,17 @@ def run_gamma(args, sp, wl):
             "note": (f"FP32 filter and FP32 MFMA Gram/rotation with FP64 Cholesky-QR and eigensolve; both forms "
                      f"from the same start after {args.warmup + args.steps} passes; {n_occ} occupied states"),
         }
+        for nm, md in (("fp32", sp.GEMM_NATIVE), ("bf16x3", sp.GEMM_BF16X3)):
+            jb = mixed_job_leg(sp, ctx, cell, X0, v0, args.steps, args.warmup, md)
+            d = np.abs(jb["ritz"][:n_occ] - main["ritz"][:n_occ])
+            result["mixed"]["job_with_final_fp64_pass_" + nm] = {
+                "value": jb["value"], "job_ms": jb["job_ms"], "passes": jb["passes"],
+                "speedup_vs_f64": jb["value"] / main["value"],
+                "ritz_max_abs_diff_vs_f64_occupied": float(d.max()),
+                "note": (f"{args.steps} timed passes from the same start as the FP64 form: {args.steps - 1} with the "
+                         f"FP32 filter and {nm} Rayleigh-Ritz contractions, then the final FP64 filter + "
+                         f"Rayleigh-Ritz pass on the promoted orbitals; Ritz values compared with the FP64 form "
+                         f"after the same number of passes")}
         for nm, md in (("bf16x3", sp.GEMM_BF16X3), ("bf16x6", sp.GEMM_BF16X6)):
             sx = gamma_leg(sp, ctx, cell, X0, v0, "mixed", args.steps, args.warmup, "mixed-" + nm, rr_mode=md)
             d = np.abs(sx["ritz"][:n_occ] - main["ritz"][:n_occ])
@@ -321,25 +462,43 @@ def run_gamma(args, sp, wl):
                          + ("; the rotations too, from pre-split pieces" if nm == "bf16x3" else ""))}
     if not args.no_scf:
         from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS
-        s64 = scf_leg(sp, ctx, "f64")
-        s32 = scf_leg(sp, ctx, "mixed")
-        result["scf"] = {"f64": s64, "mixed": s32,
-                         "mixed_energy_diff_per_atom": abs(s32["energy"] - s64["energy"]) / s64["n_atoms"],
-                         "note": "40^3 SCF cell (held-out seed), atomic-superposition start, density residual tol"}
+        ref = scf_leg(sp, ctx, "f64", tol=1e-9)
+        e_ref = ref["energy"] if ref["converged"] else None
+        s64 = scf_leg(sp, ctx, "f64", e_ref=e_ref)
+        s32 = scf_leg(sp, ctx, "mixed", e_ref=e_ref)
+        result["scf"] = {
+            "f64": s64, "mixed": s32, "reference": {"energy": ref["energy"], "converged": ref["converged"],
+                                                   "iterations": ref["iterations"], "tol": 1e-9},
+            "mixed_energy_diff_per_atom": abs(s32["energy"] - s64["energy"]) / s64["n_atoms"],
+            "note": ("40^3 SCF cell (held-out seed), atomic-superposition start; wall_s: to the density residual "
+                     "tol; wall_s_to_1e-5_Ha_per_atom: to the first iteration from which the Harris-Foulkes free "
+                     "energy stays within 1e-5 Ha/atom of the FP64 SCF converged to a residual of 1e-9")}
         result["scf"]["pseudocharge_f64"] = scf_leg(sp, ctx, "f64", pseudocharge=True)
         if os.path.exists(DEFAULT_WEIGHTS):
-            sl = scf_leg(sp, ctx, "f64", learned=True)
+            sl = scf_leg(sp, ctx, "f64", learned=True, e_ref=e_ref)
             result["scf"]["learned_f64"] = sl
             result["scf"]["learned_energy_diff_per_atom"] = abs(sl["energy"] - s64["energy"]) / s64["n_atoms"]
-    if not args.no_cpu_baseline:
-        k = args.cpu_orbitals
-        log(f"[bench] cpu baseline: oracle filter on {k} orbitals ...")
-        lmin, lmax = main["bounds"]
-        dtc = cpu_baseline(cell, X0, cell.degree, 0.5 * (lmin + lmax), lmax, k)
+    if args.config == "c2" and not args.no_batched:
+        # the batched configurations, summarised beside the headline (FP64 and mixed)
+        for name in ("c3", "c4"):
+            for prec in ("f64", "mixed"):
+                log(f"[bench] batched {name} {prec} ...")
+                res, cfg = batched_config(args, sp, wl, ctx, name, prec, min(args.steps, 3), 1)
+                result.setdefault("batched", {})[f"{name}_{prec}"] = {
+                    "value": res["value"], "unit": UNIT, "ms_per_step": res["ms_per_step"], "steps": min(args.steps, 3),
+                    "filter_ms": res["filter_ms"], "filter_throughput": res["filter_throughput"],
+                    "dtype": res["dtype"], "roofline": res["roofline"], "workload": cfg["workload"]}
+    if cpu is not None:
         result["cpu_baseline"] = {
-            "value": nd * k / dtc, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": (f"oracle Chebyshev filter (degree {cell.degree}) on {k} of the {ns} orbitals of the same "
-                       f"cell, numpy FP64, one thread, {dtc:.1f} s; Rayleigh-Ritz not included"),
+            "value": nd * ns / cpu["pass_s"], "unit": UNIT, "cores": cpu["cores"], "kind": "oracle",
+            "pass_s": cpu["pass_s"], "filter_s_sample": cpu["filter_s_sample"], "rr_s": cpu["rr_s"],
+            "sample": (f"one {args.config} CheFSI pass of the numpy FP64 oracle on {cpu['cores']} host cores: "
+                       f"Chebyshev filter (degree {cell.degree}) timed on {cpu['filter_cols']} of the {ns} orbitals "
+                       f"(one worker process per core, one orbital per oracle call; "
+                       f"{cpu['filter_s_sample']:.1f} s) and scaled by {ns / cpu['filter_cols']:g} (orbitals are "
+                       f"independent); Rayleigh-Ritz (Householder QR and eigh with BLAS on all cores, H Q column by "
+                       f"column in the workers) timed in full on the {nd} x {ns} block ({cpu['rr_s']:.1f} s); "
+                       f"the oracle is the parity reference, not a tuned CPU code"),
         }
     ctx.close()
     return result
@@ -437,9 +596,10 @@ def batched_leg(sp, ctx, probs, precision, steps, warmup, n_elec_k=None, rr_mode
                                                                         sp.C128: "c128", sp.C64: "c64"}[dt]}
 
 
-def run_batched(args, sp, wl):
-    ctx = sp.Context(0)
-    if args.config == "c3":
+def batched_config(args, sp, wl, ctx, name, precision, steps, warmup, rr="native"):
+    """One batched configuration (c3: the 8 k-points of the 48^3 complex cell; c4: the 24
+    uneven cells): returns (leg result, config description)."""
+    if name == "c3":
         cell, X0, rng = wl.config_cell("c3", with_orbitals=False)
         ks, ws = wl.mp2_kpoints(cell.L)
         probs = []
@@ -451,11 +611,9 @@ def run_batched(args, sp, wl):
                 f"(shifted 2x2x2 Monkhorst-Pack), N_s={cell.n_s} per k-point, degree {cell.degree}; all k-points "
                 f"in one batched stencil launch per step, HIP-graph-captured; step = filter + Rayleigh-Ritz per "
                 f"k-point + Fermi + density")
-        n_elec = cell.n_elec
-        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, n_elec, RR_MODES[args.rr],
-                          not args.no_autotune)
+        res = batched_leg(sp, ctx, probs, precision, steps, warmup, cell.n_elec, RR_MODES[rr], not args.no_autotune)
         cfg = {"workload": desc, "n_d": cell.n_d, "n_s": cell.n_s, "degree": cell.degree, "n_k": 8,
-               "rr_contractions": args.rr}
+               "rr_contractions": rr}
     else:
         cells = wl.uneven_cells(24)
         probs = [(c, None, X, wl.lanczos_start(r, c.n_d), 1.0) for c, X, r in cells]
@@ -463,10 +621,15 @@ def run_batched(args, sp, wl):
         desc = (f"c4: 24 independent periodic cells, grids {sorted(set(sizes))}^3 (h=0.5 bohr), atoms 8-48, "
                 f"N_s 32-256, degree 16-24 by size; every cell in one batched stencil launch per step, "
                 f"HIP-graph-captured; step = filter + Rayleigh-Ritz of every cell")
-        res = batched_leg(sp, ctx, probs, args.precision, args.steps, args.warmup, None, RR_MODES[args.rr],
-                          not args.no_autotune)
-        cfg = {"workload": desc, "n_cells": 24, "grid_sizes": sizes, "rr_contractions": args.rr,
+        res = batched_leg(sp, ctx, probs, precision, steps, warmup, None, RR_MODES[rr], not args.no_autotune)
+        cfg = {"workload": desc, "n_cells": 24, "grid_sizes": sizes, "rr_contractions": rr,
                "total_point_states": int(sum(c.n_d * c.n_s for c, _, _ in cells))}
+    return res, cfg
+
+
+def run_batched(args, sp, wl):
+    ctx = sp.Context(0)
+    res, cfg = batched_config(args, sp, wl, ctx, args.config, args.precision, args.steps, args.warmup, args.rr)
     ctx.close()
     return {"metric": METRIC, "value": res["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
@@ -530,7 +693,10 @@ def main():
     ap.add_argument("--rr", default="native", choices=list(RR_MODES),
                     help="Rayleigh-Ritz contractions of the --precision mixed form: FP32 MFMA or split-BF16")
     ap.add_argument("--no-scf", action="store_true")
-    ap.add_argument("--cpu-orbitals", type=int, default=4)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="c2: leave out the c3 / c4 batched summaries of the default line")
+    ap.add_argument("--cpu-cols", type=int, default=32,
+                    help="orbitals on which the oracle's filter is timed for cpu_baseline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -543,9 +709,18 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1603_04339_amd import sparc as sp
     from paper_1603_04339_amd import workloads as wl
 
+    gamma_in, cpu = None, None
+    if args.config in ("c1", "c2") and not args.calib_copy:
+        cell, X0, rng = wl.config_cell(args.config)
+        gamma_in = (cell, X0, wl.lanczos_start(rng, cell.n_d))
+        if not args.no_cpu_baseline:
+            # before anything touches the GPU: the oracle's worker processes are forked
+            log(f"[bench] cpu baseline: oracle CheFSI pass on {cpu_cores()} cores ...")
+            cpu = cpu_baseline(*gamma_in, cols=args.cpu_cols)
+
+    from paper_1603_04339_amd import sparc as sp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.calib_copy:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
@@ -559,7 +734,7 @@ def main():
         return
     sp.load()
     if args.config in ("c1", "c2"):
-        result = run_gamma(args, sp, wl)
+        result = run_gamma(args, sp, wl, *gamma_in, cpu=cpu)
     elif args.config == "bands":
         result = run_bands(args, sp, wl)
     else:
