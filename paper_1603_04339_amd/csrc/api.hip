@@ -305,6 +305,9 @@ static int sub_vec(sparc_dtype dt, hipStream_t s, void* w, const void* t, int64_
   return SPARC_EINVAL;
 }
 
+// Chebyshev filter of degree m (three-term recurrence, one stencil step per degree):
+// each step projects its input onto the projectors, then the stencil step applies the
+// local and (inside the step, or with the scatter kernel after it) non-local terms.
 int filter_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n_s, int32_t degree, double lcut, double lmax,
                 void* Wb, void* alpha) {
   const double c = 0.5 * (lmax + lcut), e = 0.5 * (lmax - lcut);

@@ -1,9 +1,11 @@
 // Batched CheFSI over several (cell, k) problems: the Chebyshev filters of all
 // problems advance together, one stencil launch per recurrence step covering every
-// problem (per-problem arguments in a device table), the projector gather/scatter
-// launched per problem, and the whole sequence captured once into a HIP graph.  The
-// coefficients (which change with the filter bounds of every pass) live in device
-// tables rewritten before each replay, so the captured graph is reused unchanged.
+// problem (per-problem arguments in a device table) with the projector scatter applied
+// inside it, the projections of each step's input launched per problem, and the whole
+// sequence captured once into a HIP graph.  The coefficients (which change with the
+// filter bounds of every pass) live in device tables rewritten before each replay, so
+// the captured graph is reused unchanged.  A problem without fused tables for the
+// plan's tile shape scatters with a separate launch.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -26,6 +28,7 @@ struct sparc_filter_plan {
   int dir;   // some problem has a Dirichlet direction
   std::vector<sparc_ham*> H;
   std::vector<void*> X, W, alpha;
+  std::vector<char> fused;        // the problem applies its projectors inside the step
   std::vector<int64_t> ldx;
   std::vector<int> n_s, deg;
   // per step: participating problems, their table and work-group offsets
@@ -36,6 +39,7 @@ struct sparc_filter_plan {
   char* dev_tables;
   int* dev_wg;
   double* dev_a;                  // [max_deg][n_prob] scatter scale per step
+  std::vector<size_t> nl_lds;     // dynamic LDS of step j's launch
   std::vector<char> host_tables;
   std::vector<int> host_wg;
   std::vector<double> host_a;
@@ -61,8 +65,9 @@ static int plan_enqueue(sparc_filter_plan* P) {
       SPARC_TRY(nl_project(P->H[p], x, ld, P->n_s[p], P->alpha[p]));
     }
     SPARC_TRY(step_table_launch(P->ctx, P->dt, P->n_o, P->tile, P->dev_tables + P->table_off[j],
-                                P->dev_wg + P->wg_off[j], (int)mem.size(), P->total_wg[j], P->dir));
+                                P->dev_wg + P->wg_off[j], (int)mem.size(), P->total_wg[j], P->dir, P->nl_lds[j]));
     for (int p : mem) {
+      if (P->fused[p]) continue;
       void* out = (j % 2 == 0) ? P->W[p] : P->X[p];
       const int64_t ldo = (j % 2 == 0) ? P->H[p]->n_d : P->ldx[p];
       SPARC_TRY(nl_scatter(P->H[p], P->alpha[p], P->n_s[p], 0.0, P->dev_a + (size_t)j * P->n_prob + p, out, ldo));
@@ -102,13 +107,16 @@ static int plan_tables(sparc_filter_plan* P, const double* lcut, const double* l
         s.z = s.out; s.ldz = s.ldo;
         s.a = 2.0 / e; s.b = -2.0 * c / e; s.c = -1.0;
       }
+      s.alpha = P->fused[p] ? P->alpha[p] : nullptr;
       P->host_a[(size_t)j * P->n_prob + p] = s.a;
       d.push_back(s);
       hs.push_back(P->H[p]);
     }
+    P->nl_lds[j] = 0;
     if (d.empty()) continue;
     int64_t tot = step_table_build(hs.data(), d.data(), (int)d.size(), P->tile,
-                                   P->host_tables.data() + P->table_off[j], P->host_wg.data() + P->wg_off[j]);
+                                   P->host_tables.data() + P->table_off[j], P->host_wg.data() + P->wg_off[j],
+                                   &P->nl_lds[j]);
     if (tot < 0) return fail(SPARC_EINVAL, "filter plan: bad dtype");
     P->total_wg[j] = tot;
   }
@@ -176,6 +184,7 @@ int sparc_filter_plan_create(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H
   P->dev_wg = (int*)w;
   w += al256((size_t)P->max_deg * (n_prob + 1) * sizeof(int));
   P->dev_a = (double*)w;
+  P->nl_lds.assign(P->max_deg, 0);
   P->members.resize(P->max_deg);
   P->total_wg.assign(P->max_deg, 0);
   size_t toff = 0, woff = 0;
@@ -206,6 +215,7 @@ int sparc_filter_plan_create(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H
     }
     if (tuned_tile(H[big], n_s[big], &t)) P->tile = t;
   }
+  for (int p = 0; p < n_prob; ++p) P->fused.push_back(nl_step_fused(H[p], P->tile) ? 1 : 0);
   P->use_graph = use_graph != 0;
   P->cap_stream = nullptr;
   P->graph = nullptr;

@@ -88,6 +88,22 @@ __device__ __forceinline__ void nt_store(cf v, cf* p) {
   __builtin_nontemporal_store(v.im, q + 1);
 }
 
+// atomic add into work-group (LDS) memory: each real component separately
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(cd* p, cd v) {
+  lds_add(&p->re, v.re);
+  lds_add(&p->im, v.im);
+}
+__device__ __forceinline__ void lds_add(cf* p, cf v) {
+  lds_add(&p->re, v.re);
+  lds_add(&p->im, v.im);
+}
+
 // wave64 butterfly sum
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

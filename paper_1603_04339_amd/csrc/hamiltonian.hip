@@ -3,6 +3,7 @@
 // projectors) and scatter kernels, the stencil-step launch logic (tile choice,
 // autotuner, batched step tables) and the H*X entry point.  The stencil step
 // kernels themselves are in hstep_impl.hpp.
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -149,6 +150,153 @@ int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alph
   return fail(SPARC_EINVAL, "nl_project: bad dtype");
 }
 
+// ------------------------------------------------------------ non-local scatter inside the step
+// Per tile shape: the atoms whose support meets each column tile (its "slots", in atom
+// order) and the entries of every (tile, plane), node-major within the plane, with the
+// slot-projector index resolved.
+int nl_tables_build(sparc_ham* H, const std::vector<int32_t>& sup_ptr, const std::vector<int32_t>& sup_idx,
+                    const std::vector<int32_t>& nodes, const std::vector<int32_t>& ptr,
+                    const std::vector<int32_t>& key, const std::vector<double>& cre,
+                    const std::vector<double>& cim) {
+  const int n1 = H->grid.n[0], n2 = H->grid.n[1], n3 = H->grid.n[2];
+  const int na = H->n_atoms_nl;
+  const int64_t n12 = (int64_t)n1 * n2;
+  for (int t = 0; t < kNumTiles; ++t) {
+    NlTileTable& T = H->nlt[t];
+    const int tx = kTiles[t].tx, ty = kTiles[t].ty;
+    const int tiles_x = (n1 + tx - 1) / tx, tiles = tiles_x * ((n2 + ty - 1) / ty);
+    T.tiles = tiles;
+    T.smax = 0;
+    // slots: the atoms of each tile, and the slot of (tile, atom)
+    std::vector<std::vector<int32_t>> tile_atoms(tiles);
+    std::vector<int> stamp(tiles, -1);
+    for (int a = 0; a < na; ++a)
+      for (int q = sup_ptr[a]; q < sup_ptr[a + 1]; ++q) {
+        const int64_t g = sup_idx[q];
+        const int tl = (int)(g % n1) / tx + tiles_x * ((int)((g / n1) % n2) / ty);
+        if (stamp[tl] != a) {
+          stamp[tl] = a;
+          tile_atoms[tl].push_back(a);
+        }
+      }
+    int smax = 0;
+    for (const auto& v : tile_atoms) smax = std::max(smax, (int)v.size());
+    if (smax == 0 || smax > kNlMaxSlots) continue;  // this shape keeps the separate scatter
+    auto slot_of = [&](int tl, int a) {
+      const auto& v = tile_atoms[tl];
+      return (int)(std::lower_bound(v.begin(), v.end(), a) - v.begin());
+    };
+    // entries, one per (node, atom), bucketed by (tile, plane); nodes ascend in g, so
+    // within a bucket they come out in ascending tile-local node order
+    const int pw = 4;  // chi~ values per entry (zero past the atom's own projectors)
+    std::vector<int32_t> tpp((size_t)tiles * n3 + 1, 0);
+    std::vector<int32_t> bucket(nodes.size());
+    size_t n_grp = 0;
+    for (size_t i = 0; i < nodes.size(); ++i) {
+      const int64_t g = nodes[i];
+      const int x = (int)(g % n1), y = (int)((g / n1) % n2), z = (int)(g / n12);
+      bucket[i] = (x / tx + tiles_x * (y / ty)) * n3 + z;
+      int groups = 0;
+      for (int e = ptr[i]; e < ptr[i + 1]; ++e)
+        if (e == ptr[i] || (key[e] >> 2) != (key[e - 1] >> 2)) ++groups;
+      tpp[bucket[i] + 1] += groups;
+      n_grp += groups;
+    }
+    for (size_t b = 0; b + 1 < tpp.size(); ++b) tpp[b + 1] += tpp[b];
+    int maxb = 0;
+    for (size_t b = 0; b + 1 < tpp.size(); ++b) maxb = std::max(maxb, tpp[b + 1] - tpp[b]);
+    std::vector<int32_t> fill(tpp.begin(), tpp.end() - 1), ent(n_grp);
+    std::vector<double> vre(n_grp * pw, 0.0), vim(n_grp * pw, 0.0);
+    for (size_t i = 0; i < nodes.size(); ++i) {
+      const int64_t g = nodes[i];
+      const int x = (int)(g % n1), y = (int)((g / n1) % n2);
+      const int tl = bucket[i] / n3;
+      const int local = (x - (tl % tiles_x) * tx) + tx * (y - (tl / tiles_x) * ty);
+      int o = -1;
+      for (int e = ptr[i]; e < ptr[i + 1]; ++e) {
+        const int a = key[e] >> 2, p = key[e] & 3;
+        if (e == ptr[i] || a != (key[e - 1] >> 2)) {
+          o = fill[bucket[i]]++;
+          ent[o] = local | (slot_of(tl, a) << 16);
+        }
+        vre[(size_t)o * pw + p] = cre[e];
+        vim[(size_t)o * pw + p] = cim[e];
+      }
+    }
+    std::vector<int32_t> slots((size_t)tiles * smax, -1);
+    for (int tl = 0; tl < tiles; ++tl)
+      for (size_t i = 0; i < tile_atoms[tl].size(); ++i) slots[(size_t)tl * smax + i] = tile_atoms[tl][i];
+    const size_t n_val = n_grp * pw;
+    std::vector<char> val;
+    val.resize(n_val * elem_bytes(H->dtype));
+    for (size_t e = 0; e < n_val; ++e) {
+      switch (H->dtype) {
+        case SPARC_R64: ((double*)val.data())[e] = vre[e]; break;
+        case SPARC_R32: ((float*)val.data())[e] = (float)vre[e]; break;
+        case SPARC_C128: ((cd*)val.data())[e] = cd{vre[e], vim[e]}; break;
+        case SPARC_C64: ((cf*)val.data())[e] = cf{(float)vre[e], (float)vim[e]}; break;
+      }
+    }
+    SPARC_HIP(hipMalloc((void**)&T.slots, slots.size() * 4));
+    SPARC_HIP(hipMemcpy(T.slots, slots.data(), slots.size() * 4, hipMemcpyHostToDevice));
+    SPARC_HIP(hipMalloc((void**)&T.tp_ptr, tpp.size() * 4));
+    SPARC_HIP(hipMemcpy(T.tp_ptr, tpp.data(), tpp.size() * 4, hipMemcpyHostToDevice));
+    SPARC_HIP(hipMalloc((void**)&T.tp_ent, std::max<size_t>(n_grp, 1) * 4));
+    SPARC_HIP(hipMalloc(&T.tp_val, std::max<size_t>(val.size(), 16)));
+    if (n_grp) {
+      SPARC_HIP(hipMemcpy(T.tp_ent, ent.data(), n_grp * 4, hipMemcpyHostToDevice));
+      SPARC_HIP(hipMemcpy(T.tp_val, val.data(), val.size(), hipMemcpyHostToDevice));
+    }
+    T.max_bucket = maxb;
+    T.smax = smax;
+  }
+  return SPARC_OK;
+}
+
+void nl_tables_free(sparc_ham* H) {
+  for (int t = 0; t < kNlTileShapes; ++t) {
+    NlTileTable& T = H->nlt[t];
+    for (void* p : {(void*)T.slots, (void*)T.tp_ptr, (void*)T.tp_ent, T.tp_val})
+      if (p) hipFree(p);
+    T = NlTileTable();
+  }
+}
+
+// the plane buffers and the fused rows of tile shape t fit the work-group's LDS
+static bool nl_lds_fits(const sparc_ham* H, int t) {
+  const int tx = kTiles[t].tx, ty = kTiles[t].ty, no = H->grid.n_o;
+  const size_t eb = elem_bytes(H->dtype);
+  const size_t plane = 2 * (size_t)(tx + 2 * no) * (ty + 2 * no) * eb;
+  const size_t rows = ((size_t)H->nlt[t].smax * 4 * eb + 15) / 16 * 16 + 2 * (size_t)tx * ty * eb +
+                      ((size_t)H->grid.n[2] + 1) * 4;
+  return plane + rows <= kNlMaxLds;
+}
+
+bool nl_step_fused(const sparc_ham* H, int t) {
+  return H->nl_fused && H->n_proj > 0 && H->n_nlpts > 0 && H->nlt[t].smax > 0 && nl_lds_fits(H, t);
+}
+
+// sets the fused non-local fields of a step (tile shape t); false when the step keeps
+// the separate scatter (no projectors, no tables for this shape, no projections given)
+template <typename E>
+static bool nl_fill(sparc_ham* H, StepArgs<E>& A, int t, double a, const void* alpha, int32_t n_s) {
+  typedef typename elem<E>::real R;
+  A.nl_val = nullptr;
+  if (!alpha || !nl_step_fused(H, t)) return false;
+  const NlTileTable& T = H->nlt[t];
+  A.nl_tpp = T.tp_ptr;
+  A.nl_ent = T.tp_ent;
+  A.nl_val = (const E*)T.tp_val;
+  A.nl_slots = T.slots;
+  A.nl_smax = T.smax;
+  A.atom_pbeg = H->atom_pbeg;
+  A.gamma = (const R*)H->gamma_d;
+  A.alpha = (const E*)alpha;
+  A.lda = alpha_ld(n_s);
+  A.nla = (R)a;
+  return true;
+}
+
 int heuristic_tile(int n1, int n2, size_t elem_size) {
   const char* env = getenv("SPARC_HSTEP_TILE");
   if (env) {
@@ -191,7 +339,7 @@ int tuned_tile(sparc_ham* H, int32_t n_s, int* t) {
 }
 
 template <typename E>
-static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best) {
+static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best, double a, const void* alpha) {
   sparc_ctx* ctx = H->ctx;
   hipEvent_t e0, e1;
   SPARC_HIP(hipEventCreate(&e0));
@@ -204,10 +352,12 @@ static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best) {
   for (int t = 0; t < kNumTiles && rc == SPARC_OK; ++t) {
     if (kTiles[t].tx * kTiles[t].ty > 1024) continue;
     StepArgs<E> B = A;
+    nl_fill(H, B, t, a, alpha, n_s);
+    const StepArgs<E> B0 = B;
     rc = hstep_single<E>(ctx, B, n_s, H->grid.n_o, t);  // warm-up
     if (rc != SPARC_OK) break;
     hipEventRecord(e0, ctx->stream);
-    B = A;
+    B = B0;
     rc = hstep_single<E>(ctx, B, n_s, H->grid.n_o, t);
     hipEventRecord(e1, ctx->stream);
     if (rc != SPARC_OK) break;
@@ -255,7 +405,7 @@ template <typename E>
 static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
                       int32_t n_s, double a, double b, double c, const void* alpha, int flags) {
   typedef typename elem<E>::real R;
-  StepArgs<E> A;
+  StepArgs<E> A{};
   A.n1 = H->grid.n[0];
   A.n2 = H->grid.n[1];
   A.n3 = H->grid.n[2];
@@ -279,12 +429,16 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
   A.dmask = dirichlet_mask(H->grid);
   A.zplane = (const E*)H->zplane;
+  const bool nonlocal = H->n_proj > 0 && H->n_nlpts > 0 && !(flags & STEP_NO_NONLOCAL);
+  if (nonlocal && !alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
+  const void* al = nonlocal ? alpha : nullptr;
   int t = heuristic_tile(A.n1, A.n2, sizeof(E));
-  if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && z == nullptr && out != x) SPARC_TRY(autotune(H, A, n_s, &t));
-  int rc = hstep_single<E>(H->ctx, A, n_s, H->grid.n_o, t);
-  if (rc != SPARC_OK || H->n_proj == 0 || H->n_nlpts == 0 || (flags & STEP_NO_NONLOCAL)) return rc;
-  if (!alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
-  return nl_scatter(H, alpha, n_s, a, nullptr, out, ldo);
+  if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && z == nullptr && out != x)
+    SPARC_TRY(autotune(H, A, n_s, &t, a, al));
+  const bool fused = nl_fill(H, A, t, a, al, n_s);
+  SPARC_TRY(hstep_single<E>(H->ctx, A, n_s, H->grid.n_o, t));
+  if (nonlocal && !fused) SPARC_TRY(nl_scatter(H, alpha, n_s, a, nullptr, out, ldo));
+  return SPARC_OK;
 }
 
 // ------------------------------------------------------------ batched step tables
@@ -314,6 +468,7 @@ static void fill_args(sparc_ham* H, const StepDesc& d, StepArgs<E>& A) {
   for (int s = 0; s < 3; ++s) A.kl[s] = H->grid.kpt[s] * H->grid.L[s];
   A.dmask = dirichlet_mask(H->grid);
   A.zplane = (const E*)H->zplane;
+  A.nl_val = nullptr;
 }
 
 size_t step_args_bytes(sparc_dtype dt) {
@@ -326,36 +481,45 @@ size_t step_args_bytes(sparc_dtype dt) {
   return 0;
 }
 
+// Builds the step table of n problems.  A problem whose StepDesc carries projections
+// (alpha) applies its projectors inside the step when its Hamiltonian has tables for
+// the tile shape.  *nl_lds: dynamic LDS bytes of the widest fused problem.
 template <typename E>
-static int64_t build_t(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg) {
+static int64_t build_t(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg,
+                       size_t* nl_lds) {
   StepArgs<E>* T = (StepArgs<E>*)table;
   int64_t total = 0;
+  size_t lds = 0;
   for (int p = 0; p < n; ++p) {
     fill_args<E>(H[p], d[p], T[p]);
     wg[p] = (int)total;
     total += plan_problem(T[p], kTiles[tile].tx, kTiles[tile].ty, H[p]->grid.n_o, d[p].n_s, H[p]->ctx->n_cu);
+    if (d[p].alpha) nl_fill(H[p], T[p], tile, d[p].a, d[p].alpha, d[p].n_s);
+    lds = std::max(lds, nl_lds_bytes(T[p], kTiles[tile].tx * kTiles[tile].ty));
   }
   wg[n] = (int)total;
+  if (nl_lds) *nl_lds = lds;
   return total;
 }
 
-int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg) {
+int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg,
+                         size_t* nl_lds) {
   switch (H[0]->dtype) {
-    case SPARC_R64: return build_t<double>(H, d, n, tile, table, wg);
-    case SPARC_R32: return build_t<float>(H, d, n, tile, table, wg);
-    case SPARC_C128: return build_t<cd>(H, d, n, tile, table, wg);
-    case SPARC_C64: return build_t<cf>(H, d, n, tile, table, wg);
+    case SPARC_R64: return build_t<double>(H, d, n, tile, table, wg, nl_lds);
+    case SPARC_R32: return build_t<float>(H, d, n, tile, table, wg, nl_lds);
+    case SPARC_C128: return build_t<cd>(H, d, n, tile, table, wg, nl_lds);
+    case SPARC_C64: return build_t<cf>(H, d, n, tile, table, wg, nl_lds);
   }
   return -1;
 }
 
 int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
-                      int n, int64_t total, int dir) {
+                      int n, int64_t total, int dir, size_t nl_lds) {
   switch (dt) {
-    case SPARC_R64: return hstep_batched<double>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
-    case SPARC_R32: return hstep_batched<float>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
-    case SPARC_C128: return hstep_batched<cd>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
-    case SPARC_C64: return hstep_batched<cf>(ctx, dev_table, dev_wg, n, total, no, tile, dir);
+    case SPARC_R64: return hstep_batched<double>(ctx, dev_table, dev_wg, n, total, no, tile, dir, nl_lds);
+    case SPARC_R32: return hstep_batched<float>(ctx, dev_table, dev_wg, n, total, no, tile, dir, nl_lds);
+    case SPARC_C128: return hstep_batched<cd>(ctx, dev_table, dev_wg, n, total, no, tile, dir, nl_lds);
+    case SPARC_C64: return hstep_batched<cf>(ctx, dev_table, dev_wg, n, total, no, tile, dir, nl_lds);
   }
   return fail(SPARC_EINVAL, "batched step: bad dtype");
 }

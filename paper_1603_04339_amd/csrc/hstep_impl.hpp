@@ -38,6 +38,50 @@ __device__ __forceinline__ void bloch_factor(const double* kl, int wx, int wy, i
   }
 }
 
+// one fused non-local entry e: the atom's projector terms at its node, added into the
+// plane buffer nb
+// the four chi~ values of an entry (zero past the atom's own projectors) as vector loads
+__device__ __forceinline__ void nl_vals(const double* p, double (&v)[4]) {
+  const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+__device__ __forceinline__ void nl_vals(const float* p, float (&v)[4]) {
+  const float4 a = *(const float4*)p;
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = a.z;
+  v[3] = a.w;
+}
+__device__ __forceinline__ void nl_vals(const cd* p, cd (&v)[4]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 a = *(const double2*)(p + i);
+    v[i] = cd{a.x, a.y};
+  }
+}
+__device__ __forceinline__ void nl_vals(const cf* p, cf (&v)[4]) {
+  const float4 a = *(const float4*)p, b = *(const float4*)(p + 2);
+  v[0] = cf{a.x, a.y};
+  v[1] = cf{a.z, a.w};
+  v[2] = cf{b.x, b.y};
+  v[3] = cf{b.z, b.w};
+}
+
+template <typename E>
+__device__ __forceinline__ void nl_entry(const StepArgs<E>& A, int e, const E* alds, E* nb) {
+  const int k = A.nl_ent[e];
+  const E* al = alds + (k >> 16) * 4;
+  E v[4];
+  nl_vals(A.nl_val + (int64_t)e * 4, v);
+  E c = zero<E>();
+#pragma unroll
+  for (int p = 0; p < 4; ++p) c = fmae(c, v[p], al[p]);
+  lds_add(nb + (k & 0xffff), c);
+}
+
 // One recurrence step on one (tile, orbital, z chunk): out = a(-1/2 Lap_h) x + (a V + b) x + c z.
 // Each thread owns one (x, y) column of the TX x TY tile and marches through the z
 // chunk with a register queue of the 2 NO + 1 planes around the current one (z
@@ -45,9 +89,9 @@ __device__ __forceinline__ void bloch_factor(const double* kl, int wx, int wy, i
 // staged in LDS (double-buffered, one barrier per plane).  Threads whose column lies
 // past the grid edge (partial tiles) load the periodic image, with the Bloch factor,
 // so the LDS plane is always complete.
-template <typename E, int TX, int TY, int NO, bool DIR>
+template <typename E, int TX, int TY, int NO, bool DIR, bool NL>
 __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n, int zi,
-                                           E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
+                                           E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)], char* nl_lds) {
   typedef typename elem<E>::real R;
   constexpr int NT = TX * TY;
   constexpr int PX = TX + 2 * NO;
@@ -172,6 +216,39 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
     vn = vp[g];
     if (zp) zn = nt_load(zp + g);
   }
+  // Non-local operator: the projector term of plane z + 1 is accumulated in LDS during
+  // step z (one atomic add per (node, atom) entry, entries spread over the threads)
+  // and added by each node's owner before its store at step z + 1.  alds holds
+  // nla * gamma_P * alpha_P of this orbital for the tile's slots; tpl the entry
+  // offsets of the chunk's planes.  A step's entries are loaded before its plane
+  // prefetch, so waiting for them never waits for the prefetch.
+  E* alds = nullptr;
+  E* nlb = nullptr;
+  int* tpl = nullptr;
+  if constexpr (NL) {
+    const int smax4 = A.nl_smax * 4;
+    const int32_t* slots = A.nl_slots + (int64_t)tile * A.nl_smax;
+    alds = (E*)nl_lds;
+    nlb = (E*)(nl_lds + ((size_t)smax4 * sizeof(E) + 15) / 16 * 16);
+    tpl = (int*)(nlb + 2 * NT);
+    for (int i = tid; i < smax4; i += NT) {
+      const int a = slots[i >> 2], p = i & 3;
+      E v = zero<E>();
+      if (a >= 0) {
+        const int pb = A.atom_pbeg[a];
+        if (p < A.atom_pbeg[a + 1] - pb)
+          v = scale((R)(A.nla * A.gamma[pb + p]), A.alpha[(int64_t)(pb + p) * A.lda + n]);
+      }
+      alds[i] = v;
+    }
+    const int32_t* tpp = A.nl_tpp + (int64_t)tile * n3 + zb;
+    for (int i = tid; i <= ze - zb; i += NT) tpl[i] = tpp[i];
+    nlb[tid] = zero<E>();
+    nlb[NT + tid] = zero<E>();
+    __syncthreads();
+  }
+  if constexpr (NL)
+    for (int e = tpl[0] + tid; e < tpl[1]; e += NT) nl_entry(A, e, alds, nlb);
   int step = 0;
   for (int z = zb; z < ze; ++z, ++step, g += plane_sz) {
     if constexpr (elem<E>::is_cplx) q[2 * NO] = rot(qn, qc, qs);
@@ -209,6 +286,24 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
       if (zp) zv = nt_load(zp + g);
     }
     __syncthreads();
+    // projector term of this node (complete since the barrier) and the first entry of
+    // plane z + 1 for this thread, applied after the store
+    E nlt = zero<E>();
+    int ek = -1, e0 = 0, e1 = 0;
+    E ev[4];
+    if constexpr (NL) {
+      E* nb = nlb + (step & 1) * NT;
+      nlt = nb[tid];
+      nb[tid] = zero<E>();
+      if (z + 1 < ze) {
+        e0 = __builtin_amdgcn_readfirstlane(tpl[z + 1 - zb]);
+        e1 = __builtin_amdgcn_readfirstlane(tpl[z + 2 - zb]);
+        if (e0 + tid < e1) {
+          ek = A.nl_ent[e0 + tid];
+          nl_vals(A.nl_val + (int64_t)(e0 + tid) * 4, ev);
+        }
+      }
+    }
     if (inside) {
       E lap = scale(A.centre, q[NO]);
 #pragma unroll
@@ -219,7 +314,22 @@ __device__ __forceinline__ void hstep_body(const StepArgs<E>& A, int tile, int n
       }
       E r = fmar(lap, (R)(A.va * v + A.vb), q[NO]);
       if (zp) r = fmar(r, A.zc, zv);
+      if constexpr (NL) r = r + nlt;
       nt_store(r, op + g);
+    }
+    if constexpr (NL) {
+      // projector terms of plane z + 1 into the other buffer (its owners cleared it
+      // before this step's barrier; they read it after the next one).  Applied after
+      // the store, where the loop waits for the plane prefetch anyway.
+      E* nb = nlb + ((step + 1) & 1) * NT;
+      if (ek >= 0) {
+        const E* al = alds + (ek >> 16) * 4;
+        E c = zero<E>();
+#pragma unroll
+        for (int p = 0; p < 4; ++p) c = fmae(c, ev[p], al[p]);
+        lds_add(nb + (ek & 0xffff), c);
+      }
+      for (int e = e0 + tid + NT; e < e1; e += NT) nl_entry(A, e, alds, nb);
     }
 #pragma unroll
     for (int d = 0; d < 2 * NO; ++d) q[d] = q[d + 1];
@@ -237,30 +347,32 @@ __device__ __forceinline__ int64_t xcd_order(int64_t L, int64_t G) {
   return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
-template <typename E, int TX, int TY, int NO, bool DIR>
+template <typename E, int TX, int TY, int NO, bool DIR, bool NL>
 __device__ __forceinline__ void hstep_local(const StepArgs<E>& A, int64_t local,
-                                            E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)]) {
+                                            E (&plane)[2][(TY + 2 * NO) * (TX + 2 * NO)], char* nl_lds) {
   // tiles fastest (neighbouring tiles share halo columns in L2), then orbitals, then z chunks
   const int tile = (int)(local % A.tiles);
   const int64_t rest = local / A.tiles;
   const int n = (int)(rest % A.ns);
   const int zi = (int)(rest / A.ns);
-  hstep_body<E, TX, TY, NO, DIR>(A, tile, n, zi, plane);
+  hstep_body<E, TX, TY, NO, DIR, NL>(A, tile, n, zi, plane, nl_lds);
 }
 
-template <typename E, int TX, int TY, int NO, bool DIR>
+template <typename E, int TX, int TY, int NO, bool DIR, bool NL>
 __global__ __launch_bounds__(TX* TY) void hstep_kernel(StepArgs<E> A) {
   __shared__ __align__(16) E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
-  hstep_local<E, TX, TY, NO, DIR>(A, xcd_order(blockIdx.x, gridDim.x), plane);
+  extern __shared__ __align__(16) char nl_lds[];
+  hstep_local<E, TX, TY, NO, DIR, NL>(A, xcd_order(blockIdx.x, gridDim.x), plane, nl_lds);
 }
 
 // Several (cell, k) problems in one launch: work-group b (in XCD order) belongs to the
 // problem p with wg_off[p] <= b < wg_off[p+1]; inside it, the logical order of a
 // single-problem launch.
-template <typename E, int TX, int TY, int NO, bool DIR>
+template <typename E, int TX, int TY, int NO, bool DIR, bool NL>
 __global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>* __restrict__ probs,
                                                                     const int* __restrict__ wg_off, int n_probs) {
   __shared__ __align__(16) E plane[2][(TY + 2 * NO) * (TX + 2 * NO)];
+  extern __shared__ __align__(16) char nl_lds[];
   const int b = (int)xcd_order(blockIdx.x, gridDim.x);
   int lo = 0, hi = n_probs - 1;
   while (lo < hi) {
@@ -269,32 +381,45 @@ __global__ __launch_bounds__(TX* TY) void hstep_batched_kernel(const StepArgs<E>
     else hi = mid - 1;
   }
   const StepArgs<E> A = probs[lo];
-  hstep_local<E, TX, TY, NO, DIR>(A, b - wg_off[lo], plane);
+  if (NL && !A.nl_val) {
+    hstep_local<E, TX, TY, NO, DIR, false>(A, b - wg_off[lo], plane, nl_lds);
+    return;
+  }
+  hstep_local<E, TX, TY, NO, DIR, NL>(A, b - wg_off[lo], plane, nl_lds);
 }
 
 template <typename E, int TX, int TY, int NO>
 static int launch_single_t(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s) {
   const int64_t G = plan_problem(A, TX, TY, NO, n_s, ctx->n_cu);
   if (G > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "stencil step: too many work-groups");
+  const size_t lds = nl_lds_bytes(A, TX * TY);
   int t = timer_begin(ctx, "hstep");
-  if (A.dmask) hstep_kernel<E, TX, TY, NO, true><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
-  else hstep_kernel<E, TX, TY, NO, false><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
+  if (A.nl_val) {
+    if (A.dmask) hstep_kernel<E, TX, TY, NO, true, true><<<(unsigned)G, TX * TY, lds, ctx->stream>>>(A);
+    else hstep_kernel<E, TX, TY, NO, false, true><<<(unsigned)G, TX * TY, lds, ctx->stream>>>(A);
+  } else {
+    if (A.dmask) hstep_kernel<E, TX, TY, NO, true, false><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
+    else hstep_kernel<E, TX, TY, NO, false, false><<<(unsigned)G, TX * TY, 0, ctx->stream>>>(A);
+  }
   timer_end(ctx, t);
   return check_launch("hstep_kernel");
 }
 
 template <typename E, int TX, int TY, int NO>
 static int launch_batched_t(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total_wg,
-                            int dir) {
+                            int dir, size_t nl_lds) {
   if (total_wg <= 0) return SPARC_OK;
   if (total_wg > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "batched step: too many work-groups");
   int t = timer_begin(ctx, "hstep");
-  if (dir)
-    hstep_batched_kernel<E, TX, TY, NO, true><<<(unsigned)total_wg, TX * TY, 0, ctx->stream>>>(
-        (const StepArgs<E>*)dprobs, dwg, n_probs);
-  else
-    hstep_batched_kernel<E, TX, TY, NO, false><<<(unsigned)total_wg, TX * TY, 0, ctx->stream>>>(
-        (const StepArgs<E>*)dprobs, dwg, n_probs);
+  const StepArgs<E>* P = (const StepArgs<E>*)dprobs;
+  const unsigned G = (unsigned)total_wg;
+  if (nl_lds) {
+    if (dir) hstep_batched_kernel<E, TX, TY, NO, true, true><<<G, TX * TY, nl_lds, ctx->stream>>>(P, dwg, n_probs);
+    else hstep_batched_kernel<E, TX, TY, NO, false, true><<<G, TX * TY, nl_lds, ctx->stream>>>(P, dwg, n_probs);
+  } else {
+    if (dir) hstep_batched_kernel<E, TX, TY, NO, true, false><<<G, TX * TY, 0, ctx->stream>>>(P, dwg, n_probs);
+    else hstep_batched_kernel<E, TX, TY, NO, false, false><<<G, TX * TY, 0, ctx->stream>>>(P, dwg, n_probs);
+  }
   timer_end(ctx, t);
   return check_launch("hstep_batched_kernel");
 }
@@ -334,8 +459,8 @@ static int single_no(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int no, int t)
 
 template <typename E, int NO>
 static int batched_tile(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n_probs, int64_t total, int t,
-                        int dir) {
-#define CALL(tx, ty) launch_batched_t<E, tx, ty, NO>(ctx, dprobs, dwg, n_probs, total, dir)
+                        int dir, size_t nl_lds) {
+#define CALL(tx, ty) launch_batched_t<E, tx, ty, NO>(ctx, dprobs, dwg, n_probs, total, dir, nl_lds)
   SPARC_TILE_SWITCH(t, CALL)
 #undef CALL
 }
@@ -346,16 +471,17 @@ int hstep_single(sparc_ctx* ctx, StepArgs<E>& A, int32_t n_s, int no, int t) {
 }
 
 template <typename E>
-int hstep_batched(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n, int64_t total, int no, int t, int dir) {
+int hstep_batched(sparc_ctx* ctx, const void* dprobs, const int* dwg, int n, int64_t total, int no, int t, int dir,
+                  size_t nl_lds) {
   switch (no) {
-    case 1: return batched_tile<E, 1>(ctx, dprobs, dwg, n, total, t, dir);
-    case 2: return batched_tile<E, 2>(ctx, dprobs, dwg, n, total, t, dir);
-    case 3: return batched_tile<E, 3>(ctx, dprobs, dwg, n, total, t, dir);
-    case 4: return batched_tile<E, 4>(ctx, dprobs, dwg, n, total, t, dir);
-    case 5: return batched_tile<E, 5>(ctx, dprobs, dwg, n, total, t, dir);
-    case 6: return batched_tile<E, 6>(ctx, dprobs, dwg, n, total, t, dir);
-    case 7: return batched_tile<E, 7>(ctx, dprobs, dwg, n, total, t, dir);
-    case 8: return batched_tile<E, 8>(ctx, dprobs, dwg, n, total, t, dir);
+    case 1: return batched_tile<E, 1>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
+    case 2: return batched_tile<E, 2>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
+    case 3: return batched_tile<E, 3>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
+    case 4: return batched_tile<E, 4>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
+    case 5: return batched_tile<E, 5>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
+    case 6: return batched_tile<E, 6>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
+    case 7: return batched_tile<E, 7>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
+    case 8: return batched_tile<E, 8>(ctx, dprobs, dwg, n, total, t, dir, nl_lds);
   }
   return fail(SPARC_EINVAL, "batched step: n_o=%d unsupported", no);
 }

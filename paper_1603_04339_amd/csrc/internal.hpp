@@ -80,6 +80,28 @@ inline int dirichlet_mask(const sparc_grid& g) { return (g.bc[0] == 1 ? 1 : 0) |
 // z-chunks of the local-force box per atom (partial sums reduced in a fixed order)
 constexpr int kForceChunks = 8;
 
+// Tables of the non-local scatter applied inside the stencil step: the step adds
+// V_nl x to its output at the nodes with projector support, from entry lists per
+// (column tile, z plane).  Limits of the fused form; beyond them a cell uses the
+// separate scatter kernel.
+constexpr int kNlMaxSlots = 64;       // atoms whose support meets one column tile
+constexpr int kNlTileShapes = 6;      // the stencil tile shapes (kTiles)
+constexpr size_t kNlMaxLds = 65536;   // LDS bytes of one fused work-group (planes + rows)
+
+// per stencil tile shape: the atoms ("slots") whose projector support meets each
+// column tile, and the entries of each (tile, plane): one per (node, atom) with the
+// tile-local node index and the slot packed as node | slot << 16, and the atom's
+// four chi~ values at the node (zero past the atom's own projectors)
+struct NlTileTable {
+  int32_t tiles = 0;          // column tiles of the shape
+  int32_t smax = 0;           // slots per tile (the widest tile); 0: no tables for this shape
+  int32_t max_bucket = 0;     // entries of the fullest (tile, plane)
+  int32_t* slots = nullptr;   // [tiles * smax] atom index, -1 past the tile's own count
+  int32_t* tp_ptr = nullptr;  // [tiles * n3 + 1] first entry of (tile, plane)
+  int32_t* tp_ent = nullptr;  // [entries] node | slot << 16, ascending node within a bucket
+  void* tp_val = nullptr;     // [entries * 4] chi~ (element type)
+};
+
 struct sparc_ham {
   sparc_ctx* ctx;
   sparc_grid grid;
@@ -123,6 +145,8 @@ struct sparc_ham {
   int32_t* nl_atom;     // [n_atoms_nl] atom index of each projector-carrying atom
   void* zplane;         // [n1 n2] zero elements (Dirichlet z only; read for planes past a face)
   double gtap[3][8];    // FD gradient weights w~_p / h_s per direction, p = 1..n_o
+  bool nl_fused;        // the stencil step applies the projectors (tables built)
+  NlTileTable nlt[kNlTileShapes];
 };
 
 namespace sparc {
@@ -146,6 +170,8 @@ extern sparc_ctx* g_timer_ctx;
 //   alpha: projections [n_s][n_proj] of x (already scaled by dV), from nl_project.
 //   flags: STEP_NO_VEFF drops the potential term, STEP_NO_NONLOCAL the projector term
 //   (both together give a * (-1/2 Lap_h x) + b x + c z, used by the Poisson solver).
+//   With tables for the chosen tile shape the projector term is applied inside the
+//   stencil kernel; otherwise the scatter kernel runs after it.
 enum { STEP_NO_VEFF = 1, STEP_NO_NONLOCAL = 2 };
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
              int32_t n_s, double a, double b, double c, const void* alpha, int flags = 0);
@@ -153,6 +179,16 @@ int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alph
 //   out += a * V_nl-scatter(alpha); a from a device scalar when a_dev != nullptr
 int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out, int64_t ldo);
 int heuristic_tile(int n1, int n2, size_t elem_size);
+// non-local scatter inside the stencil step (hamiltonian.hip): per tile shape tables
+// from the node-major entries (nodes ascending, entries of node i in [ptr[i], ptr[i+1]),
+// key 4 atom + p, chi~ as (re, im))
+int nl_tables_build(sparc_ham* H, const std::vector<int32_t>& sup_ptr, const std::vector<int32_t>& sup_idx,
+                    const std::vector<int32_t>& nodes, const std::vector<int32_t>& ptr,
+                    const std::vector<int32_t>& key, const std::vector<double>& cre,
+                    const std::vector<double>& cim);
+void nl_tables_free(sparc_ham* H);
+// whether the batched plan's problems apply their projectors inside the step
+bool nl_step_fused(const sparc_ham* H, int tile);
 // batched stencil steps over several Hamiltonians (same dtype and n_o): a host table of
 // per-problem step arguments and work-group offsets is built, uploaded by the caller, and
 // launched as one kernel
@@ -165,11 +201,14 @@ struct StepDesc {
   int64_t ldo;
   int n_s;
   double a, b, c;
+  const void* alpha;  // projections of x (the projectors are applied inside the step), or nullptr
 };
 size_t step_args_bytes(sparc_dtype dt);
-int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg);
+//   nl_lds: dynamic LDS bytes of the launch (the widest fused problem)
+int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile, void* table, int* wg,
+                         size_t* nl_lds = nullptr);
 int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
-                      int n, int64_t total, int dir);
+                      int n, int64_t total, int dir, size_t nl_lds = 0);
 int tuned_tile(sparc_ham* H, int32_t n_s, int* t);
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
 // partial sums of the non-local force (forces.hip)
