@@ -201,6 +201,15 @@ int density_from_orbitals(sparc_ctx* ctx, int32_t n_k, const void* const* X, con
                           int32_t n_s, sparc_dtype dtype, const double* occ_w, int64_t n_d,
                           double dV, double* rho_dev);
 
+/* Measurement: the streaming rate of the recurrence's memory pattern alone, the
+ * practical HBM ceiling of the stencil step (which reads two blocks and writes one per
+ * recurrence step, Sec. 3.4 Chebyshev filter).  c = 2 a - b over n doubles (device,
+ * 16-byte aligned, n even; a, b read, c written), one warm-up launch then reps timed
+ * launches on the context's stream; *ms_per_launch (host) gets the mean launch time.
+ * Synchronous.  Bytes moved per launch: 24 n. */
+int sparc_stream_triad(sparc_ctx* ctx, const double* a, const double* b, double* c, int64_t n, int32_t reps,
+                       double* ms_per_launch);
+
 /* Fermi level and occupations (Sec. 3.4 electron-count constraint; Sec. 2
  * Fermi-Dirac occupations): mu with 2 sum_b w_b sum_n g_nb = n_elec by Brent's
  * method (the paper's Fermi-level solver, Sec. 4) on the bracket
@@ -251,7 +260,10 @@ int sparc_ctx_set_autotune(sparc_ctx* ctx, int enable);
  * model: V_eff = V_loc + V_H + V_x (Slater exchange), -Lap_h V_H =
  * 4 pi (rho - mean rho) solved by conjugate gradients on the FD Laplacian,
  * density mixing (linear, or Anderson with relaxation `mix` and history
- * `mix_history`), Harris–Foulkes energy at the input density, stop when
+ * `mix_history`; with kerker_k0 > 0 the mixed residual f is Kerker-preconditioned,
+ * f - k0^2 g with (-Lap_h + k0^2) g = f solved by conjugate gradients, which damps the
+ * long-wavelength charge sloshing of the density iteration), Harris–Foulkes energy at
+ * the input density, stop when
  * ||rho_out - rho_in|| / ||rho_in|| < tol.  The first step runs n_first_passes
  * CheFSI passes from X0 before forming the density.
  * electrostatics = SPARC_ELEC_PSEUDOCHARGE replaces the jellium form by the paper's
@@ -277,6 +289,7 @@ typedef struct {
   const double* lanczos_v0_dev;/* device [N_d] FP64 Lanczos start vector              */
   int32_t electrostatics;      /* SPARC_ELEC_JELLIUM (0) or SPARC_ELEC_PSEUDOCHARGE   */
   double eps_b;                /* pseudocharge truncation tolerance (0: 1e-8)         */
+  double kerker_k0;            /* Kerker wavenumber of the mixing (bohr^-1; 0: none)  */
 } sparc_scf_params;
 
 typedef struct {

@@ -105,6 +105,19 @@ def poisson(rho, grid: Grid):
     return np.real(np.fft.ifftn(vhat)).reshape(-1)
 
 
+def kerker(f, grid: Grid, k0: float):
+    """Kerker preconditioner of a density residual (damping of the long-wavelength
+    charge-sloshing modes of the mixing, a standard companion of the Anderson mixing
+    of Sec. 4): P f = sigma(G) / (sigma(G) + k0^2) f-hat per plane wave, sigma the
+    symbol of -Lap_h, so P removes the G = 0 component and leaves the short waves
+    nearly unchanged.  Written as f - k0^2 g with (-Lap_h + k0^2) g = f, solved
+    exactly by the DFT."""
+    n1, n2, n3 = grid.n
+    fhat = np.fft.fftn(np.asarray(f, dtype=np.float64).reshape(n3, n2, n1))
+    ghat = fhat / (laplacian_symbol(grid) + k0 * k0)
+    return np.asarray(f, dtype=np.float64) - k0 * k0 * np.real(np.fft.ifftn(ghat)).reshape(-1)
+
+
 def slater(rho):
     """Slater exchange: returns (eps_x, V_x) per grid point (the exchange part
     of the LDA of Sec. 2)."""
@@ -163,13 +176,14 @@ def sad_density(grid: Grid, R, width, Z, n_elec: float):
     return rho * (n_elec / (grid.dV * rho.sum()))
 
 
-def anderson_update(x, f, hist_x, hist_f, beta: float, m: int):
+def anderson_update(x, f, hist_x, hist_f, beta: float, m: int, precond=None):
     """Anderson extrapolation of the fixed-point iteration x -> x + f (the SCF
     acceleration named in Sec. 4, relaxation beta, history m): with the
     differences dX_i = x_i - x_{i-1} and dF_i = f_i - f_{i-1} of the last m
     iterates, gamma minimises ||f - dF gamma||_2, and
-    x_new = (x - dX gamma) + beta (f - dF gamma).  hist_x, hist_f hold the
-    previous iterates and residuals (updated in place).  m = 0 is linear mixing."""
+    x_new = (x - dX gamma) + beta P (f - dF gamma), P the preconditioner (identity
+    when precond is None).  hist_x, hist_f hold the previous iterates and residuals
+    (updated in place).  m = 0 is (preconditioned) linear mixing."""
     if m > 0 and hist_x:
         dX = np.stack([x - hist_x[-1]] + [hist_x[i + 1] - hist_x[i] for i in range(len(hist_x) - 1)][::-1], axis=1)
         dF = np.stack([f - hist_f[-1]] + [hist_f[i + 1] - hist_f[i] for i in range(len(hist_f) - 1)][::-1], axis=1)
@@ -183,13 +197,13 @@ def anderson_update(x, f, hist_x, hist_f, beta: float, m: int):
     hist_f.append(f.copy())
     del hist_x[:-m or None]
     del hist_f[:-m or None]
-    return xb + beta * fb
+    return xb + beta * (fb if precond is None else precond(fb))
 
 
 def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.01,
         mix: float = 0.3, tol: float = 1e-6, max_iter: int = 100, n_first_passes: int = 4,
         rho_init=None, lanczos_v0=None, lanczos_steps: int = 20, callback=None, mix_history: int = 0,
-        psd=None):
+        psd=None, kerker_k0: float = 0.0):
     """Minimal SCF of Sec. 2 ("fixed-point iteration ... accelerated using
     mixing") with the CheFSI policy of Sec. 3.4: the first SCF step runs
     n_first_passes filter + Rayleigh-Ritz passes from the random X0 before the
@@ -200,7 +214,9 @@ def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.0
     lambda_cut = (lambda_min + lambda_max)/2 for the first pass, then the largest
     Ritz value of the previous pass.
     Mixing: mix_history = 0 is linear density mixing rho_in + mix (rho_out - rho_in);
-    mix_history > 0 is Anderson extrapolation with relaxation mix and that history.
+    mix_history > 0 is Anderson extrapolation with relaxation mix and that history;
+    kerker_k0 > 0 preconditions the mixed residual with the Kerker filter of that
+    wavenumber (bohr^-1).
     Electrostatics: psd = None is the jellium form; psd = the dict of
     oracle.pseudocharge.electrostatics_setup switches to pseudocharges (vloc must then
     be zero: the electrons see phi).
@@ -242,7 +258,8 @@ def scf(grid: Grid, vloc, projs, X0, n_elec: float, degree: int, kT: float = 0.0
         if err < tol:
             converged = True
             break
-        rho_in = anderson_update(rho_in, rho_out - rho_in, hx, hf, mix, mix_history)
+        pre = (lambda f: kerker(f, grid, kerker_k0)) if kerker_k0 > 0 else None
+        rho_in = anderson_update(rho_in, rho_out - rho_in, hx, hf, mix, mix_history, pre)
         vh = potential(rho_in)
     return {"energy": F, "mu": mu, "iterations": it, "converged": converged,
             "rho": rho_in, "ritz": lam, "history": history, "X": X, "phi": vh, "occ": g}

@@ -3,7 +3,9 @@
 //   -Lap_h V_H = 4 pi (rho - mean rho)          (conjugate gradients, FD Laplacian)
 //   CheFSI: n_first_passes filter + Rayleigh-Ritz passes on the first step, then one
 //   Fermi level, occupations, density; Harris-Foulkes free energy at rho_in
-//   rho_in <- rho_in + mix (rho_out - rho_in) until ||rho_out - rho_in|| < tol ||rho_in||
+//   rho_in <- rho_in + mix P(rho_out - rho_in), Anderson-extrapolated over the last
+//   mix_history iterates, P the Kerker filter (or the identity), until
+//   ||rho_out - rho_in|| < tol ||rho_in||
 // Every step runs in device kernels; the host only sequences calls and reads
 // back scalars (Fermi level, residuals, energy).  With an FP32 filter the passes
 // run on an FP32 copy of the orbitals until the density residual stalls near
@@ -273,8 +275,11 @@ struct GammaSet {
   const double* dx[AMAX];
   const double* df[AMAX];
 };
+// x <- xbar + beta fbar (fbar_out == nullptr), or x <- xbar and fbar_out <- fbar (the
+// preconditioned form adds beta P(fbar) afterwards); xbar = x - dX gamma, fbar = f - dF gamma
 __global__ void anderson_update_kernel(int64_t n, int m, GammaSet S, const double* __restrict__ gamma,
-                                       const double* __restrict__ f, double beta, double* __restrict__ x) {
+                                       const double* __restrict__ f, double beta, double* __restrict__ x,
+                                       double* __restrict__ fbar_out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   double xb = x[i], fb = f[i];
@@ -283,7 +288,18 @@ __global__ void anderson_update_kernel(int64_t n, int m, GammaSet S, const doubl
     xb -= g * S.dx[k][i];
     fb -= g * S.df[k][i];
   }
-  x[i] = xb + beta * fb;
+  if (fbar_out) {
+    x[i] = xb;
+    fbar_out[i] = fb;
+  } else {
+    x[i] = xb + beta * fb;
+  }
+}
+// Kerker step: x += beta (f - k2 g), g the Helmholtz solution of f
+__global__ void kerker_mix_kernel(int64_t n, double* __restrict__ x, const double* __restrict__ f,
+                                  const double* __restrict__ g, double k2, double beta) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] += beta * (f[i] - k2 * g[i]);
 }
 __global__ void diff_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -324,14 +340,33 @@ struct Poisson {
   double *b, *r, *p, *Ap, *part, *sc;  // sc: [0] rr, [1] pAp, [2] rr_new, [3] sum, [4] bb
   int iters_total = 0;
 
+  double shift = 0.0;  // k^2 of the Helmholtz form (-Lap_h + k^2); 0: Poisson
+
   int apply(const double* x, double* y) {
-    // -Lap_h x = 2 * (-1/2 Lap_h x): stencil only
-    return ham_step(H, x, n, nullptr, 0, y, n, 1, 2.0, 0.0, 0.0, nullptr, STEP_NO_VEFF | STEP_NO_NONLOCAL);
+    // -Lap_h x + shift x = 2 * (-1/2 Lap_h x) + shift x: stencil only
+    return ham_step(H, x, n, nullptr, 0, y, n, 1, 2.0, shift, 0.0, nullptr, STEP_NO_VEFF | STEP_NO_NONLOCAL);
+  }
+
+  // (-Lap_h + k2) g = f by conjugate gradients from g = 0 (the operator is positive
+  // definite for k2 > 0)
+  int solve_helmholtz(hipStream_t s, const double* f, double* g, double k2, double tol, int max_it) {
+    SPARC_HIP(hipMemsetAsync(g, 0, n * 8, s));
+    copy_kernel<<<GRID1(n)>>>(n, f, b);
+    shift = k2;
+    const int rc = cg(s, g, tol, max_it, false);
+    shift = 0.0;
+    return rc;
   }
 
   int solve(hipStream_t s, const double* rho, double* v, double tol, int max_it) {
     SPARC_TRY(reduce(s, n, rho, nullptr, RED_SUM, part, sc + 3));
     poisson_rhs_kernel<<<GRID1(n)>>>(n, rho, sc + 3, b);
+    return cg(s, v, tol, max_it, true);
+  }
+
+  // conjugate gradients on apply(v) = b from the current v; zero_mean: remove the mean
+  // of v on exit (the Poisson form)
+  int cg(hipStream_t s, double* v, double tol, int max_it, bool zero_mean) {
     SPARC_TRY(reduce(s, n, b, b, RED_DOT, part, sc + 4));
     SPARC_TRY(apply(v, r));
     residual_kernel<<<GRID1(n)>>>(n, b, r);
@@ -358,6 +393,7 @@ struct Poisson {
     }
     iters_total += it + 1;
     if (it >= max_it) return fail(SPARC_ENOCONV, "poisson: CG did not converge in %d iterations", max_it);
+    if (!zero_mean) return check_launch("helmholtz");
     SPARC_TRY(reduce(s, n, v, nullptr, RED_SUM, part, sc + 3));
     sub_mean_kernel<<<GRID1(n)>>>(n, v, sc + 3);
     return check_launch("poisson");
@@ -446,6 +482,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
   if (!P->x0_dev || !P->lanczos_v0_dev) return fail(SPARC_EINVAL, "sparc_scf_run: x0_dev and lanczos_v0_dev needed");
   if (P->filt != SPARC_R64 && P->filt != SPARC_R32) return fail(SPARC_EINVAL, "sparc_scf_run: filt must be R64 or R32");
   if (P->mix_history < 0 || P->mix_history > AMAX) return fail(SPARC_EINVAL, "sparc_scf_run: mix_history outside 0..%d", AMAX);
+  if (!(P->kerker_k0 >= 0) || !std::isfinite(P->kerker_k0)) return fail(SPARC_EINVAL, "sparc_scf_run: kerker_k0 must be >= 0");
   if (!res->rho_dev || !res->ritz_dev) return fail(SPARC_EINVAL, "sparc_scf_run: result buffers missing");
   const auto t_start = std::chrono::steady_clock::now();
   hipStream_t s = ctx->stream;
@@ -498,6 +535,13 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
     SPARC_TRY(B.alloc(&apart, (size_t)ABLK * (AMAX + 1) * (AMAX + 2) / 2));
   }
   int a_count = 0, a_head = 0;
+  // Kerker preconditioning of the mixed residual: f - k0^2 g, (-Lap_h + k0^2) g = f
+  const double kk2 = P->kerker_k0 > 0 ? P->kerker_k0 * P->kerker_k0 : 0.0;
+  double *kf = nullptr, *kg = nullptr;
+  if (kk2 > 0) {
+    SPARC_TRY(B.alloc(&kf, n));
+    SPARC_TRY(B.alloc(&kg, n));
+  }
   size_t wf64 = sparc_workspace_bytes(H64, ns, SPARC_OP_FILTER), wr64 = sparc_workspace_bytes(H64, ns, SPARC_OP_RR);
   size_t wl = sparc_workspace_bytes(H64, P->lanczos_steps, SPARC_OP_LANCZOS);
   size_t wbytes = std::max({wf64, wr64, wl});
@@ -611,8 +655,19 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
       break;
     }
     prev_err = err;
+    // rho_in += mix P(f) with the Helmholtz solve of the Kerker form (f in kf)
+    auto kerker_mix = [&]() -> int {
+      SPARC_TRY(PS.solve_helmholtz(s, kf, kg, kk2, 1e-10, 20000));
+      kerker_mix_kernel<<<GRID1(n)>>>(n, rho_in, kf, kg, kk2, P->mix);
+      return check_launch("kerker_mix_kernel");
+    };
     if (am == 0) {
-      mix_kernel<<<GRID1(n)>>>(n, rho_in, rho_out, P->mix);
+      if (kk2 > 0) {
+        diff_kernel<<<GRID1(n)>>>(n, rho_out, rho_in, kf);
+        SPARC_TRY(kerker_mix());
+      } else {
+        mix_kernel<<<GRID1(n)>>>(n, rho_in, rho_out, P->mix);
+      }
     } else {
       diff_kernel<<<GRID1(n)>>>(n, rho_out, rho_in, fcur);
       if (it > 1) {  // new differences into the ring
@@ -624,7 +679,12 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
       SPARC_HIP(hipMemcpyAsync(xprev, rho_in, n * 8, hipMemcpyDeviceToDevice, s));
       SPARC_HIP(hipMemcpyAsync(fprev, fcur, n * 8, hipMemcpyDeviceToDevice, s));
       if (a_count == 0) {
-        mix_kernel<<<GRID1(n)>>>(n, rho_in, rho_out, P->mix);
+        if (kk2 > 0) {
+          SPARC_HIP(hipMemcpyAsync(kf, fcur, n * 8, hipMemcpyDeviceToDevice, s));
+          SPARC_TRY(kerker_mix());
+        } else {
+          mix_kernel<<<GRID1(n)>>>(n, rho_in, rho_out, P->mix);
+        }
       } else {
         VecSet vs;
         GammaSet gs;
@@ -638,7 +698,8 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
         launch_multi_dot(s, ABLK, n, a_count, vs, apart);
         multi_dot_final_kernel<<<1, 256, 0, s>>>(ABLK, npairs, apart, apairs);
         anderson_solve_kernel<<<1, 64, 0, s>>>(a_count, apairs, agamma);
-        anderson_update_kernel<<<GRID1(n)>>>(n, a_count, gs, agamma, fcur, P->mix, rho_in);
+        anderson_update_kernel<<<GRID1(n)>>>(n, a_count, gs, agamma, fcur, P->mix, rho_in, kk2 > 0 ? kf : nullptr);
+        if (kk2 > 0) SPARC_TRY(kerker_mix());
       }
     }
     SPARC_TRY(check_launch("density mixing"));

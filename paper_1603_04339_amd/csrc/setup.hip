@@ -497,11 +497,11 @@ int sparc_ham_create(sparc_ctx* ctx, const sparc_grid* grid, const sparc_atoms* 
           cim[e] = T.vim[vi];
         }
   }
-  // the projector scatter inside the stencil step: by default for FP64 real blocks,
-  // where it measured faster than the separate scatter; SPARC_NL_FUSED=1 / 0 forces it
-  // on / off for every element type
+  // the projector scatter inside the stencil step, on request (SPARC_NL_FUSED=1): the
+  // separate projection and scatter kernels are the default, as fast or faster on the
+  // measured cells (FP64 within 2 %, FP32 and complex slower fused)
   const char* fenv = getenv("SPARC_NL_FUSED");
-  const bool fuse = fenv ? fenv[0] == '1' : dtype == SPARC_R64;
+  const bool fuse = fenv && fenv[0] == '1';
   H->nl_fused = H->n_proj > 0 && H->max_proj_per_atom <= 4 && fuse;
   std::vector<char> pv, ec, gm;
   pack(dtype, T.vre, T.vim, pv);

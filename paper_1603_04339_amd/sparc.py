@@ -55,7 +55,7 @@ class sparc_scf_params(C.Structure):
                 ("kT", C.c_double), ("mix", C.c_double), ("tol", C.c_double), ("n_elec", C.c_double),
                 ("poisson_tol", C.c_double), ("filt", C.c_int), ("rr", C.c_int), ("final_fp64_pass", C.c_int32),
                 ("rho_init_dev", C.c_void_p), ("x0_dev", C.c_void_p), ("lanczos_v0_dev", C.c_void_p),
-                ("electrostatics", C.c_int32), ("eps_b", C.c_double)]
+                ("electrostatics", C.c_int32), ("eps_b", C.c_double), ("kerker_k0", C.c_double)]
 
 
 class sparc_scf_result(C.Structure):
@@ -92,6 +92,8 @@ _SIGS = {
                                         C.c_int32, C.c_int, C.c_void_p, C.c_int64, C.c_double, C.c_void_p]),
     "sparc_fermi": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.c_double,
                               C.c_double, C.c_void_p, C.POINTER(C.c_double)]),
+    "sparc_stream_triad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                     C.POINTER(C.c_double)]),
     "sparc_filter_plan_workspace_bytes": (C.c_size_t, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
                                                         C.POINTER(C.c_int32)]),
     "sparc_filter_plan_create": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -382,6 +384,13 @@ def sparc_fermi(ctx: Context, lam, wk, n_elec: float, kT: float, occ_w=None):
     _check(load().sparc_fermi(ctx.handle, nk, ns, _ptr(lam), _dptr(w), float(n_elec), float(kT), _ptr(occ_w),
                               C.byref(mu)))
     return mu.value
+
+
+def stream_triad(ctx: Context, a, b, c, reps: int = 10) -> float:
+    """sparc_stream_triad on three equal FP64 device tensors; returns ms per launch."""
+    ms = C.c_double()
+    _check(load().sparc_stream_triad(ctx.handle, _ptr(a), _ptr(b), _ptr(c), a.numel(), int(reps), C.byref(ms)))
+    return ms.value
 
 
 def _arr(ctype, vals):

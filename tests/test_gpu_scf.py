@@ -32,24 +32,29 @@ def _small_scf_cell():
     return cell, X0, v0
 
 
-def _params(cell, X0, v0, filt=sp.R64, tol=1e-9, max_iter=200):
+def _params(cell, X0, v0, filt=sp.R64, tol=1e-9, max_iter=200, k0=0.0):
     return dict(n_s=cell.n_s, degree=20, n_first_passes=4, max_iter=max_iter, lanczos_steps=20, mix_history=7,
                 kT=0.01, mix=0.3,
                 tol=tol, n_elec=cell.n_elec, poisson_tol=1e-12, filt=filt, rr=sp.GEMM_NATIVE, final_fp64_pass=1,
-                rho_init_dev=None, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda())
+                rho_init_dev=None, x0_dev=torch.from_numpy(X0).cuda(), lanczos_v0_dev=torch.from_numpy(v0).cuda(),
+                kerker_k0=k0)
 
 
-@pytest.fixture(scope="module")
-def oracle_ref():
+def _oracle(k0):
     cell, X0, v0 = _small_scf_cell()
     grid = Grid(n=cell.n, L=cell.L)
     V = local_potential(grid, cell.positions, cell.depth, cell.width)
     P = projectors(grid, cell.positions, cell.chan_atom, cell.chan_l, cell.chan_gamma, cell.chan_rc)
     rho0 = sad_density(grid, cell.positions, cell.width, cell.Z, cell.n_elec)
     out = oracle_scf(grid, V, P, X0.T, cell.n_elec, degree=20, rho_init=rho0, lanczos_v0=v0, tol=1e-9,
-                     max_iter=200, mix=0.3, mix_history=7)
+                     max_iter=200, mix=0.3, mix_history=7, kerker_k0=k0)
     assert out["converged"]
     return cell, X0, v0, out
+
+
+@pytest.fixture(scope="module")
+def oracle_ref():
+    return _oracle(0.0)
 
 
 def _run(ctx, cell, prm):
@@ -65,8 +70,26 @@ def test_scf_matches_oracle(ctx, oracle_ref):
     print(f"gpu: {out['iterations']} it, F={out['energy']:.10f}; oracle {ref['iterations']} it, F={ref['energy']:.10f}")
     assert out["converged"]
     assert abs(out["energy"] - ref["energy"]) / cell.n_atoms < 1e-6
+    # the same mixing sequence on both sides: iteration counts within rounding of the stop test
+    assert abs(out["iterations"] - ref["iterations"]) <= 2
     np.testing.assert_allclose(rho.cpu().numpy(), ref["rho"], atol=1e-6 * np.abs(ref["rho"]).max())
     np.testing.assert_allclose(ritz.cpu().numpy(), ref["ritz"], atol=1e-6)
+
+
+def test_scf_kerker_matches_oracle(ctx, oracle_ref):
+    """Kerker-preconditioned Anderson mixing (k0 = 1 bohr^-1): the same fixed point as
+    the plain mixing (free energy within 1e-6 Ha/atom of the unpreconditioned oracle),
+    and the same path as the oracle with the Kerker filter (iteration counts within 2,
+    energies within 1e-6 Ha/atom)."""
+    cell, X0, v0, ref = oracle_ref
+    kcell, _, _, kref = _oracle(1.0)
+    out, rho, ritz = _run(ctx, cell, _params(cell, X0, v0, k0=1.0))
+    print(f"kerker gpu: {out['iterations']} it, F={out['energy']:.10f}; oracle {kref['iterations']} it, "
+          f"F={kref['energy']:.10f}; plain oracle {ref['iterations']} it")
+    assert out["converged"]
+    assert abs(out["energy"] - kref["energy"]) / cell.n_atoms < 1e-6
+    assert abs(out["energy"] - ref["energy"]) / cell.n_atoms < 1e-6
+    assert abs(out["iterations"] - kref["iterations"]) <= 2
 
 
 @pytest.mark.parametrize("rr", [sp.GEMM_NATIVE, sp.GEMM_BF16X6, sp.GEMM_BF16X3], ids=["fp32", "bf16x6", "bf16x3"])

@@ -9,7 +9,7 @@ import pytest
 
 from oracle.fd import Grid, minus_half_laplacian
 from oracle.scf import (occupations, fermi_level, density, poisson, slater, entropy_term,
-                        harris_foulkes, sad_density, anderson_update, scf)
+                        harris_foulkes, sad_density, anderson_update, kerker, scf)
 from oracle.chefsi import rayleigh_ritz
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -203,6 +203,40 @@ def test_anderson_linear_map_terminates():
     x = rng.standard_normal(d)
     f = M @ x + c - x
     np.testing.assert_array_equal(anderson_update(x, f, [], [], 0.3, 0), x + 0.3 * f)
+
+
+def test_kerker_plane_waves_textbook_symbol():
+    """Kerker filter on plane waves of a second-order grid (n_o = 1): the factor
+    sigma / (sigma + k0^2) with the textbook symbol of the 3-point Laplacian,
+    sigma(G) = sum_s (4 / h_s^2) sin^2(G_s h_s / 2); a constant is removed."""
+    grid = Grid(n=(10, 12, 9), L=(5.0, 7.2, 4.5), n_o=1)
+    X = grid.coords()
+    k0 = 0.9
+    for m in ((1, 0, 0), (2, -3, 1), (0, 1, 4)):
+        G = np.array([2 * math.pi * m[s] / grid.L[s] for s in range(3)])
+        f = np.cos(X @ G + 0.3)
+        sig = sum(4.0 / grid.h[s] ** 2 * math.sin(G[s] * grid.h[s] / 2) ** 2 for s in range(3))
+        np.testing.assert_allclose(kerker(f, grid, k0), sig / (sig + k0 * k0) * f, atol=1e-13)
+    np.testing.assert_allclose(kerker(np.full(grid.n_d, 2.5), grid, k0), 0.0, atol=1e-13)
+
+
+def test_anderson_preconditioned_linear_map_terminates():
+    """With a fixed nonsingular linear preconditioner P the update
+    x_bar + beta P f_bar spans the Krylov space of P (M - I): finite termination as in
+    the unpreconditioned case (a wrong placement of P breaks it)."""
+    rng = np.random.default_rng(6)
+    d = 6
+    M = rng.standard_normal((d, d))
+    M *= 0.9 / np.max(np.abs(np.linalg.eigvals(M)))
+    c = rng.standard_normal(d)
+    B = rng.standard_normal((d, d))
+    Pm = B @ B.T + 0.5 * np.eye(d)
+    xs = np.linalg.solve(np.eye(d) - M, c)
+    x = np.zeros(d)
+    hx, hf = [], []
+    for _ in range(d + 1):
+        x = anderson_update(x, M @ x + c - x, hx, hf, 0.4, d, lambda f: Pm @ f)
+    assert np.linalg.norm(x - xs) < 1e-9 * np.linalg.norm(xs)
 
 
 def test_anderson_constrained_form():
