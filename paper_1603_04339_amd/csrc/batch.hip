@@ -1,11 +1,11 @@
 // Batched CheFSI over several (cell, k) problems: the Chebyshev filters of all
-// problems advance together, one stencil launch per recurrence step covering every
-// problem (per-problem arguments in a device table) with the projector scatter applied
-// inside it, the projections of each step's input launched per problem, and the whole
-// sequence captured once into a HIP graph.  The coefficients (which change with the
+// problems advance together; every recurrence step is one launch of the projections of
+// all problems, one stencil launch over all problems and one launch of the projector
+// scatters of all problems (each with per-problem arguments in a device table; the
+// scatter runs inside the stencil step for problems with fused tables), and the whole
+// sequence is captured once into a HIP graph.  The coefficients (which change with the
 // filter bounds of every pass) live in device tables rewritten before each replay, so
-// the captured graph is reused unchanged.  A problem without fused tables for the
-// plan's tile shape scatters with a separate launch.
+// the captured graph is reused unchanged.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -40,6 +40,16 @@ struct sparc_filter_plan {
   int* dev_wg;
   double* dev_a;                  // [max_deg][n_prob] scatter scale per step
   std::vector<size_t> nl_lds;     // dynamic LDS of step j's launch
+  // projections and scatters of step j: argument blocks [max_deg][n_prob] and
+  // work-group offsets [max_deg][n_prob + 1] (device, then host copies)
+  NlBatchArgs* dev_gather;
+  NlBatchArgs* dev_scatter;
+  int* dev_goff;
+  int* dev_soff;
+  std::vector<NlBatchArgs> host_gather, host_scatter;
+  std::vector<int> host_goff, host_soff, n_gather, n_scatter;
+  std::vector<int64_t> gather_wg, scatter_wg;
+  int maxp;
   std::vector<char> host_tables;
   std::vector<int> host_wg;
   std::vector<double> host_a;
@@ -57,21 +67,15 @@ static int plan_enqueue(sparc_filter_plan* P) {
   const size_t eb = elem_bytes(P->dt);
   for (int j = 0; j < P->max_deg; ++j) {
     const auto& mem = P->members[j];
-    // projections of the step input
-    for (int p : mem) {
-      const bool first = (j == 0);
-      const void* x = first ? P->X[p] : ((j - 1) % 2 == 0 ? P->W[p] : P->X[p]);
-      const int64_t ld = first ? P->ldx[p] : ((j - 1) % 2 == 0 ? P->H[p]->n_d : P->ldx[p]);
-      SPARC_TRY(nl_project(P->H[p], x, ld, P->n_s[p], P->alpha[p]));
-    }
+    // projections of the step input (all problems, one launch)
+    const size_t t0 = (size_t)j * P->n_prob, o0 = (size_t)j * (P->n_prob + 1);
+    SPARC_TRY(nl_gather_batched(P->ctx, P->dt, P->maxp, P->dev_gather + t0, P->dev_goff + o0, P->n_gather[j],
+                                P->gather_wg[j]));
     SPARC_TRY(step_table_launch(P->ctx, P->dt, P->n_o, P->tile, P->dev_tables + P->table_off[j],
                                 P->dev_wg + P->wg_off[j], (int)mem.size(), P->total_wg[j], P->dir, P->nl_lds[j]));
-    for (int p : mem) {
-      if (P->fused[p]) continue;
-      void* out = (j % 2 == 0) ? P->W[p] : P->X[p];
-      const int64_t ldo = (j % 2 == 0) ? P->H[p]->n_d : P->ldx[p];
-      SPARC_TRY(nl_scatter(P->H[p], P->alpha[p], P->n_s[p], 0.0, P->dev_a + (size_t)j * P->n_prob + p, out, ldo));
-    }
+    // projector scatters of the problems that do not apply them inside the step (one launch)
+    SPARC_TRY(nl_scatter_batched(P->ctx, P->dt, P->dev_scatter + t0, P->dev_soff + o0, P->n_scatter[j],
+                                 P->scatter_wg[j], P->dev_a + (size_t)j * P->n_prob));
   }
   // Y_m of an odd degree sits in the work block
   for (int p = 0; p < P->n_prob; ++p)
@@ -88,6 +92,8 @@ static int plan_tables(sparc_filter_plan* P, const double* lcut, const double* l
   for (int j = 0; j < P->max_deg; ++j) {
     d.clear();
     hs.clear();
+    P->n_gather[j] = P->n_scatter[j] = 0;
+    P->gather_wg[j] = P->scatter_wg[j] = 0;
     for (int p : P->members[j]) {
       const double c = 0.5 * (lmax[p] + lcut[p]), e = 0.5 * (lmax[p] - lcut[p]);
       StepDesc s;
@@ -111,7 +117,25 @@ static int plan_tables(sparc_filter_plan* P, const double* lcut, const double* l
       P->host_a[(size_t)j * P->n_prob + p] = s.a;
       d.push_back(s);
       hs.push_back(P->H[p]);
+      // projections of Y_j and (separate form) the scatter into Y_{j+1}
+      NlBatchArgs nb;
+      int gw = 0, sw = 0;
+      nl_batch_args(P->H[p], s.x, s.ldx, s.out, s.ldo, s.n_s, P->alpha[p], p, &nb, &gw, &sw);
+      if (gw > 0) {
+        P->host_gather[(size_t)j * P->n_prob + P->n_gather[j]] = nb;
+        P->host_goff[(size_t)j * (P->n_prob + 1) + P->n_gather[j]] = (int)P->gather_wg[j];
+        P->gather_wg[j] += gw;
+        P->n_gather[j]++;
+      }
+      if (sw > 0 && !P->fused[p]) {
+        P->host_scatter[(size_t)j * P->n_prob + P->n_scatter[j]] = nb;
+        P->host_soff[(size_t)j * (P->n_prob + 1) + P->n_scatter[j]] = (int)P->scatter_wg[j];
+        P->scatter_wg[j] += sw;
+        P->n_scatter[j]++;
+      }
     }
+    P->host_goff[(size_t)j * (P->n_prob + 1) + P->n_gather[j]] = (int)P->gather_wg[j];
+    P->host_soff[(size_t)j * (P->n_prob + 1) + P->n_scatter[j]] = (int)P->scatter_wg[j];
     P->nl_lds[j] = 0;
     if (d.empty()) continue;
     int64_t tot = step_table_build(hs.data(), d.data(), (int)d.size(), P->tile,
@@ -140,6 +164,8 @@ size_t sparc_filter_plan_workspace_bytes(int32_t n_prob, sparc_ham* const* H, co
   b += al256((size_t)max_deg * n_prob * step_args_bytes(H[0]->dtype));
   b += al256((size_t)max_deg * (n_prob + 1) * sizeof(int));
   b += al256((size_t)max_deg * n_prob * sizeof(double));
+  b += 2 * al256((size_t)max_deg * n_prob * sizeof(NlBatchArgs));
+  b += 2 * al256((size_t)max_deg * (n_prob + 1) * sizeof(int));
   return b;
 }
 
@@ -184,6 +210,24 @@ int sparc_filter_plan_create(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H
   P->dev_wg = (int*)w;
   w += al256((size_t)P->max_deg * (n_prob + 1) * sizeof(int));
   P->dev_a = (double*)w;
+  w += al256((size_t)P->max_deg * n_prob * sizeof(double));
+  P->dev_gather = (NlBatchArgs*)w;
+  w += al256((size_t)P->max_deg * n_prob * sizeof(NlBatchArgs));
+  P->dev_scatter = (NlBatchArgs*)w;
+  w += al256((size_t)P->max_deg * n_prob * sizeof(NlBatchArgs));
+  P->dev_goff = (int*)w;
+  w += al256((size_t)P->max_deg * (n_prob + 1) * sizeof(int));
+  P->dev_soff = (int*)w;
+  P->host_gather.assign((size_t)P->max_deg * n_prob, NlBatchArgs{});
+  P->host_scatter.assign((size_t)P->max_deg * n_prob, NlBatchArgs{});
+  P->host_goff.assign((size_t)P->max_deg * (n_prob + 1), 0);
+  P->host_soff.assign((size_t)P->max_deg * (n_prob + 1), 0);
+  P->n_gather.assign(P->max_deg, 0);
+  P->n_scatter.assign(P->max_deg, 0);
+  P->gather_wg.assign(P->max_deg, 0);
+  P->scatter_wg.assign(P->max_deg, 0);
+  P->maxp = 0;
+  for (int p = 0; p < n_prob; ++p) P->maxp = std::max(P->maxp, H[p]->max_proj_per_atom);
   P->nl_lds.assign(P->max_deg, 0);
   P->members.resize(P->max_deg);
   P->total_wg.assign(P->max_deg, 0);
@@ -261,6 +305,14 @@ int sparc_filter_plan_run(sparc_filter_plan* P, const double* lambda_cut, const 
   SPARC_HIP(hipMemcpyAsync(P->dev_tables, P->host_tables.data(), P->table_bytes, hipMemcpyHostToDevice, s));
   SPARC_HIP(hipMemcpyAsync(P->dev_wg, P->host_wg.data(), P->host_wg.size() * sizeof(int), hipMemcpyHostToDevice, s));
   SPARC_HIP(hipMemcpyAsync(P->dev_a, P->host_a.data(), P->host_a.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  SPARC_HIP(hipMemcpyAsync(P->dev_gather, P->host_gather.data(), P->host_gather.size() * sizeof(NlBatchArgs),
+                           hipMemcpyHostToDevice, s));
+  SPARC_HIP(hipMemcpyAsync(P->dev_scatter, P->host_scatter.data(), P->host_scatter.size() * sizeof(NlBatchArgs),
+                           hipMemcpyHostToDevice, s));
+  SPARC_HIP(hipMemcpyAsync(P->dev_goff, P->host_goff.data(), P->host_goff.size() * sizeof(int), hipMemcpyHostToDevice,
+                           s));
+  SPARC_HIP(hipMemcpyAsync(P->dev_soff, P->host_soff.data(), P->host_soff.size() * sizeof(int), hipMemcpyHostToDevice,
+                           s));
   if (P->use_graph) {
     int t = timer_begin(P->ctx, "filter_graph");
     SPARC_HIP(hipGraphLaunch(P->exec, s));

@@ -19,19 +19,13 @@ namespace sparc {
 // (leading dimension lda, a multiple of NB), so each entry reads NB coefficients
 // in one vector load.
 template <typename E, int NB>
-__global__ __launch_bounds__(256) void nl_scatter_kernel(int n_pts, const int32_t* __restrict__ pts,
-                                                         const int32_t* __restrict__ ptr,
-                                                         const int32_t* __restrict__ ent_proj,
-                                                         const E* __restrict__ ent_coef,
-                                                         const E* __restrict__ alpha, int lda, int n_s,
-                                                         typename elem<E>::real a, const double* a_dev,
-                                                         E* __restrict__ y, int64_t ldy) {
-  // orbital groups fastest in the grid: consecutive work-groups share the same nodes'
-  // entry lists (from L2)
-  const int i = blockIdx.y * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void nl_scatter_body(int i, int nb0, int n_pts, const int32_t* __restrict__ pts,
+                                                const int32_t* __restrict__ ptr,
+                                                const int32_t* __restrict__ ent_proj,
+                                                const E* __restrict__ ent_coef, const E* __restrict__ alpha,
+                                                int lda, int n_s, typename elem<E>::real a, E* __restrict__ y,
+                                                int64_t ldy) {
   if (i >= n_pts) return;
-  if (a_dev) a = (typename elem<E>::real)(*a_dev);
-  const int nb0 = blockIdx.x * NB;
   const int64_t g = pts[i];
   const int e0 = ptr[i], ne = ptr[i + 1] - e0;
   E acc[NB];
@@ -52,20 +46,54 @@ __global__ __launch_bounds__(256) void nl_scatter_kernel(int n_pts, const int32_
     if (nb0 + j < n_s) y[g + (int64_t)(nb0 + j) * ldy] = fmar(yv[j], a, acc[j]);
 }
 
+template <typename E, int NB>
+__global__ __launch_bounds__(256) void nl_scatter_kernel(int n_pts, const int32_t* __restrict__ pts,
+                                                         const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ ent_proj,
+                                                         const E* __restrict__ ent_coef,
+                                                         const E* __restrict__ alpha, int lda, int n_s,
+                                                         typename elem<E>::real a, const double* a_dev,
+                                                         E* __restrict__ y, int64_t ldy) {
+  // orbital groups fastest in the grid: consecutive work-groups share the same nodes'
+  // entry lists (from L2)
+  if (a_dev) a = (typename elem<E>::real)(*a_dev);
+  nl_scatter_body<E, NB>(blockIdx.y * blockDim.x + threadIdx.x, blockIdx.x * NB, n_pts, pts, ptr, ent_proj, ent_coef,
+                         alpha, lda, n_s, a, y, ldy);
+}
+
+// Several problems in one launch (work-group b of problem p as in nl_gather_batched_kernel;
+// inside it the single-problem order, orbital blocks fastest); the scale comes from the
+// device step table (a_dev[p]), so one captured launch serves every pass
+template <typename E, int NB>
+__global__ __launch_bounds__(256) void nl_scatter_batched_kernel(const NlBatchArgs* __restrict__ probs,
+                                                                 const int* __restrict__ off, int n_probs,
+                                                                 const double* __restrict__ a_dev) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n_probs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const NlBatchArgs& P = probs[lo];
+  const int local = b - off[lo];
+  const int groups = (P.n_s + NB - 1) / NB;
+  nl_scatter_body<E, NB>((local / groups) * 256 + (int)threadIdx.x, (local % groups) * NB, P.n_pts, P.pts, P.ptr,
+                         P.ent_proj, (const E*)P.ent_coef, (const E*)P.alpha, P.lda, P.n_s,
+                         (typename elem<E>::real)a_dev[P.slot], (E*)P.y, P.ldy);
+}
+
 // Non-local gather: alpha[p][n] = dV * sum_{t in supp(atom)} conj(chi~_p(t)) x(g_t, n)
 // One work-group per (atom, block of NB orbitals).
 template <typename E, int MAXP, int NB>
-__global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x, int64_t ldx, int n_s,
-                                                        const int32_t* __restrict__ sup_ptr,
-                                                        const int32_t* __restrict__ sup_idx,
-                                                        const int32_t* __restrict__ atom_pbeg,
-                                                        const int64_t* __restrict__ proj_voff,
-                                                        const E* __restrict__ pval, double dV,
-                                                        E* __restrict__ alpha, int lda) {
+__device__ __forceinline__ void nl_gather_body(int a, int nb0, const E* __restrict__ x, int64_t ldx, int n_s,
+                                               const int32_t* __restrict__ sup_ptr,
+                                               const int32_t* __restrict__ sup_idx,
+                                               const int32_t* __restrict__ atom_pbeg,
+                                               const int64_t* __restrict__ proj_voff, const E* __restrict__ pval,
+                                               double dV, E* __restrict__ alpha, int lda) {
   typedef typename elem<E>::real R;
   constexpr int NV = elem<E>::is_cplx ? 2 : 1;
-  const int a = blockIdx.x;
-  const int nb0 = blockIdx.y * NB;
   const int t0 = sup_ptr[a], t1 = sup_ptr[a + 1];
   const int pb = atom_pbeg[a], np = atom_pbeg[a + 1] - pb;
   E acc[MAXP][NB];
@@ -116,7 +144,38 @@ __global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x,
   }
 }
 
-// projections are stored [projector][orbital] with the orbital count padded to a multiple of 8
+template <typename E, int MAXP, int NB>
+__global__ __launch_bounds__(256) void nl_gather_kernel(const E* __restrict__ x, int64_t ldx, int n_s,
+                                                        const int32_t* __restrict__ sup_ptr,
+                                                        const int32_t* __restrict__ sup_idx,
+                                                        const int32_t* __restrict__ atom_pbeg,
+                                                        const int64_t* __restrict__ proj_voff,
+                                                        const E* __restrict__ pval, double dV,
+                                                        E* __restrict__ alpha, int lda) {
+  nl_gather_body<E, MAXP, NB>(blockIdx.x, blockIdx.y * NB, x, ldx, n_s, sup_ptr, sup_idx, atom_pbeg, proj_voff, pval,
+                              dV, alpha, lda);
+}
+
+// Several problems in one launch: work-group b belongs to the problem p with
+// off[p] <= b < off[p+1], and inside it to (atom, orbital block) in the order of the
+// single-problem grid (atoms fastest).
+template <typename E, int MAXP, int NB>
+__global__ __launch_bounds__(256) void nl_gather_batched_kernel(const NlBatchArgs* __restrict__ probs,
+                                                                const int* __restrict__ off, int n_probs) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n_probs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const NlBatchArgs& P = probs[lo];
+  const int local = b - off[lo];
+  nl_gather_body<E, MAXP, NB>(local % P.n_atoms, (local / P.n_atoms) * NB, (const E*)P.x, P.ldx, P.n_s, P.sup_ptr,
+                              P.sup_idx, P.atom_pbeg, P.proj_voff, (const E*)P.pval, P.dV, (E*)P.alpha, P.lda);
+}
+
+// projections are stored [projector][orbital] with the orbital count padded to a multiple of 16
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s) {
   return (size_t)std::max(H->n_proj, 1) * (size_t)alpha_ld(n_s) * elem_bytes(H->dtype);
 }
@@ -295,6 +354,83 @@ static bool nl_fill(sparc_ham* H, StepArgs<E>& A, int t, double a, const void* a
   A.lda = alpha_ld(n_s);
   A.nla = (R)a;
   return true;
+}
+
+template <typename E>
+static constexpr int gather_nb() { return elem<E>::is_cplx ? 4 : 8; }
+constexpr int kScatterNB = 16;
+
+void nl_batch_args(const sparc_ham* H, const void* x, int64_t ldx, void* y, int64_t ldy, int n_s, void* alpha,
+                   int slot, NlBatchArgs* o, int* gather_wg, int* scatter_wg) {
+  o->x = x;
+  o->ldx = ldx;
+  o->y = y;
+  o->ldy = ldy;
+  o->n_s = n_s;
+  o->lda = alpha_ld(n_s);
+  o->n_atoms = H->n_atoms_nl;
+  o->n_pts = (int)H->n_nlpts;
+  o->slot = slot;
+  o->sup_ptr = H->sup_ptr;
+  o->sup_idx = H->sup_idx;
+  o->atom_pbeg = H->atom_pbeg;
+  o->proj_voff = H->proj_voff;
+  o->pval = H->pval;
+  o->dV = H->dV;
+  o->alpha = alpha;
+  o->pts = H->nl_pts;
+  o->ptr = H->nl_ptr;
+  o->ent_proj = H->ent_proj;
+  o->ent_coef = H->ent_coef;
+  const int gnb = dtype_complex(H->dtype) ? 4 : 8;
+  const bool any = H->n_proj > 0 && H->n_nlpts > 0;
+  *gather_wg = any ? H->n_atoms_nl * ((n_s + gnb - 1) / gnb) : 0;
+  *scatter_wg = any ? (int)((H->n_nlpts + 255) / 256) * ((n_s + kScatterNB - 1) / kScatterNB) : 0;
+}
+
+template <typename E>
+static int gather_batched_t(sparc_ctx* ctx, int maxp, const NlBatchArgs* tab, const int* off, int n, int64_t total) {
+  if (total <= 0) return SPARC_OK;
+  if (total > INT32_MAX) return fail(SPARC_ESHAPE, "batched projections: too many work-groups");
+  int t = timer_begin(ctx, "nl_gather");
+  if (maxp <= 1) nl_gather_batched_kernel<E, 1, gather_nb<E>()><<<(unsigned)total, 256, 0, ctx->stream>>>(tab, off, n);
+  else nl_gather_batched_kernel<E, 4, gather_nb<E>()><<<(unsigned)total, 256, 0, ctx->stream>>>(tab, off, n);
+  timer_end(ctx, t);
+  return check_launch("nl_gather_batched_kernel");
+}
+
+int nl_gather_batched(sparc_ctx* ctx, sparc_dtype dt, int maxp, const NlBatchArgs* tab, const int* off, int n,
+                      int64_t total) {
+  if (maxp > 4) return fail(SPARC_EINVAL, "batched projections: more than 4 projector functions on one atom");
+  switch (dt) {
+    case SPARC_R64: return gather_batched_t<double>(ctx, maxp, tab, off, n, total);
+    case SPARC_R32: return gather_batched_t<float>(ctx, maxp, tab, off, n, total);
+    case SPARC_C128: return gather_batched_t<cd>(ctx, maxp, tab, off, n, total);
+    case SPARC_C64: return gather_batched_t<cf>(ctx, maxp, tab, off, n, total);
+  }
+  return fail(SPARC_EINVAL, "batched projections: bad dtype");
+}
+
+template <typename E>
+static int scatter_batched_t(sparc_ctx* ctx, const NlBatchArgs* tab, const int* off, int n, int64_t total,
+                             const double* a_dev) {
+  if (total <= 0) return SPARC_OK;
+  if (total > INT32_MAX) return fail(SPARC_ESHAPE, "batched scatter: too many work-groups");
+  int t = timer_begin(ctx, "nl_scatter");
+  nl_scatter_batched_kernel<E, kScatterNB><<<(unsigned)total, 256, 0, ctx->stream>>>(tab, off, n, a_dev);
+  timer_end(ctx, t);
+  return check_launch("nl_scatter_batched_kernel");
+}
+
+int nl_scatter_batched(sparc_ctx* ctx, sparc_dtype dt, const NlBatchArgs* tab, const int* off, int n, int64_t total,
+                       const double* a_dev) {
+  switch (dt) {
+    case SPARC_R64: return scatter_batched_t<double>(ctx, tab, off, n, total, a_dev);
+    case SPARC_R32: return scatter_batched_t<float>(ctx, tab, off, n, total, a_dev);
+    case SPARC_C128: return scatter_batched_t<cd>(ctx, tab, off, n, total, a_dev);
+    case SPARC_C64: return scatter_batched_t<cf>(ctx, tab, off, n, total, a_dev);
+  }
+  return fail(SPARC_EINVAL, "batched scatter: bad dtype");
 }
 
 int heuristic_tile(int n1, int n2, size_t elem_size) {

@@ -179,6 +179,29 @@ int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alph
 //   out += a * V_nl-scatter(alpha); a from a device scalar when a_dev != nullptr
 int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out, int64_t ldo);
 int heuristic_tile(int n1, int n2, size_t elem_size);
+// projections and scatters of several problems in one launch each (hamiltonian.hip): one
+// argument block per problem in a device table, work-group offsets per problem
+struct NlBatchArgs {
+  const void* x;      // gather input block
+  int64_t ldx;
+  void* y;            // scatter output block
+  int64_t ldy;
+  int n_s, lda, n_atoms, n_pts, slot;  // slot: index of the problem's scatter scale
+  const int32_t *sup_ptr, *sup_idx, *atom_pbeg;
+  const int64_t* proj_voff;
+  const void* pval;
+  double dV;
+  void* alpha;
+  const int32_t *pts, *ptr, *ent_proj;
+  const void* ent_coef;
+};
+//   argument block of one problem; *gather_wg / *scatter_wg: its work-groups in each launch
+void nl_batch_args(const sparc_ham* H, const void* x, int64_t ldx, void* y, int64_t ldy, int n_s, void* alpha,
+                   int slot, NlBatchArgs* out, int* gather_wg, int* scatter_wg);
+int nl_gather_batched(sparc_ctx* ctx, sparc_dtype dt, int maxp, const NlBatchArgs* dev_tab, const int* dev_off,
+                      int n, int64_t total);
+int nl_scatter_batched(sparc_ctx* ctx, sparc_dtype dt, const NlBatchArgs* dev_tab, const int* dev_off, int n,
+                       int64_t total, const double* a_dev);
 // non-local scatter inside the stencil step (hamiltonian.hip): per tile shape tables
 // from the node-major entries (nodes ascending, entries of node i in [ptr[i], ptr[i+1]),
 // key 4 atom + p, chi~ as (re, im))
