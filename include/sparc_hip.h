@@ -160,6 +160,21 @@ size_t sparc_workspace_bytes(const sparc_ham* ham, int32_t n_s, int32_t op);
 int fd_hamiltonian_apply(sparc_ham* ham, const void* X, int64_t ldx, void* Y, int64_t ldy,
                          int32_t n_s, void* work, size_t work_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): Y = H X as fd_hamiltonian_apply,
+ * with the projections held in a static device array of this library
+ * (fd_hamiltonian_apply_noalloc_max_bytes() = 16 MiB; one copy per device, resident
+ * until the process ends, its address looked up by sparc_ctx_create) instead of a
+ * workspace.  Allocates nothing, creates no events and never synchronises; the stencil
+ * tile is the heuristic one, or one the context's autotuner has already chosen.
+ * Every call on one device shares that array: calls that overlap on one device (two
+ * streams, two threads) race and must be ordered by the caller.  Errors: as
+ * fd_hamiltonian_apply; ENOMEM when the projections (SPARC_OP_APPLY bytes of
+ * sparc_workspace_bytes) exceed the array, EDEVICE if the array was not found. */
+size_t fd_hamiltonian_apply_noalloc_max_bytes(void);
+int fd_hamiltonian_apply_noalloc(sparc_ham* ham, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                                 int32_t n_s);
+
 /* Chebyshev filter (Sec. 3.4, Eq. of the filter): X <- C_m((H - c)/e) X with
  * c = (lambda_max + lambda_cut)/2, e = (lambda_max - lambda_cut)/2, by the
  * three-term recurrence Y_1 = (H - c)X/e, Y_{j+1} = 2(H - c)Y_j/e - Y_{j-1}

@@ -24,12 +24,12 @@ struct Carver {
 };
 static size_t al(size_t b) { return ((b + 255) / 256) * 256; }
 
-static int check_ham(const sparc_ham* H, const char* who) {
+int check_ham(const sparc_ham* H, const char* who) {
   if (!H) return fail(SPARC_EINVAL, "%s: ham is NULL", who);
   return SPARC_OK;
 }
 
-static int check_block(const sparc_ham* H, const void* X, int64_t ldx, int32_t n_s, const char* who) {
+int check_block(const sparc_ham* H, const void* X, int64_t ldx, int32_t n_s, const char* who) {
   if (!X) return fail(SPARC_EINVAL, "%s: block pointer is NULL", who);
   if (n_s < 1) return fail(SPARC_ESHAPE, "%s: n_s=%d < 1", who, n_s);
   if (ldx < H->n_d) return fail(SPARC_ESHAPE, "%s: ld=%lld < N_d=%lld", who, (long long)ldx, (long long)H->n_d);

@@ -569,7 +569,7 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   if (nonlocal && !alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
   const void* al = nonlocal ? alpha : nullptr;
   int t = heuristic_tile(A.n1, A.n2, sizeof(E));
-  if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && z == nullptr && out != x)
+  if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && !(flags & STEP_NO_TUNE) && z == nullptr && out != x)
     SPARC_TRY(autotune(H, A, n_s, &t, a, al));
   const bool fused = nl_fill(H, A, t, a, al, n_s);
   SPARC_TRY(hstep_single<E>(H->ctx, A, n_s, H->grid.n_o, t));

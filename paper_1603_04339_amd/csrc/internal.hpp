@@ -169,13 +169,21 @@ extern sparc_ctx* g_timer_ctx;
 //   Runs the stencil/potential/recurrence kernel, then the non-local scatter into out.
 //   alpha: projections [n_s][n_proj] of x (already scaled by dV), from nl_project.
 //   flags: STEP_NO_VEFF drops the potential term, STEP_NO_NONLOCAL the projector term
-//   (both together give a * (-1/2 Lap_h x) + b x + c z, used by the Poisson solver).
+//   (both together give a * (-1/2 Lap_h x) + b x + c z, used by the Poisson solver);
+//   STEP_NO_TUNE keeps the heuristic tile (or an already tuned one) where the autotuner
+//   would time the shapes (it creates events and synchronises).
 //   With tables for the chosen tile shape the projector term is applied inside the
 //   stencil kernel; otherwise the scatter kernel runs after it.
-enum { STEP_NO_VEFF = 1, STEP_NO_NONLOCAL = 2 };
+enum { STEP_NO_VEFF = 1, STEP_NO_NONLOCAL = 2, STEP_NO_TUNE = 4 };
 int ham_step(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
              int32_t n_s, double a, double b, double c, const void* alpha, int flags = 0);
 int nl_project(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha);
+// argument checks shared by the entry points (api.hip)
+int check_ham(const sparc_ham* H, const char* who);
+int check_block(const sparc_ham* H, const void* X, int64_t ldx, int32_t n_s, const char* who);
+// device address of this library's static scratch on `device` (noalloc.hip); called with
+// the device current when a context is created
+int noalloc_scratch_init(int device);
 //   out += a * V_nl-scatter(alpha); a from a device scalar when a_dev != nullptr
 int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out, int64_t ldo);
 int heuristic_tile(int n1, int n2, size_t elem_size);

@@ -265,6 +265,7 @@ int sparc_ctx_create(int device, void* hip_stream, sparc_ctx** out) {
     return fail(SPARC_EDEVICE, "sparc_ctx_create: device %d not available (%d devices, %s)", device, n,
                 hipGetErrorString(e));
   SPARC_HIP(hipSetDevice(device));
+  SPARC_TRY(noalloc_scratch_init(device));
   hipDeviceProp_t prop;
   SPARC_HIP(hipGetDeviceProperties(&prop, device));
   sparc_ctx* c = new sparc_ctx;

@@ -82,6 +82,9 @@ _SIGS = {
     "sparc_workspace_bytes": (C.c_size_t, [C.c_void_p, C.c_int32, C.c_int32]),
     "fd_hamiltonian_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
                                        C.c_void_p, C.c_size_t]),
+    "fd_hamiltonian_apply_noalloc_max_bytes": (C.c_size_t, []),
+    "fd_hamiltonian_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                               C.c_int32]),
     "chebyshev_filter": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_double,
                                    C.c_double, C.c_void_p, C.c_size_t]),
     "rayleigh_ritz": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int, C.c_void_p, C.c_void_p,
@@ -325,6 +328,17 @@ def fd_hamiltonian_apply(ham: Hamiltonian, X, Y, work):
     Y, ldy, _ = _block(Y, ham)
     _check(load().fd_hamiltonian_apply(ham.handle, _ptr(X), ldx, _ptr(Y), ldy, ns, _ptr(work), work.numel()))
     return Y
+
+
+def fd_hamiltonian_apply_noalloc(ham: Hamiltonian, X, Y):
+    X, ldx, ns = _block(X, ham)
+    Y, ldy, _ = _block(Y, ham)
+    _check(load().fd_hamiltonian_apply_noalloc(ham.handle, _ptr(X), ldx, _ptr(Y), ldy, ns))
+    return Y
+
+
+def noalloc_max_bytes() -> int:
+    return int(load().fd_hamiltonian_apply_noalloc_max_bytes())
 
 
 def chebyshev_filter(ham: Hamiltonian, X, degree: int, lambda_cut: float, lambda_max: float, work):
