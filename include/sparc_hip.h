@@ -238,9 +238,9 @@ int sparc_fermi(sparc_ctx* ctx, int32_t n_k, int32_t n_s, const double* lambda_d
 /* ---- batched forms: several (cell, k) problems advanced together --------------------
  * A filter plan binds n_prob Hamiltonians (same context, dtype and stencil order) to
  * their orbital blocks X[p] (ld ldx[p], n_s[p] states) and filter degrees.  Each
- * recurrence step of every problem runs in one stencil launch covering all problems
- * (per-problem arguments in a device table); the projector gather/scatter run per
- * problem.  With use_graph the whole sequence is captured once into a HIP graph
+ * recurrence step of every problem is one launch of the projections of all problems,
+ * one stencil launch covering all problems and one launch of the projector scatters
+ * of all problems (per-problem arguments in device tables).  With use_graph the whole sequence is captured once into a HIP graph
  * (on a private stream) and replayed by sparc_filter_plan_run; the coefficients,
  * which depend on the bounds, are uploaded to device tables before each replay.
  * Results equal those of chebyshev_filter on each problem.  work: caller-owned,

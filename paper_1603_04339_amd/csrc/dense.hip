@@ -5,10 +5,11 @@
 //   * Hermitian eigensolver: Householder reduction to a real symmetric
 //     tridiagonal (blocked: one work-group per 32-column panel, the trailing
 //     update on many work-groups; matrix resident in L2), eigenvalues by Sturm
-//     bisection (one thread per eigenvalue), eigenvectors by inverse iteration
-//     with pivoted tridiagonal LU (one thread per cluster of close eigenvalues,
-//     Gram-Schmidt inside a cluster), and the back-transformation by the
-//     Householder reflectors (one wave per column).
+//     multisection (one wave per eigenvalue, 64 Sturm counts per round),
+//     eigenvectors by inverse iteration with pivoted tridiagonal LU (one 64-lane
+//     work-group per cluster of close eigenvalues, the factorisation on lane 0 with
+//     its factors in LDS, Gram-Schmidt inside a cluster), and the
+//     back-transformation by the Householder reflectors (one wave per column).
 // Matrices are column-major with leading dimension n; complex matrices are
 // interleaved (re, im).
 #include <algorithm>

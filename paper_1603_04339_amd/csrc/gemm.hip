@@ -414,10 +414,50 @@ __global__ void gram_reduce_kernel(int na, int nb, int n_slab, const double* __r
   }
 }
 
+// The same sum for small outputs over many slabs: one wave per output element, lanes
+// over the slabs (lane l takes slabs l, l + 64, ...), then a fixed butterfly.
+__global__ __launch_bounds__(256) void gram_reduce_wave_kernel(int na, int nb, int n_slab,
+                                                               const double* __restrict__ part, double* __restrict__ C,
+                                                               int ldc, int cplx, int herm) {
+  const int64_t idx = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (idx >= (int64_t)na * nb) return;
+  int i = (int)(idx % na), j = (int)(idx / na);
+  int si = i, sj = j;
+  bool conj_ = false;
+  if (herm && i > j) { si = j; sj = i; conj_ = true; }
+  const int64_t mat = (int64_t)na * nb * (cplx ? 2 : 1);
+  const int64_t off = (si + (int64_t)sj * na) * (cplx ? 2 : 1);
+  double re = 0, im = 0;
+  for (int s = lane; s < n_slab; s += 64) {
+    re += part[s * mat + off];
+    if (cplx) im += part[s * mat + off + 1];
+  }
+  re = wave_sum(re);
+  if (cplx) im = wave_sum(im);
+  if (lane != 0) return;
+  if (herm && i == j) im = 0;
+  if (cplx) {
+    C[2 * (i + (int64_t)j * ldc)] = re;
+    C[2 * (i + (int64_t)j * ldc) + 1] = conj_ ? -im : im;
+  } else {
+    C[i + (int64_t)j * ldc] = re;
+  }
+}
+
 struct GramPlan {
   int tiles_a, tiles_b, n_tiles, n_slab;
   int64_t slab_len;
 };
+
+// Most slabs a product may use (sizes the partial-sum workspace): 256 in general, up to
+// 2048 for skinny products (na * nb <= 32, e.g. the Lanczos projections), so that these
+// too spread over the chip.  cap * na * nb never decreases with na * nb, so a workspace
+// sized for a product also fits every smaller one.
+static int64_t gram_cap(int na, int nb) {
+  const int64_t e = std::max<int64_t>(1, (int64_t)na * nb);
+  return std::max<int64_t>(256, std::min<int64_t>(2048, 65536 / e));
+}
 
 static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T) {
   GramPlan p;
@@ -427,10 +467,12 @@ static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T)
   for (int tj = 0; tj < p.tiles_b; ++tj)
     for (int ti = 0; ti < p.tiles_a; ++ti)
       if (!herm || ti <= tj) p.n_tiles++;
-  // 256 slabs (each at least 2048 nodes): with an even tile count the items fill whole
-  // rounds of the persistent grid (two work-groups on each of 256 CUs)
-  (void)n_cu;
-  int64_t s = std::max<int64_t>(1, std::min<int64_t>(256, N / 2048));
+  // slabs of 2048 nodes; where that leaves fewer (slab, tile) items than two rounds of
+  // work-groups on every CU (four for small outputs), shorter slabs down to 256 nodes
+  const int64_t items_min = (int64_t)(((int64_t)na * nb <= 1024) ? 4 : 2) * std::max(n_cu, 1);
+  int64_t s = N / 2048;
+  if (s * p.n_tiles < items_min) s = std::min<int64_t>((items_min + p.n_tiles - 1) / p.n_tiles, N / 256);
+  s = std::max<int64_t>(1, std::min<int64_t>(gram_cap(na, nb), s));
   p.slab_len = (N + s - 1) / s;
   p.slab_len = ((p.slab_len + 15) / 16) * 16;
   p.n_slab = (int)((N + p.slab_len - 1) / p.slab_len);
@@ -438,10 +480,26 @@ static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T)
 }
 
 size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt) {
-  GramPlan p = gram_plan(N, n_a, n_b, false, 256, 64);
-  // plans for other CU counts use at most 256 slabs
-  int64_t slabs = 256;  // plans never use more slabs
-  return (size_t)slabs * n_a * n_b * 8 * (dtype_complex(dt) ? 2 : 1);
+  (void)N;
+  return (size_t)gram_cap(n_a, n_b) * n_a * n_b * 8 * (dtype_complex(dt) ? 2 : 1);
+}
+
+// tile edge of the native products: the smallest of 32, 64 and the type's full tile that
+// covers the larger dimension of the output (less padding in the MFMA blocks)
+template <typename E>
+static int native_tile(int na, int nb) {
+  const int m = std::max(na, nb);
+  if (m <= 32) return 32;
+  if (m <= 64 || elem<E>::is_cplx) return 64;
+  return 128;
+}
+
+template <typename E, int T>
+static void gram_native_launch(hipStream_t s, int grid, int64_t N, int na, int nb, const E* A, int64_t lda,
+                               const E* B, int64_t ldb, const GramPlan& p, int herm, double* part, int remap,
+                               int vec) {
+  gram_kernel<E, T, 16><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
+                                              herm, part, remap, vec);
 }
 
 template <typename E>
@@ -449,7 +507,10 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
                   int ldc, void* work, size_t work_bytes, int n_cu, bool herm_result,
                   sparc_gemm_mode mode = SPARC_GEMM_NATIVE) {
   const bool herm = (na == nb) && (herm_result || ((A == B) && (lda == ldb)));
-  constexpr int T = gram_tile<E>::T;
+  const bool split = mode != SPARC_GEMM_NATIVE;
+  if constexpr (sizeof(typename elem<E>::real) == 8)
+    if (split) return fail(SPARC_EINVAL, "gram: split-BF16 modes take FP32 blocks");
+  const int T = split ? gram_tile<E>::T : native_tile<E>(na, nb);
   GramPlan p = gram_plan(N, na, nb, herm, n_cu, T);
   // persistent grid: two work-groups per CU (a multiple of 8), at most one per item
   const int items = p.n_slab * p.n_tiles;
@@ -462,26 +523,34 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
   int remap = (grid % 8 == 0) ? 1 : 0;
   int tmr = timer_begin(g_timer_ctx, "gram");
   const int vec = (lda % 2 == 0 && ldb % 2 == 0 && ((uintptr_t)A % 16) == 0 && ((uintptr_t)B % 16) == 0) ? 1 : 0;
+  bool launched = false;
   if constexpr (sizeof(typename elem<E>::real) == 4) {
-    if (mode == SPARC_GEMM_BF16X3)
-      gram_split_kernel<E, T, 32, 2><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
-                                                           p.n_tiles, herm ? 1 : 0, part, remap, vec);
-    else if (mode == SPARC_GEMM_BF16X6)
-      gram_split_kernel<E, T, 32, 3><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
-                                                           p.n_tiles, herm ? 1 : 0, part, remap, vec);
-    else
-      gram_kernel<E, T, 16><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
-                                                  p.n_tiles, herm ? 1 : 0, part, remap, vec);
-  } else {
-    if (mode != SPARC_GEMM_NATIVE) return fail(SPARC_EINVAL, "gram: split-BF16 modes take FP32 blocks");
-    gram_kernel<E, T, 16><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a, p.n_tiles,
-                                                herm ? 1 : 0, part, remap, vec);
+    constexpr int TS = gram_tile<E>::T;
+    if (mode == SPARC_GEMM_BF16X3) {
+      gram_split_kernel<E, TS, 32, 2><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
+                                                            p.n_tiles, herm ? 1 : 0, part, remap, vec);
+      launched = true;
+    } else if (mode == SPARC_GEMM_BF16X6) {
+      gram_split_kernel<E, TS, 32, 3><<<grid, 256, 0, s>>>(N, na, nb, A, lda, B, ldb, p.n_slab, p.slab_len, p.tiles_a,
+                                                            p.n_tiles, herm ? 1 : 0, part, remap, vec);
+      launched = true;
+    }
+  }
+  if (!launched) {
+    if (T == 32) gram_native_launch<E, 32>(s, grid, N, na, nb, A, lda, B, ldb, p, herm ? 1 : 0, part, remap, vec);
+    else if (T == 64) gram_native_launch<E, 64>(s, grid, N, na, nb, A, lda, B, ldb, p, herm ? 1 : 0, part, remap, vec);
+    else if constexpr (!elem<E>::is_cplx)
+      gram_native_launch<E, 128>(s, grid, N, na, nb, A, lda, B, ldb, p, herm ? 1 : 0, part, remap, vec);
   }
   timer_end(g_timer_ctx, tmr);
   SPARC_TRY(check_launch("gram_kernel"));
   int64_t ne = (int64_t)na * nb;
-  gram_reduce_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(na, nb, p.n_slab, part, (double*)C, ldc,
-                                                                  cplx ? 1 : 0, herm ? 1 : 0);
+  if (ne <= 4096 && p.n_slab > 64)
+    gram_reduce_wave_kernel<<<(unsigned)((ne + 3) / 4), 256, 0, s>>>(na, nb, p.n_slab, part, (double*)C, ldc,
+                                                                     cplx ? 1 : 0, herm ? 1 : 0);
+  else
+    gram_reduce_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(na, nb, p.n_slab, part, (double*)C, ldc,
+                                                                    cplx ? 1 : 0, herm ? 1 : 0);
   return check_launch("gram_reduce_kernel");
 }
 
@@ -661,10 +730,19 @@ __global__ __launch_bounds__(256) void rotate_kernel(int64_t N, int n_in, int n_
       }
 }
 
+template <typename E, int T>
+static void rotate_launch(hipStream_t s, int64_t total, int64_t N, int n_in, int n_out, const E* A, int64_t lda,
+                          const double* Q, int ldq, E* Out, int64_t ldo, int tiles_n, int remap, int q_upper, int vec,
+                          int qvec) {
+  rotate_kernel<E, T><<<(unsigned)total, 256, 0, s>>>(N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap,
+                                                       total, q_upper, vec, qvec);
+}
+
 template <typename E>
 static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, int64_t lda, const double* Q, int ldq,
                     E* Out, int64_t ldo, int q_upper) {
-  constexpr int T = gram_tile<E>::T;
+  // tile edge from the output width (rows of A per work-group = output columns per tile)
+  const int T = n_out <= 32 ? 32 : (n_out <= 64 || elem<E>::is_cplx) ? 64 : 128;
   int tiles_n = (n_out + T - 1) / T;
   int64_t tiles_m = (N + T - 1) / T;
   int64_t total = tiles_m * tiles_n;
@@ -673,8 +751,10 @@ static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, i
   int tmr = timer_begin(g_timer_ctx, "rotate");
   const int vec = (lda % 2 == 0 && ((uintptr_t)A % 16) == 0) ? 1 : 0;
   const int qvec = (ldq % 2 == 0 && ((uintptr_t)Q % 16) == 0) ? 1 : 0;
-  rotate_kernel<E, T><<<(unsigned)total, 256, 0, s>>>(N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap,
-                                                       total, q_upper, vec, qvec);
+  if (T == 32) rotate_launch<E, 32>(s, total, N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap, q_upper, vec, qvec);
+  else if (T == 64) rotate_launch<E, 64>(s, total, N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap, q_upper, vec, qvec);
+  else if constexpr (!elem<E>::is_cplx)
+    rotate_launch<E, 128>(s, total, N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap, q_upper, vec, qvec);
   timer_end(g_timer_ctx, tmr);
   return check_launch("rotate_kernel");
 }
