@@ -418,6 +418,7 @@ def run_gamma(args, sp, wl, cell, X0, v0, cpu=None):
     import torch
     log(f"[bench] {args.config}: n={cell.n} N_s={cell.n_s} m={cell.degree}")
     ctx = sp.Context(0)
+    sp.set_autotune(ctx, not args.no_autotune)  # stencil tile and GEMM shapes timed in the warm-up
     main = gamma_leg(sp, ctx, cell, X0, v0, args.precision, args.steps, args.warmup, args.precision,
                      rr_mode=RR_MODES[args.rr])
     nd, ns = cell.n_d, cell.n_s
@@ -435,7 +436,7 @@ def run_gamma(args, sp, wl, cell, X0, v0, cpu=None):
                          f"degree {cell.degree}, Gamma point, "
                          f"{'FP64' if args.precision == 'f64' else 'FP32 filter/GEMMs + FP64 dense'}; "
                          f"step = filter + Rayleigh-Ritz + Fermi + density"),
-            "n_d": nd, "n_s": ns, "degree": cell.degree, "n_k": 1,
+            "n_d": nd, "n_s": ns, "degree": cell.degree, "n_k": 1, "autotune": not args.no_autotune,
         },
         "filter_ms": main["filter_ms"], "filter_throughput": main["filter_throughput"],
         "roofline": main["roofline"], "step_breakdown_ms": main["step_breakdown_ms"],
@@ -708,7 +709,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="batched configs: keep the heuristic stencil tile instead of timing every shape")
+                    help="keep the heuristic stencil tile and GEMM shapes instead of timing them per shape")
     ap.add_argument("--rr", default="native", choices=list(RR_MODES),
                     help="Rayleigh-Ritz contractions of the --precision mixed form: FP32 MFMA or split-BF16")
     ap.add_argument("--no-scf", action="store_true")

@@ -339,7 +339,7 @@ static int rr_rotate(sparc_ham* H, sparc_gemm_mode mode, int32_t n, const void* 
   hipStream_t s = H->ctx->stream;
   if (mode == SPARC_GEMM_BF16X3 && dtype_single(H->dtype) && n % 16 == 0)
     return rotate_split_x3(s, H->dtype, H->n_d, n, n, A, lda, Q, n, Out, ldo, q_upper, w.W2, w.qp);
-  return rotate(s, H->dtype, H->n_d, n, n, A, lda, Q, n, Out, ldo, q_upper);
+  return rotate(s, H->dtype, H->n_d, n, n, A, lda, Q, n, Out, ldo, q_upper, H->ctx);
 }
 
 int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode, double* ritz, RRWork& w,
@@ -353,7 +353,7 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
   g_timer_ctx = H->ctx;
   int info = 0;
   // pass 1: T1 from the Gram matrix of X (shifted if it is numerically singular)
-  SPARC_TRY(gram(s, dt, N, n, n, X, ldx, X, ldx, w.M, n, w.gw, w.gw_bytes, mode, ncu));
+  SPARC_TRY(gram(s, dt, N, n, n, X, ldx, X, ldx, w.M, n, w.gw, w.gw_bytes, mode, ncu, false, H->ctx));
   bool shifted = false;
   SPARC_TRY(chol_orth(s, cp, n, w.M, w.T1, w.info, w.cw, 0.0));
   SPARC_HIP(hipMemcpyAsync(&info, w.info, 4, hipMemcpyDeviceToHost, s));
@@ -371,7 +371,7 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
   }
   SPARC_TRY(rr_rotate(H, mode, n, X, ldx, w.T1, w.W1, N, 1, w));
   if (shifted) {  // one more explicit pass after a shifted factorisation
-    SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W1, N, w.M, n, w.gw, w.gw_bytes, mode, ncu));
+    SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W1, N, w.M, n, w.gw, w.gw_bytes, mode, ncu, false, H->ctx));
     SPARC_TRY(chol_orth(s, cp, n, w.M, w.T1, w.info, w.cw, 0.0));
     SPARC_HIP(hipMemcpyAsync(&info, w.info, 4, hipMemcpyDeviceToHost, s));
     SPARC_HIP(hipStreamSynchronize(s));
@@ -384,12 +384,12 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
                                hipMemcpyDeviceToDevice, s));
   }
   // pass 2 (implicit): T2 from the Gram matrix of X1 = X T1
-  SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W1, N, w.M, n, w.gw, w.gw_bytes, mode, ncu));
+  SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W1, N, w.M, n, w.gw, w.gw_bytes, mode, ncu, false, H->ctx));
   SPARC_TRY(chol_orth(s, cp, n, w.M, w.T2, w.info, w.cw, 0.0));
   // H X1 and the projected matrix A1 = X1^H H X1 (Hermitian: its upper triangle, mirrored)
   SPARC_TRY(nl_project(H, w.W1, N, n, w.alpha));
   SPARC_TRY(ham_step(H, w.W1, N, nullptr, 0, w.W2, N, n, 1.0, 0.0, 0.0, w.alpha));
-  SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W2, N, w.A1, n, w.gw, w.gw_bytes, mode, ncu, true));
+  SPARC_TRY(gram(s, dt, N, n, n, w.W1, N, w.W2, N, w.A1, n, w.gw, w.gw_bytes, mode, ncu, true, H->ctx));
   // H~ = T2^H A1 T2 (FP64, Hermitian by the same mirror), symmetrised
   SPARC_TRY(rotate(s, sdt, n, n, n, w.A1, n, w.T2, n, w.tmp, n, 1));
   SPARC_TRY(gram(s, sdt, n, n, n, w.T2, n, w.tmp, n, w.A1, n, w.gw, w.gw_bytes, SPARC_GEMM_NATIVE, ncu, true));

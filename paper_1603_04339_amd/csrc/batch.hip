@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "devmath.hpp"
@@ -147,6 +149,89 @@ static int plan_tables(sparc_filter_plan* P, const double* lcut, const double* l
   return SPARC_OK;
 }
 
+// Stencil tile of a plan when the context autotunes: every shape is timed on the plan's
+// own batched step over all problems, in the recurrence's memory pattern (X_p read,
+// W_p read and written: x = X_p, z = out = W_p), three launches back to back after a
+// warm-up, best of two such runs; X is only read and W is workspace.  The choice is
+// kept per set of problem shapes.
+static std::mutex g_plan_tune_mu;
+static std::map<std::vector<int>, int> g_plan_tune;
+
+static int plan_tune_tile(sparc_filter_plan* P) {
+  std::vector<int> key;
+  for (int p = 0; p < P->n_prob; ++p) {
+    const sparc_ham* h = P->H[p];
+    key.insert(key.end(), {h->grid.n[0], h->grid.n[1], h->grid.n[2], P->n_s[p], (int)h->dtype, h->grid.n_o,
+                           dirichlet_mask(h->grid)});
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_plan_tune_mu);
+    auto it = g_plan_tune.find(key);
+    if (it != g_plan_tune.end()) { P->tile = it->second; return SPARC_OK; }
+  }
+  sparc_ctx* ctx = P->ctx;
+  const int n = P->n_prob;
+  std::vector<StepDesc> d(n);
+  std::vector<sparc_ham*> hs(P->H);
+  hipEvent_t e0, e1;
+  SPARC_HIP(hipEventCreate(&e0));
+  SPARC_HIP(hipEventCreate(&e1));
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  int best = P->tile, rc = SPARC_OK;
+  float best_ms = 1e30f;
+  char* tab = P->host_tables.data() + P->table_off[0];
+  int* wg = P->host_wg.data() + P->wg_off[0];
+  // step 0 has every problem as a member: its table and offsets hold n blocks
+  const size_t tab_bytes = (P->max_deg > 1 ? P->table_off[1] : P->table_bytes) - P->table_off[0];
+  for (int t = 0; t < tile_shape_count() && rc == SPARC_OK; ++t) {
+    if (tile_shape_threads(t) > 1024) continue;
+    for (int p = 0; p < n; ++p) {
+      StepDesc& s = d[p];
+      const int64_t nd = P->H[p]->n_d;
+      s.n_s = P->n_s[p];
+      s.x = P->X[p]; s.ldx = P->ldx[p];
+      s.z = P->W[p]; s.ldz = nd;
+      s.out = P->W[p]; s.ldo = nd;
+      s.a = 0.05; s.b = 0.0; s.c = 0.0;
+      s.alpha = nl_step_fused(P->H[p], t) ? P->alpha[p] : nullptr;
+    }
+    size_t lds = 0;
+    const int64_t tot = step_table_build(hs.data(), d.data(), n, t, tab, wg, &lds);
+    if (tot < 0) { rc = fail(SPARC_EINVAL, "filter plan: bad dtype"); break; }
+    hipError_t e = hipMemcpyAsync(P->dev_tables + P->table_off[0], tab, tab_bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P->dev_wg + P->wg_off[0], wg, (size_t)(n + 1) * sizeof(int), hipMemcpyHostToDevice,
+                         ctx->stream);
+    if (e != hipSuccess) { rc = fail(SPARC_EDEVICE, "filter plan: %s", hipGetErrorString(e)); break; }
+    auto launch = [&]() {
+      return step_table_launch(ctx, P->dt, P->n_o, t, P->dev_tables + P->table_off[0], P->dev_wg + P->wg_off[0], n,
+                               tot, P->dir, lds);
+    };
+    rc = launch();  // warm-up
+    float t_best = 1e30f;
+    for (int r = 0; r < 2 && rc == SPARC_OK; ++r) {
+      hipEventRecord(e0, ctx->stream);
+      for (int q = 0; q < 3 && rc == SPARC_OK; ++q) rc = launch();
+      hipEventRecord(e1, ctx->stream);
+      if (rc != SPARC_OK) break;
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      t_best = std::min(t_best, ms);
+    }
+    if (rc == SPARC_OK && t_best < best_ms) { best_ms = t_best; best = t; }
+  }
+  ctx->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SPARC_OK) return rc;
+  P->tile = best;
+  std::lock_guard<std::mutex> lk(g_plan_tune_mu);
+  g_plan_tune[key] = best;
+  return SPARC_OK;
+}
+
 }  // namespace sparc
 
 extern "C" {
@@ -251,13 +336,8 @@ int sparc_filter_plan_create(sparc_ctx* ctx, int32_t n_prob, sparc_ham* const* H
   P->dir = 0;
   for (int p = 0; p < n_prob; ++p) P->dir |= dirichlet_mask(H[p]->grid) != 0 ? 1 : 0;
   if (ctx->autotune) {
-    int t;
-    if (!tuned_tile(H[big], n_s[big], &t)) {
-      int rc = fd_hamiltonian_apply(H[big], X[big], ldx[big], P->W[big], H[big]->n_d, n_s[big], P->alpha[big],
-                                    alpha_bytes(H[big], n_s[big]));
-      if (rc != SPARC_OK) { delete P; return rc; }
-    }
-    if (tuned_tile(H[big], n_s[big], &t)) P->tile = t;
+    int rc = plan_tune_tile(P);
+    if (rc != SPARC_OK) { delete P; return rc; }
   }
   for (int p = 0; p < n_prob; ++p) P->fused.push_back(nl_step_fused(H[p], P->tile) ? 1 : 0);
   P->use_graph = use_graph != 0;

@@ -17,6 +17,10 @@
 // A[i][k] in lane i + 16k, B[k][j] in lane j + 16k.  Result element v of lane
 // l is C[l/16 + 4v][l%16] for f64 and C[4(l/16) + v][l%16] for f32.
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
 
 #include "devmath.hpp"
 
@@ -459,7 +463,7 @@ static int64_t gram_cap(int na, int nb) {
   return std::max<int64_t>(256, std::min<int64_t>(2048, 65536 / e));
 }
 
-static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T) {
+static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T, int64_t slabs = 0) {
   GramPlan p;
   p.tiles_a = (na + T - 1) / T;
   p.tiles_b = (nb + T - 1) / T;
@@ -472,6 +476,7 @@ static GramPlan gram_plan(int64_t N, int na, int nb, bool herm, int n_cu, int T)
   const int64_t items_min = (int64_t)(((int64_t)na * nb <= 1024) ? 4 : 2) * std::max(n_cu, 1);
   int64_t s = N / 2048;
   if (s * p.n_tiles < items_min) s = std::min<int64_t>((items_min + p.n_tiles - 1) / p.n_tiles, N / 256);
+  if (slabs > 0) s = slabs;  // a tuned count
   s = std::max<int64_t>(1, std::min<int64_t>(gram_cap(na, nb), s));
   p.slab_len = (N + s - 1) / s;
   p.slab_len = ((p.slab_len + 15) / 16) * 16;
@@ -502,16 +507,12 @@ static void gram_native_launch(hipStream_t s, int grid, int64_t N, int na, int n
                                               herm, part, remap, vec);
 }
 
+// one product with tile edge T and (when slabs > 0) that many slabs
 template <typename E>
-static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t lda, const E* B, int64_t ldb, void* C,
-                  int ldc, void* work, size_t work_bytes, int n_cu, bool herm_result,
-                  sparc_gemm_mode mode = SPARC_GEMM_NATIVE) {
-  const bool herm = (na == nb) && (herm_result || ((A == B) && (lda == ldb)));
-  const bool split = mode != SPARC_GEMM_NATIVE;
-  if constexpr (sizeof(typename elem<E>::real) == 8)
-    if (split) return fail(SPARC_EINVAL, "gram: split-BF16 modes take FP32 blocks");
-  const int T = split ? gram_tile<E>::T : native_tile<E>(na, nb);
-  GramPlan p = gram_plan(N, na, nb, herm, n_cu, T);
+static int gram_launch(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t lda, const E* B, int64_t ldb,
+                       void* C, int ldc, void* work, size_t work_bytes, int n_cu, bool herm, sparc_gemm_mode mode, int T,
+                       int64_t slabs) {
+  GramPlan p = gram_plan(N, na, nb, herm, n_cu, T, slabs);
   // persistent grid: two work-groups per CU (a multiple of 8), at most one per item
   const int items = p.n_slab * p.n_tiles;
   int grid = std::min(items, 2 * n_cu);
@@ -554,14 +555,106 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
   return check_launch("gram_reduce_kernel");
 }
 
+// ------------------------------------------------------------ GEMM shape tuner
+// With a context that autotunes, the first product of a new shape (N, n_a, n_b, type,
+// Hermitian) times the tile edges next to the heuristic's (32 / 64 / 128) and, for the
+// Gram, slab counts of half, one and two times the plan's, each launch once to warm up
+// and twice timed with HIP events, and keeps the fastest; the heuristic's own choice is
+// among the candidates.  Later products of that shape reuse it.
+struct GemmChoice { int T; int64_t slabs; };
+static std::mutex g_gemm_tune_mu;
+static std::map<std::tuple<int64_t, int, int, int, int, int>, GemmChoice> g_gemm_tune;
+
+static bool gemm_lookup(const std::tuple<int64_t, int, int, int, int, int>& key, GemmChoice* c) {
+  std::lock_guard<std::mutex> lk(g_gemm_tune_mu);
+  auto it = g_gemm_tune.find(key);
+  if (it == g_gemm_tune.end()) return false;
+  *c = it->second;
+  return true;
+}
+
+static void gemm_store(const std::tuple<int64_t, int, int, int, int, int>& key, GemmChoice c) {
+  std::lock_guard<std::mutex> lk(g_gemm_tune_mu);
+  g_gemm_tune[key] = c;
+}
+
+template <typename E>
+static std::vector<int> tile_candidates(int T0) {
+  std::vector<int> v;
+  for (int T : {32, 64, 128}) {
+    if (T == 128 && elem<E>::is_cplx) continue;
+    if (T >= T0 / 2 && T <= T0 * 2) v.push_back(T);
+  }
+  return v;
+}
+
+// times fn() (one warm-up, then the best of two timed calls) on stream s; -1 on failure
+template <typename F>
+static float time_best(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F&& fn) {
+  if (fn() != SPARC_OK) return -1.0f;
+  float best = 1e30f;
+  for (int r = 0; r < 2; ++r) {
+    hipEventRecord(e0, s);
+    if (fn() != SPARC_OK) return -1.0f;
+    hipEventRecord(e1, s);
+    hipEventSynchronize(e1);
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, ms);
+  }
+  return best;
+}
+
+template <typename E>
+static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t lda, const E* B, int64_t ldb, void* C,
+                  int ldc, void* work, size_t work_bytes, int n_cu, bool herm_result,
+                  sparc_gemm_mode mode = SPARC_GEMM_NATIVE, sparc_ctx* tune = nullptr) {
+  const bool herm = (na == nb) && (herm_result || ((A == B) && (lda == ldb)));
+  const bool split = mode != SPARC_GEMM_NATIVE;
+  if constexpr (sizeof(typename elem<E>::real) == 8)
+    if (split) return fail(SPARC_EINVAL, "gram: split-BF16 modes take FP32 blocks");
+  GemmChoice c{split ? gram_tile<E>::T : native_tile<E>(na, nb), 0};
+  if (split || !tune || !tune->autotune)
+    return gram_launch<E>(s, N, na, nb, A, lda, B, ldb, C, ldc, work, work_bytes, n_cu, herm, mode, c.T, c.slabs);
+  const auto key = std::make_tuple(N, na, nb, (int)(sizeof(E) * 2 + (elem<E>::is_cplx ? 1 : 0)), herm ? 1 : 0, 0);
+  if (!gemm_lookup(key, &c)) {
+    hipEvent_t e0, e1;
+    SPARC_HIP(hipEventCreate(&e0));
+    SPARC_HIP(hipEventCreate(&e1));
+    const bool timing = tune->timing;
+    tune->timing = false;
+    const int cap_bytes_slabs = (int)std::min<int64_t>(gram_cap(na, nb),
+                                                       (int64_t)(work_bytes / ((size_t)na * nb * 8 *
+                                                                               (elem<E>::is_cplx ? 2 : 1))));
+    float best = 1e30f;
+    GemmChoice pick = c;
+    for (int T : tile_candidates<E>(c.T)) {
+      const int64_t s0 = gram_plan(N, na, nb, herm, n_cu, T).n_slab;
+      for (int64_t sl : {s0, s0 / 2, s0 * 2}) {
+        if (sl < 1 || sl > cap_bytes_slabs || (sl != s0 && N / sl < 64)) continue;
+        const float ms = time_best(s, e0, e1, [&]() {
+          return gram_launch<E>(s, N, na, nb, A, lda, B, ldb, C, ldc, work, work_bytes, n_cu, herm, mode, T, sl);
+        });
+        if (ms >= 0 && ms < best) { best = ms; pick = GemmChoice{T, sl}; }
+      }
+    }
+    tune->timing = timing;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c = pick;
+    gemm_store(key, c);
+  }
+  return gram_launch<E>(s, N, na, nb, A, lda, B, ldb, C, ldc, work, work_bytes, n_cu, herm, mode, c.T, c.slabs);
+}
+
 int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t na, int32_t nb, const void* A, int64_t lda, const void* B,
          int64_t ldb, void* C, int32_t ldc, void* work, size_t work_bytes, sparc_gemm_mode mode, int n_cu,
-         bool herm_result) {
+         bool herm_result, sparc_ctx* tune) {
   switch (dt) {
-    case SPARC_R64: return gram_t<double>(s, N, na, nb, (const double*)A, lda, (const double*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
-    case SPARC_R32: return gram_t<float>(s, N, na, nb, (const float*)A, lda, (const float*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
-    case SPARC_C128: return gram_t<cd>(s, N, na, nb, (const cd*)A, lda, (const cd*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
-    case SPARC_C64: return gram_t<cf>(s, N, na, nb, (const cf*)A, lda, (const cf*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode);
+    case SPARC_R64: return gram_t<double>(s, N, na, nb, (const double*)A, lda, (const double*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode, tune);
+    case SPARC_R32: return gram_t<float>(s, N, na, nb, (const float*)A, lda, (const float*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode, tune);
+    case SPARC_C128: return gram_t<cd>(s, N, na, nb, (const cd*)A, lda, (const cd*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode, tune);
+    case SPARC_C64: return gram_t<cf>(s, N, na, nb, (const cf*)A, lda, (const cf*)B, ldb, C, ldc, work, work_bytes, n_cu, herm_result, mode, tune);
   }
   return fail(SPARC_EINVAL, "gram: bad dtype");
 }
@@ -739,10 +832,8 @@ static void rotate_launch(hipStream_t s, int64_t total, int64_t N, int n_in, int
 }
 
 template <typename E>
-static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, int64_t lda, const double* Q, int ldq,
-                    E* Out, int64_t ldo, int q_upper) {
-  // tile edge from the output width (rows of A per work-group = output columns per tile)
-  const int T = n_out <= 32 ? 32 : (n_out <= 64 || elem<E>::is_cplx) ? 64 : 128;
+static int rotate_run(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, int64_t lda, const double* Q, int ldq,
+                      E* Out, int64_t ldo, int q_upper, int T) {
   int tiles_n = (n_out + T - 1) / T;
   int64_t tiles_m = (N + T - 1) / T;
   int64_t total = tiles_m * tiles_n;
@@ -757,6 +848,38 @@ static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, i
     rotate_launch<E, 128>(s, total, N, n_in, n_out, A, lda, Q, ldq, Out, ldo, tiles_n, remap, q_upper, vec, qvec);
   timer_end(g_timer_ctx, tmr);
   return check_launch("rotate_kernel");
+}
+
+template <typename E>
+static int rotate_t(hipStream_t s, int64_t N, int n_in, int n_out, const E* A, int64_t lda, const double* Q, int ldq,
+                    E* Out, int64_t ldo, int q_upper, sparc_ctx* tune) {
+  // tile edge from the output width (rows of A per work-group = output columns per tile);
+  // tuned like the Gram's when the context asks for it (Out is rewritten by every candidate)
+  int T = n_out <= 32 ? 32 : (n_out <= 64 || elem<E>::is_cplx) ? 64 : 128;
+  if (tune && tune->autotune) {
+    const auto key = std::make_tuple(N, n_in, n_out, (int)(sizeof(E) * 2 + (elem<E>::is_cplx ? 1 : 0)), q_upper, 1);
+    GemmChoice c{T, 0};
+    if (!gemm_lookup(key, &c)) {
+      hipEvent_t e0, e1;
+      SPARC_HIP(hipEventCreate(&e0));
+      SPARC_HIP(hipEventCreate(&e1));
+      const bool timing = tune->timing;
+      tune->timing = false;
+      float best = 1e30f;
+      for (int Tc : tile_candidates<E>(T)) {
+        const float ms = time_best(s, e0, e1, [&]() {
+          return rotate_run<E>(s, N, n_in, n_out, A, lda, Q, ldq, Out, ldo, q_upper, Tc);
+        });
+        if (ms >= 0 && ms < best) { best = ms; c.T = Tc; }
+      }
+      tune->timing = timing;
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      gemm_store(key, c);
+    }
+    T = c.T;
+  }
+  return rotate_run<E>(s, N, n_in, n_out, A, lda, Q, ldq, Out, ldo, q_upper, T);
 }
 
 // ---------------------------------------------------------------- rotate, split-BF16 (x3) from pre-split pieces
@@ -930,12 +1053,12 @@ int rotate_split_x3(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int3
 }
 
 int rotate(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A, int64_t lda,
-           const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper) {
+           const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper, sparc_ctx* tune) {
   switch (dt) {
-    case SPARC_R64: return rotate_t<double>(s, N, n_in, n_out, (const double*)A, lda, (const double*)Q, ldq, (double*)Out, ldo, q_upper);
-    case SPARC_R32: return rotate_t<float>(s, N, n_in, n_out, (const float*)A, lda, (const double*)Q, ldq, (float*)Out, ldo, q_upper);
-    case SPARC_C128: return rotate_t<cd>(s, N, n_in, n_out, (const cd*)A, lda, (const double*)Q, ldq, (cd*)Out, ldo, q_upper);
-    case SPARC_C64: return rotate_t<cf>(s, N, n_in, n_out, (const cf*)A, lda, (const double*)Q, ldq, (cf*)Out, ldo, q_upper);
+    case SPARC_R64: return rotate_t<double>(s, N, n_in, n_out, (const double*)A, lda, (const double*)Q, ldq, (double*)Out, ldo, q_upper, tune);
+    case SPARC_R32: return rotate_t<float>(s, N, n_in, n_out, (const float*)A, lda, (const double*)Q, ldq, (float*)Out, ldo, q_upper, tune);
+    case SPARC_C128: return rotate_t<cd>(s, N, n_in, n_out, (const cd*)A, lda, (const double*)Q, ldq, (cd*)Out, ldo, q_upper, tune);
+    case SPARC_C64: return rotate_t<cf>(s, N, n_in, n_out, (const cf*)A, lda, (const double*)Q, ldq, (cf*)Out, ldo, q_upper, tune);
   }
   return fail(SPARC_EINVAL, "rotate: bad dtype");
 }

@@ -456,8 +456,11 @@ int heuristic_tile(int n1, int n2, size_t elem_size) {
 
 // ------------------------------------------------------------ autotuner
 // The first non-in-place step for a new (grid, states, type, stencil) key times every
-// tile shape once (after one warm-up launch) with HIP events on the context's stream
-// and keeps the fastest; later steps with that key reuse the choice.
+// tile shape the way the filter runs it: recurrence steps (two blocks read, one written:
+// out = a H x + b x + 0 * out) three times back to back after a warm-up, best of two
+// such runs, with HIP events on the context's stream, and keeps the fastest.  x is only
+// read; out (the caller's output block) is overwritten by the real launch that follows.
+// Later steps with that key reuse the choice.
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int, int, int>, int> g_tune_cache;
 
@@ -474,6 +477,17 @@ int tuned_tile(sparc_ham* H, int32_t n_s, int* t) {
              ? 1 : 0;
 }
 
+void tune_store(sparc_ham* H, int32_t n_s, int t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[std::make_tuple(H->grid.n[0], H->grid.n[1], H->grid.n[2], n_s, (int)H->dtype, H->grid.n_o)] = t;
+}
+
+int tile_shape_count() { return kNumTiles; }
+int tile_shape_threads(int t) { return (t >= 0 && t < kNumTiles) ? kTiles[t].tx * kTiles[t].ty : 0; }
+
+constexpr int kTuneBurst = 3;  // launches timed back to back
+constexpr int kTuneRuns = 2;   // best of
+
 template <typename E>
 static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best, double a, const void* alpha) {
   sparc_ctx* ctx = H->ctx;
@@ -488,26 +502,33 @@ static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best, double
   for (int t = 0; t < kNumTiles && rc == SPARC_OK; ++t) {
     if (kTiles[t].tx * kTiles[t].ty > 1024) continue;
     StepArgs<E> B = A;
+    B.z = A.out;  // the recurrence operand: read as the filter reads Y_{j-1}
+    B.ldz = A.ldo;
+    B.zc = 0;
     nl_fill(H, B, t, a, alpha, n_s);
     const StepArgs<E> B0 = B;
     rc = hstep_single<E>(ctx, B, n_s, H->grid.n_o, t);  // warm-up
-    if (rc != SPARC_OK) break;
-    hipEventRecord(e0, ctx->stream);
-    B = B0;
-    rc = hstep_single<E>(ctx, B, n_s, H->grid.n_o, t);
-    hipEventRecord(e1, ctx->stream);
-    if (rc != SPARC_OK) break;
-    hipEventSynchronize(e1);
-    float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best_ms) { best_ms = ms; *best = t; }
+    float t_best = 1e30f;
+    for (int r = 0; r < kTuneRuns && rc == SPARC_OK; ++r) {
+      hipEventRecord(e0, ctx->stream);
+      for (int q = 0; q < kTuneBurst && rc == SPARC_OK; ++q) {
+        B = B0;
+        rc = hstep_single<E>(ctx, B, n_s, H->grid.n_o, t);
+      }
+      hipEventRecord(e1, ctx->stream);
+      if (rc != SPARC_OK) break;
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      t_best = std::min(t_best, ms);
+    }
+    if (rc == SPARC_OK && t_best < best_ms) { best_ms = t_best; *best = t; }
   }
   ctx->timing = timing;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc != SPARC_OK) return rc;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[std::make_tuple(A.n1, A.n2, A.n3, n_s, (int)H->dtype, H->grid.n_o)] = *best;
+  tune_store(H, n_s, *best);
   return SPARC_OK;
 }
 

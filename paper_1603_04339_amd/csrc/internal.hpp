@@ -241,6 +241,9 @@ int64_t step_table_build(sparc_ham* const* H, const StepDesc* d, int n, int tile
 int step_table_launch(sparc_ctx* ctx, sparc_dtype dt, int no, int tile, const void* dev_table, const int* dev_wg,
                       int n, int64_t total, int dir, size_t nl_lds = 0);
 int tuned_tile(sparc_ham* H, int32_t n_s, int* t);
+// stencil tile shapes (hstep_api.hpp): count and threads per work-group of shape t
+int tile_shape_count();
+int tile_shape_threads(int t);
 size_t alpha_bytes(const sparc_ham* H, int32_t n_s);
 // partial sums of the non-local force (forces.hip)
 size_t force_nl_part_bytes(const sparc_ham* H, int32_t n_s);
@@ -253,14 +256,16 @@ inline int alpha_ld(int32_t n_s) { return ((n_s + 15) / 16) * 16; }
 //           herm_result: the caller knows C is Hermitian (A^H H A with H Hermitian): only
 //           the upper triangle is computed and the lower one is its conjugate mirror (this
 //           is automatic when A and B are the same block).
+//           tune: a context whose autotune flag selects timed tile / slab choices per shape
+//           (gram and rotate; nullptr or autotune off: the size heuristic).
 size_t gram_work_bytes(int64_t N, int32_t n_a, int32_t n_b, sparc_dtype dt);
 int gram(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_a, int32_t n_b, const void* A, int64_t lda,
          const void* B, int64_t ldb, void* C, int32_t ldc, void* work, size_t work_bytes,
-         sparc_gemm_mode mode, int n_cu, bool herm_result = false);
+         sparc_gemm_mode mode, int n_cu, bool herm_result = false, sparc_ctx* tune = nullptr);
 //   rotate: Out[N x n_out] = A[N x n_in] * Q[n_in x n_out] (Q FP64 / complex FP64, column-major ldq)
 //   q_upper: Q is upper triangular (entries below the diagonal are not read).
 int rotate(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int32_t n_out, const void* A, int64_t lda,
-           const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper = 0);
+           const void* Q, int32_t ldq, void* Out, int64_t ldo, int q_upper = 0, sparc_ctx* tune = nullptr);
 // Out = A Q with split-BF16 (x3) products from pre-split operands (FP32 / complex64
 // blocks, n_in a multiple of 16): a_pieces holds N * n_in * 2 pieces of 2 bytes per
 // real part (the size of one FP32 / complex64 N x n_in block), q_pieces 2 * n_in * n_out
