@@ -58,7 +58,8 @@ __device__ double block_sum(double v, double* sh) {
 // right-looking blocked factorisation with 64-column panels: the diagonal block is
 // factorised in LDS by one work-group, the row panel R12 = R11^{-H} S12 is formed by
 // one work-group per 64 columns, and the trailing update S22 -= R12^H R12 runs on
-// one work-group per 64 x 64 upper tile.  info = failing column + 1 (0: success);
+// one work-group per 64 x 64 upper tile.  The inverse of R is then formed by columns
+// with the kept diagonal-block inverses.  info = failing column + 1 (0: success);
 // every kernel returns early once info is set.
 constexpr int CB = 64;
 
@@ -96,62 +97,89 @@ __global__ __launch_bounds__(256) void chol_scale_kernel(int n, const T* __restr
   }
 }
 
-// factor the diagonal block S[k0:k0+kb, k0:k0+kb] in LDS; also R11^{-1} -> Rinv (kb x kb)
+// factor the diagonal block S[k0:k0+kb, k0:k0+kb] in LDS; also R11^{-1} -> Rinv (kb x kb).
+// Right-looking elimination on unscaled rows: step k subtracts conj(a_ki) a_kj / a_kk from
+// the trailing block, so row k (final after step k - 1) is only read during the step and
+// one barrier per step suffices; the rows are scaled by 1 / sqrt(a_kk) at the end.  The
+// inverse of the triangular factor is formed by 16 x 16 blocks.
 template <typename T>
 __global__ __launch_bounds__(256) void chol_diag_kernel(int n, T* __restrict__ S, int k0, int kb,
                                                         T* __restrict__ Rinv, int* info) {
   constexpr int LD = CB + 1;   // padded: column-strided accesses spread over the banks
   __shared__ T a[CB * LD];
   __shared__ T r[CB * LD];
-  __shared__ int s_fail;
+  __shared__ T tmp[3 * 16 * 16];  // sums of the off-diagonal 16-blocks of the inverse
+  __shared__ double dg[CB];
   if (*info != 0) return;
   const int tid = threadIdx.x;
   for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
     int i = idx % kb, j = idx / kb;
     a[i + j * LD] = (i <= j) ? S[(k0 + i) + (int64_t)(k0 + j) * n] : mkT<T>(0.0, 0.0);
   }
-  if (tid == 0) s_fail = 0;
   __syncthreads();
+  const int jc = tid % CB, g = tid / CB;  // column jc, rows i = k + 1 + g (mod 4); 256 threads
+  int fail = 0;
   for (int k = 0; k < kb; ++k) {
-    if (tid == 0) {
-      double akk = re_(a[k + k * LD]);
-      if (!(akk > 1e-15) || !isfinite(akk)) s_fail = k0 + k + 1;  // unit-diagonal S: relative floor
-      else a[k + k * LD] = mkT<T>(sqrt(akk), 0.0);
+    const double akk = re_(a[k + k * LD]);   // the same value in every thread
+    if (!(akk > 1e-15) || !isfinite(akk)) {  // unit-diagonal S: relative floor
+      fail = k0 + k + 1;
+      break;
     }
-    __syncthreads();
-    if (s_fail) break;
-    const double rinv = 1.0 / re_(a[k + k * LD]);
-    for (int j = k + 1 + tid; j < kb; j += blockDim.x) a[k + j * LD] = rscale(rinv, a[k + j * LD]);
-    __syncthreads();
-    const int m = kb - k - 1;
-    for (int idx = tid; idx < m * m; idx += blockDim.x) {
-      int i = k + 1 + idx % m, j = k + 1 + idx / m;
-      if (i <= j) a[i + j * LD] = sub_(a[i + j * LD], mul_(conj_(a[k + i * LD]), a[k + j * LD]));
+    if (jc > k && jc < kb) {
+      const T akj = rscale(1.0 / akk, a[k + jc * LD]);
+      for (int i = k + 1 + g; i <= jc; i += 4) a[i + jc * LD] = sub_(a[i + jc * LD], mul_(conj_(a[k + i * LD]), akj));
     }
     __syncthreads();
   }
-  if (s_fail) {
-    if (tid == 0) *info = s_fail;
+  if (fail) {
+    if (tid == 0) *info = fail;
     return;
   }
-  // R11^{-1} row by row from the bottom; the columns of a row in parallel
-  for (int i = kb - 1; i >= 0; --i) {
-    for (int j = tid; j < kb; j += blockDim.x) {
-      T x = mkT<T>(0.0, 0.0);
-      if (j >= i) {
-        // four independent partial sums: the LDS loads of one are in flight during the others
-        T s0 = mkT<T>(i == j ? 1.0 : 0.0, 0.0), s1 = mkT<T>(0.0, 0.0), s2 = s1, s3 = s1;
-        int k = i + 1;
-        for (; k + 3 <= j; k += 4) {
-          s0 = sub_(s0, mul_(a[i + k * LD], r[k + j * LD]));
-          s1 = sub_(s1, mul_(a[i + (k + 1) * LD], r[k + 1 + j * LD]));
-          s2 = sub_(s2, mul_(a[i + (k + 2) * LD], r[k + 2 + j * LD]));
-          s3 = sub_(s3, mul_(a[i + (k + 3) * LD], r[k + 3 + j * LD]));
-        }
-        for (; k <= j; ++k) s0 = sub_(s0, mul_(a[i + k * LD], r[k + j * LD]));
-        x = rscale(1.0 / re_(a[i + i * LD]), add_(add_(s0, s1), add_(s2, s3)));
+  for (int i = tid; i < kb; i += blockDim.x) dg[i] = sqrt(re_(a[i + i * LD]));
+  __syncthreads();
+  for (int idx = tid; idx < kb * kb; idx += blockDim.x) {
+    int i = idx % kb, j = idx / kb;
+    if (i < j) a[i + j * LD] = rscale(1.0 / dg[i], a[i + j * LD]);
+    else if (i == j) a[i + j * LD] = mkT<T>(dg[i], 0.0);
+  }
+  __syncthreads();
+  // R11^{-1} by 16 x 16 blocks: the diagonal blocks by back substitution (one thread per
+  // column, at most 16 rows), then the blocks at distance d = 1, 2, 3 from the diagonal,
+  // X_IJ = -X_II (sum_{K=I+1..J} R_IK X_KJ), each level in two barrier-separated halves
+  for (int idx = tid; idx < CB * CB; idx += blockDim.x) r[(idx % CB) + (idx / CB) * LD] = mkT<T>(0.0, 0.0);
+  __syncthreads();
+  constexpr int B16 = 16;
+  const int nbl = (kb + B16 - 1) / B16;
+  if (tid < kb) {
+    const int j = tid, b0 = (j / B16) * B16;
+    r[j + j * LD] = mkT<T>(1.0 / dg[j], 0.0);
+    for (int i = j - 1; i >= b0; --i) {
+      T sacc = mkT<T>(0.0, 0.0);
+      for (int k = i + 1; k <= j; ++k) sacc = add_(sacc, mul_(a[i + k * LD], r[k + j * LD]));
+      r[i + j * LD] = rscale(-1.0 / dg[i], sacc);
+    }
+  }
+  __syncthreads();
+  for (int d = 1; d < nbl; ++d) {
+    const int nblk = nbl - d;
+    for (int idx = tid; idx < nblk * B16 * B16; idx += blockDim.x) {
+      const int bI = idx / (B16 * B16), e = idx % (B16 * B16), rr = e % B16, cc = e / B16;
+      const int i = bI * B16 + rr, j = (bI + d) * B16 + cc;
+      T sacc = mkT<T>(0.0, 0.0);
+      if (i < kb && j < kb)
+        for (int k = (bI + 1) * B16; k <= j; ++k) sacc = add_(sacc, mul_(a[i + k * LD], r[k + j * LD]));
+      tmp[idx] = sacc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < nblk * B16 * B16; idx += blockDim.x) {
+      const int bI = idx / (B16 * B16), e = idx % (B16 * B16), rr = e % B16, cc = e / B16;
+      const int i = bI * B16 + rr, j = (bI + d) * B16 + cc;
+      if (i < kb && j < kb) {
+        T x = mkT<T>(0.0, 0.0);
+        const int kend = min((bI + 1) * B16, kb);
+        for (int k = i; k < kend; ++k) x = add_(x, mul_(r[i + k * LD], tmp[bI * B16 * B16 + (k - bI * B16) + cc * B16]));
+        r[i + j * LD] = sub_(mkT<T>(0.0, 0.0), x);
       }
-      r[i + j * LD] = x;
     }
     __syncthreads();
   }
@@ -218,33 +246,44 @@ __global__ __launch_bounds__(256) void chol_syrk_kernel(int n, T* __restrict__ S
   }
 }
 
-// T[:, j] = D^{-1} R^{-1} e_j (upper triangular), one wave per column.
+// T = D^{-1} R^{-1} (R upper triangular in S), one 64-lane work-group per column j:
+// x = R^{-1} e_j by 64-row blocks from the bottom, with the diagonal-block inverses of
+// the factorisation (Rinv_blk, block b at b CB^2, column-major kb x kb): the block of
+// row j is a column of its diagonal-block inverse, and each block I above it is
+// x_I = -R_II^{-1} (R_I,(I+1..) x_(I+1..)), a matrix-vector product read from L2 (lane r
+// takes row r, so the lanes read a column segment together) followed by the small
+// triangular product.  x lives in LDS.
 template <typename T>
-__global__ __launch_bounds__(64) void trinv_kernel(int n, const T* __restrict__ R, const double* __restrict__ dinv,
-                                                   T* __restrict__ Tout, const int* info) {
+__global__ __launch_bounds__(64) void trinv_col_kernel(int n, const T* __restrict__ R, const T* __restrict__ Rinv_blk,
+                                                       const double* __restrict__ dinv, T* __restrict__ Tout,
+                                                       const int* info) {
   extern __shared__ char smem[];
-  T* x = (T*)smem;
-  const int j = blockIdx.x;
-  const int lane = threadIdx.x;
+  T* x = (T*)smem;   // [n]
+  T* y = x + n;      // [CB]
   if (*info != 0) return;
-  for (int i = j; i >= 0; --i) {
-    double sr = 0, si = 0;
-    for (int k = i + 1 + lane; k <= j; k += 64) {
-      T p = mul_(R[i + (int64_t)k * n], x[k]);
-      if constexpr (sizeof(T) == 16) {
-        sr += ((const cd&)p).re;
-        si += ((const cd&)p).im;
-      } else {
-        sr += (double&)p;
-      }
+  const int j = blockIdx.x, lane = threadIdx.x;
+  const int J = j / CB, jj0 = J * CB, nJ = min(CB, n - jj0);
+  {
+    const T* Rj = Rinv_blk + (int64_t)J * CB * CB;
+    const int c = j - jj0;
+    if (lane < nJ) x[jj0 + lane] = (lane <= c) ? Rj[lane + c * nJ] : mkT<T>(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int I = J - 1; I >= 0; --I) {
+    const int i0 = I * CB;   // full blocks above the last one
+    T s0 = mkT<T>(0.0, 0.0), s1 = s0;
+    int k = i0 + CB;
+    for (; k + 1 <= j; k += 2) {
+      s0 = add_(s0, mul_(R[(i0 + lane) + (int64_t)k * n], x[k]));
+      s1 = add_(s1, mul_(R[(i0 + lane) + (int64_t)(k + 1) * n], x[k + 1]));
     }
-    sr = wave_sum(sr);
-    if constexpr (sizeof(T) == 16) si = wave_sum(si);
-    if (lane == 0) {
-      double rii = re_(R[i + (int64_t)i * n]);
-      double br = (i == j ? 1.0 : 0.0) - sr;
-      x[i] = mkT<T>(br / rii, -si / rii);
-    }
+    if (k <= j) s0 = add_(s0, mul_(R[(i0 + lane) + (int64_t)k * n], x[k]));
+    y[lane] = add_(s0, s1);
+    __syncthreads();
+    const T* Ri = Rinv_blk + (int64_t)I * CB * CB;
+    T t = mkT<T>(0.0, 0.0);
+    for (int c = lane; c < CB; ++c) t = add_(t, mul_(Ri[lane + c * CB], y[c]));
+    x[i0 + lane] = sub_(mkT<T>(0.0, 0.0), t);
     __syncthreads();
   }
   for (int i = lane; i < n; i += 64) Tout[i + (int64_t)j * n] = (i <= j) ? rscale(dinv[i], x[i]) : mkT<T>(0.0, 0.0);
@@ -252,7 +291,8 @@ __global__ __launch_bounds__(64) void trinv_kernel(int n, const T* __restrict__ 
 
 size_t chol_orth_work_bytes(int32_t n, bool cplx) {
   const size_t e = cplx ? 16 : 8;
-  return (size_t)n * n * e + 256 + (size_t)n * 8 + 256 + (size_t)CB * CB * e + 256;
+  const size_t blocks = ((size_t)n + CB - 1) / CB;  // the diagonal-block inverses, kept for the full inverse
+  return (size_t)n * n * e + 256 + (size_t)n * 8 + 256 + blocks * CB * CB * e + 256;
 }
 
 template <typename T>
@@ -268,18 +308,19 @@ static int chol_orth_t(hipStream_t s, int n, const T* M, T* Tout, int* info, voi
   SPARC_TRY(check_launch("chol_scale_kernel"));
   for (int k0 = 0; k0 < n; k0 += CB) {
     const int kb = std::min(CB, n - k0);
-    chol_diag_kernel<T><<<1, 256, 0, s>>>(n, S, k0, kb, Rinv, info);
+    T* Rb = Rinv + (size_t)(k0 / CB) * CB * CB;
+    chol_diag_kernel<T><<<1, 256, 0, s>>>(n, S, k0, kb, Rb, info);
     SPARC_TRY(check_launch("chol_diag_kernel"));
     const int m = n - k0 - kb;
     if (m <= 0) break;
     const int tiles = (m + CB - 1) / CB;
-    chol_panel_kernel<T><<<tiles, 256, 0, s>>>(n, S, k0, kb, Rinv, info);
+    chol_panel_kernel<T><<<tiles, 256, 0, s>>>(n, S, k0, kb, Rb, info);
     SPARC_TRY(check_launch("chol_panel_kernel"));
     chol_syrk_kernel<T><<<tiles * (tiles + 1) / 2, 256, 0, s>>>(n, S, k0, kb, tiles, info);
     SPARC_TRY(check_launch("chol_syrk_kernel"));
   }
-  trinv_kernel<T><<<n, 64, n * sizeof(T), s>>>(n, S, dinv, Tout, info);
-  return check_launch("trinv_kernel");
+  trinv_col_kernel<T><<<n, 64, (n + CB) * sizeof(T), s>>>(n, S, Rinv, dinv, Tout, info);
+  return check_launch("trinv_col_kernel");
 }
 
 int chol_orth(hipStream_t s, bool cplx, int32_t n, const void* M, void* T, int32_t* info_dev, void* work,
