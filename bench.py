@@ -39,7 +39,7 @@ RR_MODES = {"native": 0, "bf16x3": 1, "bf16x6": 2}
 # HBM traffic of the FP64 c2 stencil-step launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hstep_c2_96cubed_f64.md);
 # valid only for the kernel source it was measured on (checked by hash, else null)
-HSTEP_TRAFFIC = {"bytes_per_launch": 1.809424e+10, "kernel_sources_sha256": "f674b1518227c669e94f3c8ccd3cd7b245b4d22e0cc787519b3f6f7886b27b38",
+HSTEP_TRAFFIC = {"bytes_per_launch": 1.801021e+10, "kernel_sources_sha256": "36e0747923af07ad9783d1fd7730a45d889303f66045c362372561eb1f266191",
                  "profile": "profiles/hstep_c2_96cubed_f64.md"}
 UNIT = "grid-pt·states/s"
 HBM_PEAK_GBS = 8000.0
@@ -398,6 +398,10 @@ def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False, e_r
     r = {"wall_s": wall, "iterations": out["iterations"], "converged": bool(out["converged"]),
          "energy": out["energy"], "n_atoms": cell.n_atoms, "grid": list(cell.n), "n_s": cell.n_s, "tol": tol}
     hist = out["history"]
+    if len(hist):
+        last = hist[-10:, 0]
+        r["final_residual"] = float(hist[-1, 1])
+        r["energy_spread_last10_per_atom"] = float((last.max() - last.min()) / cell.n_atoms)
     if e_ref is not None and len(hist):
         ok = np.abs(hist[:, 0] - e_ref) <= 1e-5 * cell.n_atoms
         bad = np.nonzero(~ok)[0]
@@ -483,16 +487,26 @@ def run_gamma(args, sp, wl, cell, X0, v0, cpu=None):
     if not args.no_scf:
         from paper_1603_04339_amd.train_density_net import DEFAULT_WEIGHTS
         ref = scf_leg(sp, ctx, "f64", tol=1e-9)
-        e_ref = ref["energy"] if ref["converged"] else None
+        # the reference: converged to 1e-9, or settled: with one filter pass per SCF iteration
+        # the density residual of this cell floors near 1e-7 (whatever the mixing), so a run
+        # that ends below 1e-6 with its last ten free energies within 1e-9 Ha/atom is taken
+        # (the free energy's error is quadratic in the density error)
+        settled = (ref.get("final_residual", 1.0) < 1e-6 and ref.get("energy_spread_last10_per_atom", 1.0) < 1e-9)
+        e_ref = ref["energy"] if (ref["converged"] or settled) else None
         s64 = scf_leg(sp, ctx, "f64", e_ref=e_ref)
         s32 = scf_leg(sp, ctx, "mixed", e_ref=e_ref)
         result["scf"] = {
             "f64": s64, "mixed": s32, "reference": {"energy": ref["energy"], "converged": ref["converged"],
-                                                   "iterations": ref["iterations"], "tol": 1e-9},
+                                                   "iterations": ref["iterations"], "tol": 1e-9,
+                                                   "final_residual": ref.get("final_residual"),
+                                                   "energy_spread_last10_per_atom":
+                                                       ref.get("energy_spread_last10_per_atom"),
+                                                   "used": e_ref is not None},
             "mixed_energy_diff_per_atom": abs(s32["energy"] - s64["energy"]) / s64["n_atoms"],
             "note": ("40^3 SCF cell (held-out seed), atomic-superposition start; wall_s: to the density residual "
                      "tol; wall_s_to_1e-5_Ha_per_atom: to the first iteration from which the Harris-Foulkes free "
-                     "energy stays within 1e-5 Ha/atom of the FP64 SCF converged to a residual of 1e-9")}
+                     "energy stays within 1e-5 Ha/atom of the FP64 reference SCF (300 iterations, run to a "
+                     "residual of 1e-9 or until its free energy has settled)")}
         result["scf"]["pseudocharge_f64"] = scf_leg(sp, ctx, "f64", pseudocharge=True)
         if os.path.exists(DEFAULT_WEIGHTS):
             sl = scf_leg(sp, ctx, "f64", learned=True, e_ref=e_ref)
