@@ -342,6 +342,10 @@ static int rr_rotate(sparc_ham* H, sparc_gemm_mode mode, int32_t n, const void* 
   return rotate(s, H->dtype, H->n_d, n, n, A, lda, Q, n, Out, ldo, q_upper, H->ctx);
 }
 
+// Largest estimated condition number of the column-scaled Gram matrix for which one
+// Cholesky-QR pass is taken (orthonormality defect about kappa * eps); above it, two.
+constexpr double kSinglePassKappa = 50.0;
+
 int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode, double* ritz, RRWork& w,
             int32_t* info_out) {
   hipStream_t s = H->ctx->stream;
@@ -352,12 +356,37 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
   const int ncu = H->ctx->n_cu;
   g_timer_ctx = H->ctx;
   int info = 0;
-  // pass 1: T1 from the Gram matrix of X (shifted if it is numerically singular)
+  // pass 1: T1 from the Gram matrix of X (shifted if it is numerically singular), and the
+  // condition estimate of the column-scaled Gram matrix
   SPARC_TRY(gram(s, dt, N, n, n, X, ldx, X, ldx, w.M, n, w.gw, w.gw_bytes, mode, ncu, false, H->ctx));
   bool shifted = false;
   SPARC_TRY(chol_orth(s, cp, n, w.M, w.T1, w.info, w.cw, 0.0));
-  SPARC_HIP(hipMemcpyAsync(&info, w.info, 4, hipMemcpyDeviceToHost, s));
+  double* kappa_dev = (double*)((char*)w.info + 8);
+  SPARC_TRY(chol_cond_est(s, cp, n, w.M, w.T1, w.info, w.cw, kappa_dev));
+  struct { int32_t info; int32_t pad; double kappa; } st{};
+  SPARC_HIP(hipMemcpyAsync(&st, w.info, sizeof(st), hipMemcpyDeviceToHost, s));
   SPARC_HIP(hipStreamSynchronize(s));
+  info = st.info;
+  if (info == 0 && st.kappa <= kSinglePassKappa) {
+    // a nearly orthogonal block (the steady state of the iteration): one Cholesky-QR pass
+    // leaves an orthonormality defect of about kappa * eps, so H X, the projected matrix
+    // and the rotation to the Ritz vectors are taken on X itself, T = T1
+    SPARC_TRY(nl_project(H, X, ldx, n, w.alpha));
+    SPARC_TRY(ham_step(H, X, ldx, nullptr, 0, w.W2, N, n, 1.0, 0.0, 0.0, w.alpha));
+    SPARC_TRY(gram(s, dt, N, n, n, X, ldx, w.W2, N, w.A1, n, w.gw, w.gw_bytes, mode, ncu, true, H->ctx));
+    SPARC_TRY(rotate(s, sdt, n, n, n, w.A1, n, w.T1, n, w.tmp, n, 1));
+    SPARC_TRY(gram(s, sdt, n, n, n, w.T1, n, w.tmp, n, w.A1, n, w.gw, w.gw_bytes, SPARC_GEMM_NATIVE, ncu, true));
+    herm_sym_kernel<<<(unsigned)(((int64_t)n * n + 255) / 256), 256, 0, s>>>(n, (double*)w.A1, cp ? 1 : 0);
+    SPARC_TRY(check_launch("herm_sym_kernel"));
+    SPARC_TRY(heev(s, cp, n, w.A1, ritz, w.Z, w.hw));
+    // U = X (T1 Z), formed out of place and copied back
+    SPARC_TRY(rotate(s, sdt, n, n, n, w.T1, n, w.Z, n, w.Qf, n, 0));
+    SPARC_TRY(rr_rotate(H, mode, n, X, ldx, w.Qf, w.W1, N, 0, w));
+    SPARC_HIP(hipMemcpy2DAsync(X, ldx * elem_bytes(dt), w.W1, N * elem_bytes(dt), N * elem_bytes(dt), n,
+                               hipMemcpyDeviceToDevice, s));
+    if (info_out) *info_out = 0;
+    return SPARC_OK;
+  }
   if (info != 0) {
     const double shift = 11.0 * ((double)N * n + (double)n * (n + 1)) * 2.2e-16 * n;
     SPARC_TRY(chol_orth(s, cp, n, w.M, w.T1, w.info, w.cw, shift));

@@ -323,6 +323,85 @@ static int chol_orth_t(hipStream_t s, int n, const T* M, T* Tout, int* info, voi
   return check_launch("trinv_col_kernel");
 }
 
+// Condition estimate of the column-scaled Gram matrix M_s = D^{-1} M D^{-1} (D = sqrt of
+// diag M) after chol_orth: a Gershgorin bound on lambda_max(M_s) times a power-iteration
+// estimate of lambda_max(M_s^{-1}) = ||R^{-1}||_2^2 (R^{-1} = D T with T = D^{-1} R^{-1}
+// from chol_orth), from a fixed start vector.  One work-group; *out = the estimate, or
+// 1e300 after a failed factorisation.
+template <typename T>
+__global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restrict__ M, const T* __restrict__ Tm,
+                                                        const double* __restrict__ dinv, int iters,
+                                                        const int* __restrict__ info, double* __restrict__ out) {
+  extern __shared__ char smem[];
+  T* v = (T*)smem;  // [n]
+  T* y = v + n;     // [n]
+  __shared__ double red[16];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (*info != 0) {
+    if (tid == 0) *out = 1e300;
+    return;
+  }
+  // Gershgorin: largest column sum of |M_s| (M_s Hermitian)
+  double g = 0.0;
+  for (int j = tid; j < n; j += nt) {
+    double c = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const T m = M[i + (int64_t)j * n];
+      c += sqrt(re_(mul_(conj_(m), m))) * dinv[i];
+    }
+    g = fmax(g, c * dinv[j]);
+  }
+  for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = g;
+  __syncthreads();
+  g = 0.0;
+  for (int w = 0; w < nt / 64; ++w) g = fmax(g, red[w]);
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) v[i] = mkT<T>(1.0 + 0.5 * (double)((i * 7919) % 13) / 13.0, 0.0);
+  __syncthreads();
+  double mu = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    // y = B^H v, B = R^{-1} (upper triangular): y_j = sum_{i <= j} conj(T_ij / dinv_i) v_i
+    for (int j = tid; j < n; j += nt) {
+      T acc = mkT<T>(0.0, 0.0);
+      for (int i = 0; i <= j; ++i) acc = add_(acc, mul_(conj_(rscale(1.0 / dinv[i], Tm[i + (int64_t)j * n])), v[i]));
+      y[j] = acc;
+    }
+    __syncthreads();
+    // v = B y: v_i = sum_{j >= i} (T_ij / dinv_i) y_j
+    double nrm = 0.0;
+    for (int i = tid; i < n; i += nt) {
+      T acc = mkT<T>(0.0, 0.0);
+      for (int j = i; j < n; ++j) acc = add_(acc, mul_(Tm[i + (int64_t)j * n], y[j]));
+      acc = rscale(1.0 / dinv[i], acc);
+      v[i] = acc;
+      nrm += re_(mul_(conj_(acc), acc));
+    }
+    nrm = block_sum(nrm, red);
+    // v was normalised at the previous step (the first start vector is not)
+    const double sq = sqrt(nrm);
+    if (it > 0) mu = sq;
+    for (int i = tid; i < n; i += nt) v[i] = rscale(1.0 / fmax(sq, 1e-300), v[i]);
+    __syncthreads();
+  }
+  if (tid == 0) *out = g * mu;
+}
+
+template <typename T>
+static int chol_cond_est_t(hipStream_t s, int n, const T* M, const T* Tm, const int* info, void* work, double* out) {
+  char* p = (char*)work;
+  p += (((size_t)n * n * sizeof(T) + 255) / 256) * 256;
+  const double* dinv = (const double*)p;
+  cond_est_kernel<T><<<1, 1024, 2 * (size_t)n * sizeof(T), s>>>(n, M, Tm, dinv, 8, info, out);
+  return check_launch("cond_est_kernel");
+}
+
+int chol_cond_est(hipStream_t s, bool cplx, int32_t n, const void* M, const void* T, const int32_t* info_dev,
+                  void* work, double* out_dev) {
+  if (cplx) return chol_cond_est_t<cd>(s, n, (const cd*)M, (const cd*)T, info_dev, work, out_dev);
+  return chol_cond_est_t<double>(s, n, (const double*)M, (const double*)T, info_dev, work, out_dev);
+}
+
 int chol_orth(hipStream_t s, bool cplx, int32_t n, const void* M, void* T, int32_t* info_dev, void* work,
               double shift, double min_rel_diag) {
   if (cplx) return chol_orth_t<cd>(s, n, (const cd*)M, (cd*)T, info_dev, work, shift, min_rel_diag);

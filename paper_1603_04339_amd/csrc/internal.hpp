@@ -282,6 +282,10 @@ int rotate_split_x3(hipStream_t s, sparc_dtype dt, int64_t N, int32_t n_in, int3
 int chol_orth(hipStream_t s, bool cplx, int32_t n, const void* M, void* T, int32_t* info_dev, void* work,
               double shift, double min_rel_diag = 0.0);
 size_t chol_orth_work_bytes(int32_t n, bool cplx);
+// after chol_orth(M -> T) with the same work: *out_dev (device double) = estimated
+// condition number of the column-scaled M (1e300 after a failed factorisation)
+int chol_cond_est(hipStream_t s, bool cplx, int32_t n, const void* M, const void* T, const int32_t* info_dev,
+                  void* work, double* out_dev);
 //   symmetric / Hermitian eigensolve: A (n x n, overwritten) -> ascending w, eigenvectors Z (n x n)
 int heev(hipStream_t s, bool cplx, int32_t n, void* A, double* w, void* Z, void* work);
 size_t heev_work_bytes(int32_t n, bool cplx);

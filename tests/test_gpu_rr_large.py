@@ -126,3 +126,42 @@ def test_rr_fp32_ns256(ctx):
         print(f"fp32 n_s=256 {name}: max |dritz| / width {err:.2e}, orthonormality {orth:.2e}", flush=True)
     assert res["native"][0] < 1e-5 and res["native"][1] < 1e-5
     assert res["x3"][0] < 1e-4 and res["x3"][1] < 1e-4
+
+
+@pytest.mark.parametrize("well", [True, False], ids=["one_pass", "two_passes"])
+def test_rr_pass_selection(ctx, well):
+    """The number of Cholesky-QR passes follows the conditioning of the column-scaled
+    Gram matrix: a block with orthogonal columns (scaled over six decades) takes one
+    pass (two N-long Grams plus the small projected product), an aligned block two
+    (three plus one); both meet the FP64 bars against the oracle."""
+    cell, grid, V, P, Xf = _filtered((12, 12, 14), (6.0, 6.0, 7.0), 4, 65, False, (0.0, 0.0, 0.0), 7,
+                                     hard=not well)
+    if well:
+        Q, _ = np.linalg.qr(Xf)
+        Xf = Q * np.logspace(-3, 3, Q.shape[1])[None, :]
+    G = Xf.T @ Xf
+    d = 1.0 / np.sqrt(np.diag(G))
+    kappa = np.linalg.cond(G * d[:, None] * d[None, :])
+    ns = Xf.shape[1]
+    lam_ref, _ = rayleigh_ritz(Xf, grid, V, P)
+    ham = sp.Hamiltonian(ctx, cell, sp.R64)
+    X = to_dev(np.ascontiguousarray(Xf.T))
+    ritz = torch.zeros(ns, dtype=torch.float64, device="cuda:0")
+    ctx.set_timing(True)
+    sp.rayleigh_ritz(ham, X, ritz, sp.workspace(ham, ns, sp.OP_RR))
+    torch.cuda.synchronize()
+    _, n_gram = ctx.kernel_time("gram")
+    ctx.set_timing(False)
+    lam = ritz.cpu().numpy()
+    Xo = block_to_oracle(X)
+    orth = np.abs(Xo.T @ Xo - np.eye(ns)).max()
+    Hs = Xo.T @ apply_H(Xo, grid, V, P)
+    offd = np.abs(Hs - np.diag(np.diag(Hs))).max()
+    dlam = np.abs(lam - lam_ref).max()
+    print(f"\n[rr passes] well={well} kappa(scaled Gram)={kappa:.2e} grams={n_gram}: |dritz| {dlam:.2e}, "
+          f"orthonormality {orth:.2e}, off-diagonal {offd:.2e}", flush=True)
+    if well:
+        assert kappa < 10 and n_gram == 3
+    else:
+        assert kappa > 1e3 and n_gram == 4
+    assert dlam < 1e-8 and orth < 1e-10 and offd < 1e-8
