@@ -357,7 +357,7 @@ def pseudocharge_leg(sp, ctx, cell, rho, reps=3):
                      "force kernel the FD gradients of b and b~ at every node of every image box")}
 
 
-def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False, e_ref=None):
+def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False, e_ref=None, bf16=False):
     """Plain SCF (Slater exchange, CG Poisson, Anderson mixing 0.15 / history 8) on a held-out 40^3
     cell: wall time, iterations, free energy.  Started from the atomic superposition,
     or (learned=True) from the trained density network's prediction, whose
@@ -377,6 +377,7 @@ def scf_leg(sp, ctx, precision, tol=1e-6, learned=False, pseudocharge=False, e_r
     if learned:
         net = sp.DensityNet(ctx, cell.n, max_batch=1)
         net.set_params(np.load(DEFAULT_WEIGHTS))
+        net.set_bf16(bf16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rho0, used = None, None
@@ -512,6 +513,9 @@ def run_gamma(args, sp, wl, cell, X0, v0, cpu=None):
             sl = scf_leg(sp, ctx, "f64", learned=True, e_ref=e_ref)
             result["scf"]["learned_f64"] = sl
             result["scf"]["learned_energy_diff_per_atom"] = abs(sl["energy"] - s64["energy"]) / s64["n_atoms"]
+            sb = scf_leg(sp, ctx, "f64", learned=True, e_ref=e_ref, bf16=True)
+            sb["network_precision"] = "bf16 activations and weights, FP32 sums"
+            result["scf"]["learned_bf16_f64"] = sb
     if args.config == "c2" and not args.no_batched:
         # the batched configurations, summarised beside the headline (FP64 and mixed)
         for name in ("c3", "c4"):

@@ -458,6 +458,11 @@ void sparc_dnet_destroy(sparc_dnet* net);
 /* Host parameter vector in/out (sparc_dnet_num_params floats).  Setting the
  * parameters restarts Adam. */
 int sparc_dnet_set_params(sparc_dnet* net, const float* theta);
+/* Precision of the network's inference (sparc_dnet_forward, sparc_dnet_predict_density):
+ * 0 FP32 (default); 1 bfloat16 activations and weights (round-to-nearest-even of the
+ * FP32 values) with FP32 products and sums, the last layer's output and the head in
+ * FP32.  Training (loss_grad, train_step) always runs in FP32.  Errors: EINVAL. */
+int sparc_dnet_set_precision(sparc_dnet* net, int32_t bf16);
 int sparc_dnet_get_params(const sparc_dnet* net, float* theta);
 /* x_dev (FP32, N_d) = rho_dev / rho_bar: the scaling of the training targets. */
 int sparc_dnet_scale_density(sparc_dnet* net, const double* rho_dev, double n_elec, double dV, float* x_dev);

@@ -113,13 +113,35 @@ def conv3d_backward(x, W, gy, q=1):
     return gx, gW, gb
 
 
-def forward(theta, x, u, channels=CHANNELS, dilations=DILATIONS):
+def bf16_round(a):
+    """Nearest bfloat16 value (8 significant bits, ties to even, the FP32 exponent range)
+    of each element, after rounding it to FP32 (the values being rounded are FP32
+    numbers in the BF16 inference form).  From the definition: x = m 2^e with
+    0.5 <= |m| < 1, m is rounded to a multiple of 2^-8 (numpy's round is ties-to-even);
+    below 2^-126 the spacing is the fixed 2^-133 of the subnormal range."""
+    f = np.asarray(a, dtype=np.float32).astype(np.float64)
+    out = np.array(f, copy=True)
+    fin = np.isfinite(f) & (f != 0.0)
+    m, e = np.frexp(f[fin])
+    r = np.ldexp(np.round(np.ldexp(m, 8)), e - 8)
+    tiny = np.abs(f[fin]) < 2.0 ** -126
+    r[tiny] = np.round(f[fin][tiny] * 2.0 ** 133) * 2.0 ** -133
+    out[fin] = r
+    return out
+
+
+def forward(theta, x, u, channels=CHANNELS, dilations=DILATIONS, precision="fp32"):
     """x: (n3, n2, n1) scaled SAD density of one cell, u: -V_loc on the same grid.
-    Returns (yhat, cache)."""
+    precision "bf16": the weights and every layer's input are rounded to bfloat16
+    (bf16_round) and the sums are exact; the last layer's output and the head are
+    not rounded.  Returns (yhat, cache)."""
     layers = unpack(theta, channels)
+    rnd = bf16_round if precision == "bf16" else (lambda v: v)
+    if precision == "bf16":
+        layers = [(rnd(W), rnd(b)) for W, b in layers]
     a = [np.stack([x, u])]
     for l, (W, b) in enumerate(layers):
-        z = conv3d(a[-1], W, b, dilations[l])
+        z = conv3d(rnd(a[-1]), W, b, dilations[l])
         a.append(np.maximum(z, 0.0) if l < len(layers) - 1 else z)
     d = a[-1][0]
     s = x + (d - d.mean())
@@ -162,14 +184,15 @@ def adam_step(theta, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def predict_density(theta, rho_sad, vloc, n_elec, dV, charge_tol=1e-2, channels=CHANNELS, dilations=DILATIONS):
+def predict_density(theta, rho_sad, vloc, n_elec, dV, charge_tol=1e-2, channels=CHANNELS, dilations=DILATIONS,
+                    precision="fp32"):
     """Learned first density, or the SAD density as the fallback.
     Returns (rho, used_net)."""
     nv = rho_sad.size
     rho_bar = n_elec / (nv * dV)
     x = rho_sad / rho_bar
     with np.errstate(all="ignore"):
-        yhat, _ = forward(theta, x, -vloc, channels, dilations)
+        yhat, _ = forward(theta, x, -vloc, channels, dilations, precision)
         charge = float(yhat.sum()) * rho_bar * dV
     if not np.all(np.isfinite(yhat)) or not np.isfinite(charge) or abs(charge - n_elec) > charge_tol * n_elec:
         return rho_sad.copy(), False

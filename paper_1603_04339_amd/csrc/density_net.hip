@@ -110,6 +110,86 @@ __global__ __launch_bounds__(256) void conv_kernel(int n1, int n2, int n3, int q
   }
 }
 
+// BF16 inference form: activations held as bfloat16 (round-to-nearest-even of the FP32
+// value), weights rounded to bfloat16 (kept as FP32 numbers), products and sums in FP32.
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) {
+  const unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);  // NaN stays NaN
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__global__ void to_bf16_kernel(int64_t n, const float* __restrict__ x, unsigned short* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = f32_to_bf16(x[i]);
+}
+
+__global__ void round_bf16_kernel(int64_t n, const float* __restrict__ x, float* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = bf16_to_f32(f32_to_bf16(x[i]));
+}
+
+// conv_kernel with bfloat16 input activations; RELU as MODE 1 of conv_kernel; OUT16:
+// the output rounded to bfloat16, else FP32
+template <int CI, int CO, bool RELU, bool OUT16>
+__global__ __launch_bounds__(256) void conv_bf16_kernel(int n1, int n2, int n3, int q,
+                                                        const unsigned short* __restrict__ in,
+                                                        const float* __restrict__ W, const float* __restrict__ bias,
+                                                        void* __restrict__ out) {
+  const int64_t V = (int64_t)n1 * n2 * n3;
+  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (v >= V) return;
+  const int64_t b = blockIdx.y;
+  const int i = (int)(v % n1), j = (int)((v / n1) % n2), k = (int)(v / ((int64_t)n1 * n2));
+  const unsigned short* __restrict__ inb = in + b * V * CI;
+  float acc[CO];
+#pragma unroll
+  for (int co = 0; co < CO; ++co) acc[co] = bias[co];
+  for (int kz = 0; kz < 3; ++kz) {
+    const int kk = wrapi(k + q * (kz - 1), n3);
+    for (int ky = 0; ky < 3; ++ky) {
+      const int jj = wrapi(j + q * (ky - 1), n2);
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        const int ii = wrapi(i + q * (kx - 1), n1);
+        const unsigned short* __restrict__ src = inb + (((int64_t)kk * n2 + jj) * n1 + ii) * CI;
+        const float* __restrict__ w = W + ((kz * 3 + ky) * 3 + kx) * CI * CO;
+        if constexpr (CI % 4 == 0) {
+#pragma unroll 2
+          for (int c = 0; c < CI; c += 4) {
+            const uint2 p = *(const uint2*)(src + c);  // four bfloat16 values
+            const float xs[4] = {__uint_as_float(p.x << 16), __uint_as_float(p.x & 0xffff0000u),
+                                 __uint_as_float(p.y << 16), __uint_as_float(p.y & 0xffff0000u)};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+              for (int co = 0; co < CO; ++co) acc[co] = fmaf(xs[u], w[(c + u) * CO + co], acc[co]);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < CI; ++c) {
+            const float xv = bf16_to_f32(src[c]);
+#pragma unroll
+            for (int co = 0; co < CO; ++co) acc[co] = fmaf(xv, w[c * CO + co], acc[co]);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int co = 0; co < CO; ++co)
+    if (RELU) acc[co] = acc[co] < 0.0f ? 0.0f : acc[co];   // keeps a NaN a NaN
+  if constexpr (OUT16) {
+    unsigned short* __restrict__ o = (unsigned short*)out + (b * V + v) * CO;
+#pragma unroll
+    for (int co = 0; co < CO; ++co) o[co] = f32_to_bf16(acc[co]);
+  } else {
+    float* __restrict__ o = (float*)out + (b * V + v) * CO;
+#pragma unroll
+    for (int co = 0; co < CO; ++co) o[co] = acc[co];
+  }
+}
+
 // WT[26 - t][co][ci] = W[t][ci][co]: the adjoint of a correlation is the correlation
 // with the mirrored kernel and the channel roles swapped
 __global__ void transpose_w_kernel(int ci_n, int co_n, const float* __restrict__ W, float* __restrict__ WT) {
@@ -325,6 +405,15 @@ static int launch_conv(hipStream_t s, int n1, int n2, int n3, int q, int B, cons
   return check_launch("conv_kernel");
 }
 
+template <int CI, int CO, bool RELU, bool OUT16>
+static int launch_conv_bf16(hipStream_t s, int n1, int n2, int n3, int q, int B, const void* in, const float* W,
+                            const float* bias, void* out) {
+  const int64_t V = (int64_t)n1 * n2 * n3;
+  dim3 grid((unsigned)((V + 255) / 256), (unsigned)B);
+  conv_bf16_kernel<CI, CO, RELU, OUT16><<<grid, 256, 0, s>>>(n1, n2, n3, q, (const unsigned short*)in, W, bias, out);
+  return check_launch("conv_bf16_kernel");
+}
+
 template <int CI, int CO>
 static int launch_wgrad(hipStream_t s, int n1, int n2, int n3, int q, int B, const float* a, const float* gz,
                         float* part, double* bpart, float* gW, float* gb) {
@@ -357,6 +446,9 @@ struct sparc_dnet {
   double *rpart, *rsum;    // per-sample reduction partials and sums
   double* bpart;           // bias-gradient partials
   float* r2;               // squared residuals
+  int bf16;                // inference precision: 0 FP32, 1 bfloat16 activations and weights
+  bool bf_stale;           // theta_bf no longer holds the rounded theta
+  float* theta_bf;         // theta rounded to bfloat16 (FP32 numbers)
   std::vector<void*> allocs;
 };
 
@@ -373,9 +465,29 @@ static int dnet_alloc(sparc_dnet* N, void** p, size_t bytes) {
 static float* Wl(sparc_dnet* N, float* base, int l) { return base + layer_off(l); }
 static float* bl(sparc_dnet* N, float* base, int l) { return base + layer_off(l) + layer_w(l); }
 
-static int dnet_forward(sparc_dnet* N, const float* x, int B) {
+static int dnet_forward(sparc_dnet* N, const float* x, int B, bool bf16 = false) {
   hipStream_t s = N->ctx->stream;
   const int n1 = N->n[0], n2 = N->n[1], n3 = N->n[2];
+  if (bf16) {
+    const int64_t np = total_params();
+    if (N->bf_stale) {
+      round_bf16_kernel<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(np, N->theta, N->theta_bf);
+      SPARC_TRY(check_launch("round_bf16_kernel"));
+      N->bf_stale = false;
+    }
+    const int64_t ni = (int64_t)B * N->V * kCh[0];
+    to_bf16_kernel<<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(ni, x, (unsigned short*)N->a[0]);
+    SPARC_TRY(check_launch("to_bf16_kernel"));
+    float* T = N->theta_bf;
+    SPARC_TRY((launch_conv_bf16<2, 16, true, true>(s, n1, n2, n3, kDil[0], B, N->a[0], Wl(N, T, 0), bl(N, T, 0),
+                                                   N->a[1])));
+    SPARC_TRY((launch_conv_bf16<16, 32, true, true>(s, n1, n2, n3, kDil[1], B, N->a[1], Wl(N, T, 1), bl(N, T, 1),
+                                                    N->a[2])));
+    SPARC_TRY((launch_conv_bf16<32, 32, true, true>(s, n1, n2, n3, kDil[2], B, N->a[2], Wl(N, T, 2), bl(N, T, 2),
+                                                    N->a[3])));
+    return launch_conv_bf16<32, 1, false, false>(s, n1, n2, n3, kDil[3], B, N->a[3], Wl(N, T, 3), bl(N, T, 3),
+                                                 N->a[4]);
+  }
   SPARC_HIP(hipMemcpyAsync(N->a[0], x, (size_t)B * N->V * kCh[0] * sizeof(float), hipMemcpyDeviceToDevice, s));
   SPARC_TRY((launch_conv<2, 16, 1>(s, n1, n2, n3, kDil[0], B, N->a[0], Wl(N, N->theta, 0), bl(N, N->theta, 0), nullptr,
                                    N->a[1])));
@@ -478,6 +590,9 @@ int sparc_dnet_create(sparc_ctx* ctx, const int32_t* n, int32_t max_batch, sparc
     if (rc == SPARC_OK) rc = dnet_alloc(N, p, bytes);
   };
   A((void**)&N->theta, np * 4);
+  A((void**)&N->theta_bf, np * 4);
+  N->bf16 = 0;
+  N->bf_stale = true;
   A((void**)&N->grad, np * 4);
   A((void**)&N->m, np * 4);
   A((void**)&N->v, np * 4);
@@ -521,6 +636,14 @@ int sparc_dnet_set_params(sparc_dnet* N, const float* theta) {
   SPARC_HIP(hipMemset(N->m, 0, np * 4));
   SPARC_HIP(hipMemset(N->v, 0, np * 4));
   N->adam_t = 0;
+  N->bf_stale = true;
+  return SPARC_OK;
+}
+
+int sparc_dnet_set_precision(sparc_dnet* N, int32_t bf16) {
+  if (!N) return fail(SPARC_EINVAL, "sparc_dnet_set_precision: NULL handle");
+  if (bf16 != 0 && bf16 != 1) return fail(SPARC_EINVAL, "sparc_dnet_set_precision: precision must be 0 or 1");
+  N->bf16 = bf16;
   return SPARC_OK;
 }
 
@@ -553,7 +676,7 @@ int sparc_dnet_prepare_input(sparc_dnet* N, const double* rho_dev, const double*
 int sparc_dnet_forward(sparc_dnet* N, const float* x_dev, int32_t B, float* d_dev) {
   SPARC_TRY(check_batch(N, B));
   if (!x_dev || !d_dev) return fail(SPARC_EINVAL, "sparc_dnet_forward: null argument");
-  SPARC_TRY(dnet_forward(N, x_dev, B));
+  SPARC_TRY(dnet_forward(N, x_dev, B, N->bf16 != 0));
   SPARC_HIP(hipMemcpyAsync(d_dev, N->a[4], (size_t)B * N->V * 4, hipMemcpyDeviceToDevice, N->ctx->stream));
   return SPARC_OK;
 }
@@ -595,6 +718,7 @@ int sparc_dnet_adam_step(sparc_dnet* N, double lr) {
   N->adam_t += 1;
   const double c1 = 1.0 / (1.0 - std::pow(b1, N->adam_t)), c2 = 1.0 / (1.0 - std::pow(b2, N->adam_t));
   const int64_t np = total_params();
+  N->bf_stale = true;
   adam_kernel<<<(unsigned)((np + 255) / 256), 256, 0, N->ctx->stream>>>(np, N->theta, N->grad, N->m, N->v, (float)lr,
                                                                          (float)b1, (float)b2, (float)c1, (float)c2, 1e-8f);
   return check_launch("adam_kernel");
@@ -616,11 +740,12 @@ int sparc_dnet_predict_density(sparc_dnet* N, const double* rho_sad_dev, const d
   const double rho_bar = n_elec / ((double)V * dV);
   float* in = N->gz[1];   // scratch: one cell, two channels
   SPARC_TRY(sparc_dnet_prepare_input(N, rho_sad_dev, vloc_dev, n_elec, dV, in));
-  SPARC_TRY(dnet_forward(N, in, 1));
+  SPARC_TRY(dnet_forward(N, in, 1, N->bf16 != 0));
   SPARC_TRY(dnet_sample_sums(N, 1, N->a[4], nullptr));
   float* yh = N->r2;
   float* sv = N->gz[2];
-  head_predict_kernel<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(V, N->a[0], N->a[4], N->rsum, rho_bar, rho_dev, yh, sv);
+  // the head adds the correction to the FP32 input (in either precision of the network)
+  head_predict_kernel<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(V, in, N->a[4], N->rsum, rho_bar, rho_dev, yh, sv);
   SPARC_TRY(check_launch("head_predict_kernel"));
   SPARC_TRY(dnet_sample_sums(N, 1, yh, sv));
   double sums[2];

@@ -129,6 +129,7 @@ _SIGS = {
     "sparc_dnet_num_params": (C.c_int64, []),
     "sparc_dnet_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_void_p)]),
     "sparc_dnet_destroy": (None, [C.c_void_p]),
+    "sparc_dnet_set_precision": (C.c_int, [C.c_void_p, C.c_int32]),
     "sparc_dnet_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sparc_dnet_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
     "sparc_dnet_scale_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p]),
@@ -617,6 +618,10 @@ class DensityNet:
         if t.size != self.num_params:
             raise ValueError(f"expected {self.num_params} parameters, got {t.size}")
         _check(load().sparc_dnet_set_params(self.handle, t.ctypes.data_as(C.c_void_p)))
+
+    def set_bf16(self, enable: bool):
+        """bfloat16 inference (activations and weights), FP32 sums; training stays FP32."""
+        _check(load().sparc_dnet_set_precision(self.handle, 1 if enable else 0))
 
     def get_params(self):
         t = np.zeros(self.num_params, dtype=np.float32)

@@ -2,8 +2,8 @@
 FP64 oracle: atomic superposition (1e-12), network output (FP32 vs FP64,
 2e-5 of the output scale), loss (1e-5 relative) and gradient (2e-4 of the
 largest component), the first Adam step, the prediction with its charge
-renormalisation and SAD fallback, and a short training run that must lower
-the loss.  The effect of the trained network on the SCF is tested in
+renormalisation and SAD fallback, the bfloat16 inference form against the oracle's
+(2e-3), and a short training run that must lower the loss.  The effect of the trained network on the SCF is tested in
 test_gpu_learned_start.py."""
 import numpy as np
 import pytest
@@ -80,6 +80,38 @@ def test_forward_matches_oracle(ctx):
         err = np.abs(got[b] - ref).max() / np.abs(ref).max()
         print(f"forward cell {b}: max rel err {err:.2e}")
         assert err < 2e-5
+
+
+def test_forward_bf16_matches_oracle(ctx):
+    """bfloat16 inference against the oracle's bf16 form (weights, biases and every
+    layer's input rounded to bfloat16, exact sums): the GPU sums in FP32, which now and
+    then moves a hidden activation across a bfloat16 rounding boundary (one step, 2^-8
+    of its value, reaching the output through weights well below 1), so the bar is
+    2e-3 of the output scale; the FP32 network differs from the BF16 one by several
+    times that, so the bf16 oracle is what explains the GPU's result."""
+    th = _theta(1)
+    xs, us, _ = _fields(2, 2)
+    net = sp.DensityNet(ctx, N, max_batch=2)
+    net.set_params(th)
+    x = _dev_in(xs, us)
+    d32 = torch.zeros(2 * np.prod(N), dtype=torch.float32, device="cuda:0")
+    d16 = torch.zeros_like(d32)
+    net.forward(x, d32)
+    net.set_bf16(True)
+    net.forward(x, d16)
+    net.set_bf16(False)
+    d32b = torch.zeros_like(d32)
+    net.forward(x, d32b)
+    assert torch.equal(d32, d32b)   # switching back restores the FP32 network exactly
+    g16 = d16.cpu().numpy().reshape(2, N[2], N[1], N[0])
+    for b in range(2):
+        _, (_, a16, _) = dn.forward(th, xs[b], us[b], precision="bf16")
+        _, (_, a32, _) = dn.forward(th, xs[b], us[b])
+        r16, r32 = a16[-1][0], a32[-1][0]
+        e16 = np.abs(g16[b] - r16).max() / np.abs(r16).max()
+        ex = np.abs(g16[b] - r32).max() / np.abs(r32).max()
+        print(f"bf16 forward cell {b}: vs bf16 oracle {e16:.2e}, vs FP32 oracle {ex:.2e}")
+        assert e16 < 2e-3 and ex > 3 * e16
 
 
 def test_loss_grad_matches_oracle(ctx):
@@ -160,6 +192,32 @@ def test_predict_density(ctx):
     out.zero_()
     assert not net.predict_density(rho_sad, vl, cell.n_elec, dV, out, charge_tol=1e-2)
     assert torch.equal(out, rho_sad)
+
+
+def test_predict_density_bf16(ctx):
+    """bfloat16 prediction against the oracle's bf16 prediction (same fallback and
+    charge renormalisation)."""
+    cell, _, _ = wl.scf_cell(7, n=16, L=8.0)
+    n = cell.n
+    grid = Grid(n=cell.n, L=cell.L)
+    dV = grid.h[0] * grid.h[1] * grid.h[2]
+    rho_sad = torch.zeros(cell.n_d, dtype=torch.float64, device="cuda:0")
+    sp.sad_density(ctx, cell, rho_sad)
+    vl = torch.zeros_like(rho_sad)
+    sp.Hamiltonian(ctx, cell, sp.R64).get_vloc(vl)
+    net = sp.DensityNet(ctx, n, max_batch=1)
+    th = _theta(8) * 0.2
+    net.set_params(th)
+    net.set_bf16(True)
+    out = torch.zeros_like(rho_sad)
+    used = net.predict_density(rho_sad, vl, cell.n_elec, dV, out, charge_tol=0.5)
+    sh = (n[2], n[1], n[0])
+    ref, uref = dn.predict_density(th, rho_sad.cpu().numpy().reshape(sh), vl.cpu().numpy().reshape(sh),
+                                   cell.n_elec, dV, charge_tol=0.5, precision="bf16")
+    err = np.abs(out.cpu().numpy() - ref.reshape(-1)).max() / ref.max()
+    print(f"bf16 prediction vs bf16 oracle: {err:.2e}")
+    assert used and uref and err < 2e-3
+    assert abs(out.sum().item() * dV - cell.n_elec) < 1e-9 * cell.n_elec
 
 
 def test_training_lowers_loss(ctx):

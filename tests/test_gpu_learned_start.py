@@ -69,3 +69,32 @@ def test_learned_start_is_closer_and_reaches_the_same_fixed_point(ctx):
     assert len(its) >= len(HELD_OUT) - 1
     assert np.mean(ratios) < 0.8
     assert its[:, 1].mean() <= its[:, 0].mean()
+
+
+@pytest.mark.skipif(not os.path.exists(DEFAULT_WEIGHTS), reason="no trained weights file")
+def test_learned_start_bf16_reaches_the_same_fixed_point(ctx):
+    """The bfloat16 inference form of the same weights: on two held-out cells its start
+    is about as close as the FP32 prediction (start errors within 10 % of each other)
+    and the SCF from it reaches the same free energy (1e-5 Ha/atom)."""
+    theta = np.load(DEFAULT_WEIGHTS)
+    net = sp.DensityNet(ctx, (40, 40, 40), max_batch=1)
+    net.set_params(theta)
+    for cid in HELD_OUT[:2]:
+        cell, X0, v0 = wl.scf_cell(cid, split="test")
+        rho_sad, vloc = cell_start(ctx, cell)
+        r32 = torch.zeros_like(rho_sad)
+        r16 = torch.zeros_like(rho_sad)
+        net.set_bf16(False)
+        u32 = net.predict_density(rho_sad, vloc, cell.n_elec, cell_dV(cell), r32, charge_tol=CHARGE_TOL)
+        net.set_bf16(True)
+        u16 = net.predict_density(rho_sad, vloc, cell.n_elec, cell_dV(cell), r16, charge_tol=CHARGE_TOL)
+        a, rho_a = solve(ctx, cell, X0, v0, rho_init=r32)
+        b, _ = solve(ctx, cell, X0, v0, rho_init=r16)
+        e32 = torch.linalg.norm(r32 - rho_a).item()
+        e16 = torch.linalg.norm(r16 - rho_a).item()
+        de = abs(a["energy"] - b["energy"]) / cell.n_atoms
+        print(f"cell {cid}: start error FP32 {e32:.3e}, BF16 {e16:.3e} (used {u32}/{u16}); SCF iterations "
+              f"{a['iterations']} / {b['iterations']}; |dF|/atom {de:.1e}")
+        assert u32 == u16
+        assert abs(e16 - e32) <= 0.1 * e32
+        assert a["converged"] and b["converged"] and de < 1e-5

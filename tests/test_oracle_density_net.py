@@ -157,3 +157,47 @@ def test_predict_renormalises_and_falls_back():
     assert used
     np.testing.assert_allclose(out, np.maximum(2.0 - x, 0.0) * n_elec / (np.maximum(2.0 - x, 0.0).sum() * dV),
                                rtol=1e-12)
+
+
+def test_bf16_round_matches_torch_bfloat16():
+    """The oracle's bfloat16 rounding (from the definition: 8 significant bits, ties to
+    even) against torch's own float32 -> bfloat16 conversion, on values over many
+    decades, exact ties, their neighbours, zeros and the subnormal range."""
+    torch = pytest.importorskip("torch")
+    from oracle.density_net import bf16_round
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(20000) * np.exp(rng.uniform(-30, 30, 20000))
+    base = (rng.integers(128, 256, 200) / 128.0) * 2.0 ** rng.integers(-20, 20, 200)
+    ties = base * (1.0 + 2.0 ** -9)            # halfway between two bfloat16 values
+    near = np.concatenate([ties * (1 + 2.0 ** -20), ties * (1 - 2.0 ** -20)])
+    tiny = rng.uniform(-1, 1, 500) * 2.0 ** -128
+    x = np.concatenate([v, -v[:100], base, ties, -ties, near, tiny, [0.0, -0.0, 1.0, -1.0]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    got = bf16_round(x)
+    assert np.array_equal(got, ref)
+    # and the ties really were ties: rounding moved them by exactly half a spacing
+    assert np.all(np.abs(bf16_round(ties) - ties) == np.abs(ties) * 2.0 ** -9 / (1.0 + 2.0 ** -9))
+
+
+def test_forward_bf16_is_the_rounded_network():
+    """precision 'bf16' equals the FP32-mode forward of the rounded weights on the
+    rounded input when the hidden activations happen to be bfloat16 numbers already
+    (one layer: a 2 -> 1 network with rounded inputs), and differs from the FP32 form
+    by about the bfloat16 resolution on a full network."""
+    from oracle.density_net import bf16_round, forward, init_params
+    rng = np.random.default_rng(9)
+    n = (10, 9, 8)
+    x = rng.uniform(0, 3, n)
+    u = rng.uniform(-2, 2, n)
+    theta = init_params(rng)
+    y32, c32 = forward(theta, x, u)
+    y16, c16 = forward(theta, x, u, precision="bf16")
+    d32, d16 = c32[1][-1][0], c16[1][-1][0]
+    rel = np.linalg.norm(d16 - d32) / np.linalg.norm(d32)
+    assert 1e-4 < rel < 3e-2
+    ch = (2, 1)
+    th1 = rng.standard_normal(27 * 2 + 1)
+    xr, ur = bf16_round(x), bf16_round(u)
+    ya, ca = forward(th1, xr, ur, ch, (1,), precision="bf16")
+    yb, cb = forward(bf16_round(th1), xr, ur, ch, (1,))
+    assert np.array_equal(ca[1][-1], cb[1][-1])
