@@ -273,7 +273,10 @@ int sparc_ctx_set_autotune(sparc_ctx* ctx, int enable);
 /* Minimal self-consistent field (Sec. 2 SCF fixed point with mixing, Sec. 3.4
  * CheFSI schedule, Sec. 3.5 free energy) at the Gamma point in the reduced
  * model: V_eff = V_loc + V_H + V_x (Slater exchange), -Lap_h V_H =
- * 4 pi (rho - mean rho) solved by conjugate gradients on the FD Laplacian,
+ * 4 pi (rho - mean rho) solved by conjugate gradients on the FD Laplacian (warm-started
+ * from the previous V_H, to a relative residual of max(poisson_tol, min(1e-4, 1e-3 x the
+ * last density residual)): loose while the density is far from self-consistent,
+ * poisson_tol near the fixed point),
  * density mixing (linear, or Anderson with relaxation `mix` and history
  * `mix_history`; with kerker_k0 > 0 the mixed residual f is Kerker-preconditioned,
  * f - k0^2 g with (-Lap_h + k0^2) g = f solved by conjugate gradients, which damps the

@@ -558,6 +558,82 @@ int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const dou
   return fail(SPARC_EINVAL, "nl_scatter: bad dtype");
 }
 
+// ------------------------------------------------------------ small launches
+// A step whose tiled launch would not give every CU a work-group (one orbital or a few
+// on a small grid: the Poisson solves of the SCF, the Lanczos steps) runs one thread per
+// (node, orbital) instead, every tap read straight from memory (the operand is
+// L2-resident at these sizes), with the tiled kernel's arithmetic in the same order: the
+// tiled form would march a handful of work-groups through all planes one after another.
+// Periodic images carry the Bloch factor e^{i k_s L_s w}; taps past a Dirichlet face are
+// zero.
+template <typename E>
+__device__ __forceinline__ E point_tap(const StepArgs<E>& A, const E* __restrict__ xc, int ii, int jj, int kk) {
+  typedef typename elem<E>::real R;
+  const int wx = floordiv_i(ii, A.n1), wy = floordiv_i(jj, A.n2), wz = floordiv_i(kk, A.n3);
+  if (((A.dmask & 1) && wx != 0) || ((A.dmask & 2) && wy != 0) || ((A.dmask & 4) && wz != 0)) return zero<E>();
+  E v = xc[(ii - wx * A.n1) + (int64_t)A.n1 * ((jj - wy * A.n2) + (int64_t)A.n2 * (kk - wz * A.n3))];
+  if constexpr (elem<E>::is_cplx) {
+    const double th = A.kl[0] * wx + A.kl[1] * wy + A.kl[2] * wz;
+    if (th != 0.0) {
+      double sn, cs;
+      sincos(th, &sn, &cs);
+      v = rot(v, (R)cs, (R)sn);
+    }
+  }
+  return v;
+}
+
+template <typename E, int NO>
+__global__ __launch_bounds__(256) void hstep_point_kernel(StepArgs<E> A, int n_s) {
+  typedef typename elem<E>::real R;
+  const int64_t nd = (int64_t)A.n1 * A.n2 * A.n3;
+  const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (t >= nd * n_s) return;
+  const int n = (int)(t / nd);
+  const int64_t g = t - (int64_t)n * nd;
+  const int i = (int)(g % A.n1), j = (int)((g / A.n1) % A.n2), k = (int)(g / ((int64_t)A.n1 * A.n2));
+  const E* __restrict__ xc = A.x + (int64_t)n * A.ldx;
+  const E x0 = xc[g];
+  E lap = scale(A.centre, x0);
+#pragma unroll
+  for (int p = 1; p <= NO; ++p) {
+    lap = fmar(lap, A.tz[p - 1], point_tap(A, xc, i, j, k + p) + point_tap(A, xc, i, j, k - p));
+    lap = fmar(lap, A.tx[p - 1], point_tap(A, xc, i + p, j, k) + point_tap(A, xc, i - p, j, k));
+    lap = fmar(lap, A.ty[p - 1], point_tap(A, xc, i, j + p, k) + point_tap(A, xc, i, j - p, k));
+  }
+  const R v = A.veff[g];
+  E r = fmar(lap, (R)(A.va * v + A.vb), x0);
+  if (A.z) r = fmar(r, A.zc, A.z[(int64_t)n * A.ldz + g]);
+  A.out[(int64_t)n * A.ldo + g] = r;
+}
+
+template <typename E>
+static int hstep_point(sparc_ctx* ctx, const StepArgs<E>& A, int32_t n_s, int no) {
+  const int64_t total = (int64_t)A.n1 * A.n2 * A.n3 * n_s;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "stencil step: too many nodes");
+  int t = timer_begin(ctx, "hstep");
+  switch (no) {
+#define CASE(K) case K: hstep_point_kernel<E, K><<<(unsigned)blocks, 256, 0, ctx->stream>>>(A, n_s); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: timer_end(ctx, t); return fail(SPARC_EINVAL, "stencil step: n_o=%d unsupported", no);
+  }
+  timer_end(ctx, t);
+  return check_launch("hstep_point_kernel");
+}
+
+// whether a single-problem step is small enough for the point form: its tiled launch
+// would have fewer work-groups than the chip has CUs (a forced tile shape keeps the
+// tiled form)
+template <typename E>
+static bool use_point_form(const sparc_ham* H, const StepArgs<E>& A, int32_t n_s, int t) {
+  if (getenv("SPARC_HSTEP_TILE")) return false;
+  StepArgs<E> B = A;
+  const int64_t G = plan_problem(B, kTiles[t].tx, kTiles[t].ty, H->grid.n_o, n_s, H->ctx->n_cu);
+  return G < H->ctx->n_cu;
+}
+
 template <typename E>
 static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, int64_t ldz, void* out, int64_t ldo,
                       int32_t n_s, double a, double b, double c, const void* alpha, int flags) {
@@ -590,6 +666,11 @@ static int ham_step_t(sparc_ham* H, const void* x, int64_t ldx, const void* z, i
   if (nonlocal && !alpha) return fail(SPARC_EINVAL, "ham_step: projections missing");
   const void* al = nonlocal ? alpha : nullptr;
   int t = heuristic_tile(A.n1, A.n2, sizeof(E));
+  if (use_point_form(H, A, n_s, t)) {
+    SPARC_TRY(hstep_point<E>(H->ctx, A, n_s, H->grid.n_o));
+    if (nonlocal) SPARC_TRY(nl_scatter(H, alpha, n_s, a, nullptr, out, ldo));
+    return SPARC_OK;
+  }
   if (H->ctx->autotune && !tuned_tile(H, n_s, &t) && !(flags & STEP_NO_TUNE) && z == nullptr && out != x)
     SPARC_TRY(autotune(H, A, n_s, &t, a, al));
   const bool fused = nl_fill(H, A, t, a, al, n_s);

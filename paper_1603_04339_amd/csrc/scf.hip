@@ -378,14 +378,16 @@ struct Poisson {
     if (bb == 0.0) return SPARC_OK;
     int it = 0;
     for (; it < max_it; ++it) {
+      // r.r of the current and of the updated residual alternate between sc[0] and sc[2]
+      double* rr0 = sc + ((it & 1) ? 2 : 0);
+      double* rr1 = sc + ((it & 1) ? 0 : 2);
       SPARC_TRY(apply(p, Ap));
       SPARC_TRY(reduce(s, n, p, Ap, RED_DOT, part, sc + 1));
-      cg_update_xr_kernel<<<GRID1(n)>>>(n, v, r, p, Ap, sc + 0, sc + 1);
-      SPARC_TRY(reduce(s, n, r, r, RED_DOT, part, sc + 2));
-      cg_update_p_kernel<<<GRID1(n)>>>(n, p, r, sc + 2, sc + 0);
-      SPARC_HIP(hipMemcpyAsync(sc + 0, sc + 2, 8, hipMemcpyDeviceToDevice, s));
+      cg_update_xr_kernel<<<GRID1(n)>>>(n, v, r, p, Ap, rr0, sc + 1);
+      SPARC_TRY(reduce(s, n, r, r, RED_DOT, part, rr1));
+      cg_update_p_kernel<<<GRID1(n)>>>(n, p, r, rr1, rr0);
       if (it % 8 == 7) {
-        SPARC_HIP(hipMemcpyAsync(&rr, sc + 2, 8, hipMemcpyDeviceToHost, s));
+        SPARC_HIP(hipMemcpyAsync(&rr, rr1, 8, hipMemcpyDeviceToHost, s));
         SPARC_HIP(hipStreamSynchronize(s));
         if (!std::isfinite(rr)) return fail(SPARC_ENAN, "poisson: non-finite residual");
         if (rr <= tol * tol * bb) break;
@@ -581,14 +583,17 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
 
   Poisson PS{H64, n, pb, pr, pp, pAp, part, sc};
   const double ptol = P->poisson_tol > 0 ? P->poisson_tol : 1e-10;
-  // phi (or V_H) of the current input density
-  auto solve_potential = [&]() -> int {
-    if (!psd) return PS.solve(s, rho_in, vh, ptol, 20000);
+  // phi (or V_H) of the current input density, warm-started from the previous one; the
+  // CG tolerance follows the SCF: a thousandth of the last density residual, at most
+  // 1e-4 and at least poisson_tol, which the final iterations reach
+  auto solve_potential = [&](double res) -> int {
+    const double tol_now = std::max(ptol, std::min(1e-4, 1e-3 * res));
+    if (!psd) return PS.solve(s, rho_in, vh, tol_now, 20000);
     add_kernel<<<GRID1(n)>>>(n, rho_in, bpsd, rhob);
     SPARC_TRY(check_launch("add_kernel"));
-    return PS.solve(s, rhob, vh, ptol, 20000);
+    return PS.solve(s, rhob, vh, tol_now, 20000);
   };
-  SPARC_TRY(solve_potential());
+  SPARC_TRY(solve_potential(1.0));
 
   double lmin = 0, lmax = 0, lcut = 0;
   bool have_ritz = false;
@@ -703,7 +708,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
       }
     }
     SPARC_TRY(check_launch("density mixing"));
-    SPARC_TRY(solve_potential());
+    SPARC_TRY(solve_potential(err));
   }
   res->energy = F;
   res->mu = mu;
