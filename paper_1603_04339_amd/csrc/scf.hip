@@ -23,9 +23,15 @@ namespace sparc {
 // partial sums of f(i) per block (deterministic two-pass reduction)
 enum RedOp { RED_SUM = 0, RED_DOT = 1, RED_DIFF2 = 2 };
 
-__global__ __launch_bounds__(256) void reduce_partial_kernel(int64_t n, const double* __restrict__ a,
-                                                             const double* __restrict__ b, int op,
-                                                             double* __restrict__ part) {
+constexpr int RED_BLOCKS = 1024;
+
+// One launch per reduction: every block reduces its grid-stride share and stores the
+// partial; the last block to finish (device-scope release/acquire on a ticket word that
+// follows the RED_BLOCKS partials) sums the partials in block order and resets the
+// ticket.  The partials are read with device-scope loads, past any stale L1 line.
+__global__ __launch_bounds__(256) void reduce_kernel(int64_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b, int op, double* part,
+                                                     double* __restrict__ out) {
   double s = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double v;
@@ -35,28 +41,36 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(int64_t n, const do
     s += v;
   }
   __shared__ double red[4];
+  __shared__ int last;
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ __launch_bounds__(256) void reduce_final_kernel(int nparts, const double* __restrict__ part,
-                                                           double* __restrict__ out) {
-  double s = 0;
-  for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
-  __shared__ double red[4];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  unsigned* ticket = (unsigned*)(part + RED_BLOCKS);
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&part[blockIdx.x], red[0] + red[1] + red[2] + red[3], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1) ? 1 : 0;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+  if (!last) return;
+  double t2 = 0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+    t2 += __hip_atomic_load(&part[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  t2 = wave_sum(t2);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *out = red[0] + red[1] + red[2] + red[3];
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-constexpr int RED_BLOCKS = 1024;
-
+// part: RED_BLOCKS doubles and the ticket word (zeroed once after allocation)
 static int reduce(hipStream_t s, int64_t n, const double* a, const double* b, int op, double* part, double* out) {
-  reduce_partial_kernel<<<RED_BLOCKS, 256, 0, s>>>(n, a, b, op, part);
-  reduce_final_kernel<<<1, 256, 0, s>>>(RED_BLOCKS, part, out);
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + 1023) / 1024));
+  reduce_kernel<<<blocks, 256, 0, s>>>(n, a, b, op, part, out);
   return check_launch("reduce");
 }
 
@@ -410,7 +424,7 @@ static double host_scalar(hipStream_t s, const double* d) {
 }
 
 // Superposition of atomic densities (the SCF start of Sec. 4), renormalised so that
-// h^3 sum rho = n_elec; part: RED_BLOCKS doubles, sc: 8 doubles of scratch.
+// h^3 sum rho = n_elec; part: RED_BLOCKS doubles and a zeroed ticket word, sc: 8 doubles of scratch.
 // Synchronous (the renormalisation factor is read back to the host).
 static int sad_fill(hipStream_t s, Buffers& B, const sparc_grid* grid, const sparc_atoms* atoms, double n_elec,
                     double* rho_in, double* part, double* sc) {
@@ -459,9 +473,10 @@ extern "C" int sparc_sad_density(sparc_ctx* ctx, const sparc_grid* grid, const s
   if (!(n_elec > 0)) return fail(SPARC_EINVAL, "sparc_sad_density: n_elec must be positive");
   Buffers B;
   double *part, *sc;
-  SPARC_TRY(B.alloc(&part, RED_BLOCKS));
+  SPARC_TRY(B.alloc(&part, RED_BLOCKS + 2));
   SPARC_TRY(B.alloc(&sc, 16));
   hipStream_t s = ctx->stream;
+  SPARC_HIP(hipMemsetAsync(part + RED_BLOCKS, 0, 16, s));
   return sad_fill(s, B, grid, atoms, n_elec, rho_dev, part, sc);
 }
 
@@ -512,8 +527,9 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
   SPARC_TRY(B.alloc(&X, (size_t)n * ns));
   SPARC_TRY(B.alloc(&ritz, ns));
   SPARC_TRY(B.alloc(&occ, ns));
-  SPARC_TRY(B.alloc(&part, RED_BLOCKS));
+  SPARC_TRY(B.alloc(&part, RED_BLOCKS + 2));
   SPARC_TRY(B.alloc(&sc, 16));
+  SPARC_HIP(hipMemsetAsync(part + RED_BLOCKS, 0, 16, ctx->stream));
   SPARC_TRY(B.alloc(&pb, n));
   SPARC_TRY(B.alloc(&pr, n));
   SPARC_TRY(B.alloc(&pp, n));
