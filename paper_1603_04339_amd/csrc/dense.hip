@@ -1052,9 +1052,11 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
     T* Vb = (T*)scr;       // [NB][n] each; the inverse-iteration scratch is free until then
     T* Wb = Vb + (size_t)NB * n;
     SPARC_HIP(hipFuncSetAttribute((const void*)latrd_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
+    // about two threads per row (the barriers of a larger group cost more than it adds)
+    const int lt = std::min(1024, std::max(256, ((2 * n + 63) / 64) * 64));
     for (int i0 = 0; i0 < n - 1; i0 += NB) {
       const int jb = std::min(NB, n - 1 - i0);
-      latrd_kernel<T><<<1, 1024, lds2, s>>>(n, i0, jb, A, d, e, tau, Vb, Wb);
+      latrd_kernel<T><<<1, lt, lds2, s>>>(n, i0, jb, A, d, e, tau, Vb, Wb);
       SPARC_TRY(check_launch("latrd_kernel"));
       const int c0 = i0 + jb, m = n - c0;
       if (m > 0) {
@@ -1067,7 +1069,7 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
     hetrd_kernel<T><<<1, 64, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
   } else if (lds2 <= 150 * 1024) {
     SPARC_HIP(hipFuncSetAttribute((const void*)hetrd2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
-    hetrd2_kernel<T><<<1, 1024, lds2, s>>>(n, A, d, e, tau);
+    hetrd2_kernel<T><<<1, n < 64 ? 128 : 1024, lds2, s>>>(n, A, d, e, tau);
   } else {
     int nt = n >= 1024 ? 1024 : ((n + 63) / 64) * 64;
     hetrd_kernel<T><<<1, nt, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);

@@ -29,17 +29,7 @@ constexpr int RED_BLOCKS = 1024;
 // partial; the last block to finish (device-scope release/acquire on a ticket word that
 // follows the RED_BLOCKS partials) sums the partials in block order and resets the
 // ticket.  The partials are read with device-scope loads, past any stale L1 line.
-__global__ __launch_bounds__(256) void reduce_kernel(int64_t n, const double* __restrict__ a,
-                                                     const double* __restrict__ b, int op, double* part,
-                                                     double* __restrict__ out) {
-  double s = 0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double v;
-    if (op == RED_SUM) v = a[i];
-    else if (op == RED_DOT) v = a[i] * b[i];
-    else { double d = a[i] - b[i]; v = d * d; }
-    s += v;
-  }
+__device__ void finish_reduction(double s, double* part, double* __restrict__ out) {
   __shared__ double red[4];
   __shared__ int last;
   s = wave_sum(s);
@@ -67,10 +57,43 @@ __global__ __launch_bounds__(256) void reduce_kernel(int64_t n, const double* __
   }
 }
 
+__global__ __launch_bounds__(256) void reduce_kernel(int64_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b, int op, double* part,
+                                                     double* __restrict__ out) {
+  double s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double v;
+    if (op == RED_SUM) v = a[i];
+    else if (op == RED_DOT) v = a[i] * b[i];
+    else { double d = a[i] - b[i]; v = d * d; }
+    s += v;
+  }
+  finish_reduction(s, part, out);
+}
+
+// conjugate-gradient update x += a p, r -= a Ap (a = rr / pAp) and the new r.r, one launch
+__global__ __launch_bounds__(256) void cg_xr_rr_kernel(int64_t n, double* __restrict__ x, double* __restrict__ r,
+                                                       const double* __restrict__ p, const double* __restrict__ Ap,
+                                                       const double* rr, const double* pAp, double* part,
+                                                       double* __restrict__ rr_new) {
+  const double a = (*rr) / (*pAp);
+  double s = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * Ap[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  finish_reduction(s, part, rr_new);
+}
+
+static int red_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + 1023) / 1024));
+}
+
 // part: RED_BLOCKS doubles and the ticket word (zeroed once after allocation)
 static int reduce(hipStream_t s, int64_t n, const double* a, const double* b, int op, double* part, double* out) {
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + 1023) / 1024));
-  reduce_kernel<<<blocks, 256, 0, s>>>(n, a, b, op, part, out);
+  reduce_kernel<<<red_blocks(n), 256, 0, s>>>(n, a, b, op, part, out);
   return check_launch("reduce");
 }
 
@@ -116,14 +139,6 @@ __global__ void poisson_rhs_kernel(int64_t n, const double* __restrict__ rho, co
 }
 
 // CG updates with device scalars: alpha = rr / pAp
-__global__ void cg_update_xr_kernel(int64_t n, double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                                    const double* __restrict__ Ap, const double* rr, const double* pAp) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double a = (*rr) / (*pAp);
-  x[i] += a * p[i];
-  r[i] -= a * Ap[i];
-}
 __global__ void cg_update_p_kernel(int64_t n, double* __restrict__ p, const double* __restrict__ r, const double* rr_new,
                                    const double* rr_old) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -397,8 +412,7 @@ struct Poisson {
       double* rr1 = sc + ((it & 1) ? 0 : 2);
       SPARC_TRY(apply(p, Ap));
       SPARC_TRY(reduce(s, n, p, Ap, RED_DOT, part, sc + 1));
-      cg_update_xr_kernel<<<GRID1(n)>>>(n, v, r, p, Ap, rr0, sc + 1);
-      SPARC_TRY(reduce(s, n, r, r, RED_DOT, part, rr1));
+      cg_xr_rr_kernel<<<red_blocks(n), 256, 0, s>>>(n, v, r, p, Ap, rr0, sc + 1, part, rr1);
       cg_update_p_kernel<<<GRID1(n)>>>(n, p, r, rr1, rr0);
       if (it % 8 == 7) {
         SPARC_HIP(hipMemcpyAsync(&rr, rr1, 8, hipMemcpyDeviceToHost, s));
