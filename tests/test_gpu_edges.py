@@ -178,3 +178,40 @@ def test_every_tile_shape_batched(ctx, tile_env):
             print(f"batched tile {t} problem {i}: {err:.2e}")
             assert err < 1e-12
         plan.close()
+
+
+@pytest.mark.parametrize("dt,k,bc", [("r64", (0.0, 0.0, 0.0), (0, 0, 1)), ("c128", (0.21, -0.13, 0.3), (0, 0, 0)),
+                                     ("r32", (0.0, 0.0, 0.0), (1, 0, 0)), ("c64", (0.17, 0.0, -0.29), (0, 1, 0))],
+                         ids=["r64_zslab", "c128_bloch", "r32_xslab", "c64_bloch_yslab"])
+def test_point_form_matches_tiled_and_oracle(ctx, tile_env, dt, k, bc):
+    """A step whose tiled launch would leave CUs idle runs one thread per (node,
+    orbital); a forced tile shape keeps the tiled kernel.  Both against the oracle H X
+    on a grid no tile divides, with Bloch phases and a Dirichlet direction, and against
+    each other."""
+    cplx = dt.startswith("c")
+    cell, rng = _cell(61, n=(37, 29, 21), L=(14.8, 11.6, 8.4))
+    cell.bc = bc
+    kk = tuple(0.0 if b else kv for kv, b in zip(k, bc))
+    grid, V, P = oracle_setup(cell, kk)
+    X = rng.standard_normal((3, grid.n_d))
+    if cplx:
+        X = X + 1j * rng.standard_normal((3, grid.n_d))
+    single = dt in ("r32", "c64")
+    tdt = {"r64": torch.float64, "c128": torch.complex128, "r32": torch.float32, "c64": torch.complex64}[dt]
+    ham = sp.Hamiltonian(ctx, cell, {"r64": sp.R64, "c128": sp.C128, "r32": sp.R32, "c64": sp.C64}[dt], kpt=kk)
+    Xd = to_dev(X, tdt)
+    Xr = block_to_oracle(Xd).astype(np.complex128 if cplx else np.float64)
+    ref = apply_H(Xr, grid, V, P)
+    w = sp.workspace(ham, 3, sp.OP_APPLY)
+    os.environ.pop("SPARC_HSTEP_TILE", None)
+    Yp = torch.zeros_like(Xd)
+    sp.fd_hamiltonian_apply(ham, Xd, Yp, w)   # 3 orbitals on a small grid: the point form
+    os.environ["SPARC_HSTEP_TILE"] = "1"
+    Yt = torch.zeros_like(Xd)
+    sp.fd_hamiltonian_apply(ham, Xd, Yt, w)   # the tiled kernel, 32 x 16
+    ep = colnorm_err(block_to_oracle(Yp).astype(Xr.dtype), ref)
+    et = colnorm_err(block_to_oracle(Yt).astype(Xr.dtype), ref)
+    ept = colnorm_err(block_to_oracle(Yp).astype(Xr.dtype), block_to_oracle(Yt).astype(Xr.dtype))
+    print(f"{dt} bc={bc}: point {ep:.2e}, tiled {et:.2e}, point vs tiled {ept:.2e}")
+    tol = 2e-5 if single else 1e-12
+    assert ep < tol and et < tol and ept < tol
