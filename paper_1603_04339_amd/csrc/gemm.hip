@@ -557,10 +557,11 @@ static int gram_launch(hipStream_t s, int64_t N, int na, int nb, const E* A, int
 
 // ------------------------------------------------------------ GEMM shape tuner
 // With a context that autotunes, the first product of a new shape (N, n_a, n_b, type,
-// Hermitian) times the tile edges next to the heuristic's (32 / 64 / 128) and, for the
-// Gram, slab counts of half, one and two times the plan's, each launch once to warm up
-// and twice timed with HIP events, and keeps the fastest; the heuristic's own choice is
-// among the candidates.  Later products of that shape reuse it.
+// Hermitian, one or two operands) times the tile edges next to the heuristic's
+// (32 / 64 / 128) and, for the Gram, slab counts of half, one and two times the plan's,
+// each launch once to warm up and twice timed with HIP events, and keeps the fastest;
+// the heuristic's own choice is among the candidates.  Later products of that shape
+// reuse it.
 struct GemmChoice { int T; int64_t slabs; };
 static std::mutex g_gemm_tune_mu;
 static std::map<std::tuple<int64_t, int, int, int, int, int>, GemmChoice> g_gemm_tune;
@@ -616,7 +617,9 @@ static int gram_t(hipStream_t s, int64_t N, int na, int nb, const E* A, int64_t 
   GemmChoice c{split ? gram_tile<E>::T : native_tile<E>(na, nb), 0};
   if (split || !tune || !tune->autotune)
     return gram_launch<E>(s, N, na, nb, A, lda, B, ldb, C, ldc, work, work_bytes, n_cu, herm, mode, c.T, c.slabs);
-  const auto key = std::make_tuple(N, na, nb, (int)(sizeof(E) * 2 + (elem<E>::is_cplx ? 1 : 0)), herm ? 1 : 0, 0);
+  // kind 0: one operand (A^H A), 2: two (they read twice the data)
+  const int kind = (A == B && lda == ldb) ? 0 : 2;
+  const auto key = std::make_tuple(N, na, nb, (int)(sizeof(E) * 2 + (elem<E>::is_cplx ? 1 : 0)), herm ? 1 : 0, kind);
   if (!gemm_lookup(key, &c)) {
     hipEvent_t e0, e1;
     SPARC_HIP(hipEventCreate(&e0));
