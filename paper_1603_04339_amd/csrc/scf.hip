@@ -368,6 +368,7 @@ struct Poisson {
   int64_t n;
   double *b, *r, *p, *Ap, *part, *sc;  // sc: [0] rr, [1] pAp, [2] rr_new, [3] sum, [4] bb
   int iters_total = 0;
+  int last_iters = 0;  // iterations of the previous solve: the next one is checked from 3/4 of it
 
   double shift = 0.0;  // k^2 of the Helmholtz form (-Lap_h + k^2); 0: Poisson
 
@@ -414,7 +415,9 @@ struct Poisson {
       SPARC_TRY(reduce(s, n, p, Ap, RED_DOT, part, sc + 1));
       cg_xr_rr_kernel<<<red_blocks(n), 256, 0, s>>>(n, v, r, p, Ap, rr0, sc + 1, part, rr1);
       cg_update_p_kernel<<<GRID1(n)>>>(n, p, r, rr1, rr0);
-      if (it % 8 == 7) {
+      // the residual is read back (a host synchronisation) every 8 iterations, from 3/4
+      // of the previous solve's count on (warm-started solves take similar counts)
+      if (it % 8 == 7 && it >= (3 * last_iters) / 4 - 8) {
         SPARC_HIP(hipMemcpyAsync(&rr, rr1, 8, hipMemcpyDeviceToHost, s));
         SPARC_HIP(hipStreamSynchronize(s));
         if (!std::isfinite(rr)) return fail(SPARC_ENAN, "poisson: non-finite residual");
@@ -422,6 +425,7 @@ struct Poisson {
       }
     }
     iters_total += it + 1;
+    last_iters = it + 1;
     if (it >= max_it) return fail(SPARC_ENOCONV, "poisson: CG did not converge in %d iterations", max_it);
     if (!zero_mean) return check_launch("helmholtz");
     SPARC_TRY(reduce(s, n, v, nullptr, RED_SUM, part, sc + 3));
@@ -632,7 +636,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
     d2f_block_kernel<<<GRID1((int64_t)n * ns)>>>((int64_t)n * ns, X, X32);
     SPARC_TRY(check_launch("d2f_block_kernel"));
   }
-  double F = 0, mu = 0, err = 1, prev_err = 1e300;
+  double F = 0, mu = 0, err = 1, prev_err = 1e300, lcut_next = 0;
   int it = 1;
   int converged = 0;
   for (; it <= P->max_iter; ++it) {
@@ -643,7 +647,9 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
     if (it == 1) SPARC_TRY(lanczos_bounds(H64, P->lanczos_v0_dev, P->lanczos_steps, work, wbytes, &lmin, &lmax));
     const int passes = (it == 1) ? P->n_first_passes : 1;
     for (int ps = 0; ps < passes; ++ps) {
-      lcut = have_ritz ? host_scalar(s, ritz + ns - 1) : 0.5 * (lmin + lmax);
+      // the largest Ritz value of the previous pass (read with the last iteration's
+      // energy after the first iteration's passes)
+      lcut = !have_ritz ? 0.5 * (lmin + lmax) : (it > 1 && ps == 0) ? lcut_next : host_scalar(s, ritz + ns - 1);
       if (use32) {
         SPARC_TRY(chebyshev_filter(H32, X32, n, ns, P->degree, lcut, lmax, work, wbytes));
         SPARC_TRY(rayleigh_ritz(H32, X32, n, ns, P->rr, ritz, work, wbytes, nullptr));
@@ -655,24 +661,23 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
     }
     const double wk = 1.0;
     SPARC_TRY(sparc_fermi(ctx, 1, ns, ritz, &wk, P->n_elec, P->kT, occ, &mu));
-    // Harris-Foulkes free energy at rho_in
+    // Harris-Foulkes free energy at rho_in, the output density and its residual; the
+    // energy terms, the residual norms and the next filter cut come back in one
+    // synchronisation
     band_entropy_kernel<<<1, 256, 0, s>>>(ns, ritz, occ, P->kT, sc + 8);
     SPARC_TRY(reduce(s, n, edc, nullptr, RED_SUM, part, sc + 10));
-    double be[3];
-    SPARC_HIP(hipMemcpyAsync(be, sc + 8, 3 * 8, hipMemcpyDeviceToHost, s));
-    SPARC_HIP(hipStreamSynchronize(s));
-    F = be[0] + dV * be[2] + be[1] + e_psd;
-    if (!std::isfinite(F)) return fail(SPARC_ENAN, "sparc_scf_run: non-finite energy at iteration %d", it);
-    // output density from the current block
     const void* xs[1] = {use32 ? (const void*)X32 : (const void*)X};
     const int64_t lds[1] = {n};
     SPARC_TRY(density_from_orbitals(ctx, 1, xs, lds, ns, use32 ? SPARC_R32 : SPARC_R64, occ, n, dV, rho_out));
     SPARC_TRY(reduce(s, n, rho_out, rho_in, RED_DIFF2, part, sc + 11));
     SPARC_TRY(reduce(s, n, rho_in, rho_in, RED_DOT, part, sc + 12));
-    double dd[2];
-    SPARC_HIP(hipMemcpyAsync(dd, sc + 11, 16, hipMemcpyDeviceToHost, s));
+    double hv[5];
+    SPARC_HIP(hipMemcpyAsync(hv, sc + 8, 5 * 8, hipMemcpyDeviceToHost, s));
+    SPARC_HIP(hipMemcpyAsync(&lcut_next, ritz + ns - 1, 8, hipMemcpyDeviceToHost, s));
     SPARC_HIP(hipStreamSynchronize(s));
-    err = std::sqrt(dd[0] / dd[1]);
+    F = hv[0] + dV * hv[2] + hv[1] + e_psd;
+    if (!std::isfinite(F)) return fail(SPARC_ENAN, "sparc_scf_run: non-finite energy at iteration %d", it);
+    err = std::sqrt(hv[3] / hv[4]);
     if (res->history) {
       res->history[3 * (it - 1)] = F;
       res->history[3 * (it - 1) + 1] = err;
