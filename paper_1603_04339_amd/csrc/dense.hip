@@ -328,9 +328,12 @@ static int chol_orth_t(hipStream_t s, int n, const T* M, T* Tout, int* info, voi
 // estimate of lambda_max(M_s^{-1}) = ||R^{-1}||_2^2 (R^{-1} = D T with T = D^{-1} R^{-1}
 // from chol_orth), from a fixed start vector.  One work-group; *out = the estimate, or
 // 1e300 after a failed factorisation.
-template <typename T>
-__global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restrict__ M, const T* __restrict__ Tm,
-                                                        const double* __restrict__ dinv, int iters,
+// With STAGE (small n) the triangle of T, 1 / D^{-1} and the scaled |M| are first put in
+// LDS with coalesced loads, so the column sums and the power iterations read no global
+// memory; the arithmetic is the same in both forms.
+template <typename T, bool STAGE>
+__global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restrict__ M, const T* __restrict__ Tg,
+                                                        const double* __restrict__ dinv_g, int iters,
                                                         const int* __restrict__ info, double* __restrict__ out) {
   extern __shared__ char smem[];
   T* v = (T*)smem;  // [n]
@@ -341,15 +344,36 @@ __global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restri
     if (tid == 0) *out = 1e300;
     return;
   }
+  const T* Tm = Tg;
+  double* rinv = nullptr;   // 1 / dinv (STAGE)
+  double* am = nullptr;     // |M_ij| dinv_i (STAGE)
+  if constexpr (STAGE) {
+    T* ts = y + n;          // [n][n], upper triangle filled
+    rinv = (double*)(ts + (size_t)n * n);
+    am = rinv + n;
+    for (int q = tid; q < n * n; q += nt) {
+      const int i = q % n, j = q / n;
+      if (i <= j) ts[q] = Tg[q];
+      const T m = M[q];
+      am[q] = sqrt(re_(mul_(conj_(m), m))) * dinv_g[i];
+    }
+    for (int i = tid; i < n; i += nt) rinv[i] = 1.0 / dinv_g[i];
+    __syncthreads();
+    Tm = ts;
+  }
   // Gershgorin: largest column sum of |M_s| (M_s Hermitian)
   double g = 0.0;
   for (int j = tid; j < n; j += nt) {
     double c = 0.0;
     for (int i = 0; i < n; ++i) {
-      const T m = M[i + (int64_t)j * n];
-      c += sqrt(re_(mul_(conj_(m), m))) * dinv[i];
+      if constexpr (STAGE) {
+        c += am[i + (int64_t)j * n];
+      } else {
+        const T m = M[i + (int64_t)j * n];
+        c += sqrt(re_(mul_(conj_(m), m))) * dinv_g[i];
+      }
     }
-    g = fmax(g, c * dinv[j]);
+    g = fmax(g, c * dinv_g[j]);
   }
   for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o, 64));
   if ((tid & 63) == 0) red[tid >> 6] = g;
@@ -359,12 +383,16 @@ __global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restri
   __syncthreads();
   for (int i = tid; i < n; i += nt) v[i] = mkT<T>(1.0 + 0.5 * (double)((i * 7919) % 13) / 13.0, 0.0);
   __syncthreads();
+  auto ri = [&](int i) -> double {
+    if constexpr (STAGE) return rinv[i];
+    else return 1.0 / dinv_g[i];
+  };
   double mu = 0.0;
   for (int it = 0; it < iters; ++it) {
     // y = B^H v, B = R^{-1} (upper triangular): y_j = sum_{i <= j} conj(T_ij / dinv_i) v_i
     for (int j = tid; j < n; j += nt) {
       T acc = mkT<T>(0.0, 0.0);
-      for (int i = 0; i <= j; ++i) acc = add_(acc, mul_(conj_(rscale(1.0 / dinv[i], Tm[i + (int64_t)j * n])), v[i]));
+      for (int i = 0; i <= j; ++i) acc = add_(acc, mul_(conj_(rscale(ri(i), Tm[i + (int64_t)j * n])), v[i]));
       y[j] = acc;
     }
     __syncthreads();
@@ -373,7 +401,7 @@ __global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restri
     for (int i = tid; i < n; i += nt) {
       T acc = mkT<T>(0.0, 0.0);
       for (int j = i; j < n; ++j) acc = add_(acc, mul_(Tm[i + (int64_t)j * n], y[j]));
-      acc = rscale(1.0 / dinv[i], acc);
+      acc = rscale(ri(i), acc);
       v[i] = acc;
       nrm += re_(mul_(conj_(acc), acc));
     }
@@ -394,7 +422,14 @@ static int chol_cond_est_t(hipStream_t s, int n, const T* M, const T* Tm, const 
   const double* dinv = (const double*)p;
   // one thread per column up to 1024 (a small matrix keeps the barriers of a small group)
   const int threads = std::min(1024, ((n + 63) / 64) * 64);
-  cond_est_kernel<T><<<1, threads, 2 * (size_t)n * sizeof(T), s>>>(n, M, Tm, dinv, 8, info, out);
+  const size_t staged = ((size_t)n * n + 2 * n) * sizeof(T) + ((size_t)n * n + n) * 8;
+  if (staged <= 150 * 1024) {
+    SPARC_HIP(hipFuncSetAttribute((const void*)cond_est_kernel<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)staged));
+    cond_est_kernel<T, true><<<1, threads, staged, s>>>(n, M, Tm, dinv, 8, info, out);
+  } else {
+    cond_est_kernel<T, false><<<1, threads, 2 * (size_t)n * sizeof(T), s>>>(n, M, Tm, dinv, 8, info, out);
+  }
   return check_launch("cond_est_kernel");
 }
 
@@ -609,6 +644,98 @@ __global__ __launch_bounds__(1024) void hetrd2_kernel(int n, T* __restrict__ A, 
     __syncthreads();
   }
   if (tid == 0) d[n - 1] = re_(A[(n - 1) + (int64_t)(n - 1) * n]);
+}
+
+// The same reduction for n <= 64 with the whole matrix in LDS (column-major, leading
+// dimension n + 1), four waves: lane r of every wave owns row r, wave q the columns
+// c = q mod 4 of the matrix-vector product and of the rank-2 update.  Sums over rows are
+// wave butterflies, whose result is the same on every lane of every wave, so each wave
+// forms the same reflector without exchanging it.  The matrix is read once and written
+// back once.
+template <typename T>
+__global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__ A, double* __restrict__ d,
+                                                          double* __restrict__ e, T* __restrict__ tau) {
+  extern __shared__ char smem[];
+  const int ld = n + 1;
+  T* a = (T*)smem;       // [n][ld]
+  T* v = a + n * ld;     // [64]
+  T* w = v + 64;         // [64]
+  T* part = w + 64;      // [4][64]
+  const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+  for (int c = q; c < n; c += 4)
+    if (r < n) a[r + c * ld] = A[r + (int64_t)c * n];
+  __syncthreads();
+  for (int i = 0; i < n - 1; ++i) {
+    const int r0 = i + 1;
+    double xn = 0.0;
+    if (r >= i + 2 && r < n) {
+      const T x = a[r + i * ld];
+      xn = re_(mul_(conj_(x), x));
+    }
+    xn = wave_sum(xn);
+    const T alpha = a[r0 + i * ld];
+    const double ar = re_(alpha);
+    double ai = 0;
+    if constexpr (sizeof(T) == 16) ai = ((const cd&)alpha).im;
+    T tau_i, scl;
+    double beta;
+    if (xn == 0.0 && ai == 0.0) {
+      tau_i = mkT<T>(0.0, 0.0);
+      beta = ar;
+      scl = mkT<T>(0.0, 0.0);
+    } else {
+      beta = -copysign(sqrt(ar * ar + ai * ai + xn), ar);
+      tau_i = mkT<T>((beta - ar) / beta, -ai / beta);
+      const double dr = ar - beta, di = ai, den = dr * dr + di * di;
+      scl = mkT<T>(dr / den, -di / den);
+    }
+    const bool trivial = re_(mul_(conj_(tau_i), tau_i)) == 0.0;
+    T vr = mkT<T>(0.0, 0.0);
+    if (r == r0) vr = mkT<T>(1.0, 0.0);
+    else if (r > r0 && r < n) vr = mul_(a[r + i * ld], scl);
+    __syncthreads();   // every wave has read column i
+    if (q == 0) {
+      if (r > r0 && r < n) a[r + i * ld] = vr;
+      v[r] = vr;
+    }
+    __syncthreads();
+    if (!trivial) {
+      // p = tau A_sub v (partial products over this wave's columns), alpha2 = -1/2 tau
+      // (p^H v), w = p + alpha2 v
+      T acc = mkT<T>(0.0, 0.0);
+      if (r >= r0 && r < n) {
+        int c = r0 + ((q - r0) & 3);
+        for (; c < n; c += 4) acc = add_(acc, mul_(a[r + c * ld], v[c]));
+      }
+      part[q * 64 + r] = acc;
+      __syncthreads();
+      const T sum = add_(add_(part[r], part[64 + r]), add_(part[128 + r], part[192 + r]));
+      const T pr = (r >= r0 && r < n) ? mul_(tau_i, sum) : mkT<T>(0.0, 0.0);
+      const T t = mul_(conj_(pr), vr);
+      double sr = wave_sum(re_(t)), si = 0.0;
+      if constexpr (sizeof(T) == 16) si = wave_sum(((const cd&)t).im);
+      const T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(sr, si)));
+      const T wr = add_(pr, mul_(a2, vr));
+      if (q == 0) w[r] = wr;
+      __syncthreads();
+      // A_sub -= v w^H + w v^H over this wave's columns
+      if (r >= r0 && r < n) {
+        int c = r0 + ((q - r0) & 3);
+        for (; c < n; c += 4)
+          a[r + c * ld] = sub_(a[r + c * ld], add_(mul_(vr, conj_(w[c])), mul_(wr, conj_(v[c]))));
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      e[i] = beta;
+      d[i] = re_(a[i + i * ld]);
+      tau[i] = tau_i;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) d[n - 1] = re_(a[(n - 1) + (n - 1) * ld]);
+  for (int c = q; c < n; c += 4)
+    if (r < n) A[r + (int64_t)c * n] = a[r + c * ld];
 }
 
 // Blocked Householder tridiagonalisation (lower; panel / trailing-update split).
@@ -1067,6 +1194,11 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
     last_diag_kernel<T><<<1, 64, 0, s>>>(n, A, d);
   } else if (n == 1) {
     hetrd_kernel<T><<<1, 64, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
+  } else if (n <= 64) {
+    const size_t lds_s = ((size_t)n * (n + 1) + 384) * sizeof(T);
+    SPARC_HIP(hipFuncSetAttribute((const void*)hetrd_small_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds_s));
+    hetrd_small_kernel<T><<<1, 256, lds_s, s>>>(n, A, d, e, tau);
   } else if (lds2 <= 150 * 1024) {
     SPARC_HIP(hipFuncSetAttribute((const void*)hetrd2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
     hetrd2_kernel<T><<<1, n < 64 ? 128 : 1024, lds2, s>>>(n, A, d, e, tau);

@@ -180,22 +180,33 @@ size_t alpha_bytes(const sparc_ham* H, int32_t n_s) {
   return (size_t)std::max(H->n_proj, 1) * (size_t)alpha_ld(n_s) * elem_bytes(H->dtype);
 }
 
+template <typename E, int MAXP, int NB>
+static void nl_gather_launch(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha) {
+  dim3 grid(H->n_atoms_nl, (n_s + NB - 1) / NB);
+  nl_gather_kernel<E, MAXP, NB><<<grid, 256, 0, H->ctx->stream>>>(
+      (const E*)x, ldx, n_s, H->sup_ptr, H->sup_idx, H->atom_pbeg, H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha,
+      alpha_ld(n_s));
+}
+
+// One work-group per (atom, NB orbitals): NB = 8 (4 complex), or 2 (1 complex) when that
+// would leave fewer than two work-groups per CU (few atoms and orbitals: the SCF cells),
+// which spreads each atom's sums over more CUs
 template <typename E>
 static int nl_project_t(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha) {
   if (H->n_proj == 0) return SPARC_OK;
-  hipStream_t st = H->ctx->stream;
-  constexpr int NB = elem<E>::is_cplx ? 4 : 8;
-  dim3 grid(H->n_atoms_nl, (n_s + NB - 1) / NB);
+  constexpr int NBW = elem<E>::is_cplx ? 4 : 8, NBN = NBW / 4;
+  const bool narrow = (int64_t)H->n_atoms_nl * ((n_s + NBW - 1) / NBW) < 2 * (int64_t)H->ctx->n_cu;
   int t = timer_begin(H->ctx, "nl_gather");
   struct End { sparc_ctx* c; int t; ~End() { timer_end(c, t); } } end_{H->ctx, t};
-  if (H->max_proj_per_atom <= 1)
-    nl_gather_kernel<E, 1, NB><<<grid, 256, 0, st>>>((const E*)x, ldx, n_s, H->sup_ptr, H->sup_idx, H->atom_pbeg,
-                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, alpha_ld(n_s));
-  else if (H->max_proj_per_atom <= 4)
-    nl_gather_kernel<E, 4, NB><<<grid, 256, 0, st>>>((const E*)x, ldx, n_s, H->sup_ptr, H->sup_idx, H->atom_pbeg,
-                                                     H->proj_voff, (const E*)H->pval, H->dV, (E*)alpha, alpha_ld(n_s));
-  else
+  if (H->max_proj_per_atom <= 1) {
+    if (narrow) nl_gather_launch<E, 1, NBN>(H, x, ldx, n_s, alpha);
+    else nl_gather_launch<E, 1, NBW>(H, x, ldx, n_s, alpha);
+  } else if (H->max_proj_per_atom <= 4) {
+    if (narrow) nl_gather_launch<E, 4, NBN>(H, x, ldx, n_s, alpha);
+    else nl_gather_launch<E, 4, NBW>(H, x, ldx, n_s, alpha);
+  } else {
     return fail(SPARC_EINVAL, "nl_project: more than 4 projector functions on one atom");
+  }
   return check_launch("nl_gather_kernel");
 }
 
@@ -632,6 +643,152 @@ static bool use_point_form(const sparc_ham* H, const StepArgs<E>& A, int32_t n_s
   StepArgs<E> B = A;
   const int64_t G = plan_problem(B, kTiles[t].tx, kTiles[t].ty, H->grid.n_o, n_s, H->ctx->n_cu);
   return G < H->ctx->n_cu;
+}
+
+// ------------------------------------------------------------ conjugate-gradient iteration
+// g = r.r and d = w.r from the block partials of the last cg_apply_kernel, added in the
+// same fixed order by every block (so every block takes the same step)
+__device__ __forceinline__ void cg_sums(const CgIter& C, double& g, double& d) {
+  __shared__ double red[2][4];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < C.nparts; i += 256) {
+    a += C.part[i];
+    b += C.part[kCgBlocks + i];
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  g = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+  d = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+}
+
+// node-wise part of iteration it: the step scalars, then p = r + beta p, s = w + beta s,
+// x += alpha p, r -= alpha s
+__global__ __launch_bounds__(256) void cg_update_kernel(int64_t nd, CgIter C) {
+  double g, d;
+  cg_sums(C, g, d);
+  double beta = 0.0, alpha = g / d;
+  if (C.it > 0) {
+    const double* pv = C.sc + 4 * ((C.it + 1) % 2);
+    beta = g / pv[0];
+    alpha = g / (d - beta * g / pv[2]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* cv = C.sc + 4 * (C.it % 2);
+    cv[0] = g;
+    cv[1] = d;
+    cv[2] = alpha;
+  }
+  const int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x;
+  if (t >= nd) return;
+  const double rt = C.r[t];
+  const double pn = fma(beta, C.p[t], rt);
+  const double sn = fma(beta, C.s[t], C.w[t]);
+  C.p[t] = pn;
+  C.s[t] = sn;
+  C.x[t] = fma(alpha, pn, C.x[t]);
+  C.r[t] = fma(-alpha, sn, rt);
+}
+
+// r.r of the current residual into sc[8] (for the convergence test)
+__global__ __launch_bounds__(256) void cg_norm_kernel(CgIter C) {
+  double g, d;
+  cg_sums(C, g, d);
+  if (threadIdx.x == 0) C.sc[8] = g;
+}
+
+// w = A r with the point-form taps; block partials of r.r and w.r
+template <int NO>
+__global__ __launch_bounds__(256) void cg_apply_kernel(StepArgs<double> A, CgIter C) {
+  const int64_t nd = (int64_t)A.n1 * A.n2 * A.n3;
+  const double* __restrict__ r = C.r;
+  double a = 0.0, b = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)256 + threadIdx.x; t < nd; t += (int64_t)gridDim.x * 256) {
+    const int i = (int)(t % A.n1), j = (int)((t / A.n1) % A.n2), k = (int)(t / ((int64_t)A.n1 * A.n2));
+    const double r0 = r[t];
+    double lap = A.centre * r0;
+#pragma unroll
+    for (int q = 1; q <= NO; ++q) {
+      lap = fmar(lap, A.tz[q - 1], point_tap(A, r, i, j, k + q) + point_tap(A, r, i, j, k - q));
+      lap = fmar(lap, A.tx[q - 1], point_tap(A, r, i + q, j, k) + point_tap(A, r, i - q, j, k));
+      lap = fmar(lap, A.ty[q - 1], point_tap(A, r, i, j + q, k) + point_tap(A, r, i, j - q, k));
+    }
+    const double w0 = fmar(lap, A.vb, r0);
+    C.w[t] = w0;
+    a = fma(r0, r0, a);
+    b = fma(w0, r0, b);
+  }
+  __shared__ double red[2][4];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    C.part[blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    C.part[kCgBlocks + blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+static StepArgs<double> cg_args(const sparc_ham* H, double a, double b) {
+  StepArgs<double> A{};
+  A.n1 = H->grid.n[0];
+  A.n2 = H->grid.n[1];
+  A.n3 = H->grid.n[2];
+  A.centre = a * H->centre;
+  for (int p = 0; p < 8; ++p) {
+    A.tx[p] = a * H->tap[0][p];
+    A.ty[p] = a * H->tap[1][p];
+    A.tz[p] = a * H->tap[2][p];
+  }
+  A.vb = b;
+  A.dmask = dirichlet_mask(H->grid);
+  return A;
+}
+
+bool cg_point_form(sparc_ham* H) {
+  if (H->dtype != SPARC_R64) return false;
+  StepArgs<double> A = cg_args(H, 1.0, 0.0);
+  return use_point_form<double>(H, A, 1, heuristic_tile(A.n1, A.n2, sizeof(double)));
+}
+
+int cg_blocks(const sparc_ham* H) {
+  const int64_t nd = (int64_t)H->grid.n[0] * H->grid.n[1] * H->grid.n[2];
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kCgBlocks, (nd + 255) / 256));
+}
+
+int cg_apply(sparc_ham* H, double a, double b, const CgIter& C) {
+  if (H->dtype != SPARC_R64) return fail(SPARC_EINVAL, "cg_apply: FP64 operator only");
+  if (C.nparts != cg_blocks(H)) return fail(SPARC_EINVAL, "cg_apply: nparts must be cg_blocks()");
+  const StepArgs<double> A = cg_args(H, a, b);
+  hipStream_t st = H->ctx->stream;
+  const unsigned blocks = (unsigned)C.nparts;
+  switch (H->grid.n_o) {
+#define CASE(K) case K: cg_apply_kernel<K><<<blocks, 256, 0, st>>>(A, C); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return fail(SPARC_EINVAL, "cg_apply: n_o=%d unsupported", H->grid.n_o);
+  }
+  return check_launch("cg_apply_kernel");
+}
+
+int cg_iterate(sparc_ham* H, double a, double b, const CgIter& C) {
+  const int64_t nd = (int64_t)H->grid.n[0] * H->grid.n[1] * H->grid.n[2];
+  if ((nd + 255) / 256 > (int64_t)INT32_MAX) return fail(SPARC_ESHAPE, "cg_iterate: grid too large");
+  cg_update_kernel<<<(unsigned)((nd + 255) / 256), 256, 0, H->ctx->stream>>>(nd, C);
+  SPARC_TRY(check_launch("cg_update_kernel"));
+  return cg_apply(H, a, b, C);
+}
+
+int cg_residual_norm(sparc_ham* H, const CgIter& C) {
+  cg_norm_kernel<<<1, 256, 0, H->ctx->stream>>>(C);
+  return check_launch("cg_norm_kernel");
 }
 
 template <typename E>

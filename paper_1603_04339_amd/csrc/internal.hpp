@@ -187,6 +187,35 @@ int noalloc_scratch_init(int device);
 //   out += a * V_nl-scatter(alpha); a from a device scalar when a_dev != nullptr
 int nl_scatter(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out, int64_t ldo);
 int heuristic_tile(int n1, int n2, size_t elem_size);
+// Conjugate gradients on A = a (-1/2 Lap_h) + b (FP64, one orbital) in two launches per
+// iteration, for grids whose stencil step runs in point form (cg_point_form).  In the
+// Chronopoulos-Gear arrangement, which needs one reduction phase per iteration: from
+// g = r.r, d = w.r (w = A r) of the current residual and g, alpha of the previous
+// iteration, beta = g / g_prev (0 on the first iteration) and
+// alpha = g / (d - beta g / alpha_prev) (g / d on the first); then, node by node,
+//   p = r + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+// and w = A r with the block partials of the new g and d (cg_apply).  All vectors are
+// updated in place (s = A p).  part: 2 * kCgBlocks doubles of block partials (nparts =
+// cg_blocks() of them used); sc: two slots of four doubles (g, d, alpha, unused) written
+// by iteration it into slot it % 2, and sc[8] for cg_residual_norm.  The first iteration
+// needs r, w = cg_apply(r) (which leaves its partials) and p = s = 0.
+constexpr int kCgBlocks = 1024;
+struct CgIter {
+  double* r;
+  double* w;
+  double* s;
+  double* p;
+  double* x;
+  double* sc;
+  double* part;
+  int nparts;
+  int it;
+};
+bool cg_point_form(sparc_ham* H);
+int cg_blocks(const sparc_ham* H);
+int cg_apply(sparc_ham* H, double a, double b, const CgIter& C);
+int cg_iterate(sparc_ham* H, double a, double b, const CgIter& C);
+int cg_residual_norm(sparc_ham* H, const CgIter& C);
 // projections and scatters of several problems in one launch each (hamiltonian.hip): one
 // argument block per problem in a device table, work-group offsets per problem
 struct NlBatchArgs {

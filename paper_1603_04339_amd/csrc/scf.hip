@@ -25,36 +25,11 @@ enum RedOp { RED_SUM = 0, RED_DOT = 1, RED_DIFF2 = 2 };
 
 constexpr int RED_BLOCKS = 1024;
 
-// One launch per reduction: every block reduces its grid-stride share and stores the
-// partial; the last block to finish (device-scope release/acquire on a ticket word that
-// follows the RED_BLOCKS partials) sums the partials in block order and resets the
-// ticket.  The partials are read with device-scope loads, past any stale L1 line.
-__device__ void finish_reduction(double s, double* part, double* __restrict__ out) {
-  __shared__ double red[4];
-  __shared__ int last;
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  unsigned* ticket = (unsigned*)(part + RED_BLOCKS);
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&part[blockIdx.x], red[0] + red[1] + red[2] + red[3], __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  double t2 = 0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
-    t2 += __hip_atomic_load(&part[i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-  t2 = wave_sum(t2);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t2;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    *out = red[0] + red[1] + red[2] + red[3];
-    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+// One launch per reduction (finish_sums: block partials, then the last block adds them
+// in block order)
+__device__ __forceinline__ void finish_reduction(double s, double* part, double* __restrict__ out) {
+  double v[1] = {s};
+  finish_sums<1>(v, part, RED_BLOCKS, out);
 }
 
 __global__ __launch_bounds__(256) void reduce_kernel(int64_t n, const double* __restrict__ a,
@@ -254,51 +229,81 @@ static void launch_multi_dot(hipStream_t s, int nblk, int64_t n, int m, const Ve
     default: multi_dot_partial_kernel<9><<<nblk, 256, 0, s>>>(n, vs, part); break;
   }
 }
-__global__ void multi_dot_final_kernel(int nblocks, int npairs, const double* __restrict__ part, double* __restrict__ out) {
-  for (int q = threadIdx.x; q < npairs; q += blockDim.x) {
-    double s = 0;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * npairs + q];
-    out[q] = s;
-  }
-}
-// gamma from (dF^T dF) gamma = dF^T f by Gaussian elimination with partial pivoting;
-// a pivot below 1e-14 of the largest diagonal drops that direction (gamma_k = 0)
-__global__ void anderson_solve_kernel(int m, const double* __restrict__ pairs, double* __restrict__ gamma) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double A[AMAX][AMAX + 1];
-  const int nv = m + 1;
-  auto pidx = [&](int a, int b) {  // index of pair (a <= b)
-    int q = 0;
-    for (int r = 0; r < a; ++r) q += nv - r;
-    return q + (b - a);
-  };
-  double dmax = 0;
-  for (int i = 0; i < m; ++i) {
-    for (int j = 0; j < m; ++j) A[i][j] = pairs[pidx(min(i, j), max(i, j))];
-    A[i][m] = pairs[pidx(i, m)];
-    dmax = fmax(dmax, A[i][i]);
-  }
-  int perm[AMAX];
-  bool dead[AMAX];
-  for (int i = 0; i < m; ++i) { perm[i] = i; dead[i] = false; }
-  for (int k = 0; k < m; ++k) {
-    int p = k;
-    for (int i = k + 1; i < m; ++i) if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
-    if (p != k) for (int j = 0; j <= m; ++j) { double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
-    if (fabs(A[k][k]) <= 1e-14 * dmax) { dead[k] = true; continue; }
-    for (int i = k + 1; i < m; ++i) {
-      double f = A[i][k] / A[k][k];
-      for (int j = k; j <= m; ++j) A[i][j] -= f * A[k][j];
+// gamma from (dF^T dF) gamma = dF^T f by Gaussian elimination with partial pivoting; a
+// pivot below 1e-14 of the largest diagonal drops that direction (gamma_k = 0).  One
+// work-group of 256 threads: the pair sums over the multi-dot blocks (one wave per pair,
+// lanes over blocks), then the elimination in LDS (a row operation per thread).
+__global__ __launch_bounds__(256) void anderson_gamma_kernel(int nblocks, int m, const double* __restrict__ part,
+                                                             double* __restrict__ pairs, double* __restrict__ gamma) {
+  __shared__ double pr[(AMAX + 1) * (AMAX + 2) / 2];
+  __shared__ double A[AMAX][AMAX + 1];
+  __shared__ double f[AMAX];
+  __shared__ double dmax;
+  __shared__ int piv;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nv = m + 1, np = nv * (nv + 1) / 2;
+  for (int q = wv; q < np; q += 4) {
+    double v = 0;
+    for (int b = lane; b < nblocks; b += 64) v += part[(int64_t)b * np + q];
+    v = wave_sum(v);
+    if (lane == 0) {
+      pr[q] = v;
+      pairs[q] = v;
     }
   }
-  double x[AMAX];
-  for (int k = m - 1; k >= 0; --k) {
-    if (dead[k]) { x[k] = 0; continue; }
-    double s = A[k][m];
-    for (int j = k + 1; j < m; ++j) s -= A[k][j] * x[j];
-    x[k] = s / A[k][k];
+  __syncthreads();
+  auto pidx = [&](int a, int b) {  // index of pair (a <= b)
+    return a * nv - a * (a - 1) / 2 + (b - a);
+  };
+  for (int e = tid; e < m * (m + 1); e += 256) {
+    const int i = e / (m + 1), j = e % (m + 1);
+    A[i][j] = (j < m) ? pr[pidx(min(i, j), max(i, j))] : pr[pidx(i, m)];
   }
-  for (int i = 0; i < m; ++i) gamma[i] = x[i];
+  __syncthreads();
+  if (tid == 0) {
+    double d = 0;
+    for (int i = 0; i < m; ++i) d = fmax(d, A[i][i]);
+    dmax = d;
+  }
+  bool dead[AMAX];
+  for (int k = 0; k < m; ++k) {
+    if (tid == 0) {
+      int p = k;
+      for (int i = k + 1; i < m; ++i)
+        if (fabs(A[i][k]) > fabs(A[p][k])) p = i;
+      piv = p;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != k && tid <= m) {
+      const double t = A[k][tid];
+      A[k][tid] = A[p][tid];
+      A[p][tid] = t;
+    }
+    __syncthreads();
+    dead[k] = fabs(A[k][k]) <= 1e-14 * dmax;
+    if (dead[k]) continue;
+    if (tid > k && tid < m) f[tid] = A[tid][k] / A[k][k];
+    __syncthreads();
+    for (int e = tid; e < (m - k - 1) * (m + 1 - k); e += 256) {
+      const int i = k + 1 + e / (m + 1 - k), j = k + e % (m + 1 - k);
+      A[i][j] -= f[i] * A[k][j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double x[AMAX];
+    for (int k = m - 1; k >= 0; --k) {
+      if (dead[k]) {
+        x[k] = 0;
+        continue;
+      }
+      double s = A[k][m];
+      for (int j = k + 1; j < m; ++j) s -= A[k][j] * x[j];
+      x[k] = s / A[k][k];
+    }
+    for (int i = 0; i < m; ++i) gamma[i] = x[i];
+  }
 }
 struct GammaSet {
   const double* dx[AMAX];
@@ -371,6 +376,10 @@ struct Poisson {
   int last_iters = 0;  // iterations of the previous solve: the next one is checked from 3/4 of it
 
   double shift = 0.0;  // k^2 of the Helmholtz form (-Lap_h + k^2); 0: Poisson
+  // two-launch iterations (cg_iterate) on grids whose stencil step runs in point form:
+  // w = A r and s = A p, the scalar ring and its partial sums
+  bool fused = false;
+  double *w = nullptr, *sv = nullptr, *cs = nullptr, *cpart = nullptr;
 
   int apply(const double* x, double* y) {
     // -Lap_h x + shift x = 2 * (-1/2 Lap_h x) + shift x: stencil only
@@ -397,6 +406,7 @@ struct Poisson {
   // conjugate gradients on apply(v) = b from the current v; zero_mean: remove the mean
   // of v on exit (the Poisson form)
   int cg(hipStream_t s, double* v, double tol, int max_it, bool zero_mean) {
+    if (fused) return cg_fused(s, v, tol, max_it, zero_mean);
     SPARC_TRY(reduce(s, n, b, b, RED_DOT, part, sc + 4));
     SPARC_TRY(apply(v, r));
     residual_kernel<<<GRID1(n)>>>(n, b, r);
@@ -424,6 +434,10 @@ struct Poisson {
         if (rr <= tol * tol * bb) break;
       }
     }
+    return finish(s, v, it, max_it, zero_mean);
+  }
+
+  int finish(hipStream_t s, double* v, int it, int max_it, bool zero_mean) {
     iters_total += it + 1;
     last_iters = it + 1;
     if (it >= max_it) return fail(SPARC_ENOCONV, "poisson: CG did not converge in %d iterations", max_it);
@@ -431,6 +445,39 @@ struct Poisson {
     SPARC_TRY(reduce(s, n, v, nullptr, RED_SUM, part, sc + 3));
     sub_mean_kernel<<<GRID1(n)>>>(n, v, sc + 3);
     return check_launch("poisson");
+  }
+
+  // The same iteration in two launches per step (cg_iterate): r = b - A v, w = A r and
+  // their dot products start it; p and s start at zero.
+  int cg_fused(hipStream_t s, double* v, double tol, int max_it, bool zero_mean) {
+    CgIter C{r, w, sv, p, v, cs, cpart, cg_blocks(H), 0};
+    SPARC_TRY(reduce(s, n, b, b, RED_DOT, part, sc + 4));
+    SPARC_TRY(apply(v, r));
+    residual_kernel<<<GRID1(n)>>>(n, b, r);
+    SPARC_TRY(cg_apply(H, 2.0, shift, C));
+    SPARC_TRY(cg_residual_norm(H, C));
+    SPARC_HIP(hipMemsetAsync(p, 0, n * 8, s));
+    SPARC_HIP(hipMemsetAsync(sv, 0, n * 8, s));
+    double bb = 0, rr = 0;
+    SPARC_HIP(hipMemcpyAsync(&bb, sc + 4, 8, hipMemcpyDeviceToHost, s));
+    SPARC_HIP(hipMemcpyAsync(&rr, cs + 8, 8, hipMemcpyDeviceToHost, s));
+    SPARC_HIP(hipStreamSynchronize(s));
+    if (bb == 0.0) return SPARC_OK;
+    if (!std::isfinite(rr)) return fail(SPARC_ENAN, "poisson: non-finite residual");
+    if (rr <= tol * tol * bb) return finish(s, v, -1, max_it, zero_mean);
+    int it = 0;
+    for (; it < max_it; ++it) {
+      C.it = it;
+      SPARC_TRY(cg_iterate(H, 2.0, shift, C));
+      if (it % 8 == 7 && it >= (3 * last_iters) / 4 - 8) {
+        SPARC_TRY(cg_residual_norm(H, C));
+        SPARC_HIP(hipMemcpyAsync(&rr, cs + 8, 8, hipMemcpyDeviceToHost, s));
+        SPARC_HIP(hipStreamSynchronize(s));
+        if (!std::isfinite(rr)) return fail(SPARC_ENAN, "poisson: non-finite residual");
+        if (rr <= tol * tol * bb) break;
+      }
+    }
+    return finish(s, v, it, max_it, zero_mean);
   }
 };
 
@@ -616,6 +663,13 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
   }
 
   Poisson PS{H64, n, pb, pr, pp, pAp, part, sc};
+  if (cg_point_form(H64)) {
+    PS.fused = true;
+    SPARC_TRY(B.alloc(&PS.w, n));
+    SPARC_TRY(B.alloc(&PS.sv, n));
+    SPARC_TRY(B.alloc(&PS.cs, 12));
+    SPARC_TRY(B.alloc(&PS.cpart, 2 * kCgBlocks));
+  }
   const double ptol = P->poisson_tol > 0 ? P->poisson_tol : 1e-10;
   // phi (or V_H) of the current input density, warm-started from the previous one; the
   // CG tolerance follows the SCF: a thousandth of the last density residual, at most
@@ -736,8 +790,7 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
         vs.v[a_count] = fcur;
         const int npairs = (a_count + 1) * (a_count + 2) / 2;
         launch_multi_dot(s, ABLK, n, a_count, vs, apart);
-        multi_dot_final_kernel<<<1, 256, 0, s>>>(ABLK, npairs, apart, apairs);
-        anderson_solve_kernel<<<1, 64, 0, s>>>(a_count, apairs, agamma);
+        anderson_gamma_kernel<<<1, 256, 0, s>>>(ABLK, a_count, apart, apairs, agamma);
         anderson_update_kernel<<<GRID1(n)>>>(n, a_count, gs, agamma, fcur, P->mix, rho_in, kk2 > 0 ? kf : nullptr);
         if (kk2 > 0) SPARC_TRY(kerker_mix());
       }

@@ -76,6 +76,24 @@ def test_scf_matches_oracle(ctx, oracle_ref):
     np.testing.assert_allclose(ritz.cpu().numpy(), ref["ritz"], atol=1e-6)
 
 
+def test_scf_tiled_cg_path(ctx, oracle_ref, monkeypatch):
+    """The SCF with every stencil step forced into the tiled form: the Poisson solves then
+    take the four-launch conjugate-gradient loop instead of the two-launch one that the
+    point-form grids use.  Same fixed point: free energy within 1e-6 Ha/atom of the oracle
+    and within 1e-9 Ha/atom of the default run."""
+    cell, X0, v0, ref = oracle_ref
+    base, _, _ = _run(ctx, cell, _params(cell, X0, v0))
+    monkeypatch.setenv("SPARC_HSTEP_TILE", "1")
+    out, rho, ritz = _run(ctx, cell, _params(cell, X0, v0))
+    monkeypatch.delenv("SPARC_HSTEP_TILE")
+    print(f"tiled: {out['iterations']} it, F={out['energy']:.12f}; default {base['iterations']} it, "
+          f"F={base['energy']:.12f}")
+    assert out["converged"]
+    assert abs(out["energy"] - ref["energy"]) / cell.n_atoms < 1e-6
+    assert abs(out["energy"] - base["energy"]) / cell.n_atoms < 1e-9
+    np.testing.assert_allclose(ritz.cpu().numpy(), ref["ritz"], atol=1e-6)
+
+
 def test_scf_kerker_matches_oracle(ctx, oracle_ref):
     """Kerker-preconditioned Anderson mixing (k0 = 1 bohr^-1): the same fixed point as
     the plain mixing (free energy within 1e-6 Ha/atom of the unpreconditioned oracle),
