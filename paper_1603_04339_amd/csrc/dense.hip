@@ -40,9 +40,9 @@ __device__ __forceinline__ cd add_(cd a, cd b) { return a + b; }
 __device__ __forceinline__ double rscale(double s, double v) { return s * v; }
 __device__ __forceinline__ cd rscale(double s, cd v) { return {s * v.re, s * v.im}; }
 
-// block-wide sum of a double (blockDim multiple of 64, <= 1024)
+// block-wide sum of a double (blockDim multiple of 64, <= 1024), the same on every thread
 __device__ double block_sum(double v, double* sh) {
-  v = wave_sum(v);
+  v = wave_sum_dpp(v);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
   if (lane == 0) sh[w] = v;
@@ -365,6 +365,7 @@ __global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restri
   double g = 0.0;
   for (int j = tid; j < n; j += nt) {
     double c = 0.0;
+#pragma unroll 8
     for (int i = 0; i < n; ++i) {
       if constexpr (STAGE) {
         c += am[i + (int64_t)j * n];
@@ -392,6 +393,7 @@ __global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restri
     // y = B^H v, B = R^{-1} (upper triangular): y_j = sum_{i <= j} conj(T_ij / dinv_i) v_i
     for (int j = tid; j < n; j += nt) {
       T acc = mkT<T>(0.0, 0.0);
+#pragma unroll 8
       for (int i = 0; i <= j; ++i) acc = add_(acc, mul_(conj_(rscale(ri(i), Tm[i + (int64_t)j * n])), v[i]));
       y[j] = acc;
     }
@@ -400,6 +402,7 @@ __global__ __launch_bounds__(1024) void cond_est_kernel(int n, const T* __restri
     double nrm = 0.0;
     for (int i = tid; i < n; i += nt) {
       T acc = mkT<T>(0.0, 0.0);
+#pragma unroll 8
       for (int j = i; j < n; ++j) acc = add_(acc, mul_(Tm[i + (int64_t)j * n], y[j]));
       acc = rscale(ri(i), acc);
       v[i] = acc;
@@ -650,8 +653,8 @@ __global__ __launch_bounds__(1024) void hetrd2_kernel(int n, T* __restrict__ A, 
 // dimension n + 1), four waves: lane r of every wave owns row r, wave q the columns
 // c = q mod 4 of the matrix-vector product and of the rank-2 update.  Sums over rows are
 // wave butterflies, whose result is the same on every lane of every wave, so each wave
-// forms the same reflector without exchanging it.  The matrix is read once and written
-// back once.
+// forms the same reflector without exchanging it (register-only DPP sums).  The matrix
+// is read once and written back once.
 template <typename T>
 __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__ A, double* __restrict__ d,
                                                           double* __restrict__ e, T* __restrict__ tau) {
@@ -672,7 +675,7 @@ __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__
       const T x = a[r + i * ld];
       xn = re_(mul_(conj_(x), x));
     }
-    xn = wave_sum(xn);
+    xn = wave_sum_dpp(xn);
     const T alpha = a[r0 + i * ld];
     const double ar = re_(alpha);
     double ai = 0;
@@ -705,6 +708,7 @@ __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__
       T acc = mkT<T>(0.0, 0.0);
       if (r >= r0 && r < n) {
         int c = r0 + ((q - r0) & 3);
+#pragma unroll 4
         for (; c < n; c += 4) acc = add_(acc, mul_(a[r + c * ld], v[c]));
       }
       part[q * 64 + r] = acc;
@@ -712,8 +716,8 @@ __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__
       const T sum = add_(add_(part[r], part[64 + r]), add_(part[128 + r], part[192 + r]));
       const T pr = (r >= r0 && r < n) ? mul_(tau_i, sum) : mkT<T>(0.0, 0.0);
       const T t = mul_(conj_(pr), vr);
-      double sr = wave_sum(re_(t)), si = 0.0;
-      if constexpr (sizeof(T) == 16) si = wave_sum(((const cd&)t).im);
+      double sr = wave_sum_dpp(re_(t)), si = 0.0;
+      if constexpr (sizeof(T) == 16) si = wave_sum_dpp(((const cd&)t).im);
       const T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(sr, si)));
       const T wr = add_(pr, mul_(a2, vr));
       if (q == 0) w[r] = wr;
@@ -721,6 +725,7 @@ __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__
       // A_sub -= v w^H + w v^H over this wave's columns
       if (r >= r0 && r < n) {
         int c = r0 + ((q - r0) & 3);
+#pragma unroll 4
         for (; c < n; c += 4)
           a[r + c * ld] = sub_(a[r + c * ld], add_(mul_(vr, conj_(w[c])), mul_(wr, conj_(v[c]))));
       }
@@ -767,6 +772,7 @@ __global__ __launch_bounds__(1024) void latrd_kernel(int n, int i0, int jb, T* _
     if (j > 0) {
       for (int r = i + tid; r < n; r += nt) {
         T a = A[r + (int64_t)i * n];
+#pragma unroll 8
         for (int k = 0; k < j; ++k) {
           const int64_t o = (int64_t)k * n;
           a = sub_(a, add_(mul_(V[o + r], conj_(W[o + i])), mul_(W[o + r], conj_(V[o + i]))));
@@ -867,19 +873,21 @@ __global__ __launch_bounds__(1024) void latrd_kernel(int n, int i0, int jb, T* _
         const int k = task >> 1;
         const T* u = ((task & 1) ? V : W) + (int64_t)k * n;
         double pr = 0, pi = 0;
+#pragma unroll 4
         for (int r = r0 + lane; r < n; r += 64) {
           T t = mul_(conj_(u[r]), v[r]);
           pr += re_(t);
           if constexpr (sizeof(T) == 16) pi += ((cd&)t).im;
         }
-        pr = wave_sum(pr);
-        if constexpr (sizeof(T) == 16) pi = wave_sum(pi);
+        pr = wave_sum_dpp(pr);
+        if constexpr (sizeof(T) == 16) pi = wave_sum_dpp(pi);
         if (lane == 0) pq[task & 1][k] = mkT<T>(pr, pi);
       }
       __syncthreads();
       for (int r = r0 + tid; r < n; r += nt) {
         T acc = mkT<T>(0.0, 0.0);
         for (int q = 0; q < nwave; ++q) acc = add_(acc, part[q * n + r]);
+#pragma unroll 8
         for (int k = 0; k < j; ++k) {
           const int64_t o = (int64_t)k * n;
           acc = sub_(acc, add_(mul_(V[o + r], pq[0][k]), mul_(W[o + r], pq[1][k])));
