@@ -724,7 +724,8 @@ def main():
     # 2 + 4 passes: the six CheFSI iterations of the c2 workload (the first two from the
     # random start take the ill-conditioned, two-pass Cholesky-QR route)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "bands"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "bands", "scf"],
+                    help="scf: only the FP64 SCF leg of the default line (40^3 cell), run twice, the second timed")
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -775,6 +776,12 @@ def main():
     sp.load()
     if args.config in ("c1", "c2"):
         result = run_gamma(args, sp, wl, *gamma_in, cpu=cpu)
+    elif args.config == "scf":
+        ctx = sp.Context(0)
+        scf_leg(sp, ctx, "f64")   # first run: library set-up and kernel loading
+        result = {"config": {"workload": "40^3 SCF cell (held-out seed), FP64, atomic-superposition start"},
+                  "scf": {"f64": scf_leg(sp, ctx, "f64")}}
+        ctx.close()
     elif args.config == "bands":
         result = run_bands(args, sp, wl)
     else:
