@@ -1036,7 +1036,8 @@ __global__ __launch_bounds__(64) void inviter_kernel(int n, const double* __rest
   double* du = dd + n;
   double* du2 = du + n;
   double* b = du2 + n;
-  unsigned char* ip = (unsigned char*)(b + n);
+  double* rd = b + n;    // 1 / diagonal of U
+  unsigned char* ip = (unsigned char*)(rd + n);
   const int j0 = blockIdx.x;
   const int lane = threadIdx.x;
   const double tnorm = fmax(*tnorm_p, 1e-300);
@@ -1066,49 +1067,70 @@ __global__ __launch_bounds__(64) void inviter_kernel(int n, const double* __rest
     }
     __syncthreads();
     if (lane == 0) {
-      // LU with partial pivoting of T - lam I (general tridiagonal form)
+      // LU with partial pivoting of T - lam I (general tridiagonal form); the entries
+      // that step i updates for step i + 1 (the diagonal and super-diagonal element) are
+      // carried in registers, the rest read from LDS ahead of the chain
+      double dcur = dd[0], ucur = (n > 1) ? du[0] : 0.0;
+#pragma unroll 4
       for (int i = 0; i < n - 1; ++i) {
-        double di = dd[i], li = dl[i];
-        if (fabs(di) >= fabs(li)) {
+        const double li = dl[i], dnext = dd[i + 1], unext = (i < n - 2) ? du[i + 1] : 0.0;
+        if (fabs(dcur) >= fabs(li)) {
           ip[i] = 0;
-          if (di == 0.0) { di = eps * tnorm; dd[i] = di; }
-          double f = li / di;
+          if (dcur == 0.0) dcur = eps * tnorm;
+          dd[i] = dcur;
+          const double f = li / dcur;
           dl[i] = f;
-          dd[i + 1] = dd[i + 1] - f * du[i];
+          du[i] = ucur;
           if (i < n - 2) du2[i] = 0.0;
+          dcur = dnext - f * ucur;
+          ucur = unext;
         } else {
           ip[i] = 1;
-          double f = di / li;
+          const double f = dcur / li;
           dd[i] = li;
           dl[i] = f;
-          double t = du[i];
-          du[i] = dd[i + 1];
-          dd[i + 1] = t - f * dd[i + 1];
-          if (i < n - 2) {
-            du2[i] = du[i + 1];
-            du[i + 1] = -f * du[i + 1];
-          }
+          du[i] = dnext;
+          dcur = ucur - f * dnext;
+          if (i < n - 2) du2[i] = unext;
+          ucur = -f * unext;
         }
       }
-      if (dd[n - 1] == 0.0) dd[n - 1] = eps * tnorm;
+      if (dcur == 0.0) dcur = eps * tnorm;
+      dd[n - 1] = dcur;
     }
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) rd[i] = 1.0 / dd[i];
     __syncthreads();
     for (int it = 0; it < 4; ++it) {
       if (lane == 0) {
-        // forward: row interchanges and multipliers
+        // forward: row interchanges and multipliers (the running element in a register;
+        // both cases formed and one selected, so the loop has no branch)
+        double bc = b[0];
+#pragma unroll 4
         for (int i = 0; i < n - 1; ++i) {
-          if (ip[i] == 0) {
-            b[i + 1] = b[i + 1] - dl[i] * b[i];
-          } else {
-            double t = b[i];
-            b[i] = b[i + 1];
-            b[i + 1] = t - dl[i] * b[i];
-          }
+          const double bn = b[i + 1], l = dl[i];
+          const bool sw = ip[i] != 0;
+          const double keep = bn - l * bc, swap = bc - l * bn;
+          b[i] = sw ? bn : bc;
+          bc = sw ? swap : keep;
         }
-        // back substitution with U (diagonal dd, super du, super-2 du2)
-        b[n - 1] = b[n - 1] / dd[n - 1];
-        if (n > 1) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / dd[n - 2];
-        for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+        b[n - 1] = bc;
+        // back substitution with U (reciprocal diagonal rd, super du, super-2 du2), the
+        // last two solved elements in registers
+        double x1 = b[n - 1] * rd[n - 1], x2 = 0.0;
+        b[n - 1] = x1;
+        if (n > 1) {
+          x2 = x1;
+          x1 = (b[n - 2] - du[n - 2] * x2) * rd[n - 2];
+          b[n - 2] = x1;
+        }
+#pragma unroll 4
+        for (int i = n - 3; i >= 0; --i) {
+          const double xi = (b[i] - du[i] * x1 - du2[i] * x2) * rd[i];
+          b[i] = xi;
+          x2 = x1;
+          x1 = xi;
+        }
       }
       __syncthreads();
       // orthogonalise against the earlier vectors of the cluster (twice)
@@ -1129,6 +1151,65 @@ __global__ __launch_bounds__(64) void inviter_kernel(int n, const double* __rest
 }
 
 // ------------------------------------------------------------ back-transformation Z = Q Y
+// The same product with the column held in registers (row r = lane + 64 k in z[k], RPL
+// rows per lane) and the next reflector and tau loaded while the current one is applied;
+// the wave sums are register-only (DPP).
+template <typename T, int RPL>
+__global__ __launch_bounds__(256) void ormtr_reg_kernel(int n, const T* __restrict__ A, const T* __restrict__ tau,
+                                                        const double* __restrict__ Y, T* __restrict__ Z) {
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n) return;   // whole waves
+  T z[RPL], vn[RPL];
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) {
+    const int r = lane + 64 * k;
+    z[k] = mkT<T>(r < n ? Y[r + (int64_t)c * n] : 0.0, 0.0);
+  }
+  auto load_v = [&](int i, T (&vv)[RPL]) {
+    const T* __restrict__ v = A + (int64_t)i * n;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      const int r = lane + 64 * k;
+      vv[k] = (r == i + 1) ? mkT<T>(1.0, 0.0) : ((r > i + 1 && r < n) ? v[r] : mkT<T>(0.0, 0.0));
+    }
+  };
+  if (n < 2) {
+    if (lane < n) Z[lane + (int64_t)c * n] = z[0];
+    return;
+  }
+  load_v(n - 2, vn);
+  T tn = tau[n - 2];
+  for (int i = n - 2; i >= 0; --i) {
+    T vc[RPL];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) vc[k] = vn[k];
+    const T ti = tn;
+    if (i > 0) {
+      load_v(i - 1, vn);
+      tn = tau[i - 1];
+    }
+    double sr = 0, si = 0;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      const T p = mul_(conj_(vc[k]), z[k]);
+      sr += re_(p);
+      if constexpr (sizeof(T) == 16) si += ((const cd&)p).im;
+    }
+    sr = wave_sum_dpp(sr);
+    if constexpr (sizeof(T) == 16) si = wave_sum_dpp(si);
+    const T sc = mul_(ti, mkT<T>(sr, si));
+#pragma unroll
+    for (int k = 0; k < RPL; ++k)
+      if (lane + 64 * k > i) z[k] = sub_(z[k], mul_(vc[k], sc));
+  }
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) {
+    const int r = lane + 64 * k;
+    if (r < n) Z[r + (int64_t)c * n] = z[k];
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void ormtr_kernel(int n, const T* __restrict__ A, const T* __restrict__ tau,
                                                     const double* __restrict__ Y, T* __restrict__ Z) {
@@ -1218,11 +1299,18 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
   SPARC_HIP(hipFuncSetAttribute((const void*)bisect_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * n * 8));
   bisect_kernel<<<(n + 3) / 4, 256, 2 * n * 8, s>>>(n, d, e, w, tn);
   SPARC_TRY(check_launch("bisect_kernel"));
-  const size_t lds_inv = (size_t)n * (5 * 8 + 1);
+  const size_t lds_inv = (size_t)n * (6 * 8 + 1);
   SPARC_HIP(hipFuncSetAttribute((const void*)inviter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_inv));
   inviter_kernel<<<n, 64, lds_inv, s>>>(n, d, e, w, tn, Y);
   SPARC_TRY(check_launch("inviter_kernel"));
-  ormtr_kernel<T><<<(n + 3) / 4, 256, 0, s>>>(n, A, tau, Y, Z);
+  const unsigned gb = (unsigned)((n + 3) / 4);
+  const int rpl = (n + 63) / 64;
+  if (rpl <= 1) ormtr_reg_kernel<T, 1><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
+  else if (rpl <= 2) ormtr_reg_kernel<T, 2><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
+  else if (rpl <= 4) ormtr_reg_kernel<T, 4><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
+  else if (rpl <= 8) ormtr_reg_kernel<T, 8><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
+  else if (rpl <= 16 && sizeof(T) == 8) ormtr_reg_kernel<T, 16><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
+  else ormtr_kernel<T><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
   return check_launch("ormtr_kernel");
 }
 
