@@ -766,33 +766,66 @@ __global__ __launch_bounds__(1024) void latrd_kernel(int n, int i0, int jb, T* _
   __shared__ double s_beta;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, nwave = nt >> 6;
+  __shared__ T s_alpha;
+  // one row per thread (n <= blockDim.x): thread r keeps its element of column i in a
+  // register through the update, the reflector and the scaling, and its element of y
+  // through the correction and the dot product
+  const bool one = n <= nt;
   for (int j = 0; j < jb; ++j) {
     const int i = i0 + j, r0 = i + 1;
-    // (1) column i up to date with the panel's earlier reflectors
-    if (j > 0) {
-      for (int r = i + tid; r < n; r += nt) {
-        T a = A[r + (int64_t)i * n];
-#pragma unroll 8
-        for (int k = 0; k < j; ++k) {
-          const int64_t o = (int64_t)k * n;
-          a = sub_(a, add_(mul_(V[o + r], conj_(W[o + i])), mul_(W[o + r], conj_(V[o + i]))));
-        }
-        A[r + (int64_t)i * n] = a;
-      }
-      __syncthreads();
-    }
-    // (2) reflector of A(i+2:n, i) (as hetrd2_kernel)
+    T* Vj = V + (int64_t)j * n;
+    T* Wj = W + (int64_t)j * n;
+    T areg = mkT<T>(0.0, 0.0);
     double xn = 0;
-    for (int r = i + 2 + tid; r < n; r += nt) {
-      T x = A[r + (int64_t)i * n];
-      xn += re_(mul_(conj_(x), x));
+    if (one) {
+      // (1) column i up to date with the panel's earlier reflectors, (2) its norm below
+      // the sub-diagonal; alpha from the thread of row i + 1, d[i] from that of row i
+      const int r = tid;
+      if (r >= i && r < n) {
+        areg = A[r + (int64_t)i * n];
+        if (j > 0) {
+#pragma unroll 8
+          for (int k = 0; k < j; ++k) {
+            const int64_t o = (int64_t)k * n;
+            areg = sub_(areg, add_(mul_(V[o + r], conj_(W[o + i])), mul_(W[o + r], conj_(V[o + i]))));
+          }
+          if (r <= r0) A[r + (int64_t)i * n] = areg;
+        }
+        if (r == r0) s_alpha = areg;
+        if (r == i) d[i] = re_(areg);
+        if (r >= i + 2) xn = re_(mul_(conj_(areg), areg));
+      }
+      xn = block_sum(xn, red);
+    } else {
+      // (1) column i up to date with the panel's earlier reflectors
+      if (j > 0) {
+        for (int r = i + tid; r < n; r += nt) {
+          T a = A[r + (int64_t)i * n];
+#pragma unroll 8
+          for (int k = 0; k < j; ++k) {
+            const int64_t o = (int64_t)k * n;
+            a = sub_(a, add_(mul_(V[o + r], conj_(W[o + i])), mul_(W[o + r], conj_(V[o + i]))));
+          }
+          A[r + (int64_t)i * n] = a;
+        }
+        __syncthreads();
+      }
+      // (2) reflector of A(i+2:n, i) (as hetrd2_kernel)
+      for (int r = i + 2 + tid; r < n; r += nt) {
+        T x = A[r + (int64_t)i * n];
+        xn += re_(mul_(conj_(x), x));
+      }
+      xn = block_sum(xn, red);
+      if (tid == 0) {
+        s_alpha = A[i + 1 + (int64_t)i * n];
+        d[i] = re_(A[i + (int64_t)i * n]);
+      }
     }
-    xn = block_sum(xn, red);
     if (tid == 0) {
-      T alpha = A[i + 1 + (int64_t)i * n];
+      const T alpha = s_alpha;
       double ar = re_(alpha);
       double ai = 0;
-      if constexpr (sizeof(T) == 16) ai = ((cd&)alpha).im;
+      if constexpr (sizeof(T) == 16) ai = ((const cd&)alpha).im;
       if (xn == 0.0 && ai == 0.0) {
         s_tau = mkT<T>(0.0, 0.0);
         s_beta = ar;
@@ -804,24 +837,36 @@ __global__ __launch_bounds__(1024) void latrd_kernel(int n, int i0, int jb, T* _
         double dr = ar - beta, di = ai, den = dr * dr + di * di;
         s_scale = mkT<T>(dr / den, -di / den);
       }
-      d[i] = re_(A[i + (int64_t)i * n]);
     }
     __syncthreads();
     const T tau_i = s_tau;
     const double beta = s_beta;
     const bool trivial = re_(mul_(conj_(tau_i), tau_i)) == 0.0;
-    T* Vj = V + (int64_t)j * n;
-    T* Wj = W + (int64_t)j * n;
-    for (int r = tid; r < n; r += nt) {
-      T val = mkT<T>(0.0, 0.0);
-      if (r == r0) {
-        val = mkT<T>(1.0, 0.0);
-      } else if (r > r0) {
-        val = mul_(A[r + (int64_t)i * n], s_scale);
-        A[r + (int64_t)i * n] = val;
+    if (one) {
+      const int r = tid;
+      if (r < n) {
+        T val = mkT<T>(0.0, 0.0);
+        if (r == r0) {
+          val = mkT<T>(1.0, 0.0);
+        } else if (r > r0) {
+          val = mul_(areg, s_scale);
+          A[r + (int64_t)i * n] = val;
+        }
+        if (r >= r0) v[r] = val;
+        Vj[r] = val;
       }
-      if (r >= r0) v[r] = val;
-      Vj[r] = val;
+    } else {
+      for (int r = tid; r < n; r += nt) {
+        T val = mkT<T>(0.0, 0.0);
+        if (r == r0) {
+          val = mkT<T>(1.0, 0.0);
+        } else if (r > r0) {
+          val = mul_(A[r + (int64_t)i * n], s_scale);
+          A[r + (int64_t)i * n] = val;
+        }
+        if (r >= r0) v[r] = val;
+        Vj[r] = val;
+      }
     }
     __syncthreads();
     if (!trivial) {
@@ -884,27 +929,49 @@ __global__ __launch_bounds__(1024) void latrd_kernel(int n, int i0, int jb, T* _
         if (lane == 0) pq[task & 1][k] = mkT<T>(pr, pi);
       }
       __syncthreads();
-      for (int r = r0 + tid; r < n; r += nt) {
-        T acc = mkT<T>(0.0, 0.0);
-        for (int q = 0; q < nwave; ++q) acc = add_(acc, part[q * n + r]);
+      if (one) {
+        // y = tau (A_old v - V (W^H v) - W (V^H v)) for this thread's row, kept in a register
+        const int r = tid;
+        T yr = mkT<T>(0.0, 0.0), vr = mkT<T>(0.0, 0.0);
+        if (r >= r0 && r < n) {
+          T acc = mkT<T>(0.0, 0.0);
+          for (int q = 0; q < nwave; ++q) acc = add_(acc, part[q * n + r]);
 #pragma unroll 8
-        for (int k = 0; k < j; ++k) {
-          const int64_t o = (int64_t)k * n;
-          acc = sub_(acc, add_(mul_(V[o + r], pq[0][k]), mul_(W[o + r], pq[1][k])));
+          for (int k = 0; k < j; ++k) {
+            const int64_t o = (int64_t)k * n;
+            acc = sub_(acc, add_(mul_(V[o + r], pq[0][k]), mul_(W[o + r], pq[1][k])));
+          }
+          yr = mul_(tau_i, acc);
+          vr = v[r];
         }
-        y[r] = mul_(tau_i, acc);
+        const T t = mul_(conj_(yr), vr);
+        double pr = block_sum(re_(t), red), pi = 0.0;
+        if constexpr (sizeof(T) == 16) pi = block_sum(((const cd&)t).im, red);
+        const T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(pr, pi)));
+        if (r < n) Wj[r] = (r >= r0) ? add_(yr, mul_(a2, vr)) : mkT<T>(0.0, 0.0);
+      } else {
+        for (int r = r0 + tid; r < n; r += nt) {
+          T acc = mkT<T>(0.0, 0.0);
+          for (int q = 0; q < nwave; ++q) acc = add_(acc, part[q * n + r]);
+#pragma unroll 8
+          for (int k = 0; k < j; ++k) {
+            const int64_t o = (int64_t)k * n;
+            acc = sub_(acc, add_(mul_(V[o + r], pq[0][k]), mul_(W[o + r], pq[1][k])));
+          }
+          y[r] = mul_(tau_i, acc);
+        }
+        __syncthreads();
+        double pr = 0, pi = 0;
+        for (int r = r0 + tid; r < n; r += nt) {
+          T t = mul_(conj_(y[r]), v[r]);
+          pr += re_(t);
+          if constexpr (sizeof(T) == 16) pi += ((cd&)t).im;
+        }
+        pr = block_sum(pr, red);
+        if constexpr (sizeof(T) == 16) pi = block_sum(pi, red);
+        const T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(pr, pi)));
+        for (int r = tid; r < n; r += nt) Wj[r] = (r >= r0) ? add_(y[r], mul_(a2, v[r])) : mkT<T>(0.0, 0.0);
       }
-      __syncthreads();
-      double pr = 0, pi = 0;
-      for (int r = r0 + tid; r < n; r += nt) {
-        T t = mul_(conj_(y[r]), v[r]);
-        pr += re_(t);
-        if constexpr (sizeof(T) == 16) pi += ((cd&)t).im;
-      }
-      pr = block_sum(pr, red);
-      if constexpr (sizeof(T) == 16) pi = block_sum(pi, red);
-      const T a2 = mul_(mkT<T>(-0.5, 0.0), mul_(tau_i, mkT<T>(pr, pi)));
-      for (int r = tid; r < n; r += nt) Wj[r] = (r >= r0) ? add_(y[r], mul_(a2, v[r])) : mkT<T>(0.0, 0.0);
     } else {
       for (int r = tid; r < n; r += nt) Wj[r] = mkT<T>(0.0, 0.0);
     }
