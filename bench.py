@@ -40,7 +40,9 @@ RR_MODES = {"native": 0, "bf16x3": 1, "bf16x6": 2}
 # WRITE_SIZE runs scaled by a plain-copy calibration (profiles/hstep_c2_96cubed_f64.md);
 # valid only for the kernel source it was measured on (checked by hash, else null)
 HSTEP_TRAFFIC = {"bytes_per_launch": 1.801021e+10, "kernel_sources_sha256": "699531794552c49dd525f3f825aa7764dc6e6f8f7c1c1367a7791afeaebf2dd1",
-                 "profile": "profiles/hstep_c2_96cubed_f64.md"}
+                 "profile": "profiles/hstep_c2_96cubed_f64.md",
+                 # the FP32 step of the mixed form on the same block, from the same runs
+                 "bytes_per_launch_f32": 8.2072e+09}
 UNIT = "grid-pt·states/s"
 HBM_PEAK_GBS = 8000.0
 
@@ -157,15 +159,17 @@ def roofline_obj(kernel, total_bytes, ms, n, traffic=None):
             "bytes_per_launch": total_bytes / n}
 
 
-def measured_traffic():
-    """Counter-measured bytes per c2 FP64 stencil launch, if the kernel sources are
-    the ones the counters were taken on."""
+def measured_traffic(f32=False):
+    """Counter-measured bytes per c2 stencil launch (FP64, or FP32 with f32), if the
+    kernel sources are the ones the counters were taken on."""
     import hashlib
     h = hashlib.sha256()
     for f in ("hstep_api.hpp", "hstep_impl.hpp"):
         with open(os.path.join(ROOT, "paper_1603_04339_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return HSTEP_TRAFFIC["bytes_per_launch"] if h.hexdigest() == HSTEP_TRAFFIC["kernel_sources_sha256"] else None
+    if h.hexdigest() != HSTEP_TRAFFIC["kernel_sources_sha256"]:
+        return None
+    return HSTEP_TRAFFIC["bytes_per_launch_f32" if f32 else "bytes_per_launch"]
 
 
 # ---------------------------------------------------------------------------------------------
@@ -236,8 +240,9 @@ def gamma_leg(sp, ctx, cell, X0, v0, precision, steps, warmup, label, rr_mode=0)
         "value": nd * ns / (t_total / steps), "ms_per_step": 1e3 * t_total / steps,
         "filter_ms": filt, "filter_throughput": nd * ns / (filt * 1e-3),
         "roofline": roofline_obj("hstep (12th-order stencil + V_eff + recurrence, LDS-tiled)", total, hs_ms, hs_n,
-                                 measured_traffic() if (dt == sp.R64 and tuple(cell.n) == (96, 96, 96)
-                                                        and cell.n_s == 512) else None),
+                                 measured_traffic(dt == sp.R32) if (dt in (sp.R64, sp.R32)
+                                                                    and tuple(cell.n) == (96, 96, 96)
+                                                                    and cell.n_s == 512) else None),
         "ritz": ritz.cpu().numpy(), "bounds": (lmin, lmax), "n_proj": ham.n_proj, "forces": forces,
         "pseudocharge": psd, "gram_ms_per_step": gm_ms / steps,
         "step_breakdown_ms": {"stencil": hs_ms / steps, "projector_gather": ga_ms / steps,
