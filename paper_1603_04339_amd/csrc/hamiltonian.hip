@@ -543,18 +543,27 @@ static int autotune(sparc_ham* H, StepArgs<E>& A, int32_t n_s, int* best, double
   return SPARC_OK;
 }
 
-template <typename E>
-static int nl_scatter_t(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out,
-                        int64_t ldo) {
+template <typename E, int NB>
+static void nl_scatter_launch(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out,
+                              int64_t ldo) {
   typedef typename elem<E>::real R;
-  if (H->n_proj == 0 || H->n_nlpts == 0) return SPARC_OK;
-  constexpr int NB = 16;
-  if ((H->n_nlpts + 255) / 256 > 65535) return fail(SPARC_ESHAPE, "nl_scatter: too many projector nodes");
   dim3 grid((unsigned)((n_s + NB - 1) / NB), (unsigned)((H->n_nlpts + 255) / 256));
-  int t = timer_begin(H->ctx, "nl_scatter");
   nl_scatter_kernel<E, NB><<<grid, 256, 0, H->ctx->stream>>>(
       (int)H->n_nlpts, H->nl_pts, H->nl_ptr, H->ent_proj, (const E*)H->ent_coef, (const E*)alpha, alpha_ld(n_s), n_s,
       (R)a, a_dev, (E*)out, ldo);
+}
+
+// 16 orbitals per thread, or 4 when that would leave fewer than four work-groups per CU
+// (small cells: shorter per-thread chains of loads)
+template <typename E>
+static int nl_scatter_t(sparc_ham* H, const void* alpha, int32_t n_s, double a, const double* a_dev, void* out,
+                        int64_t ldo) {
+  if (H->n_proj == 0 || H->n_nlpts == 0) return SPARC_OK;
+  if ((H->n_nlpts + 255) / 256 > 65535) return fail(SPARC_ESHAPE, "nl_scatter: too many projector nodes");
+  const int64_t wide = (int64_t)((n_s + 15) / 16) * ((H->n_nlpts + 255) / 256);
+  int t = timer_begin(H->ctx, "nl_scatter");
+  if (wide < 4 * (int64_t)H->ctx->n_cu) nl_scatter_launch<E, 4>(H, alpha, n_s, a, a_dev, out, ldo);
+  else nl_scatter_launch<E, 16>(H, alpha, n_s, a, a_dev, out, ldo);
   timer_end(H->ctx, t);
   return check_launch("nl_scatter_kernel");
 }
