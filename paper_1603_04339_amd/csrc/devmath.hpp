@@ -116,53 +116,6 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// K sums over a grid of 256-thread blocks in one launch: every block stores its K partial
-// sums (part[k * cap + block], gridDim.x <= cap); the last block to take a ticket (the
-// word after the K * cap partials, device-scope release/acquire, zero between launches)
-// adds the partials in block order, writes out[0 .. K-1] and resets the ticket.  The
-// partials are read with device-scope loads, past any stale L1 line.
-template <int K>
-__device__ void finish_sums(double (&s)[K], double* part, int cap, double* __restrict__ out) {
-  __shared__ double red[K][4];
-  __shared__ int last;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double v = wave_sum(s[k]);
-    if (lane == 0) red[k][wv] = v;
-  }
-  __syncthreads();
-  unsigned* ticket = (unsigned*)(part + (size_t)K * cap);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      __hip_atomic_store(&part[(size_t)k * cap + blockIdx.x], red[k][0] + red[k][1] + red[k][2] + red[k][3],
-                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    last = (t == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!last) return;
-  double t2[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    t2[k] = 0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
-      t2[k] += __hip_atomic_load(&part[(size_t)k * cap + i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    t2[k] = wave_sum(t2[k]);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    if (lane == 0) red[k][wv] = t2[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
-    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
 // DPP move of a double across lanes (CTRL: a DPP_* control word; all lanes active)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -187,6 +140,53 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   v += dpp_f64<0x124>(v);
   v += dpp_f64<0x128>(v);
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// K sums over a grid of 256-thread blocks in one launch: every block stores its K partial
+// sums (part[k * cap + block], gridDim.x <= cap); the last block to take a ticket (the
+// word after the K * cap partials, device-scope release/acquire, zero between launches)
+// adds the partials in block order, writes out[0 .. K-1] and resets the ticket.  The
+// partials are read with device-scope loads, past any stale L1 line.
+template <int K>
+__device__ void finish_sums(double (&s)[K], double* part, int cap, double* __restrict__ out) {
+  __shared__ double red[K][4];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double v = wave_sum_dpp(s[k]);
+    if (lane == 0) red[k][wv] = v;
+  }
+  __syncthreads();
+  unsigned* ticket = (unsigned*)(part + (size_t)K * cap);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      __hip_atomic_store(&part[(size_t)k * cap + blockIdx.x], red[k][0] + red[k][1] + red[k][2] + red[k][3],
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = (t == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return;
+  double t2[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    t2[k] = 0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+      t2[k] += __hip_atomic_load(&part[(size_t)k * cap + i], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    t2[k] = wave_sum_dpp(t2[k]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (lane == 0) red[k][wv] = t2[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+    __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 __device__ __forceinline__ int floordiv_i(int a, int b) {

@@ -664,8 +664,8 @@ __device__ __forceinline__ void cg_sums(const CgIter& C, double& g, double& d) {
     a += C.part[i];
     b += C.part[kCgBlocks + i];
   }
-  a = wave_sum(a);
-  b = wave_sum(b);
+  a = wave_sum_dpp(a);
+  b = wave_sum_dpp(b);
   if ((threadIdx.x & 63) == 0) {
     red[0][threadIdx.x >> 6] = a;
     red[1][threadIdx.x >> 6] = b;
@@ -732,8 +732,8 @@ __global__ __launch_bounds__(256) void cg_apply_kernel(StepArgs<double> A, CgIte
     b = fma(w0, r0, b);
   }
   __shared__ double red[2][4];
-  a = wave_sum(a);
-  b = wave_sum(b);
+  a = wave_sum_dpp(a);
+  b = wave_sum_dpp(b);
   if ((threadIdx.x & 63) == 0) {
     red[0][threadIdx.x >> 6] = a;
     red[1][threadIdx.x >> 6] = b;

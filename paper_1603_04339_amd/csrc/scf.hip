@@ -232,7 +232,7 @@ static void launch_multi_dot(hipStream_t s, int nblk, int64_t n, int m, const Ve
 // gamma from (dF^T dF) gamma = dF^T f by Gaussian elimination with partial pivoting; a
 // pivot below 1e-14 of the largest diagonal drops that direction (gamma_k = 0).  One
 // work-group of 256 threads: the pair sums over the multi-dot blocks (one wave per pair,
-// lanes over blocks), then the elimination in LDS (a row operation per thread).
+// lanes over blocks), then the elimination in LDS (one matrix element per thread).
 __global__ __launch_bounds__(256) void anderson_gamma_kernel(int nblocks, int m, const double* __restrict__ part,
                                                              double* __restrict__ pairs, double* __restrict__ gamma) {
   __shared__ double pr[(AMAX + 1) * (AMAX + 2) / 2];
@@ -788,7 +788,6 @@ extern "C" int sparc_scf_run(sparc_ctx* ctx, const sparc_grid* grid, const sparc
           gs.df[k] = dFh[k];
         }
         vs.v[a_count] = fcur;
-        const int npairs = (a_count + 1) * (a_count + 2) / 2;
         launch_multi_dot(s, ABLK, n, a_count, vs, apart);
         anderson_gamma_kernel<<<1, 256, 0, s>>>(ABLK, a_count, apart, apairs, agamma);
         anderson_update_kernel<<<GRID1(n)>>>(n, a_count, gs, agamma, fcur, P->mix, rho_in, kk2 > 0 ? kf : nullptr);
