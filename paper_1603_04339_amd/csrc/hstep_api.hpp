@@ -56,7 +56,7 @@ inline size_t nl_lds_bytes(const StepArgs<E>& A, int threads) {
 // the least idle work (tiles that divide n1, n2) weighted by its halo overhead;
 // SPARC_HSTEP_TILE (an index into this list) overrides it.
 struct TileShape { int tx, ty; };
-static const TileShape kTiles[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}, {48, 8}, {32, 32}};
+static const TileShape kTiles[] = {{32, 8}, {32, 16}, {64, 8}, {16, 16}, {48, 8}, {32, 32}, {40, 8}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 // z chunks of one orbital's column tile: enough work-groups to fill the chip, at least

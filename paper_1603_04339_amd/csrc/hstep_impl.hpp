@@ -432,7 +432,8 @@ static int launch_batched_t(sparc_ctx* ctx, const void* dprobs, const int* dwg, 
     case 2: return CALL(64, 8);           \
     case 3: return CALL(16, 16);          \
     case 4: return CALL(48, 8);           \
-    default: return CALL(32, 32);         \
+    case 5: return CALL(32, 32);          \
+    default: return CALL(40, 8);          \
   }
 
 template <typename E, int NO>

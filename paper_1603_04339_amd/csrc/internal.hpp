@@ -85,7 +85,7 @@ constexpr int kForceChunks = 8;
 // (column tile, z plane).  Limits of the fused form; beyond them a cell uses the
 // separate scatter kernel.
 constexpr int kNlMaxSlots = 64;       // atoms whose support meets one column tile
-constexpr int kNlTileShapes = 6;      // the stencil tile shapes (kTiles)
+constexpr int kNlTileShapes = 7;      // the stencil tile shapes (kTiles)
 constexpr size_t kNlMaxLds = 65536;   // LDS bytes of one fused work-group (planes + rows)
 
 // per stencil tile shape: the atoms ("slots") whose projector support meets each

@@ -21,7 +21,7 @@ from paper_1603_04339_amd import workloads as wl
 from tests.helpers import oracle_setup, colnorm_err, to_dev, block_to_oracle
 
 pytestmark = pytest.mark.gpu
-N_TILE_SHAPES = 6
+N_TILE_SHAPES = 7
 
 
 @pytest.fixture(scope="module")

@@ -119,7 +119,7 @@ def test_zone_boundary_bloch_fp32(ctx):
     assert colnorm_err(block_to_oracle(Y).astype(np.complex128), ref) < 2e-5
 
 
-N_TILE_SHAPES = 6   # stencil tile shapes the library can launch (indices 0..5)
+N_TILE_SHAPES = 7   # stencil tile shapes the library can launch (indices 0..6)
 
 
 @pytest.fixture
