@@ -9,7 +9,8 @@ GPU reduction runs under test:
 * N_s 128 in complex128 at a Bloch k: the complex blocked tridiagonalisation
   (n >= 64) and the complex multi-tile contractions;
 * N_s 256 in FP32 with native FP32 contractions and with split-BF16 x3 products
-  (pre-split rotations, n_s a multiple of 16).
+  (pre-split rotations, n_s a multiple of 16);
+* N_s 63 (real and complex128) and 2: the LDS tridiagonal reduction of n < 64.
 
 Blocks are filtered by the oracle and handed to both sides: either the steady state
 of CheFSI (condition number ~1e2-1e3) or a random block after one strong filter pass
@@ -91,6 +92,19 @@ def test_rr_fp64_large(ctx, ns, n, hard):
     L = tuple(0.5 * m for m in n)
     cell, grid, V, P, Xf = _filtered(n, L, 4, ns, False, (0.0, 0.0, 0.0), ns, hard)
     _check_fp64(ctx, cell, grid, V, P, Xf, (0.0, 0.0, 0.0), sp.R64)
+
+
+@pytest.mark.parametrize("ns,cplx", [(63, False), (63, True), (2, False)], ids=["ns63", "ns63-c128", "ns2"])
+def test_rr_small_tridiagonalisation(ctx, ns, cplx):
+    """N_s below 64: the tridiagonal reduction with the matrix in LDS (four waves, the
+    columns dealt out mod 4, including a last partial round), the back-transformation
+    with the column in registers, at the largest size of that path (63, real and
+    complex at a Bloch k) and at the smallest with a reflector (2)."""
+    k = (0.2, -0.15, 0.3) if cplx else (0.0, 0.0, 0.0)
+    n = (12, 12, 12)
+    print(f"\n[rr small] n={n} n_s={ns} complex={cplx}", flush=True)
+    cell, grid, V, P, Xf = _filtered(n, (6.0, 6.0, 6.0), 3, ns, cplx, k, 11 + ns, hard=(ns > 8))
+    _check_fp64(ctx, cell, grid, V, P, Xf, k, sp.C128 if cplx else sp.R64)
 
 
 def test_rr_complex128_ns128(ctx):
