@@ -1376,7 +1376,6 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
   else if (rpl <= 2) ormtr_reg_kernel<T, 2><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
   else if (rpl <= 4) ormtr_reg_kernel<T, 4><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
   else if (rpl <= 8) ormtr_reg_kernel<T, 8><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
-  else if (rpl <= 16 && sizeof(T) == 8) ormtr_reg_kernel<T, 16><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
   else ormtr_kernel<T><<<gb, 256, 0, s>>>(n, A, tau, Y, Z);
   return check_launch("ormtr_kernel");
 }
