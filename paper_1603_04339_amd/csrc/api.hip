@@ -334,6 +334,31 @@ int filter_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n_s, int32_t degree,
 // Out = A Q for the N_d-long rotations of Rayleigh-Ritz: split-BF16 (x3) products from
 // pieces made in W2 (free at every rotation) when the mode asks for them and n is a
 // multiple of 16, else the element type's MFMA
+// dst(:, c) = src(:, c) for n columns of `bytes` bytes each: one 16-byte element per
+// thread, all accesses non-temporal (the block is streamed once); falls back to a 2-D
+// runtime copy when the columns or leading dimensions are not 16-byte multiples
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void copy_cols_kernel(const v2d_t* __restrict__ src, int64_t lds,
+                                                        v2d_t* __restrict__ dst, int64_t ldd, int64_t rows) {
+  const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  if (i < rows) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[c * lds + i]), &dst[c * ldd + i]);
+}
+
+static int copy_cols(hipStream_t s, void* dst, int64_t ld_dst, const void* src, int64_t ld_src, int64_t bytes,
+                     int32_t n) {
+  const bool vec = bytes % 16 == 0 && ld_dst % 16 == 0 && ld_src % 16 == 0 && (uintptr_t)dst % 16 == 0 &&
+                   (uintptr_t)src % 16 == 0 && n <= 65535 && (bytes / 16 + 255) / 256 <= (int64_t)UINT32_MAX;
+  if (!vec) {
+    SPARC_HIP(hipMemcpy2DAsync(dst, ld_dst, src, ld_src, bytes, n, hipMemcpyDeviceToDevice, s));
+    return SPARC_OK;
+  }
+  const int64_t rows = bytes / 16;
+  copy_cols_kernel<<<dim3((unsigned)((rows + 255) / 256), (unsigned)n), 256, 0, s>>>(
+      (const v2d_t*)src, ld_src / 16, (v2d_t*)dst, ld_dst / 16, rows);
+  return check_launch("copy_cols_kernel");
+}
+
 static int rr_rotate(sparc_ham* H, sparc_gemm_mode mode, int32_t n, const void* A, int64_t lda, const void* Q,
                      void* Out, int64_t ldo, int q_upper, RRWork& w) {
   hipStream_t s = H->ctx->stream;
@@ -382,8 +407,7 @@ int rr_impl(sparc_ham* H, void* X, int64_t ldx, int32_t n, sparc_gemm_mode mode,
     // U = X (T1 Z), formed out of place and copied back
     SPARC_TRY(rotate(s, sdt, n, n, n, w.T1, n, w.Z, n, w.Qf, n, 0));
     SPARC_TRY(rr_rotate(H, mode, n, X, ldx, w.Qf, w.W1, N, 0, w));
-    SPARC_HIP(hipMemcpy2DAsync(X, ldx * elem_bytes(dt), w.W1, N * elem_bytes(dt), N * elem_bytes(dt), n,
-                               hipMemcpyDeviceToDevice, s));
+    SPARC_TRY(copy_cols(s, X, ldx * elem_bytes(dt), w.W1, N * elem_bytes(dt), N * elem_bytes(dt), n));
     if (info_out) *info_out = 0;
     return SPARC_OK;
   }
