@@ -127,7 +127,18 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(int n, T* __restrict__ S
     }
     if (jc > k && jc < kb) {
       const T akj = rscale(1.0 / akk, a[k + jc * LD]);
-      for (int i = k + 1 + g; i <= jc; i += 4) a[i + jc * LD] = sub_(a[i + jc * LD], mul_(conj_(a[k + i * LD]), akj));
+      int i = k + 1 + g;
+      // four rows at a time with every load issued before the stores (row k is not
+      // written in step k), then the remainder
+      for (; i + 12 <= jc; i += 16) {
+        const T r0 = a[k + i * LD], r1 = a[k + (i + 4) * LD], r2 = a[k + (i + 8) * LD], r3 = a[k + (i + 12) * LD];
+        const T c0 = a[i + jc * LD], c1 = a[i + 4 + jc * LD], c2 = a[i + 8 + jc * LD], c3 = a[i + 12 + jc * LD];
+        a[i + jc * LD] = sub_(c0, mul_(conj_(r0), akj));
+        a[i + 4 + jc * LD] = sub_(c1, mul_(conj_(r1), akj));
+        a[i + 8 + jc * LD] = sub_(c2, mul_(conj_(r2), akj));
+        a[i + 12 + jc * LD] = sub_(c3, mul_(conj_(r3), akj));
+      }
+      for (; i <= jc; i += 4) a[i + jc * LD] = sub_(a[i + jc * LD], mul_(conj_(a[k + i * LD]), akj));
     }
     __syncthreads();
   }
