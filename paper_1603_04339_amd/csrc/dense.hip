@@ -661,22 +661,22 @@ __global__ __launch_bounds__(1024) void hetrd2_kernel(int n, T* __restrict__ A, 
 }
 
 // The same reduction for n <= 64 with the whole matrix in LDS (column-major, leading
-// dimension n + 1), four waves: lane r of every wave owns row r, wave q the columns
-// c = q mod 4 of the matrix-vector product and of the rank-2 update.  Sums over rows are
+// dimension n + 1), eight waves: lane r of every wave owns row r, wave q the columns
+// c = q mod 8 of the matrix-vector product and of the rank-2 update.  Sums over rows are
 // wave butterflies, whose result is the same on every lane of every wave, so each wave
 // forms the same reflector without exchanging it (register-only DPP sums).  The matrix
 // is read once and written back once.
 template <typename T>
-__global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__ A, double* __restrict__ d,
+__global__ __launch_bounds__(512) void hetrd_small_kernel(int n, T* __restrict__ A, double* __restrict__ d,
                                                           double* __restrict__ e, T* __restrict__ tau) {
   extern __shared__ char smem[];
   const int ld = n + 1;
   T* a = (T*)smem;       // [n][ld]
   T* v = a + n * ld;     // [64]
   T* w = v + 64;         // [64]
-  T* part = w + 64;      // [4][64]
+  T* part = w + 64;      // [8][64]
   const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-  for (int c = q; c < n; c += 4)
+  for (int c = q; c < n; c += 8)
     if (r < n) a[r + c * ld] = A[r + (int64_t)c * n];
   __syncthreads();
   for (int i = 0; i < n - 1; ++i) {
@@ -718,13 +718,14 @@ __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__
       // (p^H v), w = p + alpha2 v
       T acc = mkT<T>(0.0, 0.0);
       if (r >= r0 && r < n) {
-        int c = r0 + ((q - r0) & 3);
-#pragma unroll 4
-        for (; c < n; c += 4) acc = add_(acc, mul_(a[r + c * ld], v[c]));
+        int c = r0 + ((q - r0) & 7);
+#pragma unroll 2
+        for (; c < n; c += 8) acc = add_(acc, mul_(a[r + c * ld], v[c]));
       }
       part[q * 64 + r] = acc;
       __syncthreads();
-      const T sum = add_(add_(part[r], part[64 + r]), add_(part[128 + r], part[192 + r]));
+      const T sum = add_(add_(add_(part[r], part[64 + r]), add_(part[128 + r], part[192 + r])),
+                         add_(add_(part[256 + r], part[320 + r]), add_(part[384 + r], part[448 + r])));
       const T pr = (r >= r0 && r < n) ? mul_(tau_i, sum) : mkT<T>(0.0, 0.0);
       const T t = mul_(conj_(pr), vr);
       double sr = wave_sum_dpp(re_(t)), si = 0.0;
@@ -735,9 +736,9 @@ __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__
       __syncthreads();
       // A_sub -= v w^H + w v^H over this wave's columns
       if (r >= r0 && r < n) {
-        int c = r0 + ((q - r0) & 3);
-#pragma unroll 4
-        for (; c < n; c += 4)
+        int c = r0 + ((q - r0) & 7);
+#pragma unroll 2
+        for (; c < n; c += 8)
           a[r + c * ld] = sub_(a[r + c * ld], add_(mul_(vr, conj_(w[c])), mul_(wr, conj_(v[c]))));
       }
       __syncthreads();
@@ -750,7 +751,7 @@ __global__ __launch_bounds__(256) void hetrd_small_kernel(int n, T* __restrict__
   }
   __syncthreads();
   if (threadIdx.x == 0) d[n - 1] = re_(a[(n - 1) + (n - 1) * ld]);
-  for (int c = q; c < n; c += 4)
+  for (int c = q; c < n; c += 8)
     if (r < n) A[r + (int64_t)c * n] = a[r + c * ld];
 }
 
@@ -1362,10 +1363,10 @@ static int heev_t(hipStream_t s, int n, T* A, double* w, T* Z, void* work) {
   } else if (n == 1) {
     hetrd_kernel<T><<<1, 64, 2 * n * sizeof(T), s>>>(n, A, d, e, tau);
   } else if (n <= 64) {
-    const size_t lds_s = ((size_t)n * (n + 1) + 384) * sizeof(T);
+    const size_t lds_s = ((size_t)n * (n + 1) + 640) * sizeof(T);
     SPARC_HIP(hipFuncSetAttribute((const void*)hetrd_small_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds_s));
-    hetrd_small_kernel<T><<<1, 256, lds_s, s>>>(n, A, d, e, tau);
+    hetrd_small_kernel<T><<<1, 512, lds_s, s>>>(n, A, d, e, tau);
   } else if (lds2 <= 150 * 1024) {
     SPARC_HIP(hipFuncSetAttribute((const void*)hetrd2_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2));
     hetrd2_kernel<T><<<1, n < 64 ? 128 : 1024, lds2, s>>>(n, A, d, e, tau);
