@@ -405,6 +405,7 @@ __global__ void gram_reduce_kernel(int na, int nb, int n_slab, const double* __r
   const int64_t mat = (int64_t)na * nb * (cplx ? 2 : 1);
   const int64_t off = (si + (int64_t)sj * na) * (cplx ? 2 : 1);
   double re = 0, im = 0;
+#pragma unroll 8
   for (int s = 0; s < n_slab; ++s) {
     re += part[s * mat + off];
     if (cplx) im += part[s * mat + off + 1];
@@ -415,6 +416,35 @@ __global__ void gram_reduce_kernel(int na, int nb, int n_slab, const double* __r
     C[2 * (i + (int64_t)j * ldc) + 1] = conj_ ? -im : im;
   } else {
     C[i + (int64_t)j * ldc] = re;
+  }
+}
+
+// The Hermitian form: one thread per element of the upper triangle (column j = block y,
+// consecutive threads consecutive rows, so the partials are read in full lines), which
+// writes the element and its mirror; the same sum in the same order as above.
+__global__ __launch_bounds__(256) void gram_reduce_herm_kernel(int n, int n_slab, const double* __restrict__ part,
+                                                               double* __restrict__ C, int ldc, int cplx) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y;
+  if (i > j || i >= n) return;
+  const int64_t mat = (int64_t)n * n * (cplx ? 2 : 1);
+  const int64_t off = (i + (int64_t)j * n) * (cplx ? 2 : 1);
+  double re = 0, im = 0;
+#pragma unroll 8
+  for (int s = 0; s < n_slab; ++s) {
+    re += part[s * mat + off];
+    if (cplx) im += part[s * mat + off + 1];
+  }
+  if (i == j) im = 0;
+  if (cplx) {
+    C[2 * (i + (int64_t)j * ldc)] = re;
+    C[2 * (i + (int64_t)j * ldc) + 1] = im;
+    if (i != j) {
+      C[2 * (j + (int64_t)i * ldc)] = re;
+      C[2 * (j + (int64_t)i * ldc) + 1] = -im;
+    }
+  } else {
+    C[i + (int64_t)j * ldc] = re;
+    if (i != j) C[j + (int64_t)i * ldc] = re;
   }
 }
 
@@ -549,6 +579,10 @@ static int gram_launch(hipStream_t s, int64_t N, int na, int nb, const E* A, int
   if (ne <= 4096 && p.n_slab > 64)
     gram_reduce_wave_kernel<<<(unsigned)((ne + 3) / 4), 256, 0, s>>>(na, nb, p.n_slab, part, (double*)C, ldc,
                                                                      cplx ? 1 : 0, herm ? 1 : 0);
+  else if (herm && na == nb && nb <= 65535)
+    gram_reduce_herm_kernel<<<dim3((unsigned)((na + 255) / 256), (unsigned)nb), 256, 0, s>>>(na, p.n_slab, part,
+                                                                                           (double*)C, ldc,
+                                                                                           cplx ? 1 : 0);
   else
     gram_reduce_kernel<<<(unsigned)((ne + 255) / 256), 256, 0, s>>>(na, nb, p.n_slab, part, (double*)C, ldc,
                                                                     cplx ? 1 : 0, herm ? 1 : 0);
