@@ -188,13 +188,14 @@ static void nl_gather_launch(sparc_ham* H, const void* x, int64_t ldx, int32_t n
       alpha_ld(n_s));
 }
 
-// One work-group per (atom, NB orbitals): NB = 8 (4 complex), or 2 (1 complex) when that
-// would leave fewer than two work-groups per CU (few atoms and orbitals: the SCF cells),
-// which spreads each atom's sums over more CUs
+// One work-group per (atom, NB orbitals): NB = 4 (measured on the c2 block: 362 us per
+// launch against 385 with 8, 387 with 2 and 491 with 16), or 2 (1 complex) when 4 would
+// leave fewer than two work-groups per CU (few atoms and orbitals: the SCF cells), which
+// spreads each atom's sums over more CUs
 template <typename E>
 static int nl_project_t(sparc_ham* H, const void* x, int64_t ldx, int32_t n_s, void* alpha) {
   if (H->n_proj == 0) return SPARC_OK;
-  constexpr int NBW = elem<E>::is_cplx ? 4 : 8, NBN = NBW / 4;
+  constexpr int NBW = 4, NBN = elem<E>::is_cplx ? 1 : 2;
   const bool narrow = (int64_t)H->n_atoms_nl * ((n_s + NBW - 1) / NBW) < 2 * (int64_t)H->ctx->n_cu;
   int t = timer_begin(H->ctx, "nl_gather");
   struct End { sparc_ctx* c; int t; ~End() { timer_end(c, t); } } end_{H->ctx, t};
